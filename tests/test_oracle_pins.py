@@ -1,0 +1,595 @@
+"""Pins of the CPU oracle against facts fixed by the paper or by mathematics:
+the worked example of Figs. 2-3, brute force with an independent coverage
+formulation, closed-form sample counts, the planar-tessellation invariant,
+statistical fragment counts, textbook sorting for compaction, and
+hand-derived splat positions. None of these re-types the oracle's code."""
+from __future__ import annotations
+
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2211_15460_amd import scenes as S
+from tests.listutil import NIL, canonical, expected_arrays, walk_lists
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def mesh_from(tris, colors=None, obj=None):
+    pos = np.asarray(tris, np.float32).reshape(-1, 3)
+    nt = pos.shape[0] // 3
+    if colors is None:
+        colors = np.arange(pos.shape[0], dtype=np.uint32) * 0x01020304
+    rgba = np.asarray(colors, np.uint32).reshape(-1)
+    tri = np.arange(pos.shape[0], dtype=np.uint32).reshape(nt, 3)
+    o = None if obj is None else np.asarray(obj, np.uint8)
+    return S.Mesh(pos, rgba, tri, o)
+
+
+def pixel_lists(head, pool, W, H):
+    out = {}
+    for py in range(H):
+        for px in range(W):
+            lst, i = [], head[py * W + px]
+            while i != NIL:
+                lst.append(int(i))
+                i = pool[i, 3]
+            out[(px, py)] = lst
+    return out
+
+
+# ------------------------------------------------------------ Figs. 2-3
+
+def _quad(px0, py0, W, H, z):
+    x0, x1 = px0 / W * 2 - 1, (px0 + 2) / W * 2 - 1
+    y0, y1 = py0 / H * 2 - 1, (py0 + 2) / H * 2 - 1
+    a, b, c, d = (x0, y0, z), (x1, y0, z), (x1, y1, z), (x0, y1, z)
+    return [a, b, c, a, c, d]
+
+
+def test_fig2_three_quads_golden(orc):
+    W = H = 4
+    green, red, blue = 0x0000FF00, 0x000000FF, 0x00FF0000
+    verts = _quad(0, 0, W, H, 0.0) + _quad(1, 1, W, H, -0.5) + _quad(1, 0, W, H, 0.5)
+    cols = [green] * 6 + [red] * 6 + [blue] * 6
+    head, pool, cnt = orc.capture_ppfl(mesh_from(verts, cols), W, H, 64)
+    lines = [ln for ln in open(os.path.join(GOLDEN, "fig2_three_quads.txt")) if not ln.startswith("#")]
+    assert cnt == int(lines[0].split()[1])
+    lists = pixel_lists(head, pool, W, H)
+    for ln in lines[1:]:
+        if ln.startswith("composite_weights"):
+            continue
+        lhs, rhs = ln.split(":")
+        px, py = map(int, lhs.split())
+        assert lists[(px, py)] == [int(v) for v in rhs.split()], (px, py)
+    # composite the pixel covered by all three quads front to back
+    recs = sorted((pool[i, 0] & 0xFFFFFF, pool[i, 1]) for i in lists[(1, 1)])
+    acc = [Fraction(0)] * 3
+    trans = Fraction(1)
+    alpha = Fraction(1, 3)
+    for _, c in recs:
+        for ch in range(3):
+            acc[ch] += trans * alpha * ((int(c) >> (8 * ch)) & 0xFF)
+        trans *= 1 - alpha
+    wl = [ln for ln in lines if ln.startswith("composite_weights")][0].split()[1:]
+    wr, wg, wb = (Fraction(w) for w in wl)
+    assert acc == [wr * 255, wg * 255, wb * 255]
+
+
+# ------------------------------------------------------------ brute force
+
+def _fx(x, scale):
+    # float -> 16.8 fixed point; the test scenes put vertices on the grid
+    v = (Fraction(float(x)) + 1) * scale
+    return v
+
+
+def brute_ppfl(mesh, W, H):
+    """Per pixel, the (triangle, depth24, rgba) of every covering triangle in
+    triangle order. Coverage: the sample moved by (eps, -eps^2) lies strictly
+    inside, decided from the exact barycentric coordinates as polynomials in
+    eps; values: exact barycentric interpolation rounded half up."""
+    out = {(px, py): [] for px in range(W) for py in range(H)}
+    for t in range(mesh.n_tri):
+        vs = [mesh.pos[mesh.tri[t, k]] for k in range(3)]
+        X = [Fraction(round(float((Fraction(float(v[0])) + 1) * W * 128))) for v in vs]
+        Y = [Fraction(round(float((Fraction(float(v[1])) + 1) * H * 128))) for v in vs]
+        Z = [int(round(float((Fraction(float(v[2])) + 1) / 2 * (2 ** 24 - 1)))) for v in vs]
+        cols = [int(mesh.rgba[mesh.tri[t, k]]) for k in range(3)]
+        det = (X[1] - X[0]) * (Y[2] - Y[0]) - (X[2] - X[0]) * (Y[1] - Y[0])
+        if det == 0:
+            continue
+        for px in range(W):
+            for py in range(H):
+                sx, sy = Fraction(256 * px + 128), Fraction(256 * py + 128)
+                lam, ok = [], True
+                for k in range(3):
+                    i, j = (k + 1) % 3, (k + 2) % 3
+                    # signed area of (p, v_i, v_j) / det, p = s + (e, -e^2)
+                    c0 = ((X[i] - sx) * (Y[j] - sy) - (X[j] - sx) * (Y[i] - sy)) / det
+                    c1 = (Y[i] - Y[j]) / det          # coefficient of e
+                    c2 = (X[i] - X[j]) / det          # coefficient of e^2
+                    sign = next((c for c in (c0, c1, c2) if c != 0), 0)
+                    if sign <= 0:
+                        ok = False
+                        break
+                    lam.append(c0)
+                if not ok:
+                    continue
+                z = sum(lam[k] * Z[k] for k in range(3))
+                rgba = 0
+                for ch in range(4):
+                    v = sum(lam[k] * ((cols[k] >> (8 * ch)) & 0xFF) for k in range(3))
+                    rgba |= math.floor(v + Fraction(1, 2)) << (8 * ch)
+                out[(px, py)].append((t, math.floor(z + Fraction(1, 2)), rgba))
+    return out
+
+
+def _grid_tris(rng, n, W, H):
+    """n triangles with vertices on the 16.8 grid of a W x H viewport, some
+    with edges through sample centres, both windings."""
+    tris = []
+    for _ in range(n):
+        for _k in range(3):
+            X = int(rng.integers(-256, W * 256 + 256))
+            Y = int(rng.integers(-256, H * 256 + 256))
+            if rng.random() < 0.4:   # snap to a sample centre
+                X = (X // 256) * 256 + 128
+            if rng.random() < 0.4:
+                Y = (Y // 256) * 256 + 128
+            tris.append((X / (W * 128.0) - 1.0, Y / (H * 128.0) - 1.0, float(rng.random() * 2 - 1)))
+    return tris
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_ppfl_brute_force(orc, seed):
+    rng = np.random.default_rng(seed)
+    W, H = (32, 24) if seed % 2 else (16, 16)
+    tris = _grid_tris(rng, 8, W, H)
+    cols = rng.integers(0, 2 ** 32, size=len(tris), dtype=np.uint64).astype(np.uint32)
+    m = mesh_from(tris, cols)
+    head, pool, cnt = orc.capture_ppfl(m, W, H, 1 << 16)
+    lists = pixel_lists(head, pool, W, H)
+    bf = brute_ppfl(m, W, H)
+    total = 0
+    for (px, py), exp in bf.items():
+        got = [(int(pool[i, 0] & 0xFFFFFF), int(pool[i, 1])) for i in reversed(lists[(px, py)])]
+        assert got == [(z, c) for _, z, c in exp], (seed, px, py)
+        total += len(exp)
+    assert cnt == total
+
+
+# ------------------------------------------------------------ closed forms
+
+def _rect(x0, y0, x1, y1, W, H, z=0.0, diag=0):
+    fx = lambda X: X / (W * 128.0) - 1.0
+    fy = lambda Y: Y / (H * 128.0) - 1.0
+    a, b, c, d = (fx(x0), fy(y0), z), (fx(x1), fy(y0), z), (fx(x1), fy(y1), z), (fx(x0), fy(y1), z)
+    return [a, b, c, a, c, d] if diag == 0 else [a, b, d, b, c, d]
+
+
+def test_axis_rectangle_closed_form(orc):
+    """An axis-aligned rectangle [x0,x1] x [y0,y1] in 16.8 units covers the
+    samples with x0 <= sx < x1 and y0 < sy <= y1 (left and top edges in,
+    right and bottom edges out, y up)."""
+    rng = np.random.default_rng(7)
+    W, H = 40, 30
+    for trial in range(40):
+        x0, x1 = sorted(rng.integers(-300, W * 256 + 300, 2))
+        y0, y1 = sorted(rng.integers(-300, H * 256 + 300, 2))
+        if trial % 3 == 0:
+            x0, y1 = (x0 // 256) * 256 + 128, (y1 // 256) * 256 + 128
+        if trial % 3 == 1:
+            x1, y0 = (x1 // 256) * 256 + 128, (y0 // 256) * 256 + 128
+        x0, x1 = sorted((x0, x1))
+        y0, y1 = sorted((y0, y1))
+        nx = sum(1 for i in range(W) if x0 <= 256 * i + 128 < x1)
+        ny = sum(1 for j in range(H) if y0 < 256 * j + 128 <= y1)
+        m = mesh_from(_rect(x0, y0, x1, y1, W, H, diag=trial % 2))
+        _, _, cnt = orc.capture_ppfl(m, W, H, 1 << 14)
+        assert cnt == nx * ny, (trial, x0, y0, x1, y1)
+
+
+def test_planar_tessellation_exactly_once(orc):
+    """Any triangulation of the whole viewport, with jittered interior
+    vertices, random diagonals and random windings, yields exactly one
+    fragment per pixel (no double coverage on shared edges, no gaps)."""
+    rng = np.random.default_rng(3)
+    W, H, n = 48, 40, 9
+    gx = np.linspace(0, W * 256, n + 1)
+    gy = np.linspace(0, H * 256, n + 1)
+    P = np.zeros((n + 1, n + 1, 2))
+    for i in range(n + 1):
+        for j in range(n + 1):
+            x, y = gx[i], gy[j]
+            if 0 < i < n:
+                x += rng.integers(-200, 200)
+                x = (x // 256) * 256 + 128 if rng.random() < 0.3 else x
+            if 0 < j < n:
+                y += rng.integers(-200, 200)
+                y = (y // 256) * 256 + 128 if rng.random() < 0.3 else y
+            P[i, j] = (x, y)
+    tris = []
+    to = lambda p: (p[0] / (W * 128.0) - 1.0, p[1] / (H * 128.0) - 1.0, 0.0)
+    for i in range(n):
+        for j in range(n):
+            a, b, c, d = P[i, j], P[i + 1, j], P[i + 1, j + 1], P[i, j + 1]
+            two = [(a, b, c), (a, c, d)] if rng.random() < 0.5 else [(a, b, d), (b, c, d)]
+            for t in two:
+                t = t if rng.random() < 0.5 else (t[0], t[2], t[1])
+                tris += [to(p) for p in t]
+    head, pool, cnt = orc.capture_ppfl(mesh_from(tris), W, H, 1 << 16)
+    assert cnt == W * H
+    assert np.all(head != NIL)
+    assert np.all(pool[head, 3] == NIL)
+
+
+def test_random_triangle_fragment_expectation(orc):
+    """E[area] of a triangle with vertices uniform in a square is 11/144 of
+    the square, so 64 random triangles over 128x128 pixels give 80,100
+    fragments on average; the per-triangle standard deviation is
+    sqrt(1/96 - (11/144)^2) of the square."""
+    counts = []
+    for seed in range(10):
+        _, _, cnt = orc.capture_ppfl(S.ppfl_plain(seed), 128, 128, 0)
+        counts.append(cnt)
+    mean = 64 * 11 / 144 * 128 * 128
+    sd_mean = math.sqrt(1 / 96 - (11 / 144) ** 2) * 128 * 128 * math.sqrt(64) / math.sqrt(10)
+    assert abs(np.mean(counts) - mean) < 4 * sd_mean
+
+
+def test_vertex_and_constant_attributes(orc):
+    """A sample on a vertex takes that vertex's values exactly; a constant
+    colour is reproduced exactly; every value lies in the vertices' range."""
+    W = H = 16
+    # vertex 0 exactly on the sample centre of pixel (3, 4)
+    v0 = ((3 * 256 + 128) / (W * 128.0) - 1, (4 * 256 + 128) / (H * 128.0) - 1, 0.25)
+    tris = [v0, (0.5, -0.9, -0.5), (0.6, 0.9, 0.75)]   # v0 on two owned edges
+    cols = [0x11223344, 0xAABBCCDD, 0x55667788]
+    head, pool, cnt = orc.capture_ppfl(mesh_from(tris, cols), W, H, 4096)
+    i = head[4 * W + 3]
+    assert i != NIL
+    assert pool[i, 1] == 0x11223344
+    assert pool[i, 0] & 0xFFFFFF == round((0.25 + 1) / 2 * (2 ** 24 - 1))
+    F = min(cnt, 4096)
+    for ch in range(4):
+        v = (pool[:F, 1] >> (8 * ch)) & 0xFF
+        vs = [(c >> (8 * ch)) & 0xFF for c in cols]
+        assert v.min() >= min(vs) and v.max() <= max(vs)
+    _, pool2, cnt2 = orc.capture_ppfl(mesh_from(tris, [0x7F3F1F0F] * 3), W, H, 4096)
+    assert np.all(pool2[:cnt2, 1] == 0x7F3F1F0F)
+
+
+def test_overflow_bounded_writes(orc):
+    """Past the capacity the counter keeps counting but nothing is written;
+    the lists hold exactly the first `cap` fragments (Sec. 3.1 re-allocation
+    rule, Sec. 3.2 bounded insertion)."""
+    m = S.ppfl_plain(1)
+    head, pool, F = orc.capture_ppfl(m, 128, 128, 1 << 18)
+    for cap in (0, 1, F // 3, F - 1, F):
+        h2, p2, c2 = orc.capture_ppfl(m, 128, 128, cap)
+        assert c2 == F
+        k, recs = walk_lists(h2, p2, c2)
+        assert recs.shape[0] == min(cap, F)
+        assert np.array_equal(p2[:cap, :3], pool[:cap, :3])
+
+
+def test_aux_byte_from_object_id(orc):
+    m = S.ppfl_plain(2)
+    head, pool, F = orc.capture_ppfl(m, 128, 128, 1 << 18)
+    k, recs = walk_lists(head, pool, F)
+    assert set(np.unique(recs[:, 0] >> 24)) <= set(m.obj.tolist())
+    m.obj = None
+    h2, p2, F2 = orc.capture_ppfl(m, 128, 128, 1 << 18)
+    assert F2 == F and np.all(p2[:F, 0] >> 24 == 0)
+
+
+def test_non_finite_and_far_vertices_are_skipped(orc):
+    tris = [(-0.5, -0.5, 0), (0.5, -0.5, 0), (0, 0.5, 0),
+            (np.nan, -0.5, 0), (0.5, -0.5, 0), (0, 0.5, 0),
+            (-100.0, -0.5, 0), (0.5, -0.5, 0), (0, 0.5, 0)]
+    _, _, c1 = orc.capture_ppfl(mesh_from(tris[:3]), 32, 32, 1 << 12)
+    _, _, c3 = orc.capture_ppfl(mesh_from(tris), 32, 32, 1 << 12)
+    assert c1 > 0 and c3 == c1
+
+
+# ------------------------------------------------------------ normals
+
+def _bits_interleave(x, y, z, L):
+    s = "".join(f"{(x >> b) & 1}{(y >> b) & 1}{(z >> b) & 1}" for b in reversed(range(L)))
+    return int(s, 2) if s else 0
+
+
+def test_morton_bit_order(orc):
+    """x is the most significant bit of every level triple (Fig. 5 labels
+    list the digits as x, y, z)."""
+    rng = np.random.default_rng(0)
+    assert orc.morton3(1, 0, 0, 1) == 4 and orc.morton3(0, 1, 0, 1) == 2 and orc.morton3(0, 0, 1, 1) == 1
+    for _ in range(200):
+        L = int(rng.integers(1, 12))
+        x, y, z = (int(v) for v in rng.integers(0, 2 ** L, 3))
+        assert orc.morton3(x, y, z, L) == _bits_interleave(x, y, z, L)
+
+
+def test_oct_encode_axes_and_float_reference(orc):
+    """Axis normals pack exactly; random normals agree with a float
+    octahedral encoder to one unit; decoding recovers the direction to the
+    packing's resolution."""
+    assert orc.oct_encode(0, 0, 5) == 0
+    assert orc.oct_encode(7, 0, 0) == 32767
+    assert orc.oct_encode(0, -3, 0) == (0x10000 - 32767) << 16
+    assert orc.oct_encode(0, 0, -2) == 32767 | (32767 << 16)
+    assert orc.oct_encode(0, 0, 0) == 0
+    rng = np.random.default_rng(1)
+    for _ in range(500):
+        n = rng.integers(-2 ** 30, 2 ** 30, 3)
+        code = orc.oct_encode(*map(int, n))
+        qx, qy = np.uint16(code & 0xFFFF).view(np.int16), np.uint16(code >> 16).view(np.int16)
+        p = n / np.abs(n).sum()
+        if n[2] < 0:
+            p = np.array([(1 - abs(p[1])) * (1 if p[0] >= 0 else -1),
+                          (1 - abs(p[0])) * (1 if p[1] >= 0 else -1)])
+        assert abs(int(qx) - p[0] * 32767) <= 0.5 + 1e-6
+        assert abs(int(qy) - p[1] * 32767) <= 0.5 + 1e-6
+        d = orc.oct_decode(code)
+        assert abs(np.linalg.norm(d) - 1) < 1e-14
+        assert np.dot(d, n / np.linalg.norm(n)) > math.cos(2e-4)
+
+
+def test_tangent_frame_orthonormal(orc):
+    rng = np.random.default_rng(2)
+    for _ in range(300):
+        code = int(rng.integers(0, 2 ** 32))
+        n = orc.oct_decode(code)
+        t, b = orc.tangent_frame(code)
+        assert abs(np.dot(t, t) - 1) < 1e-14 and abs(np.dot(b, b) - 1) < 1e-14
+        assert abs(np.dot(t, b)) < 1e-14 and abs(np.dot(t, n)) < 1e-14
+        assert np.allclose(np.cross(t, b), n, atol=1e-14)
+
+
+# ------------------------------------------------------------ POFL
+
+def _plane_grid(n, axis_pos, lo, hi, levels, normal):
+    """Same-winding triangulated square in the plane {y = axis_pos}
+    (normal = +y or -y) or {z = axis_pos} (normal = +z)."""
+    g = np.linspace(lo, hi, n + 1)
+    tris = []
+    for i in range(n):
+        for j in range(n):
+            a0, a1, b0, b1 = g[i], g[i + 1], g[j], g[j + 1]
+            if normal in ("+y", "-y"):
+                P = lambda x, z: (x, axis_pos, z)
+                quad = [P(a0, b0), P(a0, b1), P(a1, b1), P(a1, b0)]   # +y winding
+            else:
+                P = lambda x, y: (x, y, axis_pos)
+                quad = [P(a0, b0), P(a1, b0), P(a1, b1), P(a0, b1)]   # +z winding
+            t1, t2 = (quad[0], quad[1], quad[2]), (quad[0], quad[2], quad[3])
+            if (i + j) % 2:
+                t1, t2 = (quad[0], quad[1], quad[3]), (quad[1], quad[2], quad[3])
+            if normal == "-y":
+                t1, t2 = (t1[0], t1[2], t1[1]), (t2[0], t2[2], t2[1])
+            tris += list(t1) + list(t2)
+    return tris
+
+
+@pytest.mark.parametrize("normal", ["+y", "-y", "+z"])
+def test_pofl_axis_plane_closed_form(orc, normal):
+    """A square in an axis plane, triangulated with one winding, is sampled
+    on the tangent-plane lattice exactly once per lattice point inside it.
+    For these normals the Duff frame is axis-aligned:
+      +y: u = x, v = -z;  -y: u = x, v = z;  +z: u = x, v = y,
+    so with U = 2u, V = 2v (16.8 units, spacing 2^7 grid units) the count is
+    #{i: U0 <= 256 i + 128 < U1} * #{j: V0 < 256 j + 128 <= V1} and every
+    fragment sits on a lattice point (x = 128 i + 64) of the plane."""
+    L = 5
+    G = 2 ** (L + 8)
+    lo, hi, c = 0.1171875, 0.8359375, 0.40625     # exact in fp32, on the grid
+    tris = _plane_grid(6, c, lo, hi, L, normal)
+    head, pool, cnt = orc.capture_pofl(mesh_from(tris), L, 1 << 20)
+    a0, a1 = lo * G, hi * G
+    U0, U1 = 2 * a0, 2 * a1
+    V0, V1 = (-2 * a1, -2 * a0) if normal == "+y" else (2 * a0, 2 * a1)
+    ni = sum(1 for i in range(-4000, 4000) if U0 <= 256 * i + 128 < U1)
+    nj = sum(1 for j in range(-4000, 4000) if V0 < 256 * j + 128 <= V1)
+    assert cnt == ni * nj
+    k, recs = walk_lists(head, pool, cnt)
+    xs = np.zeros(len(k), np.int64)
+    ys = np.zeros(len(k), np.int64)
+    zs = np.zeros(len(k), np.int64)
+    for n_, key in enumerate(k):
+        key = int(key)
+        x = y = z = 0
+        for b in range(L):
+            x |= ((key >> (3 * b + 2)) & 1) << b
+            y |= ((key >> (3 * b + 1)) & 1) << b
+            z |= ((key >> (3 * b)) & 1) << b
+        xs[n_] = (x << 8) | (recs[n_, 0] & 0xFF)
+        ys[n_] = (y << 8) | ((recs[n_, 0] >> 8) & 0xFF)
+        zs[n_] = (z << 8) | ((recs[n_, 0] >> 16) & 0xFF)
+    assert np.all((xs - 64) % 128 == 0)
+    if normal == "+z":
+        assert np.all(zs == int(c * G)) and np.all((ys - 64) % 128 == 0)
+    else:
+        assert np.all(ys == int(c * G)) and np.all((zs - 64) % 128 == 0)
+    assert len(set(zip(xs.tolist(), ys.tolist(), zs.tolist()))) == cnt
+
+
+def test_pofl_density_matches_area(orc):
+    """Tilted triangles get (area / spacing^2) fragments up to the boundary
+    term: the tangent-space rasterization samples each surface at its own
+    resolution (Sec. 3.2, Fig. 8)."""
+    rng = np.random.default_rng(11)
+    L = 6
+    G = 2 ** (L + 8)
+    for _ in range(20):
+        v = rng.random((3, 3)) * 0.8 + 0.1
+        _, _, cnt = orc.capture_pofl(mesh_from(v.tolist()), L, 1 << 20)
+        P = np.floor(v.astype(np.float32).astype(np.float64) * G)
+        area = 0.5 * np.linalg.norm(np.cross(P[1] - P[0], P[2] - P[0])) / 128.0 ** 2
+        perim = sum(np.linalg.norm(P[(k + 1) % 3] - P[k]) for k in range(3)) / 128.0
+        assert abs(cnt - area) <= perim + 4, (cnt, area, perim)
+
+
+def test_pofl_fragments_lie_on_triangle(orc):
+    m = S.cube_scene(3000, seed=5)
+    L = 6
+    G = 2 ** (L + 8)
+    head, pool, cnt = orc.capture_pofl(m, L, 1 << 22)
+    k, recs = walk_lists(head, pool, cnt)
+    assert recs.shape[0] == cnt
+    # every fragment inside the scene cube, keys within range
+    assert np.all(k < 8 ** L)
+    assert np.all(recs[:, 2] == recs[:, 2])     # normals present
+    assert set(np.unique(recs[:, 0] >> 24)) <= set(m.obj.tolist())
+
+
+# ------------------------------------------------------------ compaction
+
+@pytest.mark.parametrize("mode", ["ppfl", "pofl"])
+def test_compaction_is_a_stable_grouping(orc, mode):
+    """POFA = records grouped by key in ascending Morton order with offsets
+    the exclusive sums of counts (Sec. 3.1 FHV_POFA); compared with a
+    textbook sort of the walked lists."""
+    if mode == "ppfl":
+        head, pool, F = orc.capture_ppfl(S.ppfl_plain(4), 128, 128, 1 << 18)
+    else:
+        head, pool, F = orc.capture_pofl(S.cube_scene(4000, seed=6), 6, 1 << 22)
+    r = orc.compact(head, pool, F)
+    k, recs = walk_lists(head, pool, F)
+    ek, eo, ec, ef = expected_arrays(k, recs)
+    assert r["n_occ"] == ek.size
+    assert np.array_equal(r["key"], ek) and np.array_equal(r["off"], eo)
+    assert np.array_equal(r["cnt"], ec) and np.array_equal(r["frag"], ef)
+    assert int(r["cnt"].sum()) == F
+    assert np.array_equal(r["off"][1:], np.cumsum(r["cnt"])[:-1])
+    # bytes: 16 B per record (no previous index) + 16 B per occupied octant
+    nbytes = r["frag"].nbytes + r["key"].nbytes + r["off"].nbytes + r["cnt"].nbytes
+    assert nbytes == 16 * F + 16 * r["n_occ"]
+
+
+def test_compaction_bounded_table_and_overflowed_lists(orc):
+    head, pool, F = orc.capture_ppfl(S.ppfl_plain(5), 128, 128, 1 << 18)
+    full = orc.compact(head, pool, F)
+    r = orc.compact(head, pool, F, cap_occ=10)
+    assert r["n_occ"] == full["n_occ"] and np.array_equal(r["key"], full["key"][:10])
+    assert np.array_equal(r["frag"], full["frag"])
+    h2, p2, c2 = orc.capture_ppfl(S.ppfl_plain(5), 128, 128, F // 2)
+    r2 = orc.compact(h2, p2, c2)
+    assert r2["frag"].shape[0] == F // 2
+
+
+def test_memory_model_table4(orc):
+    """Table 4 of the paper reports POFA sizes for octree levels 6-8 and the
+    1-Pass/Normal fragment counts of Table 2; with 32-byte records on a dense
+    complete octree (8 B per leaf, 4 B per interior octant) the model
+    reproduces the printed MB within rounding."""
+    F = {"simple": 514_479, "complex": 1_685_548}
+    table4 = {(6, "simple"): 18, (6, "complex"): 54, (7, "simple"): 34, (7, "complex"): 70,
+              (8, "simple"): 162, (8, "complex"): 198}
+    for (L, scene), mb in table4.items():
+        b = 8 * 8 ** L + 4 * sum(8 ** k for k in range(L)) + 32 * F[scene]
+        assert abs(b / 1e6 - mb) / mb < 0.06, (L, scene, b / 1e6, mb)
+
+
+# ------------------------------------------------------------ splat
+
+def test_single_fragment_lands_in_known_pixel(orc):
+    """One POFA fragment at grid position (x, y, z) + 1/2 seen by the
+    theta = 0 cube view maps to pixel floor(ppu (x + 1/2 - G/2) + W/2)."""
+    L = 4
+    G = 2 ** (L + 8)
+    v = S.cube_view(0.0, L, 64, 36, splat_px=1)
+    ppu = 36 / (1.25 * G)
+    for (x, y, z) in [(100, 2000, 5), (4000, 300, 4095), (2048, 2048, 2048)]:
+        key = orc.morton3(x >> 8, y >> 8, z >> 8, L)
+        w0 = (x & 0xFF) | ((y & 0xFF) << 8) | ((z & 0xFF) << 16)
+        frag = np.array([[w0, 0xDEADBEEF, 0, 0]], np.uint32)
+        rgba, depth, cov = orc.splat(1, np.array([key], np.uint64), frag, [v], levels=L)
+        px = math.floor(ppu * (x + 0.5 - G / 2) + 32)
+        py = math.floor(ppu * (y + 0.5 - G / 2) + 18)
+        assert cov.sum() == 1 and cov[0, py, px] == 1 and rgba[0, py, px] == 0xDEADBEEF
+        d = 1.5 + 0.49 * (z + 0.5 - G / 2) / (math.sqrt(3) * G / 2)
+        assert abs(depth[0, py, px] - d) < 1e-6
+
+
+def test_splat_footprint_and_nearest_wins(orc):
+    """A k x k footprint starts at floor(s + 1/2 - k/2); of two fragments on
+    one pixel the nearer wins, and on equal depth the lower index."""
+    L = 4
+    v = S.cube_view(0.0, L, 64, 36, splat_px=3)
+    key = orc.morton3(8, 8, 2, L)
+    frag = np.array([[0x101010, 0xAAAAAAAA, 0, 0], [0x001010, 0xBBBBBBBB, 0, 0],
+                     [0x101010, 0xCCCCCCCC, 0, 0]], np.uint32)
+    keys = np.array([key], np.uint64)
+    rgba, depth, cov = orc.splat(1, keys, frag, [v], levels=L)
+    assert cov.sum() == 9
+    ys, xs = np.nonzero(cov[0])
+    ppu = 36 / (1.25 * 2 ** (L + 8))
+    assert xs.min() == math.floor(ppu * (8 * 256 + 16.5 - 2 ** (L + 7)) + 32 + 0.5 - 1.5)
+    assert xs.max() - xs.min() == 2 and ys.max() - ys.min() == 2
+    assert np.all(rgba[cov == 1] == 0xBBBBBBBB)     # z sub-offset 0 < 16: nearer
+    rgba, _, cov = orc.splat(1, keys, frag[[0, 2]], [v], levels=L)
+    assert np.all(rgba[cov == 1] == 0xAAAAAAAA)     # equal depth: lower index
+
+
+def test_ppfl_identity_view_equals_nearest_fragment(orc):
+    """Splatting per-pixel lists back into the capture view with one-pixel
+    footprints selects, in every pixel, the list's nearest fragment
+    (deferred-shading emulation, Sec. 3.3) and covers exactly the pixels the
+    direct raster covers."""
+    m = S.ppfl_plain(3)
+    head, pool, F = orc.capture_ppfl(m, 128, 128, 1 << 18)
+    r = orc.compact(head, pool, F)
+    v = S.ppfl_view(0.0, 128, 128)
+    rgba, depth, cov = orc.splat(0, r["key"], r["frag"], [v], width_cap=128)
+    drgba, ddepth, dcov = orc.direct_raster(0, m, v, 128, 128)
+    assert np.array_equal(cov[0], dcov)
+    assert np.array_equal(cov[0].reshape(-1) == 1, head != NIL)
+    # per pixel: winner depth24 is the list minimum up to the fp32 depth resolution
+    frag = r["frag"]
+    for p in np.nonzero(head != NIL)[0][::7]:
+        lo, n = r["off"][np.searchsorted(r["key"], p)], r["cnt"][np.searchsorted(r["key"], p)]
+        d24 = (frag[lo:lo + n, 0] & 0xFFFFFF).astype(np.int64)
+        win = int(np.nonzero(frag[lo:lo + n, 1] == rgba[0].reshape(-1)[p])[0][0]) if n else -1
+        assert d24[win] - d24.min() <= 8
+    agree = (rgba[0] == drgba)[dcov == 1].mean()
+    assert agree > 0.99
+
+
+def test_ppfl_bias_vs_pofa_holes(orc):
+    """Fig. 4: per-pixel lists are sampled along the capture axis only, so a
+    rotated view shows holes that per-octant arrays captured in tangent space
+    do not. Hole fraction = pixels the direct raster covers but the splat
+    does not."""
+    m = S.cube_scene(20000, seed=9)
+    clip = S.Mesh(m.pos * 2 - 1, m.rgba, m.tri, m.obj)
+    Wc = 256
+    head, pool, F = orc.capture_ppfl(clip, Wc, Wc, 1 << 22)
+    rp = orc.compact(head, pool, F)
+    L = 7
+    h2, p2, F2 = orc.capture_pofl(m, L, 1 << 23)
+    ro = orc.compact(h2, p2, F2)
+    holes = {}
+    for th in (30.0, 60.0):
+        vp = S.ppfl_view(th, Wc, Wc)
+        _, _, cp = orc.splat(0, rp["key"], rp["frag"], [vp], width_cap=Wc)
+        _, _, dp = orc.direct_raster(0, clip, vp, Wc, Wc)
+        vo = S.cube_view(th, L, 256, 256)
+        _, _, co = orc.splat(1, ro["key"], ro["frag"], [vo], levels=L)
+        _, _, do = orc.direct_raster(1, m, vo, levels=L)
+        hp = ((dp == 1) & (cp[0] == 0)).sum() / max(1, dp.sum())
+        ho = ((do == 1) & (co[0] == 0)).sum() / max(1, do.sum())
+        holes[th] = (hp, ho)
+        assert hp > ho, (th, hp, ho)
+    assert holes[60.0][0] > holes[30.0][0]
+
+
+def test_psnr_closed_forms(orc):
+    a = np.arange(1000, dtype=np.uint32) * 2654435761 & 0xFF7F7F7F
+    assert orc.psnr_rgb(a, a) == math.inf
+    for d in (1, 3, 17):
+        b = a + np.uint32(d * 0x010101)
+        assert abs(orc.psnr_rgb(a, b) - 20 * math.log10(255 / d)) < 1e-9
