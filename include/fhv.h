@@ -1,0 +1,239 @@
+/*
+ * fhv.h - C ABI of the MI355X (gfx950) fragment-history-volume library.
+ *
+ * Fragment-history volumes (Inacio and Springer, arXiv 2211.15460) record
+ * every fragment a rasterizer produces for a scene, with no culling of any
+ * kind, in pre-allocated storage (Sec. 3.1, Sec. 3.2), and reconstruct novel
+ * views from that record (Sec. 3.3). This library implements the
+ * data-parallel path:
+ *
+ *   fhv_capture  rasterize triangles into per-pixel (FHV_PPFL) or per-octant
+ *                (FHV_POFL) linked fragment lists, Sec. 3.1 "Simple Layout"
+ *                and "Octree Layout", Sec. 3.2 FHV_PPFL / FHV_POFL;
+ *   fhv_compact  turn the lists into per-octant arrays (FHV_POFA): a count
+ *                and an offset per occupied octant, offsets in Morton order,
+ *                each octant's fragments contiguous, Sec. 3.1 and 3.2
+ *                FHV_POFA;
+ *   fhv_splat    point-splat the arrays into novel views, the nearest
+ *                fragment per pixel winning, Sec. 3.3.
+ *
+ * Conventions shared by every call:
+ *   - Every buffer pointer in a struct or argument is a DEVICE pointer owned
+ *     by the caller, unless the comment says "host". The library allocates
+ *     nothing on the device; scratch memory comes in through `ws`.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream)
+ *     and the calls return without waiting for it. Results that are data
+ *     dependent (fragment counts, occupied octants) stay on the device.
+ *   - Host-side argument checks happen before anything is enqueued; a
+ *     negative status means nothing was enqueued. A positive status
+ *     FHV_EHIP + e reports HIP runtime error e from a launch.
+ *   - Calls on different streams with disjoint buffers do not interact;
+ *     calls sharing a workspace or output buffers must be ordered by the
+ *     caller.
+ *   - Records are 16 bytes, four little-endian uint32 words:
+ *       w0  PPFL: depth24 | aux << 24
+ *           POFL: sub-leaf x | y << 8 | z << 16 | aux << 24 (grid units)
+ *       w1  RGBA8 interpolated from the vertices, R in the low byte
+ *       w2  octahedral-packed face normal, int16 x | int16 y << 16
+ *       w3  lists: index of the previous fragment of the same key, or
+ *           0xFFFFFFFF; arrays: rank of the fragment's octant in the table
+ *     aux is the low byte of the triangle's object id (0 without ids).
+ *
+ * Geometry conventions (the paper fixes none of them):
+ *   - PPFL: orthographic capture of clip space [-1,1]^3 along +z into a
+ *     width x height window, y up; screen positions in 16.8 fixed point,
+ *     one sample at every pixel centre; depth24 = rint((z+1)/2 (2^24-1)).
+ *     Triangles with a vertex coordinate beyond +-64 or not finite are
+ *     skipped.
+ *   - POFL: scene cube [0,1)^3 on a grid of 2^(L+8) units per side; each
+ *     triangle is rasterized in the tangent plane of its own packed normal
+ *     (Sec. 3.2, Fig. 8) on a lattice of 2^7 grid units (2^(L+1) samples
+ *     per side) anchored at the grid origin; the fragment's leaf octant is
+ *     the top L bits of its grid position per axis, keyed by the Morton
+ *     code with x as the most significant bit of each level. Triangles with
+ *     a non-finite coordinate or a zero integer normal are skipped.
+ *   - Both: top-left fill rule for counter-clockwise triangles with y up;
+ *     both windings are rasterized; attributes are interpolated with integer
+ *     edge-function weights, (sum_k w_k a_k + floor(A/2)) / A.
+ */
+#ifndef FHV_H
+#define FHV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define FHV_API __attribute__((visibility("default")))
+#else
+#define FHV_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fhv_status;
+#define FHV_OK 0
+#define FHV_EINVAL (-1)     /* null pointer, bad mode, inconsistent sizes   */
+#define FHV_EWORKSPACE (-2) /* ws_bytes below the workspace query's result  */
+#define FHV_ERANGE (-3)     /* a size beyond what the kernels support       */
+#define FHV_EHIP 1000       /* FHV_EHIP + hipError_t from the HIP runtime   */
+
+enum { FHV_PPFL = 0, FHV_POFL = 1 };
+
+typedef struct fhv_ctx fhv_ctx; /* opaque: device id and properties         */
+typedef void* fhv_stream;       /* hipStream_t                              */
+
+/* Context for HIP device `hip_device` (made current by every call).
+ * *out receives a host object freed by fhv_destroy. */
+FHV_API fhv_status fhv_create(fhv_ctx** out, int hip_device);
+FHV_API fhv_status fhv_destroy(fhv_ctx* ctx);
+/* Static string naming a status code (never NULL). */
+FHV_API const char* fhv_status_str(fhv_status s);
+
+/* Indexed triangle soup. pos: float [n_vert][3] (PPFL: clip space; POFL:
+ * scene cube [0,1)); rgba: uint32 [n_vert]; tri: uint32 [n_tri][3] vertex
+ * indices, every index < n_vert (not checked on the device); obj: uint8
+ * [n_tri] object ids or NULL. */
+typedef struct {
+    const float* pos;
+    const uint32_t* rgba;
+    const uint32_t* tri;
+    const uint8_t* obj;
+    uint32_t n_vert;
+    uint32_t n_tri;
+} fhv_mesh;
+
+/* What to capture. PPFL: width, height in [1, 16384]; POFL: levels in
+ * [1, 10] (octree depth L). Unused fields are ignored. */
+typedef struct {
+    uint32_t mode;
+    uint32_t width;
+    uint32_t height;
+    uint32_t levels;
+} fhv_capture_desc;
+
+/* Fragment lists (Sec. 3.1, Fig. 3 and Fig. 5).
+ * head: uint32 [n_head], n_head = width*height (PPFL) or 8^L (POFL); entry
+ *       = index of the last fragment inserted for that pixel/octant, or
+ *       0xFFFFFFFF. Reset by fhv_capture.
+ * pool: uint32 [capacity][4] records, 16-byte aligned; capacity < 2^32 - 1.
+ * keys: uint32 [capacity], the pixel or octant key of every pool slot (a
+ *       sidecar that lets fhv_compact read the pool linearly).
+ * counter: one uint64; after the stream has run, the number of fragments
+ *       produced. Reset by fhv_capture. If *counter > capacity the capture
+ *       overflowed: the pool holds the first `capacity` fragments that
+ *       claimed a slot, no head or link refers to an index >= capacity, and
+ *       the caller re-allocates *counter slots and captures again (the
+ *       paper's re-allocation for the next frame, Sec. 3.1). */
+typedef struct {
+    uint32_t* head;
+    uint64_t n_head;
+    uint32_t* pool;
+    uint64_t capacity;
+    uint32_t* keys;
+    uint64_t* counter;
+} fhv_lists;
+
+/* Bytes of scratch memory fhv_capture needs for n_tri triangles; 0 for an
+ * invalid desc. */
+FHV_API size_t fhv_capture_workspace(const fhv_capture_desc* desc, uint32_t n_tri);
+
+/* Capture every rasterized fragment of `mesh` (Sec. 3.2): resets head to
+ * 0xFFFFFFFF and the counter to 0, then for every covered sample takes
+ * idx = counter++; when idx < capacity it writes the record with w3 = the
+ * key's previous head and makes idx the key's head (atomic exchange), and
+ * writes keys[idx]. Fragment order in the pool and in each list is not
+ * deterministic; the multiset of records per key is.
+ * Errors: EINVAL (null ctx/desc/mesh arrays/lists arrays, bad mode, n_head
+ * not matching desc), ERANGE (sizes out of range), EWORKSPACE. */
+FHV_API fhv_status fhv_capture(fhv_ctx* ctx, const fhv_mesh* mesh, const fhv_capture_desc* desc,
+                       const fhv_lists* lists, void* ws, size_t ws_bytes, fhv_stream stream);
+
+/* Per-octant arrays (FHV_POFA, Sec. 3.1 Fig. 6, Sec. 3.2).
+ * oct_key/oct_off/oct_cnt: [cap_occ] table of occupied keys ascending, the
+ *       offset of the key's first fragment in frag and its fragment count.
+ * frag: uint32 [cap_frag][4], 16-byte aligned; cap_frag >= the lists'
+ *       capacity.
+ * n_occ: one uint64, number of occupied keys (table rows at index >=
+ *       cap_occ are not written); n_frag: one uint64, number of fragments
+ *       in frag = min(counter, capacity). */
+typedef struct {
+    uint64_t* oct_key;
+    uint32_t* oct_off;
+    uint32_t* oct_cnt;
+    uint64_t cap_occ;
+    uint32_t* frag;
+    uint64_t cap_frag;
+    uint64_t* n_occ;
+    uint64_t* n_frag;
+} fhv_pofa;
+
+/* Bytes of scratch memory fhv_compact needs for lists of `capacity` slots. */
+FHV_API size_t fhv_compact_workspace(const fhv_capture_desc* desc, uint64_t capacity);
+
+/* Compaction (Sec. 3.2 FHV_POFA): for every occupied key in ascending
+ * order, count = its list length, offset = sum of the counts of all smaller
+ * keys; its records are stored at frag[offset .. offset+count) ascending by
+ * (w0, w1, w2) as unsigned words, with w3 = the key's rank in the table.
+ * PPFL lists compact the same way with key = py*width + px (an S-buffer-like
+ * per-pixel array). Reads the pool's first min(counter, capacity) slots and
+ * their keys; the lists must come from fhv_capture with the same desc.
+ * Errors: EINVAL, ERANGE, EWORKSPACE as for fhv_capture. */
+FHV_API fhv_status fhv_compact(fhv_ctx* ctx, const fhv_lists* lists, const fhv_capture_desc* desc,
+                       const fhv_pofa* out, void* ws, size_t ws_bytes, fhv_stream stream);
+
+/* One novel view (host struct, passed by value inside a host array).
+ * m: row-major fp32 3x4 matrix taking a fragment position to (screen x,
+ * screen y, depth) with screen units of pixels, y up, and depth > 0
+ * growing away from the viewer; each row is evaluated in fp32 as
+ * ((m0 x + m1 y) + m2 z) + m3 with no fused multiply-add. Fragment
+ * positions: PPFL (px + 1/2, py + 1/2, depth24); POFL grid position + 1/2
+ * per axis. splat_px: side k of the square footprint, >= 1. */
+typedef struct {
+    float m[12];
+    uint32_t width;
+    uint32_t height;
+    uint32_t splat_px;
+} fhv_view;
+
+/* Point splat (Sec. 3.3): every array fragment i covers the k x k pixels
+ * whose lower-left pixel is floor(s + 1/2 - k/2) per axis in every view;
+ * per pixel the smallest (fp32 depth bits << 32 | i) wins (64-bit atomic
+ * minimum); fragments with depth <= 0 or NaN are skipped. Then each pixel
+ * resolves to the winner's w1 colour, its depth and coverage 1, or to 0, 0.0
+ * and 0 when nothing covers it.
+ * Fragments whose rank has no stored table row (rank >= cap_occ) are not
+ * drawn.
+ * views: host array of n_views in [1, 32] entries sharing width, height in
+ * [1, 16384]. zbuf: uint64 [n_views][height][width] scratch, 16-byte
+ * aligned; rgba: uint32,
+ * depth: float, cov: uint8, each [n_views][height][width].
+ * Errors: EINVAL (null pointers, views of different sizes, splat_px 0 or
+ * above 64), ERANGE. */
+FHV_API fhv_status fhv_splat(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_capture_desc* desc,
+                     const fhv_view* views, uint32_t n_views, uint64_t* zbuf, uint32_t* rgba,
+                     float* depth, uint8_t* cov, fhv_stream stream);
+
+/* Kernel timing (tracing). Between fhv_profile_begin and fhv_profile_end
+ * every kernel the library enqueues is bracketed by two HIP events on the
+ * stream it runs on. fhv_profile_end waits for those events and reports,
+ * per kernel name, the number of launches and their summed duration; it
+ * writes at most `cap` entries to `out` (host array) and the number of
+ * distinct kernels to *n_out. Names are static strings owned by the
+ * library. Not for use while a caller captures the stream into a graph. */
+typedef struct {
+    const char* name;
+    uint64_t launches;
+    double total_ms;
+} fhv_kernel_stat;
+
+FHV_API fhv_status fhv_profile_begin(fhv_ctx* ctx);
+FHV_API fhv_status fhv_profile_end(fhv_ctx* ctx, fhv_kernel_stat* out, uint32_t cap,
+                                   uint32_t* n_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FHV_H */

@@ -1,0 +1,391 @@
+// Capture: rasterize every triangle into per-pixel (PPFL) or per-octant
+// (POFL) fragment lists (Sec. 3.1 "Simple Layout" / "Octree Layout",
+// Sec. 3.2 FHV_PPFL / FHV_POFL).
+//
+// Kernels, in stream order:
+//   fills     head <- 0xFFFFFFFF, counter <- 0
+//   k_setup   one thread per triangle: fixed-point vertices (PPFL: viewport
+//             transform; POFL: grid snap, exact integer normal, octahedral
+//             packing, tangent frame of the packed normal, projection),
+//             orientation, sample bounding box, number of 8x8 sample tiles
+//   scan      inclusive prefix sum of tiles per triangle
+//   k_raster  one wave per (triangle, tile) work item, one lane per sample:
+//             integer edge functions with the top-left rule, integer
+//             attribute interpolation, list append
+//
+// List append per covered sample (Sec. 3.2): the wave reserves its covered
+// samples' slots with one atomic add on the global counter; each lane with
+// a slot below the capacity swaps its index into the key's head and stores
+// {w0, rgba, normal, previous head} plus the key sidecar.
+//
+// The fp64 setup relies on IEEE-correct add, mul, div, sqrt and rint and on
+// no contraction into fused multiply-adds (built with -ffp-contract=off):
+// the tangent frame is then reproducible operation by operation.
+#include <math.h>
+
+#include "fhv_common.h"
+
+namespace fhv {
+
+namespace {
+
+__device__ __forceinline__ int32_t round_snorm(int64_t num, int64_t l1)
+{
+    const int64_t a = num < 0 ? -num : num;
+    const int64_t q = (2 * 32767 * a + l1) / (2 * l1);
+    return (int32_t)(num < 0 ? -q : q);
+}
+
+// Exact octahedral packing of an integer normal (Cigolle et al. 2014):
+// n / |n|_1 folded when n_z < 0, components rounded to multiples of
+// 1/32767 with halves away from zero; int16 x | int16 y << 16.
+__device__ uint32_t oct_pack(int64_t nx, int64_t ny, int64_t nz)
+{
+    const int64_t ax = nx < 0 ? -nx : nx, ay = ny < 0 ? -ny : ny, az = nz < 0 ? -nz : nz;
+    const int64_t l1 = ax + ay + az;
+    if (l1 == 0) return 0;
+    int32_t qx, qy;
+    if (nz >= 0) {
+        qx = round_snorm(nx, l1);
+        qy = round_snorm(ny, l1);
+    } else {
+        qx = round_snorm(nx < 0 ? -(l1 - ay) : (l1 - ay), l1);
+        qy = round_snorm(ny < 0 ? -(l1 - ax) : (l1 - ax), l1);
+    }
+    return (uint32_t)(uint16_t)(int16_t)qx | ((uint32_t)(uint16_t)(int16_t)qy << 16);
+}
+
+// Tangent (t) and bitangent (b) of the unit normal decoded from a packed
+// normal; basis of Duff et al. (JCGT 2017), t x b = n.
+__device__ void tangent_frame(uint32_t nrm, double t[3], double b[3])
+{
+    double px = (double)(int16_t)(nrm & 0xFFFFu) / 32767.0;
+    double py = (double)(int16_t)(nrm >> 16) / 32767.0;
+    double pz = 1.0 - fabs(px) - fabs(py);
+    if (pz < 0.0) {
+        const double tx = (1.0 - fabs(py)) * (px >= 0.0 ? 1.0 : -1.0);
+        const double ty = (1.0 - fabs(px)) * (py >= 0.0 ? 1.0 : -1.0);
+        px = tx;
+        py = ty;
+    }
+    const double len = sqrt(px * px + py * py + pz * pz);
+    const double nx = px / len, ny = py / len, nz = pz / len;
+    const double s = copysign(1.0, nz);
+    const double a = -1.0 / (s + nz);
+    const double c = nx * ny * a;
+    t[0] = 1.0 + s * nx * nx * a;
+    t[1] = s * c;
+    t[2] = -s * nx;
+    b[0] = c;
+    b[1] = s + ny * ny * a;
+    b[2] = -ny;
+}
+
+// Sample index range covered by [lo, hi] in 16.8 units: samples sit at
+// 256 i + 128, so the first is ceil((lo - 128) / 256), the last
+// floor((hi - 128) / 256) (arithmetic shifts round towards -inf).
+__device__ __forceinline__ void sample_range(int64_t lo, int64_t hi, int32_t* i0, int32_t* i1)
+{
+    *i0 = (int32_t)((lo - 128 + 255) >> 8);
+    *i1 = (int32_t)((hi - 128) >> 8);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_setup(const float* __restrict__ pos, const uint32_t* __restrict__ rgba,
+        const uint32_t* __restrict__ tri, const uint8_t* __restrict__ obj, uint32_t n_tri,
+        uint32_t mode, uint32_t width, uint32_t height, uint32_t levels,
+        TriRec* __restrict__ recs, uint64_t* __restrict__ tiles)
+{
+    const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= n_tri) return;
+    TriRec r;
+    int64_t X[3], Y[3];
+    int32_t a[3][3];
+    uint32_t col[3];
+    bool skip = false;
+    uint32_t nrm;
+    for (int k = 0; k < 3; ++k) col[k] = rgba[tri[3 * (uint64_t)t + k]];
+    if (mode == FHV_PPFL) {
+        int64_t q[3][3];
+        for (int k = 0; k < 3; ++k) {
+            const float* p = pos + 3 * (uint64_t)tri[3 * (uint64_t)t + k];
+            const double x = p[0], y = p[1], z = p[2];
+            if (!(fabs(x) <= 64.0 && fabs(y) <= 64.0 && fabs(z) <= 64.0)) {
+                skip = true;
+                break;
+            }
+            X[k] = (int64_t)rint((x + 1.0) * ((double)width * 128.0));
+            Y[k] = (int64_t)rint((y + 1.0) * ((double)height * 128.0));
+            double zd = rint((z + 1.0) * 0.5 * 16777215.0);
+            zd = zd < 0.0 ? 0.0 : (zd > 16777215.0 ? 16777215.0 : zd);
+            a[k][0] = (int32_t)zd;
+            a[k][1] = a[k][2] = 0;
+            q[k][0] = (int64_t)rint(x * 1048576.0);
+            q[k][1] = (int64_t)rint(y * 1048576.0);
+            q[k][2] = (int64_t)rint(z * 1048576.0);
+        }
+        if (!skip) {
+            const int64_t ux = q[1][0] - q[0][0], uy = q[1][1] - q[0][1], uz = q[1][2] - q[0][2];
+            const int64_t vx = q[2][0] - q[0][0], vy = q[2][1] - q[0][1], vz = q[2][2] - q[0][2];
+            nrm = oct_pack(uy * vz - uz * vy, uz * vx - ux * vz, ux * vy - uy * vx);
+        }
+    } else {
+        const double G = (double)(1ll << (levels + 8));
+        for (int k = 0; k < 3 && !skip; ++k) {
+            const float* p = pos + 3 * (uint64_t)tri[3 * (uint64_t)t + k];
+            for (int c = 0; c < 3; ++c) {
+                const float f = p[c];
+                if (!isfinite(f)) {
+                    skip = true;
+                    break;
+                }
+                double g = floor((double)f * G);
+                g = g < 0.0 ? 0.0 : (g > G - 1.0 ? G - 1.0 : g);
+                a[k][c] = (int32_t)g;
+            }
+        }
+        if (!skip) {
+            const int64_t ux = a[1][0] - a[0][0], uy = a[1][1] - a[0][1], uz = a[1][2] - a[0][2];
+            const int64_t vx = a[2][0] - a[0][0], vy = a[2][1] - a[0][1], vz = a[2][2] - a[0][2];
+            const int64_t nx = uy * vz - uz * vy, ny = uz * vx - ux * vz, nz = ux * vy - uy * vx;
+            if (nx == 0 && ny == 0 && nz == 0) {
+                skip = true;
+            } else {
+                nrm = oct_pack(nx, ny, nz);
+                double tt[3], bb[3];
+                tangent_frame(nrm, tt, bb);
+                for (int k = 0; k < 3; ++k) {
+                    const double px = (double)a[k][0], py = (double)a[k][1], pz = (double)a[k][2];
+                    const double u = px * tt[0] + py * tt[1] + pz * tt[2];
+                    const double v = px * bb[0] + py * bb[1] + pz * bb[2];
+                    X[k] = (int64_t)rint(2.0 * u);
+                    Y[k] = (int64_t)rint(2.0 * v);
+                }
+            }
+        }
+    }
+    uint64_t n_tiles = 0;
+    if (!skip) {
+        int64_t A = (X[1] - X[0]) * (Y[2] - Y[0]) - (Y[1] - Y[0]) * (X[2] - X[0]);
+        if (A != 0) {
+            int o[3] = {0, 1, 2};
+            if (A < 0) {
+                o[1] = 2;
+                o[2] = 1;
+                A = -A;
+            }
+            int64_t xmin = X[0], xmax = X[0], ymin = Y[0], ymax = Y[0];
+            for (int k = 1; k < 3; ++k) {
+                xmin = X[k] < xmin ? X[k] : xmin;
+                xmax = X[k] > xmax ? X[k] : xmax;
+                ymin = Y[k] < ymin ? Y[k] : ymin;
+                ymax = Y[k] > ymax ? Y[k] : ymax;
+            }
+            int32_t i0, i1, j0, j1;
+            sample_range(xmin, xmax, &i0, &i1);
+            sample_range(ymin, ymax, &j0, &j1);
+            if (mode == FHV_PPFL) {
+                i0 = i0 < 0 ? 0 : i0;
+                j0 = j0 < 0 ? 0 : j0;
+                i1 = i1 > (int32_t)width - 1 ? (int32_t)width - 1 : i1;
+                j1 = j1 > (int32_t)height - 1 ? (int32_t)height - 1 : j1;
+            }
+            for (int k = 0; k < 3; ++k) {
+                r.x[k] = (int32_t)X[o[k]];
+                r.y[k] = (int32_t)Y[o[k]];
+                r.rgba[k] = col[o[k]];
+                for (int c = 0; c < 3; ++c) r.a[k][c] = a[o[k]][c];
+            }
+            r.lo_i = i0;
+            r.lo_j = j0;
+            r.hi_i = i1;
+            r.hi_j = j1;
+            r.nrm = nrm;
+            r.aux = obj ? (uint32_t)obj[t] : 0u;
+            r.A = A;
+            r.rA = 1.0 / (double)A;
+            r.pad0 = r.pad1 = 0;
+            r.pad2 = 0;
+            if (i1 >= i0 && j1 >= j0) {
+                const uint32_t tx = (uint32_t)(i1 - i0) / kTile + 1;
+                const uint32_t ty = (uint32_t)(j1 - j0) / kTile + 1;
+                r.tiles_x = tx;
+                n_tiles = (uint64_t)tx * ty;
+            } else {
+                r.tiles_x = 0;
+            }
+            recs[t] = r;
+        }
+    }
+    tiles[t] = n_tiles;
+}
+
+// floor((w0 a0 + w1 a1 + w2 a2 + floor(A/2)) / A) for non-negative weights
+// and attributes: an fp64 estimate (within 1 of the quotient) corrected by
+// the exact remainder, which is small and therefore exact in wrapped
+// 64-bit arithmetic even when the numerator itself exceeds 64 bits.
+__device__ __forceinline__ uint32_t interp(int64_t w0, int64_t w1, int64_t w2, int32_t a0,
+                                           int32_t a1, int32_t a2, int64_t A, double rA)
+{
+    const int64_t half = A >> 1;
+    const double est = ((double)w0 * (double)a0 + (double)w1 * (double)a1 + (double)w2 * (double)a2 +
+                        (double)half) * rA;
+    int64_t q = (int64_t)floor(est);
+    const uint64_t num = (uint64_t)w0 * (uint64_t)(uint32_t)a0 + (uint64_t)w1 * (uint64_t)(uint32_t)a1 +
+                         (uint64_t)w2 * (uint64_t)(uint32_t)a2 + (uint64_t)half;
+    const int64_t rem = (int64_t)(num - (uint64_t)q * (uint64_t)A);
+    if (rem < 0)
+        q -= 1;
+    else if (rem >= A)
+        q += 1;
+    return (uint32_t)q;
+}
+
+__device__ __forceinline__ uint32_t interp_rgba(int64_t w0, int64_t w1, int64_t w2,
+                                                const uint32_t c[3], int64_t A, double rA)
+{
+    uint32_t out = 0;
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+        const int32_t c0 = (c[0] >> (8 * ch)) & 0xFF, c1 = (c[1] >> (8 * ch)) & 0xFF,
+                      c2 = (c[2] >> (8 * ch)) & 0xFF;
+        out |= interp(w0, w1, w2, c0, c1, c2, A, rA) << (8 * ch);
+    }
+    return out;
+}
+
+template <int kMode>
+__global__ void __launch_bounds__(kBlock)
+k_raster(const TriRec* __restrict__ recs, const uint64_t* __restrict__ incl, uint32_t n_tri,
+         uint32_t width, uint32_t gmax, uint32_t* __restrict__ head, uint4* __restrict__ pool,
+         uint32_t* __restrict__ keys, uint64_t cap, unsigned long long* __restrict__ counter)
+{
+    const uint64_t total = incl[n_tri - 1];
+    const int lane = __lane_id();
+    const uint64_t n_waves = (uint64_t)gridDim.x * (kBlock / kWave);
+    uint64_t w = (uint64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    uint32_t t = 0;  // triangles are visited in ascending order by each wave
+    for (; w < total; w += n_waves) {
+        w = uniform64(w);
+        // first triangle whose inclusive tile sum exceeds w
+        uint32_t lo = t, hi = n_tri - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (incl[mid] > w)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        t = uniform32(lo);
+        const TriRec& r = recs[t];
+        const uint64_t first = t ? incl[t - 1] : 0;
+        const uint32_t tile = (uint32_t)(w - first);
+        const uint32_t tx = tile % r.tiles_x, ty = tile / r.tiles_x;
+        const int32_t i = r.lo_i + (int32_t)(tx * kTile) + (lane & (kTile - 1));
+        const int32_t j = r.lo_j + (int32_t)(ty * kTile) + (lane >> 3);
+        bool cov = i <= r.hi_i && j <= r.hi_j;
+        int64_t e01 = 0, e12 = 0, e20 = 0;
+        if (cov) {
+            const int64_t px = 256 * (int64_t)i + 128, py = 256 * (int64_t)j + 128;
+            const int64_t x0 = r.x[0], x1 = r.x[1], x2 = r.x[2];
+            const int64_t y0 = r.y[0], y1 = r.y[1], y2 = r.y[2];
+            e01 = (x1 - x0) * (py - y0) - (y1 - y0) * (px - x0);
+            e12 = (x2 - x1) * (py - y1) - (y2 - y1) * (px - x1);
+            e20 = (x0 - x2) * (py - y2) - (y0 - y2) * (px - x2);
+            // top-left rule (CCW, y up): an edge owns its samples when it
+            // runs downwards, or horizontally towards -x
+            const bool o01 = (y1 < y0) || (y1 == y0 && x1 < x0);
+            const bool o12 = (y2 < y1) || (y2 == y1 && x2 < x1);
+            const bool o20 = (y0 < y2) || (y0 == y2 && x0 < x2);
+            cov = (e01 > 0 || (e01 == 0 && o01)) && (e12 > 0 || (e12 == 0 && o12)) &&
+                  (e20 > 0 || (e20 == 0 && o20));
+        }
+        const uint64_t mask = __ballot(cov);
+        if (mask == 0) continue;
+        const int leader = __ffsll((unsigned long long)mask) - 1;
+        unsigned long long base = 0;
+        if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
+        base = __shfl(base, leader, kWave);
+        if (!cov) continue;
+        const uint64_t idx = base + (uint64_t)__popcll(mask & ((1ull << lane) - 1ull));
+        if (idx >= cap) continue;
+        uint32_t key, w0;
+        const uint32_t w1 = interp_rgba(e12, e20, e01, r.rgba, r.A, r.rA);
+        if (kMode == FHV_PPFL) {
+            key = (uint32_t)j * width + (uint32_t)i;
+            const uint32_t d = interp(e12, e20, e01, r.a[0][0], r.a[1][0], r.a[2][0], r.A, r.rA);
+            w0 = d | (r.aux << 24);
+        } else {
+            // interpolation stays within the vertices' range; the clamp only
+            // keeps the key inside the head array
+            uint32_t gx = interp(e12, e20, e01, r.a[0][0], r.a[1][0], r.a[2][0], r.A, r.rA);
+            uint32_t gy = interp(e12, e20, e01, r.a[0][1], r.a[1][1], r.a[2][1], r.A, r.rA);
+            uint32_t gz = interp(e12, e20, e01, r.a[0][2], r.a[1][2], r.a[2][2], r.A, r.rA);
+            gx = gx > gmax ? gmax : gx;
+            gy = gy > gmax ? gmax : gy;
+            gz = gz > gmax ? gmax : gz;
+            key = (spread3(gx >> 8) << 2) | (spread3(gy >> 8) << 1) | spread3(gz >> 8);
+            w0 = (gx & 0xFFu) | ((gy & 0xFFu) << 8) | ((gz & 0xFFu) << 16) | (r.aux << 24);
+        }
+        const uint32_t prev = atomicExch(head + key, (uint32_t)idx);
+        pool[idx] = make_uint4(w0, w1, r.nrm, prev);
+        keys[idx] = key;
+    }
+}
+
+}  // namespace
+
+size_t capture_ws_bytes(const fhv_capture_desc* d, uint32_t n_tri)
+{
+    (void)d;
+    Carver c{nullptr, 0};
+    c.take<TriRec>(n_tri);
+    c.take<uint64_t>(n_tri);
+    c.take<uint64_t>(n_tri);
+    c.take<uint64_t>(scan_partials(n_tri));
+    return c.off + 256;
+}
+
+hipError_t capture_launch(const Device& dev, const fhv_mesh* m, const fhv_capture_desc* d,
+                          const fhv_lists* L, void* ws, hipStream_t s)
+{
+    Carver c{(char*)ws, 0};
+    TriRec* recs = c.take<TriRec>(m->n_tri);
+    uint64_t* tiles = c.take<uint64_t>(m->n_tri);
+    uint64_t* incl = c.take<uint64_t>(m->n_tri);
+    uint64_t* part = c.take<uint64_t>(scan_partials(m->n_tri));
+    hipError_t e;
+    {
+        ProfScope ps(dev, "capture.reset", s);
+        e = fill_u32(L->head, L->n_head, kNil, s);
+        if (e == hipSuccess) e = fill_u64(L->counter, 1, 0, s);
+    }
+    if (e != hipSuccess || m->n_tri == 0) return e;
+    {
+        ProfScope ps(dev, "capture.setup", s);
+        k_setup<<<dim3((m->n_tri + kBlock - 1) / kBlock), dim3(kBlock), 0, s>>>(
+            m->pos, m->rgba, m->tri, m->obj, m->n_tri, d->mode, d->width, d->height, d->levels,
+            recs, tiles);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return e;
+    {
+        ProfScope ps(dev, "capture.scan", s);
+        e = scan_u64(tiles, incl, m->n_tri, true, part, nullptr, s);
+    }
+    if (e != hipSuccess) return e;
+    const unsigned grid = (unsigned)(dev.cus * 16);
+    const uint32_t gmax = d->mode == FHV_POFL ? (1u << (d->levels + 8)) - 1u : 0u;
+    ProfScope ps(dev, "capture.raster", s);
+    if (d->mode == FHV_PPFL)
+        k_raster<FHV_PPFL><<<dim3(grid), dim3(kBlock), 0, s>>>(
+            recs, incl, m->n_tri, d->width, gmax, L->head, (uint4*)L->pool, L->keys, L->capacity,
+            (unsigned long long*)L->counter);
+    else
+        k_raster<FHV_POFL><<<dim3(grid), dim3(kBlock), 0, s>>>(
+            recs, incl, m->n_tri, d->width, gmax, L->head, (uint4*)L->pool, L->keys, L->capacity,
+            (unsigned long long*)L->counter);
+    return hipGetLastError();
+}
+
+}  // namespace fhv

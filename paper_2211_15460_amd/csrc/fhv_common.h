@@ -1,0 +1,148 @@
+// Device-side definitions shared by the HIP translation units of libfhv.
+// gfx950 (CDNA4) only: wave64, 64-bit atomics on global memory.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fhv.h"
+
+namespace fhv {
+
+constexpr uint32_t kNil = 0xFFFFFFFFu;
+constexpr int kBlock = 256;          // threads per workgroup (4 waves)
+constexpr int kWave = 64;
+constexpr int kTile = 8;             // raster tile: 8 x 8 samples = one wave
+constexpr int kBrickShift = 9;       // compaction bucket: 512 consecutive keys
+constexpr uint32_t kBrickKeys = 1u << kBrickShift;
+constexpr uint32_t kMaxViews = 32;
+
+// Triangle after setup: oriented counter-clockwise in 16.8 fixed point, with
+// its sample bounding box and per-vertex integer attributes. 128 bytes.
+struct alignas(16) TriRec {
+    int32_t x[3], y[3];      // 16.8 screen (PPFL) or tangent-plane (POFL)
+    int32_t lo_i, lo_j;      // first sample column / row
+    int32_t hi_i, hi_j;      // last sample column / row (inclusive)
+    uint32_t tiles_x;        // tiles per bbox row
+    uint32_t nrm;            // packed normal
+    uint32_t aux;            // object byte
+    uint32_t pad0;
+    uint32_t rgba[3];
+    uint32_t pad1;
+    int32_t a[3][3];         // PPFL: a[k][0] = depth24; POFL: grid xyz
+    int32_t pad2;
+    int64_t A;               // twice the area, > 0
+    double rA;               // 1 / A, for the quotient estimate
+};
+static_assert(sizeof(TriRec) == 128, "TriRec layout");
+
+struct ViewArgs {
+    float m[kMaxViews][12];
+    float c[kMaxViews];       // 1/2 - k/2
+    uint32_t k[kMaxViews];
+    uint32_t n_views;
+    uint32_t width;
+    uint32_t height;
+};
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t v)
+{
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t uniform32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+// Spread the low 10 bits of v to every third bit (bit b -> bit 3b).
+__device__ __forceinline__ uint32_t spread3(uint32_t v)
+{
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__device__ __forceinline__ uint32_t compact3(uint32_t v)
+{
+    v &= 0x09249249u;
+    v = (v | (v >> 2)) & 0x030C30C3u;
+    v = (v | (v >> 4)) & 0x0300F00Fu;
+    v = (v | (v >> 8)) & 0x030000FFu;
+    v = (v | (v >> 16)) & 0x3FFu;
+    return v;
+}
+
+}  // namespace fhv
+
+// Launchers (host side), defined next to their kernels.
+namespace fhv {
+
+struct Profiler;  // kernel timing with HIP events, owned by the context
+
+struct Device {
+    int id;
+    int cus;
+    Profiler* prof;  // non-null while profiling is on
+};
+
+void prof_mark(Profiler* p, const char* name, hipStream_t s, bool start);
+
+// Brackets the kernel launches of one scope with events when profiling.
+struct ProfScope {
+    Profiler* p;
+    const char* name;
+    hipStream_t s;
+    ProfScope(const Device& d, const char* n, hipStream_t st) : p(d.prof), name(n), s(st)
+    {
+        if (p) prof_mark(p, name, s, true);
+    }
+    ~ProfScope()
+    {
+        if (p) prof_mark(p, name, s, false);
+    }
+};
+
+hipError_t fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
+hipError_t fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
+
+// Exclusive (or inclusive) prefix sums of n values; `partial` needs
+// scan_partials(n) elements; *total (device, may be null) gets the sum.
+size_t scan_partials(uint64_t n);
+hipError_t scan_u32(const uint32_t* in, uint32_t* out, uint64_t n, bool inclusive,
+                    uint32_t* partial, uint64_t* total, hipStream_t s);
+hipError_t scan_u64(const uint64_t* in, uint64_t* out, uint64_t n, bool inclusive,
+                    uint64_t* partial, uint64_t* total, hipStream_t s);
+
+size_t capture_ws_bytes(const fhv_capture_desc* d, uint32_t n_tri);
+hipError_t capture_launch(const Device& dev, const fhv_mesh* m, const fhv_capture_desc* d,
+                          const fhv_lists* L, void* ws, hipStream_t s);
+
+size_t compact_ws_bytes(const fhv_capture_desc* d, uint64_t n_head, uint64_t capacity);
+hipError_t compact_launch(const Device& dev, const fhv_lists* L, const fhv_capture_desc* d,
+                          const fhv_pofa* out, void* ws, hipStream_t s);
+
+hipError_t splat_launch(const Device& dev, const fhv_pofa* a, const fhv_capture_desc* d,
+                        const ViewArgs& va, uint64_t* zbuf, uint32_t* rgba, float* depth,
+                        uint8_t* cov, uint64_t max_frag, hipStream_t s);
+
+// Workspace carving with 256-byte alignment.
+struct Carver {
+    char* base;
+    size_t off;
+    template <class T>
+    T* take(uint64_t n)
+    {
+        off = (off + 255) & ~(size_t)255;
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += (size_t)n * sizeof(T);
+        return p;
+    }
+};
+
+}  // namespace fhv

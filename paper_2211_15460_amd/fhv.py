@@ -1,0 +1,292 @@
+"""Python binding of libfhv (include/fhv.h): argument marshalling only.
+
+Every step of the path runs in the library's HIP kernels; this module only
+allocates device tensors with torch, fills the C structs and passes torch's
+current HIP stream. It raises if the native library is missing: there is no
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch  # loads the HIP runtime the library binds to
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfhv.so")
+
+FHV_PPFL, FHV_POFL = 0, 1
+NIL = 0xFFFFFFFF
+
+
+class FhvError(RuntimeError):
+    pass
+
+
+class Mesh_(C.Structure):
+    _fields_ = [("pos", C.c_void_p), ("rgba", C.c_void_p), ("tri", C.c_void_p),
+                ("obj", C.c_void_p), ("n_vert", C.c_uint32), ("n_tri", C.c_uint32)]
+
+
+class Desc_(C.Structure):
+    _fields_ = [("mode", C.c_uint32), ("width", C.c_uint32), ("height", C.c_uint32),
+                ("levels", C.c_uint32)]
+
+
+class Lists_(C.Structure):
+    _fields_ = [("head", C.c_void_p), ("n_head", C.c_uint64), ("pool", C.c_void_p),
+                ("capacity", C.c_uint64), ("keys", C.c_void_p), ("counter", C.c_void_p)]
+
+
+class Pofa_(C.Structure):
+    _fields_ = [("oct_key", C.c_void_p), ("oct_off", C.c_void_p), ("oct_cnt", C.c_void_p),
+                ("cap_occ", C.c_uint64), ("frag", C.c_void_p), ("cap_frag", C.c_uint64),
+                ("n_occ", C.c_void_p), ("n_frag", C.c_void_p)]
+
+
+class View_(C.Structure):
+    _fields_ = [("m", C.c_float * 12), ("width", C.c_uint32), ("height", C.c_uint32),
+                ("splat_px", C.c_uint32)]
+
+
+class KernelStat_(C.Structure):
+    _fields_ = [("name", C.c_char_p), ("launches", C.c_uint64), ("total_ms", C.c_double)]
+
+
+EXPORTS = ["fhv_create", "fhv_destroy", "fhv_status_str", "fhv_capture_workspace", "fhv_capture",
+           "fhv_compact_workspace", "fhv_compact", "fhv_splat", "fhv_profile_begin",
+           "fhv_profile_end"]
+
+_lib = None
+_ctx: dict[int, C.c_void_p] = {}
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FhvError(f"native library {LIB_PATH} is not built "
+                           "(run python -m paper_2211_15460_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.fhv_create.argtypes = [C.POINTER(P), C.c_int]
+        L.fhv_destroy.argtypes = [P]
+        L.fhv_status_str.argtypes = [C.c_int32]
+        L.fhv_status_str.restype = C.c_char_p
+        L.fhv_capture_workspace.argtypes = [C.POINTER(Desc_), C.c_uint32]
+        L.fhv_capture_workspace.restype = C.c_size_t
+        L.fhv_capture.argtypes = [P, C.POINTER(Mesh_), C.POINTER(Desc_), C.POINTER(Lists_), P,
+                                  C.c_size_t, P]
+        L.fhv_compact_workspace.argtypes = [C.POINTER(Desc_), C.c_uint64]
+        L.fhv_compact_workspace.restype = C.c_size_t
+        L.fhv_compact.argtypes = [P, C.POINTER(Lists_), C.POINTER(Desc_), C.POINTER(Pofa_), P,
+                                  C.c_size_t, P]
+        L.fhv_splat.argtypes = [P, C.POINTER(Pofa_), C.POINTER(Desc_), C.POINTER(View_), C.c_uint32,
+                                P, P, P, P, P]
+        L.fhv_profile_begin.argtypes = [P]
+        L.fhv_profile_end.argtypes = [P, C.POINTER(KernelStat_), C.c_uint32, C.POINTER(C.c_uint32)]
+        for f in ("fhv_create", "fhv_destroy", "fhv_capture", "fhv_compact", "fhv_splat",
+                  "fhv_profile_begin", "fhv_profile_end"):
+            getattr(L, f).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _check(st: int, what: str):
+    if st != 0:
+        raise FhvError(f"{what}: {lib().fhv_status_str(st).decode()} (status {st})")
+
+
+def ctx(device: int | None = None) -> C.c_void_p:
+    dev = torch.cuda.current_device() if device is None else device
+    if dev not in _ctx:
+        h = C.c_void_p()
+        _check(lib().fhv_create(C.byref(h), dev), "fhv_create")
+        _ctx[dev] = h
+    return _ctx[dev]
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ------------------------------------------------------------------ inputs
+
+@dataclass
+class DeviceMesh:
+    pos: torch.Tensor      # float32 [nv, 3]
+    rgba: torch.Tensor     # int32 view of uint32 [nv]
+    tri: torch.Tensor      # int32 view of uint32 [nt, 3]
+    obj: torch.Tensor | None   # uint8 [nt]
+
+    @property
+    def n_vert(self):
+        return int(self.pos.shape[0])
+
+    @property
+    def n_tri(self):
+        return int(self.tri.shape[0])
+
+
+def to_device(mesh, device="cuda") -> DeviceMesh:
+    """Copy a host mesh (scenes.Mesh) into device tensors."""
+    pos = torch.from_numpy(np.ascontiguousarray(mesh.pos, np.float32)).to(device)
+    rgba = torch.from_numpy(np.ascontiguousarray(mesh.rgba, np.uint32).view(np.int32)).to(device)
+    tri = torch.from_numpy(np.ascontiguousarray(mesh.tri, np.uint32).view(np.int32)).to(device)
+    obj = None if mesh.obj is None else torch.from_numpy(np.ascontiguousarray(mesh.obj, np.uint8)).to(device)
+    return DeviceMesh(pos, rgba, tri, obj)
+
+
+def desc(mode: int, width: int = 0, height: int = 0, levels: int = 0) -> Desc_:
+    return Desc_(mode, width, height, levels)
+
+
+def n_head(d: Desc_) -> int:
+    return d.width * d.height if d.mode == FHV_PPFL else 8 ** d.levels
+
+
+# ------------------------------------------------------------------ capture
+
+@dataclass
+class Lists:
+    head: torch.Tensor      # int32 [n_head] (uint32 bits)
+    pool: torch.Tensor      # int32 [cap, 4]
+    keys: torch.Tensor      # int32 [cap]
+    counter: torch.Tensor   # int64 [1]
+    capacity: int
+
+    def struct(self) -> Lists_:
+        return Lists_(self.head.data_ptr(), self.head.numel(),
+                      self.pool.data_ptr() if self.capacity else None, self.capacity,
+                      self.keys.data_ptr(), self.counter.data_ptr())
+
+
+def alloc_lists(d: Desc_, capacity: int, device="cuda") -> Lists:
+    return Lists(torch.empty(n_head(d), dtype=torch.int32, device=device),
+                 torch.empty((max(capacity, 1), 4), dtype=torch.int32, device=device),
+                 torch.empty(max(capacity, 1), dtype=torch.int32, device=device),
+                 torch.zeros(1, dtype=torch.int64, device=device), capacity)
+
+
+def capture_workspace(d: Desc_, n_tri: int) -> int:
+    return int(lib().fhv_capture_workspace(C.byref(d), n_tri))
+
+
+def capture(m: DeviceMesh, d: Desc_, lists: Lists, ws: torch.Tensor | None = None) -> Lists:
+    """fhv_capture into pre-allocated lists; returns them (counter on device)."""
+    need = capture_workspace(d, m.n_tri)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=m.pos.device)
+    mesh = Mesh_(m.pos.data_ptr(), m.rgba.data_ptr(), m.tri.data_ptr(),
+                 None if m.obj is None else m.obj.data_ptr(), m.n_vert, m.n_tri)
+    ls = lists.struct()
+    _check(lib().fhv_capture(ctx(), C.byref(mesh), C.byref(d), C.byref(ls), _ptr(ws), ws.numel(),
+                             _stream()), "fhv_capture")
+    return lists
+
+
+# ------------------------------------------------------------------ compact
+
+@dataclass
+class Pofa:
+    oct_key: torch.Tensor   # int64 [cap_occ]
+    oct_off: torch.Tensor   # int32 [cap_occ]
+    oct_cnt: torch.Tensor   # int32 [cap_occ]
+    frag: torch.Tensor      # int32 [cap_frag, 4]
+    n_occ: torch.Tensor     # int64 [1]
+    n_frag: torch.Tensor    # int64 [1]
+    cap_occ: int
+    cap_frag: int
+
+    def struct(self) -> Pofa_:
+        return Pofa_(self.oct_key.data_ptr(), self.oct_off.data_ptr(), self.oct_cnt.data_ptr(),
+                     self.cap_occ, self.frag.data_ptr(), self.cap_frag, self.n_occ.data_ptr(),
+                     self.n_frag.data_ptr())
+
+
+def alloc_pofa(cap_frag: int, cap_occ: int | None = None, device="cuda") -> Pofa:
+    cap_occ = cap_frag if cap_occ is None else cap_occ
+    return Pofa(torch.empty(max(cap_occ, 1), dtype=torch.int64, device=device),
+                torch.empty(max(cap_occ, 1), dtype=torch.int32, device=device),
+                torch.empty(max(cap_occ, 1), dtype=torch.int32, device=device),
+                torch.empty((max(cap_frag, 1), 4), dtype=torch.int32, device=device),
+                torch.zeros(1, dtype=torch.int64, device=device),
+                torch.zeros(1, dtype=torch.int64, device=device), cap_occ, cap_frag)
+
+
+def compact_workspace(d: Desc_, capacity: int) -> int:
+    return int(lib().fhv_compact_workspace(C.byref(d), capacity))
+
+
+def compact(lists: Lists, d: Desc_, out: Pofa, ws: torch.Tensor | None = None) -> Pofa:
+    need = compact_workspace(d, lists.capacity)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=lists.head.device)
+    ls = lists.struct()
+    ps = out.struct()
+    _check(lib().fhv_compact(ctx(), C.byref(ls), C.byref(d), C.byref(ps), _ptr(ws), ws.numel(),
+                             _stream()), "fhv_compact")
+    return out
+
+
+# ------------------------------------------------------------------ splat
+
+@dataclass
+class Images:
+    zbuf: torch.Tensor    # int64 [V, H, W]
+    rgba: torch.Tensor    # int32 [V, H, W]
+    depth: torch.Tensor   # float32 [V, H, W]
+    cov: torch.Tensor     # uint8 [V, H, W]
+
+
+def alloc_images(n_views: int, width: int, height: int, device="cuda") -> Images:
+    shp = (n_views, height, width)
+    return Images(torch.empty(shp, dtype=torch.int64, device=device),
+                  torch.empty(shp, dtype=torch.int32, device=device),
+                  torch.empty(shp, dtype=torch.float32, device=device),
+                  torch.empty(shp, dtype=torch.uint8, device=device))
+
+
+def views_struct(views) -> C.Array:
+    arr = (View_ * len(views))()
+    for i, v in enumerate(views):
+        arr[i].m[:] = [float(x) for x in np.asarray(v.m, np.float32).reshape(12)]
+        arr[i].width, arr[i].height, arr[i].splat_px = v.width, v.height, v.splat_px
+    return arr
+
+
+def splat(arrays: Pofa, d: Desc_, views, out: Images | None = None, vstruct=None) -> Images:
+    """fhv_splat of all views (at most 32 per call; more are split)."""
+    W, H = views[0].width, views[0].height
+    if out is None:
+        out = alloc_images(len(views), W, H, device=arrays.frag.device)
+    ps = arrays.struct()
+    for v0 in range(0, len(views), 32):
+        vs = views[v0:v0 + 32]
+        arr = vstruct if (vstruct is not None and len(views) <= 32) else views_struct(vs)
+        _check(lib().fhv_splat(ctx(), C.byref(ps), C.byref(d), arr, len(vs),
+                               _ptr(out.zbuf[v0:]), _ptr(out.rgba[v0:]), _ptr(out.depth[v0:]),
+                               _ptr(out.cov[v0:]), _stream()), "fhv_splat")
+    return out
+
+
+# ------------------------------------------------------------------ timing
+
+def profile_begin():
+    """Start bracketing every library kernel with HIP events."""
+    _check(lib().fhv_profile_begin(ctx()), "fhv_profile_begin")
+
+
+def profile_end() -> dict[str, tuple[int, float]]:
+    """Stop; returns {kernel scope name: (launches, summed ms)}."""
+    arr = (KernelStat_ * 64)()
+    n = C.c_uint32()
+    _check(lib().fhv_profile_end(ctx(), arr, 64, C.byref(n)), "fhv_profile_end")
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms))
+            for i in range(min(n.value, 64))}

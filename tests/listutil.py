@@ -7,11 +7,11 @@ import numpy as np
 NIL = 0xFFFFFFFF
 
 
-def walk_lists(head: np.ndarray, pool: np.ndarray, counter: int):
+def walk_lists(head: np.ndarray, pool: np.ndarray, counter: int, return_index: bool = False):
     """Follow every list from its head (vectorised over lists).
 
     Returns (keys, recs): for every list member its head key and its 16-byte
-    record, in walk order. Raises AssertionError if an index is out of range,
+    record, in walk order (and the pool indices when return_index). Raises AssertionError if an index is out of range,
     a pool slot is reached twice, or the walk does not visit exactly
     min(counter, cap) slots."""
     cap = pool.shape[0]
@@ -33,10 +33,25 @@ def walk_lists(head: np.ndarray, pool: np.ndarray, counter: int):
         assert steps <= F + 1, "cycle in a list"
     assert np.all(seen == 1), "pool slot not in exactly one list"
     if not out_k:
-        return np.zeros(0, np.uint64), np.zeros((0, 4), np.uint32)
+        e = (np.zeros(0, np.uint64), np.zeros((0, 4), np.uint32))
+        return e + (np.zeros(0, np.int64),) if return_index else e
     k = np.concatenate(out_k)
     i = np.concatenate(out_i)
-    return k, pool[i]
+    return (k, pool[i], i) if return_index else (k, pool[i])
+
+
+def multiset_leq(a: np.ndarray, b: np.ndarray) -> bool:
+    """True when every row of a occurs in b at least as often as in a."""
+    if a.shape[0] == 0:
+        return True
+    ua, ca = np.unique(a, axis=0, return_counts=True)
+    ub, cb = np.unique(b, axis=0, return_counts=True)
+    allr = np.concatenate([ub, ua])
+    _, inv = np.unique(allr, axis=0, return_inverse=True)
+    inv = inv.reshape(-1)
+    nb = np.zeros(inv.max() + 1, np.int64)
+    np.add.at(nb, inv[:ub.shape[0]], cb)
+    return bool(np.all(nb[inv[ub.shape[0]:]] >= ca))
 
 
 def canonical(keys: np.ndarray, recs: np.ndarray) -> np.ndarray:
