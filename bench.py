@@ -81,19 +81,59 @@ def algorithmic_bytes(F: int, n_occ: int, n_tri: int, n_head: int, n_views: int,
     }
 
 
-def cpu_baseline(mesh, views):
-    """The CPU oracle, single-threaded, on the same workload: one full step
-    (capture, compaction, three splats)."""
+# kernels behind each timed scope (POFL mode)
+SCOPE_KERNELS = {
+    "capture.reset": ["k_fill_u32"], "capture.setup": ["k_setup"], "capture.raster": ["k_raster<1>"],
+    "compact.hist": ["k_hist"], "compact.scatter": ["k_scatter"],
+    "compact.brick": ["k_brick_wave", "k_brick"], "splat.zclear": ["k_zclear"],
+    "splat.splat": ["k_splat<1>"], "splat.resolve": ["k_resolve"],
+}
+
+
+def src_digest() -> str:
+    """sha256 over the HIP sources in name order (ties counter data to code)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2211_15460_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(scope: str):
+    """HBM bytes per launch of a scope from the committed rocprofv3 counter
+    summary (profiles/traffic.json), or None when the kernels have changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path) or scope not in SCOPE_KERNELS:
+        return None
+    t = json.load(open(path))
+    if t.get("src_sha256") != src_digest():
+        return None
+    ks = t["kernels"]
+    if not all(k in ks for k in SCOPE_KERNELS[scope]):
+        return None
+    return sum(ks[k]["read_bytes"] + ks[k]["write_bytes"] for k in SCOPE_KERNELS[scope])
+
+
+def cpu_baseline(mesh, views, min_seconds: float = 10.0):
+    """The CPU oracle, single-threaded, on the same workload: full steps
+    (capture, compaction, three splats) repeated for at least min_seconds."""
     import oracle
     oracle.lib()
-    t0 = time.perf_counter()
-    head, pool, F = oracle.capture_pofl(mesh, LEVELS, 8 << 20)
-    r = oracle.compact(head, pool, F)
-    oracle.splat(1, r["key"], r["frag"], views, levels=LEVELS)
-    dt = time.perf_counter() - t0
+    n, t_all = 0, 0.0
+    while t_all < min_seconds:
+        t0 = time.perf_counter()
+        head, pool, F = oracle.capture_pofl(mesh, LEVELS, 8 << 20)
+        r = oracle.compact(head, pool, F)
+        oracle.splat(1, r["key"], r["frag"], views, levels=LEVELS)
+        t_all += time.perf_counter() - t0
+        n += 1
+        del head, pool, r
+    dt = t_all / n
     return {"value": F / dt, "unit": "fragments/s", "cores": 1, "kind": "oracle",
-            "sample": f"one full step of the same workload ({F} fragments, 3 views), "
-                      f"{dt:.2f} s on one core"}
+            "sample": f"{n} full steps of the same workload ({F} fragments, 3 views each), "
+                      f"{t_all:.1f} s on one core, {dt:.3f} s per step"}
 
 
 def main():
@@ -102,6 +142,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=256,
+                    help="size of a plain device copy run once before the steps, so that "
+                         "hardware byte counters can be calibrated against a known size")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this path runs on a single MI355X; "
@@ -135,6 +178,13 @@ def main():
         fhv.capture(dm, d, lists, ws_c)
         fhv.compact(lists, d, pofa, ws_k)
         fhv.splat(pofa, d, views, imgs, vs)
+
+    if args.copy_mib > 0:
+        src = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         step()
@@ -194,7 +244,7 @@ def main():
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
-                     "traffic": None},
+                     "traffic": measured_traffic(dom)},
         "wall_s_timed": wall,
         "host": host_info(),
         "device": torch.cuda.get_device_name(0),

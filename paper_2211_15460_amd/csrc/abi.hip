@@ -233,12 +233,14 @@ fhv_status fhv_splat(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_capture_des
     va.n_views = n_views;
     va.width = views[0].width;
     va.height = views[0].height;
+    va.all_k1 = 1;
     if (va.width < 1 || va.width > 16384 || va.height < 1 || va.height > 16384) return FHV_ERANGE;
     for (uint32_t v = 0; v < n_views; ++v) {
         if (views[v].width != va.width || views[v].height != va.height) return FHV_EINVAL;
         if (views[v].splat_px < 1 || views[v].splat_px > 64) return FHV_EINVAL;
         memcpy(va.m[v], views[v].m, sizeof(va.m[v]));
         va.k[v] = views[v].splat_px;
+        if (views[v].splat_px != 1) va.all_k1 = 0;
         va.c[v] = 0.5f - 0.5f * (float)views[v].splat_px;
     }
     fhv_status st = set_device(ctx);

@@ -9,12 +9,14 @@
 //             packing, tangent frame of the packed normal, projection),
 //             orientation, sample bounding box, number of 8x8 sample tiles
 //   scan      inclusive prefix sum of tiles per triangle
-//   k_raster  one wave per (triangle, tile) work item, one lane per sample:
-//             integer edge functions with the top-left rule, integer
-//             attribute interpolation, list append
+//   k_raster  work items are (triangle, tile) pairs; a wave takes a
+//             contiguous range of them and processes one tile at a time, one
+//             lane per sample: integer edge functions with the top-left
+//             rule, integer attribute interpolation, list append
 //
-// List append per covered sample (Sec. 3.2): the wave reserves its covered
-// samples' slots with one atomic add on the global counter; each lane with
+// List append (Sec. 3.2): the wave counts its range's covered samples and
+// reserves their slots with one atomic add on the global counter (instead
+// of one increment per fragment; the slots are the same set). Each lane with
 // a slot below the capacity swaps its index into the key's head and stores
 // {w0, rgba, normal, previous head} plus the key sidecar.
 //
@@ -254,6 +256,73 @@ __device__ __forceinline__ uint32_t interp_rgba(int64_t w0, int64_t w1, int64_t 
     return out;
 }
 
+// Edge functions and coverage of one lane's sample in tile `tile` of r.
+struct Sample {
+    bool cov;
+    int32_t i, j;
+    int64_t e01, e12, e20;
+};
+
+__device__ __forceinline__ Sample sample_of(const TriRec& r, uint32_t tile, int lane)
+{
+    Sample s;
+    const uint32_t tx = tile % r.tiles_x, ty = tile / r.tiles_x;
+    s.i = r.lo_i + (int32_t)(tx * kTile) + (lane & (kTile - 1));
+    s.j = r.lo_j + (int32_t)(ty * kTile) + (lane >> 3);
+    s.cov = s.i <= r.hi_i && s.j <= r.hi_j;
+    s.e01 = s.e12 = s.e20 = 0;
+    if (s.cov) {
+        const int64_t px = 256 * (int64_t)s.i + 128, py = 256 * (int64_t)s.j + 128;
+        const int64_t x0 = r.x[0], x1 = r.x[1], x2 = r.x[2];
+        const int64_t y0 = r.y[0], y1 = r.y[1], y2 = r.y[2];
+        s.e01 = (x1 - x0) * (py - y0) - (y1 - y0) * (px - x0);
+        s.e12 = (x2 - x1) * (py - y1) - (y2 - y1) * (px - x1);
+        s.e20 = (x0 - x2) * (py - y2) - (y0 - y2) * (px - x2);
+        // top-left rule (CCW, y up): an edge owns its samples when it runs
+        // downwards, or horizontally towards -x
+        const bool o01 = (y1 < y0) || (y1 == y0 && x1 < x0);
+        const bool o12 = (y2 < y1) || (y2 == y1 && x2 < x1);
+        const bool o20 = (y0 < y2) || (y0 == y2 && x0 < x2);
+        s.cov = (s.e01 > 0 || (s.e01 == 0 && o01)) && (s.e12 > 0 || (s.e12 == 0 && o12)) &&
+                (s.e20 > 0 || (s.e20 == 0 && o20));
+    }
+    return s;
+}
+
+// Walks work items [w0, w1) (wave-uniform), keeping the owning triangle t
+// with its first item `first` and one-past-last item `end`.
+struct ItemWalk {
+    const uint64_t* incl;
+    uint32_t t;
+    uint64_t first, end;
+    __device__ void start(uint32_t n_tri, uint64_t w0)
+    {
+        uint32_t lo = 0, hi = n_tri - 1;   // first t with incl[t] > w0
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (incl[mid] > w0)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        t = uniform32(lo);
+        first = t ? incl[t - 1] : 0;
+        end = incl[t];
+    }
+    __device__ void advance(uint64_t w)
+    {
+        while (w >= end) {
+            ++t;
+            first = end;
+            end = incl[t];
+        }
+    }
+};
+
+// Each wave owns a contiguous range of work items. It first counts the
+// covered samples of the whole range, reserves that many pool slots with a
+// single atomic add on the counter, and then walks the range again to emit
+// the fragments into consecutive slots.
 template <int kMode>
 __global__ void __launch_bounds__(kBlock)
 k_raster(const TriRec* __restrict__ recs, const uint64_t* __restrict__ incl, uint32_t n_tri,
@@ -263,73 +332,84 @@ k_raster(const TriRec* __restrict__ recs, const uint64_t* __restrict__ incl, uin
     const uint64_t total = incl[n_tri - 1];
     const int lane = __lane_id();
     const uint64_t n_waves = (uint64_t)gridDim.x * (kBlock / kWave);
-    uint64_t w = (uint64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    uint32_t t = 0;  // triangles are visited in ascending order by each wave
-    for (; w < total; w += n_waves) {
-        w = uniform64(w);
-        // first triangle whose inclusive tile sum exceeds w
-        uint32_t lo = t, hi = n_tri - 1;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (incl[mid] > w)
-                hi = mid;
-            else
-                lo = mid + 1;
+    const uint64_t wid = uniform64((uint64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave);
+    const uint64_t per = (total + n_waves - 1) / n_waves;
+    const uint64_t w0 = wid * per;
+    const uint64_t w1 = w0 + per < total ? w0 + per : total;
+    if (w0 >= w1) return;
+
+    ItemWalk it{incl, 0, 0, 0};
+    constexpr int kBatch = 4;   // tiles per step; their memory operations overlap
+    it.start(n_tri, w0);
+    uint64_t n_cov = 0;
+    for (uint64_t w = w0; w < w1; w += kBatch) {
+        uint32_t tb[kBatch], tile[kBatch];
+#pragma unroll
+        for (int g = 0; g < kBatch; ++g) {
+            tb[g] = kNil;
+            if (w + g < w1) {
+                it.advance(w + g);
+                tb[g] = it.t;
+                tile[g] = (uint32_t)(w + g - it.first);
+            }
         }
-        t = uniform32(lo);
-        const TriRec& r = recs[t];
-        const uint64_t first = t ? incl[t - 1] : 0;
-        const uint32_t tile = (uint32_t)(w - first);
-        const uint32_t tx = tile % r.tiles_x, ty = tile / r.tiles_x;
-        const int32_t i = r.lo_i + (int32_t)(tx * kTile) + (lane & (kTile - 1));
-        const int32_t j = r.lo_j + (int32_t)(ty * kTile) + (lane >> 3);
-        bool cov = i <= r.hi_i && j <= r.hi_j;
-        int64_t e01 = 0, e12 = 0, e20 = 0;
-        if (cov) {
-            const int64_t px = 256 * (int64_t)i + 128, py = 256 * (int64_t)j + 128;
-            const int64_t x0 = r.x[0], x1 = r.x[1], x2 = r.x[2];
-            const int64_t y0 = r.y[0], y1 = r.y[1], y2 = r.y[2];
-            e01 = (x1 - x0) * (py - y0) - (y1 - y0) * (px - x0);
-            e12 = (x2 - x1) * (py - y1) - (y2 - y1) * (px - x1);
-            e20 = (x0 - x2) * (py - y2) - (y0 - y2) * (px - x2);
-            // top-left rule (CCW, y up): an edge owns its samples when it
-            // runs downwards, or horizontally towards -x
-            const bool o01 = (y1 < y0) || (y1 == y0 && x1 < x0);
-            const bool o12 = (y2 < y1) || (y2 == y1 && x2 < x1);
-            const bool o20 = (y0 < y2) || (y0 == y2 && x0 < x2);
-            cov = (e01 > 0 || (e01 == 0 && o01)) && (e12 > 0 || (e12 == 0 && o12)) &&
-                  (e20 > 0 || (e20 == 0 && o20));
+#pragma unroll
+        for (int g = 0; g < kBatch; ++g)
+            if (tb[g] != kNil) n_cov += (uint64_t)__popcll(__ballot(sample_of(recs[tb[g]], tile[g], lane).cov));
+    }
+    if (n_cov == 0) return;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(counter, (unsigned long long)n_cov);
+    base = __shfl(base, 0, kWave);
+
+    it.start(n_tri, w0);
+    for (uint64_t w = w0; w < w1; w += kBatch) {
+        bool has[kBatch];
+        uint32_t key[kBatch], w0r[kBatch], w1r[kBatch], nrm[kBatch];
+        uint64_t idx[kBatch];
+#pragma unroll
+        for (int g = 0; g < kBatch; ++g) {
+            has[g] = false;
+            key[g] = 0;
+            idx[g] = 0;
+            if (w + g >= w1) continue;   // wave-uniform
+            it.advance(w + g);
+            const TriRec& r = recs[it.t];
+            const Sample sm = sample_of(r, (uint32_t)(w + g - it.first), lane);
+            const uint64_t mask = __ballot(sm.cov);
+            idx[g] = base + (uint64_t)__popcll(mask & lanemask_lt());
+            base += (uint64_t)__popcll(mask);
+            has[g] = sm.cov && idx[g] < cap;
+            if (!has[g]) continue;
+            nrm[g] = r.nrm;
+            w1r[g] = interp_rgba(sm.e12, sm.e20, sm.e01, r.rgba, r.A, r.rA);
+            if (kMode == FHV_PPFL) {
+                key[g] = (uint32_t)sm.j * width + (uint32_t)sm.i;
+                const uint32_t dz = interp(sm.e12, sm.e20, sm.e01, r.a[0][0], r.a[1][0], r.a[2][0], r.A, r.rA);
+                w0r[g] = dz | (r.aux << 24);
+            } else {
+                // interpolation stays within the vertices' range; the clamp
+                // only keeps the key inside the head array
+                uint32_t gx = interp(sm.e12, sm.e20, sm.e01, r.a[0][0], r.a[1][0], r.a[2][0], r.A, r.rA);
+                uint32_t gy = interp(sm.e12, sm.e20, sm.e01, r.a[0][1], r.a[1][1], r.a[2][1], r.A, r.rA);
+                uint32_t gz = interp(sm.e12, sm.e20, sm.e01, r.a[0][2], r.a[1][2], r.a[2][2], r.A, r.rA);
+                gx = gx > gmax ? gmax : gx;
+                gy = gy > gmax ? gmax : gy;
+                gz = gz > gmax ? gmax : gz;
+                key[g] = (spread3(gx >> 8) << 2) | (spread3(gy >> 8) << 1) | spread3(gz >> 8);
+                w0r[g] = (gx & 0xFFu) | ((gy & 0xFFu) << 8) | ((gz & 0xFFu) << 16) | (r.aux << 24);
+            }
         }
-        const uint64_t mask = __ballot(cov);
-        if (mask == 0) continue;
-        const int leader = __ffsll((unsigned long long)mask) - 1;
-        unsigned long long base = 0;
-        if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
-        base = __shfl(base, leader, kWave);
-        if (!cov) continue;
-        const uint64_t idx = base + (uint64_t)__popcll(mask & ((1ull << lane) - 1ull));
-        if (idx >= cap) continue;
-        uint32_t key, w0;
-        const uint32_t w1 = interp_rgba(e12, e20, e01, r.rgba, r.A, r.rA);
-        if (kMode == FHV_PPFL) {
-            key = (uint32_t)j * width + (uint32_t)i;
-            const uint32_t d = interp(e12, e20, e01, r.a[0][0], r.a[1][0], r.a[2][0], r.A, r.rA);
-            w0 = d | (r.aux << 24);
-        } else {
-            // interpolation stays within the vertices' range; the clamp only
-            // keeps the key inside the head array
-            uint32_t gx = interp(e12, e20, e01, r.a[0][0], r.a[1][0], r.a[2][0], r.A, r.rA);
-            uint32_t gy = interp(e12, e20, e01, r.a[0][1], r.a[1][1], r.a[2][1], r.A, r.rA);
-            uint32_t gz = interp(e12, e20, e01, r.a[0][2], r.a[1][2], r.a[2][2], r.A, r.rA);
-            gx = gx > gmax ? gmax : gx;
-            gy = gy > gmax ? gmax : gy;
-            gz = gz > gmax ? gmax : gz;
-            key = (spread3(gx >> 8) << 2) | (spread3(gy >> 8) << 1) | spread3(gz >> 8);
-            w0 = (gx & 0xFFu) | ((gy & 0xFFu) << 8) | ((gz & 0xFFu) << 16) | (r.aux << 24);
+        uint32_t prev[kBatch];
+#pragma unroll
+        for (int g = 0; g < kBatch; ++g)
+            if (has[g]) prev[g] = atomicExch(head + key[g], (uint32_t)idx[g]);
+#pragma unroll
+        for (int g = 0; g < kBatch; ++g) {
+            if (!has[g]) continue;
+            pool[idx[g]] = make_uint4(w0r[g], w1r[g], nrm[g], prev[g]);
+            keys[idx[g]] = key[g];
         }
-        const uint32_t prev = atomicExch(head + key, (uint32_t)idx);
-        pool[idx] = make_uint4(w0, w1, r.nrm, prev);
-        keys[idx] = key;
     }
 }
 

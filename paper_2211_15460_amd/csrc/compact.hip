@@ -9,17 +9,20 @@
 // 512 consecutive keys so that every bucket fits a workgroup's LDS:
 //   k_hist     per brick: fragment count (atomic add) and number of
 //              distinct keys (atomic or into a key bitmap; the first setter
-//              of a bit counts the key)
+//              of a bit counts the key); lanes of a wave that hit the same
+//              brick or bitmap word combine into one atomic
 //   scan       exclusive sums of both per-brick counts: brick fragment
 //              offsets and brick rank bases; totals = n_frag, n_occ
 //   k_scatter  every pool record to its brick's range of a staging array
 //              (slot within the brick from an atomic cursor), key in w3
-//   k_brick    one workgroup per brick: counting sort of the brick's records
-//              by key inside LDS (in place in the output when the brick is
-//              larger than LDS), a per-key insertion sort into canonical
-//              order, then the output records with w3 = rank and the
-//              brick's table rows
-#include "fhv_common.h"
+//   k_brick_wave / k_brick
+//              per brick: counting sort of its records by key inside LDS,
+//              a per-key insertion sort into canonical order, then the
+//              output records with w3 = rank and the brick's table rows.
+//              Bricks of up to 1024 records take one wave each with no
+//              workgroup barriers; larger ones a whole workgroup (in place
+//              in the output when they exceed LDS)
+#include "scan.h"
 
 namespace fhv {
 
@@ -40,13 +43,30 @@ k_hist(const uint32_t* __restrict__ keys, const uint64_t* __restrict__ counter, 
 {
     const uint64_t F = frag_count(counter, cap);
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < F; i += stride) {
-        const uint32_t key = keys[i];
-        const uint32_t b = key >> kBrickShift;
-        atomicAdd(brick_cnt + b, 1u);
-        const uint32_t bit = 1u << (key & 31);
-        const uint32_t old = atomicOr(bitmap + (key >> 5), bit);
-        if (!(old & bit)) atomicAdd(brick_occ + b, 1u);
+    const int lane = __lane_id();
+    // the loop bound is rounded up to whole waves so that every lane of a
+    // wave takes part in the wave-wide aggregation
+    const uint64_t Fw = (F + kWave - 1) & ~(uint64_t)(kWave - 1);
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < Fw; i += stride) {
+        const bool act = i < F;
+        const uint32_t key = act ? keys[i] : 0u;
+        wave_count_add<false>(brick_cnt, key >> kBrickShift, act);
+        // key bitmap: lanes hitting the same 32-key word OR their bits
+        // together; new bits count as newly occupied keys of the brick
+        const uint32_t word = key >> 5;
+        uint64_t todo = __ballot(act);
+        while (todo) {
+            const int leader = __ffsll((unsigned long long)todo) - 1;
+            const uint32_t lw = (uint32_t)__shfl((int)word, leader, kWave);
+            const uint64_t m = __ballot(act && word == lw) & todo;
+            const uint32_t bits = wave_or(((m >> lane) & 1ull) ? (1u << (key & 31)) : 0u);
+            if (lane == leader) {
+                const uint32_t old = atomicOr(bitmap + lw, bits);
+                const uint32_t fresh = (uint32_t)__popc(bits & ~old);
+                if (fresh) atomicAdd(brick_occ + (lw >> (kBrickShift - 5)), fresh);
+            }
+            todo &= ~m;
+        }
     }
 }
 
@@ -57,13 +77,16 @@ k_scatter(const uint4* __restrict__ pool, const uint32_t* __restrict__ keys,
 {
     const uint64_t F = frag_count(counter, cap);
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < F; i += stride) {
-        const uint32_t key = keys[i];
+    const uint64_t Fw = (F + kWave - 1) & ~(uint64_t)(kWave - 1);
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < Fw; i += stride) {
+        const bool act = i < F;
+        const uint32_t key = act ? keys[i] : 0u;
         const uint32_t b = key >> kBrickShift;
-        const uint32_t slot = brick_off[b] + atomicAdd(brick_cur + b, 1u);
+        const uint32_t slot = wave_count_add<true>(brick_cur, b, act);
+        if (!act) continue;
         uint4 r = pool[i];
         r.w = key;
-        stage[slot] = r;
+        stage[brick_off[b] + slot] = r;
     }
 }
 
@@ -157,6 +180,152 @@ __device__ void brick_sort(uint4* __restrict__ buf, const uint4* __restrict__ sr
     }
 }
 
+// Orders LDS traffic of one wave: its earlier LDS writes are complete and
+// visible to all its lanes before later LDS reads.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+constexpr int kWaveRecs = 1024;            // records per wave-sized brick
+constexpr int kPerLane = kWaveRecs / kWave;  // 16
+constexpr int kKeysPerLane = kBrickKeys / kWave;  // 8
+
+// One wave per brick of at most kWaveRecs records, with no workgroup
+// barriers (one-wave workgroups): records held in registers (16 per lane) are counted per key in
+// LDS, the 512 counts scanned across the wave (8 consecutive keys per lane),
+// the records grouped by key in LDS through cursors, and every record
+// written straight to its final slot: its key's offset plus its rank inside
+// the key's run in canonical order, with w3 = the key's table rank.
+__global__ void __launch_bounds__(kWave)
+k_brick_wave(const uint4* __restrict__ stage, const uint32_t* __restrict__ brick_cnt,
+             const uint32_t* __restrict__ brick_off, const uint32_t* __restrict__ brick_rank,
+             const uint32_t* __restrict__ list, const uint64_t* __restrict__ list_total,
+             uint4* __restrict__ frag, uint64_t* __restrict__ oct_key,
+             uint32_t* __restrict__ oct_off, uint32_t* __restrict__ oct_cnt, uint64_t cap_occ)
+{
+    __shared__ uint4 buf[kWaveRecs];
+    __shared__ uint32_t off[kBrickKeys], rank[kBrickKeys], cur[kBrickKeys];
+    const int lane = __lane_id();
+    const uint32_t nl = (uint32_t)(*list_total >> 32);
+    for (uint32_t li = blockIdx.x; li < nl; li += gridDim.x) {
+        const uint32_t b = list[li];
+        const uint32_t n = brick_cnt[b];
+        if (n == 0 || n > (uint32_t)kWaveRecs) continue;
+        const uint32_t o = brick_off[b], base_rank = brick_rank[b];
+        uint4 r[kPerLane];
+#pragma unroll
+        for (int k = 0; k < kPerLane; ++k) {
+            const uint32_t i = (uint32_t)(k * kWave + lane);
+            r[k] = i < n ? stage[o + i] : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < kKeysPerLane; ++k) cur[lane * kKeysPerLane + k] = 0;
+        wave_lds_sync();
+#pragma unroll
+        for (int k = 0; k < kPerLane; ++k)
+            if ((uint32_t)(k * kWave + lane) < n) atomicAdd(cur + (r[k].w & (kBrickKeys - 1)), 1u);
+        wave_lds_sync();
+        uint32_t c[kKeysPerLane], s = 0, z = 0;
+#pragma unroll
+        for (int k = 0; k < kKeysPerLane; ++k) {
+            c[k] = cur[lane * kKeysPerLane + k];
+            s += c[k];
+            z += c[k] ? 1u : 0u;
+        }
+        uint32_t si = s, zi = z;   // inclusive wave scans
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t a = (uint32_t)__shfl_up((int)si, d, kWave);
+            const uint32_t q = (uint32_t)__shfl_up((int)zi, d, kWave);
+            if (lane >= d) {
+                si += a;
+                zi += q;
+            }
+        }
+        uint32_t ps = si - s, pz = zi - z;
+#pragma unroll
+        for (int k = 0; k < kKeysPerLane; ++k) {
+            off[lane * kKeysPerLane + k] = ps;
+            cur[lane * kKeysPerLane + k] = ps;
+            rank[lane * kKeysPerLane + k] = pz;
+            ps += c[k];
+            pz += c[k] ? 1u : 0u;
+        }
+        wave_lds_sync();
+        uint32_t pos[kPerLane];
+#pragma unroll
+        for (int k = 0; k < kPerLane; ++k) {
+            pos[k] = 0;
+            if ((uint32_t)(k * kWave + lane) < n) {
+                pos[k] = atomicAdd(cur + (r[k].w & (kBrickKeys - 1)), 1u);
+                buf[pos[k]] = r[k];
+            }
+        }
+        wave_lds_sync();
+        // table rows, 8 consecutive keys per lane
+#pragma unroll
+        for (int k = 0; k < kKeysPerLane; ++k) {
+            const uint32_t leaf = lane * kKeysPerLane + k;
+            if (c[k]) {
+                const uint64_t rk = (uint64_t)base_rank + rank[leaf];
+                if (rk < cap_occ) {
+                    oct_key[rk] = ((uint64_t)b << kBrickShift) | leaf;
+                    oct_off[rk] = o + off[leaf];
+                    oct_cnt[rk] = c[k];
+                }
+            }
+        }
+        // every record's place inside its key's run: the number of records
+        // of the run that precede it in (w0, w1, w2) order, equal records
+        // ordered by their LDS position. The loop runs over positions in the
+        // run (up to the brick's longest run) with the 16 records of a lane
+        // unrolled inside, so their LDS reads overlap.
+        uint32_t mrun = 0;
+#pragma unroll
+        for (int k = 0; k < kKeysPerLane; ++k) mrun = c[k] > mrun ? c[k] : mrun;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t o2 = (uint32_t)__shfl_xor((int)mrun, d, kWave);
+            mrun = o2 > mrun ? o2 : mrun;
+        }
+        uint32_t lo[kPerLane], len[kPerLane], before[kPerLane];
+#pragma unroll
+        for (int k = 0; k < kPerLane; ++k) {
+            const uint32_t leaf = r[k].w & (kBrickKeys - 1);
+            const bool valid = (uint32_t)(k * kWave + lane) < n;
+            lo[k] = valid ? off[leaf] : 0u;
+            len[k] = valid ? cur[leaf] - lo[k] : 0u;   // cur = end of run
+            before[k] = 0;
+        }
+        for (uint32_t dd = 0; dd < mrun; ++dd) {
+            // branch-free: every lane reads (a clamped slot), so the 16 reads
+            // of an iteration are in flight together
+            uint4 y[kPerLane];
+#pragma unroll
+            for (int k = 0; k < kPerLane; ++k) {
+                const uint32_t q = lo[k] + (dd < len[k] ? dd : 0u);
+                y[k] = buf[q];
+            }
+#pragma unroll
+            for (int k = 0; k < kPerLane; ++k) {
+                const uint4 x = r[k];
+                const uint32_t q = lo[k] + dd;
+                const bool lt = rec_less(y[k], x) ||
+                                (q < pos[k] && y[k].x == x.x && y[k].y == x.y && y[k].z == x.z);
+                before[k] += (dd < len[k] && lt) ? 1u : 0u;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kPerLane; ++k)
+            if ((uint32_t)(k * kWave + lane) < n)
+                frag[o + lo[k] + before[k]] =
+                    make_uint4(r[k].x, r[k].y, r[k].z, base_rank + rank[r[k].w & (kBrickKeys - 1)]);
+        wave_lds_sync();
+    }
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_brick(const uint4* __restrict__ stage, const uint32_t* __restrict__ brick_cnt,
         const uint32_t* __restrict__ brick_off, const uint32_t* __restrict__ brick_rank,
@@ -166,19 +335,63 @@ k_brick(const uint4* __restrict__ stage, const uint32_t* __restrict__ brick_cnt,
     __shared__ uint4 lbuf[kLdsRecs];
     __shared__ uint32_t cnt[kBrickKeys], off[kBrickKeys], cur[kBrickKeys], rank[kBrickKeys],
         tmp[kBrickKeys];
-    for (uint32_t b = blockIdx.x; b < n_brick; b += gridDim.x) {
-        const uint32_t n = brick_cnt[b];
-        if (n == 0) continue;
-        const uint32_t o = brick_off[b];
-        if (n <= (uint32_t)kLdsRecs)
-            brick_sort<true>(lbuf, stage + o, n, cnt, off, cur, rank, tmp, b, o, brick_rank[b],
-                             frag + o, oct_key, oct_off, oct_cnt, cap_occ);
-        else
-            brick_sort<false>(frag + o, stage + o, n, cnt, off, cur, rank, tmp, b, o,
-                              brick_rank[b], frag + o, oct_key, oct_off, oct_cnt, cap_occ);
+    __shared__ uint32_t big[kBlock];
+    __shared__ uint32_t n_big;
+    // bricks above the wave kernel's size, found 256 at a time
+    for (uint32_t b0 = blockIdx.x * kBlock; b0 < n_brick; b0 += gridDim.x * kBlock) {
+        if (threadIdx.x == 0) n_big = 0;
+        __syncthreads();
+        const uint32_t bt = b0 + threadIdx.x;
+        if (bt < n_brick && brick_cnt[bt] > (uint32_t)kWaveRecs) big[atomicAdd(&n_big, 1u)] = bt;
+        __syncthreads();
+        const uint32_t nb = n_big;
+        for (uint32_t k = 0; k < nb; ++k) {
+            const uint32_t b = big[k];
+            const uint32_t n = brick_cnt[b];
+            const uint32_t o = brick_off[b];
+            if (n <= (uint32_t)kLdsRecs)
+                brick_sort<true>(lbuf, stage + o, n, cnt, off, cur, rank, tmp, b, o, brick_rank[b],
+                                 frag + o, oct_key, oct_off, oct_cnt, cap_occ);
+            else
+                brick_sort<false>(frag + o, stage + o, n, cnt, off, cur, rank, tmp, b, o,
+                                  brick_rank[b], frag + o, oct_key, oct_off, oct_cnt, cap_occ);
+            __syncthreads();
+        }
         __syncthreads();
     }
 }
+
+// Scan helpers. Bricks are scanned on (count | occupied << 32): the low
+// half of the exclusive prefix is the brick's fragment offset, the high half
+// its position in the list of occupied bricks.
+struct LoadBrick {
+    const uint32_t* cnt;
+    __device__ uint64_t operator()(uint64_t i) const
+    {
+        const uint32_t c = cnt[i];
+        return (uint64_t)c | ((uint64_t)(c != 0u) << 32);
+    }
+};
+
+struct StoreBrick {
+    uint32_t* off;
+    uint32_t* list;
+    __device__ void operator()(uint64_t i, uint64_t v, uint64_t ex) const
+    {
+        off[i] = (uint32_t)ex;
+        if ((uint32_t)v) list[ex >> 32] = (uint32_t)i;
+    }
+};
+
+struct LoadOcc {
+    const uint32_t* occ;
+    __device__ uint64_t operator()(uint64_t i) const { return occ[i]; }
+};
+
+struct StoreRank {
+    uint32_t* rank;
+    __device__ void operator()(uint64_t i, uint64_t, uint64_t ex) const { rank[i] = (uint32_t)ex; }
+};
 
 __global__ void k_totals(const uint64_t* __restrict__ counter, uint64_t cap,
                          uint64_t* __restrict__ n_frag)
@@ -189,7 +402,10 @@ __global__ void k_totals(const uint64_t* __restrict__ counter, uint64_t cap,
 }  // namespace
 
 struct CompactWs {
-    uint32_t *brick_cnt, *brick_occ, *brick_cur, *brick_off, *brick_rank, *bitmap, *part;
+    uint32_t *brick_cnt, *brick_occ, *brick_cur, *brick_off, *brick_rank, *bitmap;
+    uint32_t* list;         // occupied bricks, ascending
+    uint64_t* part;         // scan scratch
+    uint64_t* list_total;   // (fragments | occupied bricks << 32)
     uint4* stage;
 };
 
@@ -205,9 +421,11 @@ static CompactWs carve_compact(void* ws, uint64_t n_head, uint64_t capacity, siz
     w.brick_occ = z ? z + n_brick : nullptr;
     w.brick_cur = z ? z + 2 * n_brick : nullptr;
     w.bitmap = z ? z + 3 * n_brick : nullptr;
+    w.list = c.take<uint32_t>(n_brick);
     w.brick_off = c.take<uint32_t>(n_brick);
     w.brick_rank = c.take<uint32_t>(n_brick);
-    w.part = c.take<uint32_t>(scan_partials(n_brick));
+    w.part = c.take<uint64_t>(scan_scratch(n_brick));
+    w.list_total = c.take<uint64_t>(1);
     w.stage = c.take<uint4>(capacity);
     if (bytes) *bytes = c.off + 256;
     return w;
@@ -234,6 +452,7 @@ hipError_t compact_launch(const Device& dev, const fhv_lists* L, const fhv_captu
     {
         ProfScope ps(dev, "compact.hist", s);
         e = fill_u32(w.brick_cnt, 3 * n_brick + (L->n_head + 31) / 32, 0u, s);
+        if (e == hipSuccess) e = fill_u64(w.list_total, 1, 0, s);
         if (e != hipSuccess) return e;
         k_totals<<<dim3(1), dim3(64), 0, s>>>(L->counter, L->capacity, out->n_frag);
         k_hist<<<dim3(grid), dim3(kBlock), 0, s>>>(L->keys, L->counter, L->capacity, w.brick_cnt,
@@ -243,8 +462,11 @@ hipError_t compact_launch(const Device& dev, const fhv_lists* L, const fhv_captu
     if (e != hipSuccess) return e;
     {
         ProfScope ps(dev, "compact.scan", s);
-        e = scan_u32(w.brick_cnt, w.brick_off, n_brick, false, w.part, nullptr, s);
-        if (e == hipSuccess) e = scan_u32(w.brick_occ, w.brick_rank, n_brick, false, w.part, out->n_occ, s);
+        e = scan<uint64_t>(LoadBrick{w.brick_cnt}, StoreBrick{w.brick_off, w.list}, n_brick, w.part,
+                           w.list_total, s);
+        if (e == hipSuccess)
+            e = scan<uint64_t>(LoadOcc{w.brick_occ}, StoreRank{w.brick_rank}, n_brick, w.part,
+                               (uint64_t*)out->n_occ, s);
     }
     if (e != hipSuccess) return e;
     {
@@ -254,9 +476,16 @@ hipError_t compact_launch(const Device& dev, const fhv_lists* L, const fhv_captu
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
-    const uint64_t bmax = (uint64_t)dev.cus * 32;
-    const unsigned gbrick = (unsigned)(n_brick < bmax ? n_brick : bmax);
+    const uint64_t bmax = (uint64_t)dev.cus * 8;
+    const uint64_t gbig = (n_brick + kBlock - 1) / kBlock;
+    const unsigned gbrick = (unsigned)(gbig < bmax ? gbig : bmax);
     ProfScope ps(dev, "compact.brick", s);
+    const uint64_t wmax = (uint64_t)dev.cus * 64;
+    const unsigned gwave = (unsigned)(n_brick < wmax ? n_brick : wmax);
+    k_brick_wave<<<dim3(gwave ? gwave : 1), dim3(kWave), 0, s>>>(
+        w.stage, w.brick_cnt, w.brick_off, w.brick_rank, w.list, w.list_total, (uint4*)out->frag,
+        out->oct_key, out->oct_off, out->oct_cnt, out->cap_occ);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     k_brick<<<dim3(gbrick ? gbrick : 1), dim3(kBlock), 0, s>>>(
         w.stage, w.brick_cnt, w.brick_off, w.brick_rank, (uint32_t)n_brick, (uint4*)out->frag,
         out->oct_key, out->oct_off, out->oct_cnt, out->cap_occ);

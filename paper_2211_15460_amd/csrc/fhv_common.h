@@ -43,6 +43,7 @@ struct ViewArgs {
     uint32_t n_views;
     uint32_t width;
     uint32_t height;
+    uint32_t all_k1;        // every view has a one-pixel footprint
 };
 
 __device__ __forceinline__ uint64_t uniform64(uint64_t v)
@@ -55,6 +56,43 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
 __device__ __forceinline__ uint32_t uniform32(uint32_t v)
 {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt()
+{
+    return (1ull << __lane_id()) - 1ull;
+}
+
+__device__ __forceinline__ uint32_t wave_or(uint32_t v)
+{
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) v |= (uint32_t)__shfl_xor((int)v, d, kWave);
+    return v;
+}
+
+// Every active lane adds 1 to ctr[b]; lanes of the wave with equal b share
+// one atomic add. Returns, per active lane, the counter's value before the
+// add plus the lane's rank among the lanes sharing b (a unique slot).
+// Must be called by all lanes of the wave.
+template <bool kWantSlot>
+__device__ __forceinline__ uint32_t wave_count_add(uint32_t* ctr, uint32_t b, bool active)
+{
+    const int lane = __lane_id();
+    uint64_t todo = __ballot(active);
+    uint32_t slot = 0;
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const uint32_t lb = (uint32_t)__shfl((int)b, leader, kWave);
+        const uint64_t m = __ballot(active && b == lb) & todo;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(ctr + lb, (uint32_t)__popcll(m));
+        if (kWantSlot) {
+            base = (uint32_t)__shfl((int)base, leader, kWave);
+            if ((m >> lane) & 1ull) slot = base + (uint32_t)__popcll(m & lanemask_lt());
+        }
+        todo &= ~m;
+    }
+    return slot;
 }
 
 // Spread the low 10 bits of v to every third bit (bit b -> bit 3b).

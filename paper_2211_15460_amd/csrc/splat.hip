@@ -27,6 +27,44 @@ __global__ void __launch_bounds__(kBlock) k_zclear(uint64_t* __restrict__ z, uin
     if (t == 0 && (n & 1)) z[n - 1] = ~0ull;
 }
 
+// Position of array fragment r in the view's input space: PPFL
+// (px + 1/2, py + 1/2, depth24), POFL grid position + 1/2.
+template <int kMode>
+__device__ __forceinline__ void frag_pos(const uint4& r, uint64_t key, uint32_t cap_w, float* x,
+                                         float* y, float* z)
+{
+    if (kMode == FHV_PPFL) {
+        const uint32_t px = (uint32_t)(key % cap_w), py = (uint32_t)(key / cap_w);
+        *x = (float)px + 0.5f;
+        *y = (float)py + 0.5f;
+        *z = (float)(r.x & 0xFFFFFFu);
+    } else {
+        const uint32_t k32 = (uint32_t)key;
+        const uint32_t kx = compact3(k32 >> 2), ky = compact3(k32 >> 1), kz = compact3(k32);
+        *x = (float)((kx << 8) | (r.x & 0xFFu)) + 0.5f;
+        *y = (float)((ky << 8) | ((r.x >> 8) & 0xFFu)) + 0.5f;
+        *z = (float)((kz << 8) | ((r.x >> 16) & 0xFFu)) + 0.5f;
+    }
+}
+
+// One-pixel footprints: target z-buffer entry of fragment i in view v, or
+// none (returns false).
+__device__ __forceinline__ bool pixel_of(const ViewArgs& va, uint32_t v, float x, float y, float z,
+                                         uint64_t i, uint64_t plane, uint64_t* off,
+                                         unsigned long long* zk)
+{
+    const float* M = va.m[v];
+    const float sx = ((M[0] * x + M[1] * y) + M[2] * z) + M[3];
+    const float sy = ((M[4] * x + M[5] * y) + M[6] * z) + M[7];
+    const float d = ((M[8] * x + M[9] * y) + M[10] * z) + M[11];
+    const float fx = floorf(sx + va.c[v]), fy = floorf(sy + va.c[v]);
+    const bool ok = d > 0.0f && fx >= 0.0f && fx < (float)va.width && fy >= 0.0f &&
+                    fy < (float)va.height;
+    *off = ok ? (uint64_t)v * plane + (uint64_t)(uint32_t)fy * va.width + (uint32_t)fx : 0;
+    *zk = ((unsigned long long)__float_as_uint(d) << 32) | (unsigned long long)(uint32_t)i;
+    return ok;
+}
+
 template <int kMode>
 __global__ void __launch_bounds__(kBlock)
 k_splat(const uint4* __restrict__ frag, const uint64_t* __restrict__ oct_key,
@@ -37,23 +75,48 @@ k_splat(const uint4* __restrict__ frag, const uint64_t* __restrict__ oct_key,
     const uint64_t F = nf < cap_frag ? nf : cap_frag;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     const uint64_t plane = (uint64_t)va.width * va.height;
+    if (cap_occ == 0) return;   // no table rows: nothing to draw
+    if (va.all_k1) {
+        // one pixel per view; two fragments per iteration, and the z-buffer
+        // reads of all their views issued before any atomic, so that the
+        // memory latencies overlap
+        for (uint64_t i0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i0 < F; i0 += 2 * stride) {
+            const uint64_t i1 = i0 + stride;
+            const bool h1 = i1 < F;
+            const uint4 r0 = frag[i0];
+            const uint4 r1 = h1 ? frag[i1] : make_uint4(0, 0, 0, 0);
+            const bool v0ok = r0.w < cap_occ, v1ok = h1 && r1.w < cap_occ;
+            const uint64_t k0 = oct_key[v0ok ? r0.w : 0];
+            const uint64_t k1 = oct_key[v1ok ? r1.w : 0];
+            float x0, y0, z0, x1, y1, z1;
+            frag_pos<kMode>(r0, k0, cap_w, &x0, &y0, &z0);
+            frag_pos<kMode>(r1, k1, cap_w, &x1, &y1, &z1);
+            for (uint32_t vb = 0; vb < va.n_views; vb += 2) {
+                uint64_t off[4];
+                unsigned long long zk[4], cur[4];
+                bool ok[4];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const uint32_t v = vb + j;
+                    const bool vv = v < va.n_views;
+                    const uint32_t vc = vv ? v : 0;
+                    ok[2 * j] = pixel_of(va, vc, x0, y0, z0, i0, plane, &off[2 * j], &zk[2 * j]) && vv && v0ok;
+                    ok[2 * j + 1] = pixel_of(va, vc, x1, y1, z1, i1, plane, &off[2 * j + 1], &zk[2 * j + 1]) && vv && v1ok;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) cur[q] = zbuf[ok[q] ? off[q] : 0];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (ok[q] && zk[q] < cur[q]) atomicMin(zbuf + off[q], zk[q]);
+            }
+        }
+        return;
+    }
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < F; i += stride) {
         const uint4 r = frag[i];
         if (r.w >= cap_occ) continue;   // table row not stored
-        const uint64_t key = oct_key[r.w];
         float x, y, z;
-        if (kMode == FHV_PPFL) {
-            const uint32_t px = (uint32_t)(key % cap_w), py = (uint32_t)(key / cap_w);
-            x = (float)px + 0.5f;
-            y = (float)py + 0.5f;
-            z = (float)(r.x & 0xFFFFFFu);
-        } else {
-            const uint32_t k32 = (uint32_t)key;
-            const uint32_t kx = compact3(k32 >> 2), ky = compact3(k32 >> 1), kz = compact3(k32);
-            x = (float)((kx << 8) | (r.x & 0xFFu)) + 0.5f;
-            y = (float)((ky << 8) | ((r.x >> 8) & 0xFFu)) + 0.5f;
-            z = (float)((kz << 8) | ((r.x >> 16) & 0xFFu)) + 0.5f;
-        }
+        frag_pos<kMode>(r, oct_key[r.w], cap_w, &x, &y, &z);
         for (uint32_t v = 0; v < va.n_views; ++v) {
             const float* M = va.m[v];
             const float sx = ((M[0] * x + M[1] * y) + M[2] * z) + M[3];
@@ -64,17 +127,17 @@ k_splat(const uint4* __restrict__ frag, const uint64_t* __restrict__ oct_key,
             if (!(fx > -1073741824.0f && fx < 1073741824.0f)) continue;
             if (!(fy > -1073741824.0f && fy < 1073741824.0f)) continue;
             const int32_t k = (int32_t)va.k[v];
-            int32_t x0 = (int32_t)fx, y0 = (int32_t)fy;
-            int32_t x1 = x0 + k, y1 = y0 + k;   // exclusive
-            x0 = x0 < 0 ? 0 : x0;
-            y0 = y0 < 0 ? 0 : y0;
-            x1 = x1 > (int32_t)va.width ? (int32_t)va.width : x1;
-            y1 = y1 > (int32_t)va.height ? (int32_t)va.height : y1;
+            int32_t xa = (int32_t)fx, ya = (int32_t)fy;
+            int32_t xb = xa + k, yb = ya + k;   // exclusive
+            xa = xa < 0 ? 0 : xa;
+            ya = ya < 0 ? 0 : ya;
+            xb = xb > (int32_t)va.width ? (int32_t)va.width : xb;
+            yb = yb > (int32_t)va.height ? (int32_t)va.height : yb;
             const unsigned long long zk =
                 ((unsigned long long)__float_as_uint(d) << 32) | (unsigned long long)(uint32_t)i;
             unsigned long long* zb = zbuf + (uint64_t)v * plane;
-            for (int32_t yy = y0; yy < y1; ++yy)
-                for (int32_t xx = x0; xx < x1; ++xx) {
+            for (int32_t yy = ya; yy < yb; ++yy)
+                for (int32_t xx = xa; xx < xb; ++xx) {
                     unsigned long long* p = zb + (uint64_t)yy * va.width + xx;
                     if (zk < *p) atomicMin(p, zk);
                 }
