@@ -215,6 +215,49 @@ FHV_API fhv_status fhv_splat(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_cap
                      const fhv_view* views, uint32_t n_views, uint64_t* zbuf, uint32_t* rgba,
                      float* depth, uint8_t* cov, fhv_stream stream);
 
+/* Learned hole fill (not in the paper; fills what the splat leaves
+ * uncovered, where Sec. 3.3 suggests adapting quad sizes or deforming
+ * geometry). A U-Net of `levels` (1..4) levels with 32 * 2^l channels on
+ * level l: per level two 3x3 convolutions (padding 1) with ReLU, 2x2 max pool
+ * going down, 2x2 stride-2 transposed convolution going up concatenated
+ * (transposed first) with the level's encoder output, and a 1x1 head to 3
+ * channels: an RGB residual added to splat RGB / 255. Input channels: R, G,
+ * B, A / 255, depth - 1 where covered (0 elsewhere), coverage. Weights and
+ * activations are rounded to bfloat16 (nearest even) for the matrix cores;
+ * sums accumulate in fp32.
+ * params: fp32 vector of fhv_unet_param_count(levels) values, layer after
+ *   layer: 3x3 conv W[co][ky][kx][ci] then b[co]; transposed conv
+ *   W[dy][dx][co][ci] then b[co]; head W[k][c] then b[k]. Layer order: for
+ *   each encoder level two convs; for each decoder level from the deepest:
+ *   transposed conv, two convs; the head.
+ * Images: n_img x height x width, row-major, height and width multiples of
+ *   2^(levels-1); n_img * height * width < 2^31. */
+FHV_API uint64_t fhv_unet_param_count(uint32_t levels);
+FHV_API size_t fhv_fill_workspace(uint32_t levels, uint32_t n_img, uint32_t height, uint32_t width,
+                                  int training);
+
+/* Inference: out_rgba = clamp(splat RGB / 255 + residual, 0, 1) * 255
+ * rounded half up, alpha 255; out_residual (nullable) receives the fp32
+ * residual [n_img][height][width][3].
+ * Errors: EINVAL (null pointers, levels, sizes), ERANGE, EWORKSPACE. */
+FHV_API fhv_status fhv_fill(fhv_ctx* ctx, uint32_t levels, const float* params, const uint32_t* rgba,
+                            const float* depth, const uint8_t* cov, uint32_t n_img, uint32_t height,
+                            uint32_t width, uint32_t* out_rgba, float* out_residual, void* ws,
+                            size_t ws_bytes, fhv_stream stream);
+
+/* One training step on a batch: loss = mean over n_img*height*width*3 of
+ * (splat RGB / 255 + residual - target RGB / 255)^2, its gradient w.r.t.
+ * params by backpropagation (written to grad_out when not null), then, when
+ * step >= 1, an Adam update (beta 0.9 / 0.999, eps 1e-8, bias correction for
+ * step `step`) of params, adam_m and adam_v in place. step 0 computes the
+ * loss and gradient only. loss_out (device, nullable): one float. */
+FHV_API fhv_status fhv_fill_train_step(fhv_ctx* ctx, uint32_t levels, float* params, float* adam_m,
+                                       float* adam_v, uint32_t step, float lr, const uint32_t* rgba,
+                                       const float* depth, const uint8_t* cov,
+                                       const uint32_t* target_rgba, uint32_t n_img, uint32_t height,
+                                       uint32_t width, float* loss_out, float* grad_out, void* ws,
+                                       size_t ws_bytes, fhv_stream stream);
+
 /* Kernel timing (tracing). Between fhv_profile_begin and fhv_profile_end
  * every kernel the library enqueues is bracketed by two HIP events on the
  * stream it runs on. fhv_profile_end waits for those events and reports,

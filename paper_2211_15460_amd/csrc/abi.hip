@@ -249,4 +249,59 @@ fhv_status fhv_splat(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_capture_des
                                         arrays->cap_frag, (hipStream_t)stream));
 }
 
+static bool fill_dims_ok(uint32_t levels, uint32_t n, uint32_t h, uint32_t w)
+{
+    if (levels < 1 || levels > 4 || n == 0 || h == 0 || w == 0) return false;
+    const uint32_t m = 1u << (levels - 1);
+    return h % m == 0 && w % m == 0;
+}
+
+uint64_t fhv_unet_param_count(uint32_t levels)
+{
+    if (levels < 1 || levels > 4) return 0;
+    return fhv::nn::param_count(levels);
+}
+
+size_t fhv_fill_workspace(uint32_t levels, uint32_t n_img, uint32_t height, uint32_t width, int training)
+{
+    if (!fill_dims_ok(levels, n_img, height, width)) return 0;
+    if ((uint64_t)n_img * height * width >= (1ull << 31)) return 0;
+    return fhv::nn::fill_ws_bytes(levels, n_img, height, width, training != 0);
+}
+
+fhv_status fhv_fill(fhv_ctx* ctx, uint32_t levels, const float* params, const uint32_t* rgba,
+                    const float* depth, const uint8_t* cov, uint32_t n_img, uint32_t height,
+                    uint32_t width, uint32_t* out_rgba, float* out_residual, void* ws, size_t ws_bytes,
+                    fhv_stream stream)
+{
+    if (!ctx || !params || !rgba || !depth || !cov || !out_rgba || !ws) return FHV_EINVAL;
+    if (!fill_dims_ok(levels, n_img, height, width)) return FHV_EINVAL;
+    if ((uint64_t)n_img * height * width >= (1ull << 31)) return FHV_ERANGE;
+    if (ws_bytes < fhv::nn::fill_ws_bytes(levels, n_img, height, width, false)) return FHV_EWORKSPACE;
+    fhv_status st = set_device(ctx);
+    if (st != FHV_OK) return st;
+    fhv::ProfScope ps(ctx->dev, "fill.forward", (hipStream_t)stream);
+    return hip_status(fhv::nn::fill(levels, params, rgba, depth, cov, n_img, height, width, out_rgba,
+                                    out_residual, ws, (hipStream_t)stream));
+}
+
+fhv_status fhv_fill_train_step(fhv_ctx* ctx, uint32_t levels, float* params, float* adam_m,
+                               float* adam_v, uint32_t step, float lr, const uint32_t* rgba,
+                               const float* depth, const uint8_t* cov, const uint32_t* target_rgba,
+                               uint32_t n_img, uint32_t height, uint32_t width, float* loss_out,
+                               float* grad_out, void* ws, size_t ws_bytes, fhv_stream stream)
+{
+    if (!ctx || !params || !rgba || !depth || !cov || !target_rgba || !ws) return FHV_EINVAL;
+    if (step > 0 && (!adam_m || !adam_v)) return FHV_EINVAL;
+    if (!fill_dims_ok(levels, n_img, height, width)) return FHV_EINVAL;
+    if ((uint64_t)n_img * height * width >= (1ull << 31)) return FHV_ERANGE;
+    if (ws_bytes < fhv::nn::fill_ws_bytes(levels, n_img, height, width, true)) return FHV_EWORKSPACE;
+    fhv_status st = set_device(ctx);
+    if (st != FHV_OK) return st;
+    fhv::ProfScope ps(ctx->dev, "fill.train_step", (hipStream_t)stream);
+    return hip_status(fhv::nn::train_step(levels, params, adam_m, adam_v, step, lr, rgba, depth, cov,
+                                          target_rgba, n_img, height, width, loss_out, grad_out, ws,
+                                          (hipStream_t)stream));
+}
+
 }  // extern "C"

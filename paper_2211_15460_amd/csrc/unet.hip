@@ -1,0 +1,887 @@
+// Learned hole fill: a U-Net that predicts an RGB residual for a splat image
+// (RGBA, depth, coverage), trained and run with bfloat16 MFMA kernels and
+// fp32 accumulation. Not part of the paper: it fills the holes the point
+// splat leaves (Sec. 3.3 mentions adapting quad sizes or deforming geometry
+// for that; this network learns the fill instead).
+//
+// Network (levels L = 1..4, base 32 channels, C_l = 32 * 2^l):
+//   encoder level l: conv3x3 + ReLU, conv3x3 + ReLU, 2x2 max pool (l < L-1)
+//   decoder level l (L-2 .. 0): 2x2 stride-2 transposed conv, concat with
+//     the encoder output of level l (transposed conv first), conv3x3 + ReLU
+//     twice; head: 1x1 conv to 3 channels, a residual on splat RGB / 255.
+// Parameters: one fp32 vector, layer after layer: 3x3 conv W[co][ky][kx][ci]
+// then b[co]; transposed conv W[dy][dx][co][ci] then b[co]; head W[k][c]
+// then b[k].
+//
+// Activations are NHWC bfloat16 (round to nearest even). The encoder's second
+// convolution writes straight into the skip half of its level's concat
+// buffer, the decoder's transposed convolution into the other half, so the
+// concatenation costs nothing.
+//
+// Kernels
+//   k_conv        implicit GEMM on MFMA 16x16x32 bf16: rows = pixels of a
+//                 grid, K = taps x input channels, N = output channels; three
+//                 addressing modes: 3x3 same-size (forward, and input
+//                 gradient with flipped transposed weights), 2x2 stride-2 up
+//                 (transposed conv forward), 2x2 gather from the doubled grid
+//                 (transposed conv input gradient). Fused bias, ReLU, bf16.
+//   k_wgrad       weight gradients: GEMM over pixels, both operands staged
+//                 through LDS transposed (pixels contiguous), split over
+//                 pixel ranges with fp32 partials and a fixed-order reduction
+//   k_colsum      bias gradients, same split / reduce scheme
+//   elementwise   input packing, max pool and its gradient (plus the skip
+//                 gradient), ReLU gradient, head with residual and loss,
+//                 Adam, weight conversion to bf16 layouts
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "fhv_common.h"
+
+namespace fhv {
+namespace nn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBase = 32;
+constexpr int kInPad = 8;   // 6 input channels padded to 8
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+enum { MODE_SAME3 = 0, MODE_UP2 = 1, MODE_GATHER4 = 2 };
+
+struct ConvArgs {
+    const uint16_t* in;   // first input channel of pixel 0
+    const uint16_t* wt;   // [Cout][T * Cin] bf16 (UP2: + tap * Cout * Cin)
+    const float* bias;    // fp32 [Cout] or null
+    uint16_t* out;        // first output channel of pixel 0
+    uint32_t in_cs, out_cs;   // elements per pixel
+    uint32_t N, H, W;     // row grid: output grid (SAME3, GATHER4), input grid (UP2)
+    uint32_t Cin, Cout, T, mode, relu;
+};
+
+// Wave tile 32 pixels x 32 channels (2 x 2 MFMA 16x16x32), workgroup = 4
+// waves along x: 128 pixels of one row x 32 output channels.
+__global__ void __launch_bounds__(kBlock) k_conv(ConvArgs a)
+{
+    const int lane = __lane_id(), wv = threadIdx.x / kWave;
+    const int g = lane >> 4, l16 = lane & 15;
+    const uint32_t xtiles = (a.W + 127) / 128;
+    const uint32_t row = blockIdx.x / xtiles;
+    const uint32_t x0 = (blockIdx.x % xtiles) * 128 + wv * 32;
+    if (x0 >= a.W) return;   // whole wave past the row end
+    const uint32_t n = row / a.H, y = row % a.H;
+    const uint32_t co0 = blockIdx.y * 32;
+    const uint32_t tapz = blockIdx.z;   // UP2: output sub-position
+    const uint32_t K = a.T * a.Cin;
+    const uint16_t* wt = a.wt + (a.mode == MODE_UP2 ? (size_t)tapz * a.Cout * a.Cin : 0);
+    const uint32_t nchunk = (K + 31) / 32;
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (uint32_t c = 0; c < nchunk; ++c) {
+        const uint32_t k = c * 32 + g * 8;
+        const bool kok = k < K;
+        const uint32_t tap = kok ? k / a.Cin : 0, ci = kok ? k % a.Cin : 0;
+        u32x4 av[2], bv[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const uint32_t x = x0 + 16 * i + l16;
+            bool ok = kok && x < a.W;
+            size_t src = 0;
+            if (a.mode == MODE_SAME3) {
+                const int ys = (int)y + (int)(tap / 3) - 1, xs = (int)x + (int)(tap % 3) - 1;
+                ok = ok && ys >= 0 && ys < (int)a.H && xs >= 0 && xs < (int)a.W;
+                src = ((size_t)n * a.H + (uint32_t)ys) * a.W + (uint32_t)xs;
+            } else if (a.mode == MODE_GATHER4) {
+                const uint32_t ys = 2 * y + (tap >> 1), xs = 2 * x + (tap & 1);
+                src = ((size_t)n * 2 * a.H + ys) * (2 * (size_t)a.W) + xs;
+            } else {
+                src = (size_t)row * a.W + x;
+            }
+            av[i] = ok ? *(const u32x4*)(a.in + src * a.in_cs + ci) : u32x4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const uint32_t co = co0 + 16 * j + l16;
+            bv[j] = (kok && co < a.Cout) ? *(const u32x4*)(wt + (size_t)co * K + k) : u32x4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    __builtin_bit_cast(bf16x8, av[i]), __builtin_bit_cast(bf16x8, bv[j]), acc[i][j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const uint32_t co = co0 + 16 * j + l16;
+        if (co >= a.Cout) continue;
+        const float b = a.bias ? a.bias[co] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint32_t x = x0 + 16 * i + 4 * g + r;
+                if (x >= a.W) continue;
+                float v = acc[i][j][r] + b;
+                if (a.relu) v = v > 0.0f ? v : 0.0f;
+                size_t dst;
+                if (a.mode == MODE_UP2)
+                    dst = ((size_t)n * 2 * a.H + 2 * y + (tapz >> 1)) * (2 * (size_t)a.W) + 2 * x + (tapz & 1);
+                else
+                    dst = (size_t)row * a.W + x;
+                a.out[dst * a.out_cs + co] = f2bf(v);
+            }
+    }
+}
+
+struct WgradArgs {
+    const uint16_t* gr;   // gradient w.r.t. the layer output (first channel)
+    const uint16_t* x;    // layer input (first channel)
+    float* part;          // [splits][Cout][T][Cin]
+    uint32_t g_cs, x_cs;
+    uint32_t N, H, W;     // reduction grid: output grid (SAME3), input grid (UP2)
+    uint32_t Cin, Cout, T, mode;
+    uint32_t chunks, per_split;   // 32-pixel chunks in total / per split
+};
+
+// One wave per (32 output channels, 32 input channels, tap, split).
+__global__ void __launch_bounds__(kWave) k_wgrad(WgradArgs a)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t sg[32][40];   // [co][px]
+    __shared__ __attribute__((aligned(16))) uint16_t sx[32][40];   // [ci][px]
+    const int lane = __lane_id();
+    const int g = lane >> 4, l16 = lane & 15;
+    const uint32_t ntc = (a.Cin + 31) / 32;
+    const uint32_t co0 = (blockIdx.x / ntc) * 32, ci0 = (blockIdx.x % ntc) * 32;
+    const uint32_t tap = blockIdx.y, split = blockIdx.z;
+    const uint32_t P = a.N * a.H * a.W;
+    const uint32_t c_begin = split * a.per_split;
+    const uint32_t c_end = c_begin + a.per_split < a.chunks ? c_begin + a.per_split : a.chunks;
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int pl = lane & 31, hh = lane >> 5;   // staging: pixel, channel half
+    for (uint32_t c = c_begin; c < c_end; ++c) {
+        const uint32_t p = c * 32 + pl;
+        const bool pok = p < P;
+        const uint32_t n = p / (a.H * a.W), rem = p % (a.H * a.W), y = rem / a.W, xq = rem % a.W;
+        size_t gp, xp;
+        bool xok = pok;
+        if (a.mode == MODE_SAME3) {
+            gp = p;
+            const int ys = (int)y + (int)(tap / 3) - 1, xs = (int)xq + (int)(tap % 3) - 1;
+            xok = xok && ys >= 0 && ys < (int)a.H && xs >= 0 && xs < (int)a.W;
+            xp = ((size_t)n * a.H + (uint32_t)ys) * a.W + (uint32_t)xs;
+        } else {   // UP2: gradient lives on the doubled grid
+            gp = ((size_t)n * 2 * a.H + 2 * y + (tap >> 1)) * (2 * (size_t)a.W) + 2 * xq + (tap & 1);
+            xp = p;
+        }
+        u32x4 gv[2], xv[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const uint32_t co = co0 + 16 * hh + 8 * q;
+            gv[q] = (pok && co < a.Cout) ? *(const u32x4*)(a.gr + gp * a.g_cs + co) : u32x4{0u, 0u, 0u, 0u};
+            const uint32_t ci = ci0 + 16 * hh + 8 * q;
+            xv[q] = (xok && ci < a.Cin) ? *(const u32x4*)(a.x + xp * a.x_cs + ci) : u32x4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int ch = 16 * hh + 8 * q + 2 * e;
+                sg[ch][pl] = (uint16_t)(gv[q][e] & 0xFFFFu);
+                sg[ch + 1][pl] = (uint16_t)(gv[q][e] >> 16);
+                sx[ch][pl] = (uint16_t)(xv[q][e] & 0xFFFFu);
+                sx[ch + 1][pl] = (uint16_t)(xv[q][e] >> 16);
+            }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        u32x4 av[2], bv[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) av[i] = *(const u32x4*)&sg[16 * i + l16][8 * g];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bv[j] = *(const u32x4*)&sx[16 * j + l16][8 * g];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    __builtin_bit_cast(bf16x8, av[i]), __builtin_bit_cast(bf16x8, bv[j]), acc[i][j], 0, 0, 0);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint32_t co = co0 + 16 * i + 4 * g + r, ci = ci0 + 16 * j + l16;
+                if (co < a.Cout && ci < a.Cin)
+                    a.part[(((size_t)split * a.Cout + co) * a.T + tap) * a.Cin + ci] = acc[i][j][r];
+            }
+}
+
+// dst[layout(co, tap, ci)] = sum over splits (in order) of part; ci < Creal.
+// kind 0: 3x3 conv layout [co][tap][ci]; kind 1: transposed [tap][co][ci].
+__global__ void __launch_bounds__(kBlock)
+k_wgrad_reduce(const float* __restrict__ part, uint32_t splits, uint32_t Cout, uint32_t T,
+               uint32_t Cin, uint32_t Creal, uint32_t kind, float* __restrict__ dst)
+{
+    const size_t n = (size_t)Cout * T * Cin, i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t ci = (uint32_t)(i % Cin), tap = (uint32_t)((i / Cin) % T), co = (uint32_t)(i / ((size_t)Cin * T));
+    if (ci >= Creal) return;
+    float s = 0.0f;
+    for (uint32_t k = 0; k < splits; ++k) s += part[(size_t)k * n + i];
+    const size_t o = kind == 0 ? ((size_t)co * T + tap) * Creal + ci : ((size_t)tap * Cout + co) * Creal + ci;
+    dst[o] = s;
+}
+
+// Column sums of a [P][C] bf16 matrix (row stride cs) into fp32 partials
+// [splits][C]: thread t adds channel t % C of rows t / C, t / C + 256 / C...
+__global__ void __launch_bounds__(kBlock)
+k_colsum(const uint16_t* __restrict__ m, uint32_t cs, uint32_t P, uint32_t C, uint32_t per_split,
+         float* __restrict__ part)
+{
+    __shared__ float red[kBlock];
+    const uint32_t t = threadIdx.x;
+    const uint32_t lanes = kBlock / C;   // C divides 256 (C <= 256, power of two)
+    const uint32_t c = t % C, ph = t / C;
+    const uint32_t r0 = blockIdx.x * per_split, r1 = r0 + per_split < P ? r0 + per_split : P;
+    float s = 0.0f;
+    if (ph < lanes)
+        for (uint32_t r = r0 + ph; r < r1; r += lanes) s += bf2f(m[(size_t)r * cs + c]);
+    red[t] = s;
+    __syncthreads();
+    if (ph == 0) {
+        float tot = 0.0f;
+        for (uint32_t k = 0; k < lanes; ++k) tot += red[k * C + c];
+        part[(size_t)blockIdx.x * C + c] = tot;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_sum_splits(const float* __restrict__ part, uint32_t splits, uint32_t n, float* __restrict__ dst)
+{
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.0f;
+    for (uint32_t k = 0; k < splits; ++k) s += part[(size_t)k * n + i];
+    dst[i] = s;
+}
+
+// Splat images -> bf16 [P][8]: R, G, B, A / 255, depth - 1 (covered), cov, 0, 0.
+__global__ void __launch_bounds__(kBlock)
+k_pack_input(const uint32_t* __restrict__ rgba, const float* __restrict__ depth,
+             const uint8_t* __restrict__ cov, uint32_t P, uint16_t* __restrict__ out)
+{
+    const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= P) return;
+    const uint32_t c = rgba[p];
+    const bool cv = cov[p] != 0;
+    uint16_t v[8];
+    for (int k = 0; k < 4; ++k) v[k] = f2bf((float)((c >> (8 * k)) & 0xFFu) / 255.0f);
+    v[4] = f2bf(cv ? depth[p] - 1.0f : 0.0f);
+    v[5] = f2bf(cv ? 1.0f : 0.0f);
+    v[6] = v[7] = 0;
+    u32x4 w;
+    for (int k = 0; k < 4; ++k) w[k] = (uint32_t)v[2 * k] | ((uint32_t)v[2 * k + 1] << 16);
+    *(u32x4*)(out + (size_t)p * 8) = w;
+}
+
+// 2x2 max pool: out[n,y,x,c] (H, W = output size) from in (2H x 2W).
+__global__ void __launch_bounds__(kBlock)
+k_maxpool(const uint16_t* __restrict__ in, uint32_t in_cs, uint32_t N, uint32_t H, uint32_t W,
+          uint32_t C, uint16_t* __restrict__ out)
+{
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x, tot = (size_t)N * H * W * C;
+    if (i >= tot) return;
+    const uint32_t c = (uint32_t)(i % C);
+    const size_t p = i / C;
+    const uint32_t x = (uint32_t)(p % W), y = (uint32_t)((p / W) % H), n = (uint32_t)(p / ((size_t)W * H));
+    float m = -INFINITY;
+    uint16_t best = 0;
+    for (int k = 0; k < 4; ++k) {
+        const size_t s = ((size_t)n * 2 * H + 2 * y + (k >> 1)) * (2 * (size_t)W) + 2 * x + (k & 1);
+        const uint16_t v = in[s * in_cs + c];
+        if (bf2f(v) > m) {
+            m = bf2f(v);
+            best = v;
+        }
+    }
+    out[p * C + c] = best;
+}
+
+// Gradient w.r.t. the pooled tensor's source: the pooled gradient goes to
+// the first maximum of each window ((0,0), (0,1), (1,0), (1,1)); plus the
+// skip gradient; rounded to bf16. Grid over the source (2H x 2W).
+__global__ void __launch_bounds__(kBlock)
+k_maxpool_bwd(const uint16_t* __restrict__ src, uint32_t src_cs, const uint16_t* __restrict__ dpool,
+              const uint16_t* __restrict__ dskip, uint32_t dskip_cs, uint32_t N, uint32_t H,
+              uint32_t W, uint32_t C, uint16_t* __restrict__ out)
+{
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x, tot = (size_t)N * 4 * H * W * C;
+    if (i >= tot) return;
+    const uint32_t c = (uint32_t)(i % C);
+    const size_t p = i / C;
+    const uint32_t X = (uint32_t)(p % (2 * W)), Y = (uint32_t)((p / (2 * W)) % (2 * H)),
+                   n = (uint32_t)(p / (4 * (size_t)W * H));
+    const uint32_t y = Y >> 1, x = X >> 1, me = ((Y & 1) << 1) | (X & 1);
+    float m = -INFINITY;
+    uint32_t arg = 0;
+    for (uint32_t k = 0; k < 4; ++k) {
+        const size_t s = ((size_t)n * 2 * H + 2 * y + (k >> 1)) * (2 * (size_t)W) + 2 * x + (k & 1);
+        const float v = bf2f(src[s * src_cs + c]);
+        if (v > m) {
+            m = v;
+            arg = k;
+        }
+    }
+    float g = bf2f(dskip[p * dskip_cs + c]);
+    if (arg == me) g += bf2f(dpool[(((size_t)n * H + y) * W + x) * C + c]);
+    out[p * C + c] = f2bf(g);
+}
+
+// dz = dy where y > 0, else 0 (both bf16 [P][C], y with row stride y_cs,
+// dy with row stride dy_cs).
+__global__ void __launch_bounds__(kBlock)
+k_relu_bwd(const uint16_t* __restrict__ dy, uint32_t dy_cs, const uint16_t* __restrict__ y,
+           uint32_t y_cs, size_t P, uint32_t C, uint16_t* __restrict__ dz)
+{
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= P * C) return;
+    const size_t p = i / C;
+    const uint32_t c = (uint32_t)(i % C);
+    dz[i] = bf2f(y[p * y_cs + c]) > 0.0f ? dy[p * dy_cs + c] : (uint16_t)0;
+}
+
+// Head: residual[p][k] = b[k] + sum_c W[k][c] x[p][c] (fp32). Inference writes
+// the filled image (clamp(rgb / 255 + residual) rounded half up, alpha 255)
+// and optionally the residual.
+__global__ void __launch_bounds__(kBlock)
+k_head_fill(const uint16_t* __restrict__ x, const float* __restrict__ w, const float* __restrict__ b,
+            const uint32_t* __restrict__ rgba, uint32_t P, uint32_t* __restrict__ out,
+            float* __restrict__ residual)
+{
+    const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= P) return;
+    float r[3] = {b[0], b[1], b[2]};
+    for (int c = 0; c < kBase; ++c) {
+        const float v = bf2f(x[(size_t)p * kBase + c]);
+        for (int k = 0; k < 3; ++k) r[k] += w[k * kBase + c] * v;
+    }
+    const uint32_t s = rgba[p];
+    uint32_t o = 0xFF000000u;
+    for (int k = 0; k < 3; ++k) {
+        float v = (float)((s >> (8 * k)) & 0xFFu) / 255.0f + r[k];
+        v = v < 0.0f ? 0.0f : (v > 1.0f ? 1.0f : v);
+        o |= (uint32_t)floorf(v * 255.0f + 0.5f) << (8 * k);
+        if (residual) residual[(size_t)p * 3 + k] = r[k];
+    }
+    out[p] = o;
+}
+
+// Head in training: loss = mean over 3P of (rgb / 255 + residual - t / 255)^2.
+// Writes dX (bf16 [P][32]) and per-block partial sums: [blocks][32*3 dW, 3 db, 1 loss].
+constexpr int kHeadPart = kBase * 3 + 3 + 1;
+
+__global__ void __launch_bounds__(kBlock)
+k_head_train(const uint16_t* __restrict__ x, const float* __restrict__ w, const float* __restrict__ b,
+             const uint32_t* __restrict__ rgba, const uint32_t* __restrict__ tgt, uint32_t P,
+             uint16_t* __restrict__ dx, float* __restrict__ part)
+{
+    __shared__ float red[kBlock];
+    const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
+    const float inv_n = 1.0f / (3.0f * (float)P);
+    float xv[kBase], d[3] = {0.f, 0.f, 0.f}, l = 0.0f;
+    if (p < P) {
+        float r[3] = {b[0], b[1], b[2]};
+        for (int c = 0; c < kBase; ++c) {
+            xv[c] = bf2f(x[(size_t)p * kBase + c]);
+            for (int k = 0; k < 3; ++k) r[k] += w[k * kBase + c] * xv[c];
+        }
+        const uint32_t s = rgba[p], t = tgt[p];
+        for (int k = 0; k < 3; ++k) {
+            const float diff = ((float)((s >> (8 * k)) & 0xFFu) / 255.0f + r[k]) -
+                               (float)((t >> (8 * k)) & 0xFFu) / 255.0f;
+            l += diff * diff;
+            d[k] = 2.0f * diff * inv_n;
+        }
+        for (int c = 0; c < kBase; ++c)
+            dx[(size_t)p * kBase + c] = f2bf(w[c] * d[0] + w[kBase + c] * d[1] + w[2 * kBase + c] * d[2]);
+    } else {
+        for (int c = 0; c < kBase; ++c) xv[c] = 0.0f;
+    }
+    // block sums of dW[k][c] = d[k] x[c], db[k] = d[k], loss
+    for (int q = 0; q < kHeadPart; ++q) {
+        float v;
+        if (q < 3 * kBase) v = d[q / kBase] * xv[q % kBase];
+        else if (q < 3 * kBase + 3) v = d[q - 3 * kBase];
+        else v = l * inv_n;
+        red[threadIdx.x] = v;
+        __syncthreads();
+        for (int s = kBlock / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(size_t)blockIdx.x * kHeadPart + q] = red[0];
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_adam(float* __restrict__ th, float* __restrict__ m, float* __restrict__ v, const float* __restrict__ g,
+       uint64_t n, float lr, float c1, float c2)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = 0.9f * m[i] + 0.1f * gi;
+    const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+}
+
+// 3x3 conv weights: forward [co][tap][ci_pad] and input-gradient
+// [ci][tap'][co] with tap' = 8 - tap (spatial flip).
+__global__ void __launch_bounds__(kBlock)
+k_prep_c3(const float* __restrict__ w, uint32_t Cout, uint32_t Cin, uint32_t Cpad,
+          uint16_t* __restrict__ wf, uint16_t* __restrict__ wb)
+{
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= Cout * 9 * Cpad) return;
+    const uint32_t ci = i % Cpad, tap = (i / Cpad) % 9, co = i / (Cpad * 9);
+    const uint16_t v = ci < Cin ? f2bf(w[((size_t)co * 9 + tap) * Cin + ci]) : (uint16_t)0;
+    wf[i] = v;
+    if (wb && ci < Cin) wb[((size_t)ci * 9 + (8 - tap)) * Cout + co] = v;
+}
+
+// Transposed conv weights: forward [tap][co][ci] (= parameter layout, bf16)
+// and input-gradient [ci][tap][co].
+__global__ void __launch_bounds__(kBlock)
+k_prep_t2(const float* __restrict__ w, uint32_t Cout, uint32_t Cin, uint16_t* __restrict__ wf,
+          uint16_t* __restrict__ wb)
+{
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= 4 * Cout * Cin) return;
+    const uint32_t ci = i % Cin, co = (i / Cin) % Cout, tap = i / (Cin * Cout);
+    const uint16_t v = f2bf(w[i]);
+    wf[i] = v;
+    wb[((size_t)ci * 4 + tap) * Cout + co] = v;
+}
+
+}  // namespace nn
+}  // namespace fhv
+
+// ---------------------------------------------------------------- host side
+
+namespace fhv {
+namespace nn {
+
+namespace {
+
+struct Layer {
+    int kind;   // 0 = 3x3 conv, 1 = transposed conv, 2 = head
+    uint32_t cin, cout, cpad;
+    uint32_t lvl;          // level of the pixel grid its weight gradient sums over
+    size_t off_w, off_b;   // into the parameter vector
+    size_t wf_off, wb_off; // into the bf16 weight area (elements)
+};
+
+struct Net {
+    uint32_t L;
+    uint32_t C[4];
+    std::vector<Layer> layers;
+    size_t n_params = 0, n_wf = 0;
+
+    explicit Net(uint32_t levels) : L(levels)
+    {
+        for (uint32_t l = 0; l < 4; ++l) C[l] = (uint32_t)kBase << l;
+        uint32_t cin = 6;
+        for (uint32_t l = 0; l < L; ++l) {
+            add(0, cin, C[l], l);
+            add(0, C[l], C[l], l);
+            cin = C[l];
+        }
+        for (int l = (int)L - 2; l >= 0; --l) {
+            add(1, C[l + 1], C[l], (uint32_t)l + 1);
+            add(0, 2 * C[l], C[l], (uint32_t)l);
+            add(0, C[l], C[l], (uint32_t)l);
+        }
+        add(2, C[0], 3, 0);
+    }
+    void add(int kind, uint32_t cin, uint32_t cout, uint32_t lvl)
+    {
+        Layer y;
+        y.kind = kind;
+        y.lvl = lvl;
+        y.cin = cin;
+        y.cout = cout;
+        y.cpad = (cin + 7) / 8 * 8;
+        const size_t nw = kind == 0 ? (size_t)cout * 9 * cin : kind == 1 ? (size_t)4 * cout * cin : (size_t)cout * cin;
+        y.off_w = n_params;
+        y.off_b = n_params + nw;
+        n_params += nw + cout;
+        const size_t nwf = kind == 0 ? (size_t)cout * 9 * y.cpad : kind == 1 ? (size_t)4 * cout * cin : 0;
+        y.wf_off = n_wf;
+        y.wb_off = n_wf + nwf;
+        n_wf += 2 * nwf;
+        layers.push_back(y);
+    }
+    size_t enc(uint32_t l, uint32_t s) const { return 2 * l + s; }
+    size_t dec(uint32_t l) const { return 2 * L + 3 * (L - 2 - l); }   // t2; +1, +2 convs
+    size_t head() const { return layers.size() - 1; }
+};
+
+struct Bufs {
+    uint16_t* wt;          // bf16 weights (forward and input-gradient layouts)
+    uint16_t* x0;
+    uint16_t *e0[4], *cat[4], *elast, *pool[4], *d0[4], *d1[4];
+    // training
+    uint16_t *gh, *dz, *ga, *gb, *dcat[4];
+    float *part, *hpart, *grad;
+    size_t part_elems, hpart_elems;
+};
+
+constexpr uint32_t kWgradTarget = 4096;   // wave tiles per weight-gradient launch
+
+void wgrad_dims(uint32_t P, uint32_t Cin, uint32_t Cout, uint32_t T, uint32_t* splits, uint32_t* per)
+{
+    const uint32_t tiles = (Cout / 32) * ((Cin + 31) / 32) * T;
+    const uint32_t chunks = (P + 31) / 32;
+    uint32_t s = (kWgradTarget + tiles - 1) / tiles;
+    s = s < 1 ? 1 : (s > chunks ? chunks : s);
+    *per = (chunks + s - 1) / s;
+    *splits = (chunks + *per - 1) / *per;
+}
+
+size_t carve(const Net& net, uint32_t N, uint32_t H, uint32_t W, bool training, char* base, Bufs* b)
+{
+    Carver c{base, 0};
+    const uint32_t L = net.L;
+    auto P = [&](uint32_t l) { return (size_t)N * (H >> l) * (W >> l); };
+    b->wt = c.take<uint16_t>(net.n_wf);
+    b->x0 = c.take<uint16_t>(P(0) * kInPad);
+    for (uint32_t l = 0; l < L; ++l) {
+        b->e0[l] = c.take<uint16_t>(P(l) * net.C[l]);
+        if (l + 1 < L) {
+            b->cat[l] = c.take<uint16_t>(P(l) * 2 * net.C[l]);
+            b->pool[l] = c.take<uint16_t>(P(l + 1) * net.C[l]);
+            b->d0[l] = c.take<uint16_t>(P(l) * net.C[l]);
+            b->d1[l] = c.take<uint16_t>(P(l) * net.C[l]);
+        }
+    }
+    b->elast = c.take<uint16_t>(P(L - 1) * net.C[L - 1]);
+    if (training) {
+        size_t mx = 0, mpart = 0;
+        for (uint32_t l = 0; l < L; ++l) mx = std::max(mx, P(l) * net.C[l]);
+        b->gh = c.take<uint16_t>(P(0) * net.C[0]);
+        b->dz = c.take<uint16_t>(mx);
+        b->ga = c.take<uint16_t>(mx);
+        b->gb = c.take<uint16_t>(mx);
+        for (uint32_t l = 0; l + 1 < L; ++l) b->dcat[l] = c.take<uint16_t>(P(l) * 2 * net.C[l]);
+        // weight-gradient partials: the largest over the layers
+        for (size_t i = 0; i < net.layers.size(); ++i) {
+            const Layer& y = net.layers[i];
+            if (y.kind == 2) continue;
+            uint32_t s, per;
+            const uint32_t T = y.kind == 0 ? 9 : 4;
+            wgrad_dims((uint32_t)P(y.lvl), y.cpad, y.cout, T, &s, &per);
+            mpart = std::max(mpart, (size_t)s * y.cout * T * y.cpad);
+            mpart = std::max(mpart, (size_t)1024 * y.cout);   // bias partials
+        }
+        b->part_elems = mpart;
+        b->part = c.take<float>(mpart);
+        b->hpart_elems = ((P(0) + kBlock - 1) / kBlock) * kHeadPart;
+        b->hpart = c.take<float>(b->hpart_elems);
+        b->grad = c.take<float>(net.n_params);
+    }
+    return c.off + 256;
+}
+
+unsigned blocks(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+hipError_t conv(const uint16_t* in, uint32_t in_cs, const uint16_t* wt, const float* bias, uint16_t* out,
+                uint32_t out_cs, uint32_t N, uint32_t H, uint32_t W, uint32_t Cin, uint32_t Cout,
+                int mode, bool relu, hipStream_t s)
+{
+    ConvArgs a;
+    a.in = in;
+    a.wt = wt;
+    a.bias = bias;
+    a.out = out;
+    a.in_cs = in_cs;
+    a.out_cs = out_cs;
+    a.N = N;
+    a.H = H;
+    a.W = W;
+    a.Cin = Cin;
+    a.Cout = Cout;
+    a.T = mode == MODE_SAME3 ? 9 : (mode == MODE_GATHER4 ? 4 : 1);
+    a.mode = (uint32_t)mode;
+    a.relu = relu ? 1u : 0u;
+    const uint32_t xt = (W + 127) / 128;
+    k_conv<<<dim3(N * H * xt, (Cout + 31) / 32, mode == MODE_UP2 ? 4 : 1), dim3(kBlock), 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t wgrad(const uint16_t* gr, uint32_t g_cs, const uint16_t* x, uint32_t x_cs, uint32_t N,
+                 uint32_t H, uint32_t W, uint32_t Cin, uint32_t Creal, uint32_t Cout, int mode,
+                 float* part, size_t part_elems, float* dst, hipStream_t s)
+{
+    WgradArgs a;
+    a.gr = gr;
+    a.x = x;
+    a.part = part;
+    a.g_cs = g_cs;
+    a.x_cs = x_cs;
+    a.N = N;
+    a.H = H;
+    a.W = W;
+    a.Cin = Cin;
+    a.Cout = Cout;
+    a.T = mode == MODE_SAME3 ? 9 : 4;
+    a.mode = (uint32_t)mode;
+    const uint32_t P = N * H * W;
+    uint32_t splits = 0;
+    wgrad_dims(P, Cin, Cout, a.T, &splits, &a.per_split);
+    a.chunks = (P + 31) / 32;
+    if ((size_t)splits * Cout * a.T * Cin > part_elems) return hipErrorInvalidValue;
+    k_wgrad<<<dim3((Cout / 32) * ((Cin + 31) / 32), a.T, splits), dim3(kWave), 0, s>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_wgrad_reduce<<<blocks((size_t)Cout * a.T * Cin), dim3(kBlock), 0, s>>>(
+        part, splits, Cout, a.T, Cin, Creal, mode == MODE_SAME3 ? 0u : 1u, dst);
+    return hipGetLastError();
+}
+
+hipError_t bgrad(const uint16_t* m, uint32_t cs, uint32_t P, uint32_t C, float* part, float* dst,
+                 hipStream_t s)
+{
+    uint32_t splits = (P + 255) / 256;
+    splits = splits > 1024 ? 1024 : splits;
+    const uint32_t per = (P + splits - 1) / splits;
+    splits = (P + per - 1) / per;
+    k_colsum<<<dim3(splits), dim3(kBlock), 0, s>>>(m, cs, P, C, per, part);
+    k_sum_splits<<<blocks(C), dim3(kBlock), 0, s>>>(part, splits, C, dst);
+    return hipGetLastError();
+}
+
+#define FHV_TRY(x)                                  \
+    do {                                            \
+        hipError_t e_ = (x);                        \
+        if (e_ != hipSuccess) return e_;            \
+    } while (0)
+
+hipError_t prep_weights(const Net& net, const float* th, bool training, const Bufs& b, hipStream_t s)
+{
+    for (size_t i = 0; i < net.layers.size(); ++i) {
+        const Layer& y = net.layers[i];
+        if (y.kind == 0)
+            k_prep_c3<<<blocks((size_t)y.cout * 9 * y.cpad), dim3(kBlock), 0, s>>>(
+                th + y.off_w, y.cout, y.cin, y.cpad, b.wt + y.wf_off,
+                (training && i > 0) ? b.wt + y.wb_off : nullptr);
+        else if (y.kind == 1)
+            k_prep_t2<<<blocks((size_t)4 * y.cout * y.cin), dim3(kBlock), 0, s>>>(
+                th + y.off_w, y.cout, y.cin, b.wt + y.wf_off, b.wt + y.wb_off);
+    }
+    return hipGetLastError();
+}
+
+// Forward pass up to the head input; returns it (P0 x 32, row stride 32).
+hipError_t forward(const Net& net, const float* th, const Bufs& b, uint32_t N, uint32_t H, uint32_t W,
+                   hipStream_t s, const uint16_t** head_in)
+{
+    const uint32_t L = net.L;
+    const uint16_t* h = b.x0;
+    uint32_t h_cs = kInPad, cin = kInPad;
+    for (uint32_t l = 0; l < L; ++l) {
+        const uint32_t Hl = H >> l, Wl = W >> l, Cl = net.C[l];
+        const Layer& a0 = net.layers[net.enc(l, 0)];
+        const Layer& a1 = net.layers[net.enc(l, 1)];
+        FHV_TRY(conv(h, h_cs, b.wt + a0.wf_off, th + a0.off_b, b.e0[l], Cl, N, Hl, Wl, cin, Cl, MODE_SAME3, true, s));
+        uint16_t* o1 = l + 1 < L ? b.cat[l] + Cl : b.elast;
+        const uint32_t o1_cs = l + 1 < L ? 2 * Cl : Cl;
+        FHV_TRY(conv(b.e0[l], Cl, b.wt + a1.wf_off, th + a1.off_b, o1, o1_cs, N, Hl, Wl, Cl, Cl, MODE_SAME3, true, s));
+        if (l + 1 < L) {
+            k_maxpool<<<blocks((size_t)N * (Hl / 2) * (Wl / 2) * Cl), dim3(kBlock), 0, s>>>(
+                o1, o1_cs, N, Hl / 2, Wl / 2, Cl, b.pool[l]);
+            FHV_TRY(hipGetLastError());
+            h = b.pool[l];
+            h_cs = Cl;
+            cin = Cl;
+        }
+    }
+    h = b.elast;
+    h_cs = net.C[L - 1];
+    for (int l = (int)L - 2; l >= 0; --l) {
+        const uint32_t Hl = H >> l, Wl = W >> l, Cl = net.C[l];
+        const Layer& t = net.layers[net.dec(l)];
+        const Layer& c0 = net.layers[net.dec(l) + 1];
+        const Layer& c1 = net.layers[net.dec(l) + 2];
+        FHV_TRY(conv(h, h_cs, b.wt + t.wf_off, th + t.off_b, b.cat[l], 2 * Cl, N, Hl / 2, Wl / 2,
+                     net.C[l + 1], Cl, MODE_UP2, false, s));
+        FHV_TRY(conv(b.cat[l], 2 * Cl, b.wt + c0.wf_off, th + c0.off_b, b.d0[l], Cl, N, Hl, Wl, 2 * Cl, Cl,
+                     MODE_SAME3, true, s));
+        FHV_TRY(conv(b.d0[l], Cl, b.wt + c1.wf_off, th + c1.off_b, b.d1[l], Cl, N, Hl, Wl, Cl, Cl,
+                     MODE_SAME3, true, s));
+        h = b.d1[l];
+        h_cs = Cl;
+    }
+    *head_in = h;
+    return hipSuccess;
+}
+
+// Backward through a 3x3 conv layer i with output y (row stride y_cs) given
+// the gradient g w.r.t. y (row stride g_cs): weight and bias gradients into
+// grad, and (when gin) the input gradient into gin (row stride gin_cs).
+hipError_t conv_bwd(const Net& net, size_t i, const Bufs& b, const uint16_t* x, uint32_t x_cs,
+                    const uint16_t* y, uint32_t y_cs, const uint16_t* g, uint32_t g_cs, uint16_t* gin,
+                    uint32_t gin_cs, uint32_t N, uint32_t Hl, uint32_t Wl, hipStream_t s)
+{
+    const Layer& ly = net.layers[i];
+    const size_t P = (size_t)N * Hl * Wl;
+    k_relu_bwd<<<blocks(P * ly.cout), dim3(kBlock), 0, s>>>(g, g_cs, y, y_cs, P, ly.cout, b.dz);
+    FHV_TRY(hipGetLastError());
+    FHV_TRY(wgrad(b.dz, ly.cout, x, x_cs, N, Hl, Wl, ly.cpad, ly.cin, ly.cout, MODE_SAME3, b.part,
+                  b.part_elems, b.grad + ly.off_w, s));
+    FHV_TRY(bgrad(b.dz, ly.cout, (uint32_t)P, ly.cout, b.part, b.grad + ly.off_b, s));
+    if (gin)
+        FHV_TRY(conv(b.dz, ly.cout, b.wt + ly.wb_off, nullptr, gin, gin_cs, N, Hl, Wl, ly.cout, ly.cpad,
+                     MODE_SAME3, false, s));
+    return hipSuccess;
+}
+
+hipError_t backward(const Net& net, const float* th, const Bufs& b, uint32_t N, uint32_t H, uint32_t W,
+                    hipStream_t s)
+{
+    const uint32_t L = net.L;
+    // decoder, top level first; g is the gradient w.r.t. the level's output
+    const uint16_t* g = b.gh;
+    for (uint32_t l = 0; l + 1 < L; ++l) {
+        const uint32_t Hl = H >> l, Wl = W >> l, Cl = net.C[l];
+        const size_t it = net.dec(l);
+        FHV_TRY(conv_bwd(net, it + 2, b, b.d0[l], Cl, b.d1[l], Cl, g, Cl, b.ga, Cl, N, Hl, Wl, s));
+        FHV_TRY(conv_bwd(net, it + 1, b, b.cat[l], 2 * Cl, b.d0[l], Cl, b.ga, Cl, b.dcat[l], 2 * Cl, N, Hl,
+                         Wl, s));
+        // transposed conv: input hin on level l + 1, output gradient = first half of dcat
+        const Layer& t = net.layers[it];
+        const uint16_t* hin = (l + 2 == L) ? b.elast : b.d1[l + 1];
+        const uint32_t Cu = net.C[l + 1];
+        FHV_TRY(wgrad(b.dcat[l], 2 * Cl, hin, Cu, N, Hl / 2, Wl / 2, Cu, Cu, Cl, MODE_UP2, b.part,
+                      b.part_elems, b.grad + t.off_w, s));
+        FHV_TRY(bgrad(b.dcat[l], 2 * Cl, N * Hl * Wl, Cl, b.part, b.grad + t.off_b, s));
+        FHV_TRY(conv(b.dcat[l], 2 * Cl, b.wt + t.wb_off, nullptr, b.gb, Cu, N, Hl / 2, Wl / 2, Cl, Cu,
+                     MODE_GATHER4, false, s));
+        g = b.gb;
+    }
+    // encoder, deepest level first. The gradient stays in one buffer (each
+    // layer's ReLU-gradient kernel consumes it before the layer's input
+    // gradient overwrites it), except across a max pool, whose gradient
+    // kernel reads the pooled gradient and writes the other buffer.
+    uint16_t* cur = (uint16_t*)g;
+    for (int l = (int)L - 1; l >= 0; --l) {
+        const uint32_t Hl = H >> l, Wl = W >> l, Cl = net.C[l];
+        const uint16_t* y1 = l + 1 < (int)L ? b.cat[l] + Cl : b.elast;
+        const uint32_t y1_cs = l + 1 < (int)L ? 2 * Cl : Cl;
+        if (l + 1 < (int)L) {
+            uint16_t* nxt = cur == b.ga ? b.gb : b.ga;
+            // pooled gradient (cur, on level l + 1) plus the skip gradient
+            k_maxpool_bwd<<<blocks((size_t)N * Hl * Wl * Cl), dim3(kBlock), 0, s>>>(
+                y1, y1_cs, cur, b.dcat[l] + Cl, 2 * Cl, N, Hl / 2, Wl / 2, Cl, nxt);
+            FHV_TRY(hipGetLastError());
+            cur = nxt;
+        }
+        FHV_TRY(conv_bwd(net, net.enc(l, 1), b, b.e0[l], Cl, y1, y1_cs, cur, Cl, cur, Cl, N, Hl, Wl, s));
+        const uint16_t* x0 = l == 0 ? b.x0 : b.pool[l - 1];
+        const uint32_t x0_cs = l == 0 ? kInPad : net.C[l - 1];
+        FHV_TRY(conv_bwd(net, net.enc(l, 0), b, x0, x0_cs, b.e0[l], Cl, cur, Cl, l > 0 ? cur : nullptr,
+                         l > 0 ? net.C[l - 1] : 0, N, Hl, Wl, s));
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+uint64_t param_count(uint32_t levels) { return Net(levels).n_params; }
+
+size_t fill_ws_bytes(uint32_t levels, uint32_t N, uint32_t H, uint32_t W, bool training)
+{
+    Net net(levels);
+    Bufs b;
+    return carve(net, N, H, W, training, nullptr, &b);
+}
+
+hipError_t fill(uint32_t levels, const float* th, const uint32_t* rgba, const float* depth, const uint8_t* cov,
+                uint32_t N, uint32_t H, uint32_t W, uint32_t* out, float* residual, void* ws, hipStream_t s)
+{
+    Net net(levels);
+    Bufs b;
+    carve(net, N, H, W, false, (char*)ws, &b);
+    const uint32_t P = N * H * W;
+    k_pack_input<<<blocks(P), dim3(kBlock), 0, s>>>(rgba, depth, cov, P, b.x0);
+    FHV_TRY(hipGetLastError());
+    FHV_TRY(prep_weights(net, th, false, b, s));
+    const uint16_t* hin = nullptr;
+    FHV_TRY(forward(net, th, b, N, H, W, s, &hin));
+    const Layer& hd = net.layers[net.head()];
+    k_head_fill<<<blocks(P), dim3(kBlock), 0, s>>>(hin, th + hd.off_w, th + hd.off_b, rgba, P, out, residual);
+    return hipGetLastError();
+}
+
+hipError_t train_step(uint32_t levels, float* th, float* m, float* v, uint32_t step, float lr,
+                      const uint32_t* rgba, const float* depth, const uint8_t* cov, const uint32_t* tgt,
+                      uint32_t N, uint32_t H, uint32_t W, float* loss, float* grad_out, void* ws,
+                      hipStream_t s)
+{
+    Net net(levels);
+    Bufs b;
+    carve(net, N, H, W, true, (char*)ws, &b);
+    if (grad_out) b.grad = grad_out;
+    const uint32_t P = N * H * W;
+    k_pack_input<<<blocks(P), dim3(kBlock), 0, s>>>(rgba, depth, cov, P, b.x0);
+    FHV_TRY(hipGetLastError());
+    FHV_TRY(prep_weights(net, th, true, b, s));
+    const uint16_t* hin = nullptr;
+    FHV_TRY(forward(net, th, b, N, H, W, s, &hin));
+    const Layer& hd = net.layers[net.head()];
+    const uint32_t hb = blocks(P);
+    k_head_train<<<dim3(hb), dim3(kBlock), 0, s>>>(hin, th + hd.off_w, th + hd.off_b, rgba, tgt, P, b.gh,
+                                                   b.hpart);
+    FHV_TRY(hipGetLastError());
+    // head weight and bias gradients, and the loss
+    k_sum_splits<<<blocks(kHeadPart), dim3(kBlock), 0, s>>>(b.hpart, hb, kHeadPart, b.part);
+    FHV_TRY(hipGetLastError());
+    FHV_TRY(hipMemcpyAsync(b.grad + hd.off_w, b.part, sizeof(float) * 3 * kBase, hipMemcpyDeviceToDevice, s));
+    FHV_TRY(hipMemcpyAsync(b.grad + hd.off_b, b.part + 3 * kBase, sizeof(float) * 3, hipMemcpyDeviceToDevice, s));
+    if (loss) FHV_TRY(hipMemcpyAsync(loss, b.part + 3 * kBase + 3, sizeof(float), hipMemcpyDeviceToDevice, s));
+    FHV_TRY(backward(net, th, b, N, H, W, s));
+    if (step > 0) {   // step 0: gradients only
+        const float c1 = 1.0f - powf(0.9f, (float)step), c2 = 1.0f - powf(0.999f, (float)step);
+        k_adam<<<blocks(net.n_params), dim3(kBlock), 0, s>>>(th, m, v, b.grad, net.n_params, lr, c1, c2);
+        FHV_TRY(hipGetLastError());
+    }
+    return hipSuccess;
+}
+
+}  // namespace nn
+}  // namespace fhv

@@ -57,7 +57,8 @@ class KernelStat_(C.Structure):
 
 EXPORTS = ["fhv_create", "fhv_destroy", "fhv_status_str", "fhv_capture_workspace", "fhv_capture",
            "fhv_compact_workspace", "fhv_compact", "fhv_splat", "fhv_profile_begin",
-           "fhv_profile_end"]
+           "fhv_profile_end", "fhv_unet_param_count", "fhv_fill_workspace", "fhv_fill",
+           "fhv_fill_train_step"]
 
 _lib = None
 _ctx: dict[int, C.c_void_p] = {}
@@ -85,10 +86,18 @@ def lib():
                                   C.c_size_t, P]
         L.fhv_splat.argtypes = [P, C.POINTER(Pofa_), C.POINTER(Desc_), C.POINTER(View_), C.c_uint32,
                                 P, P, P, P, P]
+        L.fhv_unet_param_count.argtypes = [C.c_uint32]
+        L.fhv_unet_param_count.restype = C.c_uint64
+        L.fhv_fill_workspace.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int]
+        L.fhv_fill_workspace.restype = C.c_size_t
+        L.fhv_fill.argtypes = [P, C.c_uint32, P, P, P, P, C.c_uint32, C.c_uint32, C.c_uint32, P, P, P,
+                               C.c_size_t, P]
+        L.fhv_fill_train_step.argtypes = [P, C.c_uint32, P, P, P, C.c_uint32, C.c_float, P, P, P, P,
+                                          C.c_uint32, C.c_uint32, C.c_uint32, P, P, P, C.c_size_t, P]
         L.fhv_profile_begin.argtypes = [P]
         L.fhv_profile_end.argtypes = [P, C.POINTER(KernelStat_), C.c_uint32, C.POINTER(C.c_uint32)]
         for f in ("fhv_create", "fhv_destroy", "fhv_capture", "fhv_compact", "fhv_splat",
-                  "fhv_profile_begin", "fhv_profile_end"):
+                  "fhv_profile_begin", "fhv_profile_end", "fhv_fill", "fhv_fill_train_step"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -290,3 +299,46 @@ def profile_end() -> dict[str, tuple[int, float]]:
     _check(lib().fhv_profile_end(ctx(), arr, 64, C.byref(n)), "fhv_profile_end")
     return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms))
             for i in range(min(n.value, 64))}
+
+
+# ------------------------------------------------------------------ learned fill
+
+def unet_param_count(levels: int = 4) -> int:
+    return int(lib().fhv_unet_param_count(levels))
+
+
+def fill_workspace(levels: int, n_img: int, height: int, width: int, training: bool) -> int:
+    return int(lib().fhv_fill_workspace(levels, n_img, height, width, 1 if training else 0))
+
+
+def _ws(t: torch.Tensor | None, need: int, device) -> torch.Tensor:
+    if t is None or t.numel() < need:
+        t = torch.empty(max(need, 1), dtype=torch.uint8, device=device)
+    return t
+
+
+def fill(params: torch.Tensor, rgba: torch.Tensor, depth: torch.Tensor, cov: torch.Tensor,
+         levels: int = 4, residual: bool = False, ws: torch.Tensor | None = None):
+    """fhv_fill on [N, H, W] splat images; returns (rgba int32 [N,H,W],
+    residual float32 [N,H,W,3] or None)."""
+    N, H, W = rgba.shape
+    ws = _ws(ws, fill_workspace(levels, N, H, W, False), rgba.device)
+    out = torch.empty((N, H, W), dtype=torch.int32, device=rgba.device)
+    res = torch.empty((N, H, W, 3), dtype=torch.float32, device=rgba.device) if residual else None
+    _check(lib().fhv_fill(ctx(), levels, _ptr(params), _ptr(rgba), _ptr(depth), _ptr(cov), N, H, W,
+                          _ptr(out), _ptr(res), _ptr(ws), ws.numel(), _stream()), "fhv_fill")
+    return out, res
+
+
+def fill_train_step(params: torch.Tensor, m: torch.Tensor | None, v: torch.Tensor | None, step: int,
+                    lr: float, rgba: torch.Tensor, depth: torch.Tensor, cov: torch.Tensor,
+                    target: torch.Tensor, levels: int = 4, loss: torch.Tensor | None = None,
+                    grad: torch.Tensor | None = None, ws: torch.Tensor | None = None):
+    """fhv_fill_train_step; params, m, v updated in place (step >= 1)."""
+    N, H, W = rgba.shape
+    ws = _ws(ws, fill_workspace(levels, N, H, W, True), rgba.device)
+    _check(lib().fhv_fill_train_step(ctx(), levels, _ptr(params), _ptr(m), _ptr(v), step, lr,
+                                     _ptr(rgba), _ptr(depth), _ptr(cov), _ptr(target), N, H, W,
+                                     _ptr(loss), _ptr(grad), _ptr(ws), ws.numel(), _stream()),
+           "fhv_fill_train_step")
+    return ws
