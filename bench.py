@@ -3,14 +3,17 @@
 
 One step = capture of a 200,000-triangle procedural scene into per-octant
 fragment lists at octree depth 9 (512^3 leaves, 1024 samples per cube side,
-tangent-space rasterization), compaction into per-octant arrays, and point
-splats of three 1920x1080 novel views at 0, 30 and 60 degrees. Inputs are
-uploaded before the timed region; every buffer is allocated once.
+tangent-space rasterization), compaction into per-octant arrays, point
+splats of three 1920x1080 novel views at 0, 30 and 60 degrees, and the
+learned fill (4-level U-Net, bf16 matrix cores) of those three views.
+Inputs are uploaded before the timed region; every buffer is allocated once.
 
 Prints one JSON line: whole-step fragments captured per second (`value`),
-1080p views per second of the splat stage, per-kernel times from HIP events
-over the timed region, the roofline of the dominant kernel, and the CPU
-oracle timed on one host core beside it.
+1080p views per second, per-kernel times from HIP events over the timed
+region, the roofline of the dominant kernel, the learned fill's training
+throughput and its PSNR gain over the plain splat (a short training run on
+separate scenes, evaluated on held-out views), and the CPU oracle timed on
+one host core beside it.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -28,13 +31,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, vendor figure
+MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense bf16 matrix cores, vendor figure
 LEVELS = 9
 N_TRI = 200_000
 SEED = 0
 THETAS = (0.0, 30.0, 60.0)
 W_OUT, H_OUT = 1920, 1080
 WORKLOAD = ("pofl->pofa: 200k-tri procedural scene (seed 0), octree depth 9, "
-            "3 x 1920x1080 splats at 0/30/60 deg")
+            "3 x 1920x1080 splats at 0/30/60 deg + learned fill of the 3 views")
 
 
 def host_info():
@@ -83,6 +87,7 @@ def algorithmic_bytes(F: int, n_occ: int, n_tri: int, n_head: int, n_views: int,
 
 # kernels behind each timed scope (POFL mode)
 SCOPE_KERNELS = {
+    "fill.conv": ["k_conv"],
     "capture.reset": ["k_fill_u32"], "capture.setup": ["k_setup"], "capture.raster": ["k_raster<1>"],
     "compact.hist": ["k_hist"], "compact.scatter": ["k_scatter"],
     "compact.brick": ["k_brick_wave", "k_brick"], "splat.zclear": ["k_zclear"],
@@ -116,6 +121,72 @@ def measured_traffic(scope: str):
     return sum(ks[k]["read_bytes"] + ks[k]["write_bytes"] for k in SCOPE_KERNELS[scope])
 
 
+def unet_flops_per_pixel(levels: int = 4, training: bool = False) -> float:
+    """Multiply-adds x 2 per level-0 pixel of the fill network's matrix
+    products: 3x3 convs 2*9*Cin*Cout and transposed convs 2*Cin*Cout per
+    output pixel of their level, the 1x1 head 2*32*3. Training adds the
+    weight gradients (same count) and the input gradients (same count, all
+    but the first layer)."""
+    ch = [32 << l for l in range(levels)]
+    fwd, first = 0.0, 0.0
+    cin = 6
+    for l in range(levels):
+        a = 2 * 9 * cin * ch[l] / 4 ** l
+        first = a if l == 0 else first
+        fwd += a + 2 * 9 * ch[l] * ch[l] / 4 ** l
+        cin = ch[l]
+    for l in range(levels - 1):
+        fwd += 2 * ch[l + 1] * ch[l] / 4 ** l + 2 * 9 * 2 * ch[l] * ch[l] / 4 ** l + 2 * 9 * ch[l] * ch[l] / 4 ** l
+    fwd += 2 * 32 * 3
+    return 3 * fwd - first if training else fwd
+
+
+def learned_fill_report(torch, fhv, scenes, train_steps: int = 600):
+    """Train the fill on splats of separate scenes (octree depth 8, 1080p,
+    random orbit angles) against reference renders of the same views (the
+    library's per-pixel capture of the triangles, nearest fragment kept),
+    then compare PSNR of fill and plain splat on a held-out scene at 30 and
+    60 degrees. Returns the report and the trained model."""
+    import numpy as np
+    from paper_2211_15460_amd import learned_fill as LF
+    L, W, H = 8, 1920, 1080
+    rng = np.random.default_rng(0)
+    srcs, tgts = [], []
+    for s in range(4):
+        mesh = LF.training_scene(100 + s)
+        views = [scenes.cube_view(float(t), L, W, H) for t in rng.uniform(0, 90, 4)]
+        img, _ = LF.render_splats(mesh, L, views)
+        srcs.append(img)
+        tgts.append(torch.cat([LF.reference_render(mesh, L, v) for v in views]))
+    data = LF.SplatImages(*(torch.cat([getattr(i, f) for i in srcs]) for f in ("rgba", "depth", "cov")))
+    target = torch.cat(tgts)
+    model = LF.FillModel(4, 0)
+    # crops are cut before the timed loop, which then runs without host syncs
+    batches = [LF.random_crops(data, target, 8, 256, rng) for _ in range(64)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for st in range(1, train_steps + 1):
+        model.train_step(*batches[st % len(batches)], LF.lr_at(st, train_steps, 1e-3, 5e-5))
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / train_steps
+    res = {"train_steps": train_steps, "batch": "8 x 256 x 256", "train_ms_per_step": ms,
+           "train_tflops": unet_flops_per_pixel(4, True) * 8 * 256 * 256 / (ms * 1e-3) / 1e12,
+           "octree_levels": L, "eval": []}
+    mesh = LF.training_scene(0)
+    for th in (30.0, 60.0):
+        v = scenes.cube_view(th, L, W, H)
+        img, _ = LF.render_splats(mesh, L, [v])
+        ref = LF.reference_render(mesh, L, v)
+        out = model.fill(img)
+        res["eval"].append({"theta": th, "psnr_splat_db": LF.psnr_rgb(img.rgba, ref),
+                            "psnr_fill_db": LF.psnr_rgb(out, ref)})
+    res["margin_db"] = min(e["psnr_fill_db"] - e["psnr_splat_db"] for e in res["eval"])
+    res["reference"] = "library per-pixel capture of the triangles in the view, nearest fragment"
+    return res, model
+
+
 def cpu_baseline(mesh, views, min_seconds: float = 10.0):
     """The CPU oracle, single-threaded, on the same workload: full steps
     (capture, compaction, three splats) repeated for at least min_seconds."""
@@ -142,6 +213,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-train", action="store_true", help="skip the learned-fill training report")
     ap.add_argument("--copy-mib", type=int, default=256,
                     help="size of a plain device copy run once before the steps, so that "
                          "hardware byte counters can be calibrated against a known size")
@@ -173,11 +245,16 @@ def main():
     ws_c = torch.empty(fhv.capture_workspace(d, mesh.n_tri), dtype=torch.uint8, device="cuda")
     ws_k = torch.empty(fhv.compact_workspace(d, cap), dtype=torch.uint8, device="cuda")
     vs = fhv.views_struct(views)
+    from paper_2211_15460_amd import learned_fill as LF
+    fill_params = torch.from_numpy(LF.init_params(0, 4)).cuda()
+    ws_f = torch.empty(fhv.fill_workspace(4, len(views), H_OUT, W_OUT, False), dtype=torch.uint8,
+                       device="cuda")
 
     def step():
         fhv.capture(dm, d, lists, ws_c)
         fhv.compact(lists, d, pofa, ws_k)
         fhv.splat(pofa, d, views, imgs, vs)
+        fhv.fill(fill_params, imgs.rgba, imgs.depth, imgs.cov, 4, ws=ws_f)
 
     if args.copy_mib > 0:
         src = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device="cuda")
@@ -208,19 +285,34 @@ def main():
     n_head = 8 ** LEVELS
     pix = W_OUT * H_OUT
     algo = algorithmic_bytes(F, n_occ, mesh.n_tri, n_head, len(views), pix)
+    fill_flops = unet_flops_per_pixel(4) * len(views) * pix      # per step
     kernels = {}
     for name, (launches, tot) in prof.items():
+        per_step = launches / args.steps
         avg = tot / max(launches, 1)
+        if name == "fill.conv":
+            fl = fill_flops / per_step      # matrix-product flops per launch, averaged
+            kernels[name] = {"avg_ms": round(avg, 5), "launches": launches, "algo_flops": fl,
+                             "tflops": round(fl / (avg * 1e-3) / 1e12, 2) if avg > 0 else None}
+            continue
         b = algo.get(name, 0)
         kernels[name] = {"avg_ms": round(avg, 5), "launches": launches,
                          "algo_bytes": b, "gbs": round(b / (avg * 1e-3) / 1e9, 1) if avg > 0 else None}
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
     dk = kernels[dom]
-    achieved = dk["gbs"]
-    splat_ms = sum(kernels[k]["avg_ms"] for k in kernels if k.startswith("splat."))
-    capture_ms = sum(kernels[k]["avg_ms"] for k in kernels if k.startswith("capture."))
-    compact_ms = sum(kernels[k]["avg_ms"] for k in kernels if k.startswith("compact."))
+    stage = lambda pre: sum(kernels[k]["avg_ms"] * kernels[k]["launches"] / args.steps
+                            for k in kernels if k.startswith(pre))
+    splat_ms, capture_ms, compact_ms, fill_ms = stage("splat."), stage("capture."), stage("compact."), stage("fill.")
     cs_bytes = sum(algo[k] for k in algo if k.startswith(("compact.", "splat.")))
+    if dom == "fill.conv":
+        roof = {"bound": "mfma", "kernel": "k_conv (fill.conv)", "achieved": dk["tflops"],
+                "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": dk["tflops"] / MFMA_BF16_PEAK_TFLOPS if dk["tflops"] else None,
+                "traffic": measured_traffic(dom)}
+    else:
+        roof = {"bound": "hbm", "kernel": dom, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": dk["gbs"] / HBM_PEAK_GBS if dk["gbs"] else None,
+                "traffic": measured_traffic(dom)}
     out = {
         "metric": "fragments captured/s; 1080p novel views/s; learned-fill vs plain-splat PSNR",
         "value": F / (ms_step * 1e-3),
@@ -237,18 +329,21 @@ def main():
         "config": {"workload": WORKLOAD, "n_tri": mesh.n_tri, "levels": LEVELS,
                    "fragments": F, "occupied_octants": n_occ, "views": len(views),
                    "view_size": [W_OUT, H_OUT]},
-        "views_per_s_1080p": len(views) / (splat_ms * 1e-3),
+        "views_per_s_1080p": len(views) / (ms_step * 1e-3),
+        "splat_views_per_s_1080p": len(views) / (splat_ms * 1e-3),
         "capture_fragments_per_s": F / (capture_ms * 1e-3),
-        "stage_ms": {"capture": capture_ms, "compact": compact_ms, "splat": splat_ms},
+        "fill_ms_per_1080p_view": fill_ms / len(views),
+        "fill_tflops": fill_flops / (fill_ms * 1e-3) / 1e12 if fill_ms else None,
+        "stage_ms": {"capture": capture_ms, "compact": compact_ms, "splat": splat_ms, "fill": fill_ms},
         "compact_splat_hbm_frac": (cs_bytes / ((compact_ms + splat_ms) * 1e-3) / 1e9) / HBM_PEAK_GBS,
         "kernels": kernels,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
-                     "traffic": measured_traffic(dom)},
+        "roofline": roof,
         "wall_s_timed": wall,
         "host": host_info(),
         "device": torch.cuda.get_device_name(0),
     }
+    if not args.no_train:
+        out["learned_fill"], _ = learned_fill_report(torch, fhv, scenes)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, views)
     print(json.dumps(out), flush=True)

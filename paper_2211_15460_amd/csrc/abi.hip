@@ -280,8 +280,7 @@ fhv_status fhv_fill(fhv_ctx* ctx, uint32_t levels, const float* params, const ui
     if (ws_bytes < fhv::nn::fill_ws_bytes(levels, n_img, height, width, false)) return FHV_EWORKSPACE;
     fhv_status st = set_device(ctx);
     if (st != FHV_OK) return st;
-    fhv::ProfScope ps(ctx->dev, "fill.forward", (hipStream_t)stream);
-    return hip_status(fhv::nn::fill(levels, params, rgba, depth, cov, n_img, height, width, out_rgba,
+    return hip_status(fhv::nn::fill(ctx->dev, levels, params, rgba, depth, cov, n_img, height, width, out_rgba,
                                     out_residual, ws, (hipStream_t)stream));
 }
 
@@ -298,8 +297,7 @@ fhv_status fhv_fill_train_step(fhv_ctx* ctx, uint32_t levels, float* params, flo
     if (ws_bytes < fhv::nn::fill_ws_bytes(levels, n_img, height, width, true)) return FHV_EWORKSPACE;
     fhv_status st = set_device(ctx);
     if (st != FHV_OK) return st;
-    fhv::ProfScope ps(ctx->dev, "fill.train_step", (hipStream_t)stream);
-    return hip_status(fhv::nn::train_step(levels, params, adam_m, adam_v, step, lr, rgba, depth, cov,
+    return hip_status(fhv::nn::train_step(ctx->dev, levels, params, adam_m, adam_v, step, lr, rgba, depth, cov,
                                           target_rgba, n_img, height, width, loss_out, grad_out, ws,
                                           (hipStream_t)stream));
 }

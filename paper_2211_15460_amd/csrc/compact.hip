@@ -119,8 +119,15 @@ __device__ void scan512(uint32_t* v, uint32_t* tmp)
     __syncthreads();
 }
 
+// Workgroup path for one brick of n records (n above the wave kernel's
+// size). Counting sort by key from src into buf (LDS when it fits, else the
+// brick's output range), then every record goes to its key's offset plus its
+// rank inside the key's run in (w0, w1, w2) order (equal records ordered by
+// position), with w3 = the key's table rank. In LDS the placement writes the
+// output directly; otherwise it writes the brick's staging range (src, no
+// longer needed) and the result is copied to the output.
 template <bool kInLds>
-__device__ void brick_sort(uint4* __restrict__ buf, const uint4* __restrict__ src, uint32_t n,
+__device__ void brick_sort(uint4* __restrict__ buf, uint4* __restrict__ src, uint32_t n,
                            uint32_t* cnt, uint32_t* off, uint32_t* cur, uint32_t* rank,
                            uint32_t* tmp, uint32_t brick, uint32_t base_off, uint32_t base_rank,
                            uint4* __restrict__ out, uint64_t* __restrict__ oct_key,
@@ -142,41 +149,39 @@ __device__ void brick_sort(uint4* __restrict__ buf, const uint4* __restrict__ sr
     scan512(rank, tmp);
     for (int k = 0; k < 2; ++k) cur[2 * t + k] = off[2 * t + k];
     __syncthreads();
-    // counting sort by key into buf
     for (uint32_t i = t; i < n; i += kBlock) {
         const uint4 r = src[i];
         const uint32_t p = atomicAdd(cur + (r.w & (kBrickKeys - 1)), 1u);
         buf[p] = r;
     }
-    __syncthreads();
-    // canonical order inside every key, then table rows
     for (int k = 0; k < 2; ++k) {
-        const uint32_t leaf = 2 * t + k;
-        const uint32_t c = cnt[leaf], o = off[leaf];
-        for (uint32_t a = 1; a < c; ++a) {
-            const uint4 x = buf[o + a];
-            uint32_t b = a;
-            while (b > 0 && rec_less(x, buf[o + b - 1])) {
-                buf[o + b] = buf[o + b - 1];
-                --b;
-            }
-            buf[o + b] = x;
-        }
+        const uint32_t leaf = 2 * t + k, c = cnt[leaf];
         if (c) {
             const uint64_t rk = (uint64_t)base_rank + rank[leaf];
             if (rk < cap_occ) {
                 oct_key[rk] = ((uint64_t)brick << kBrickShift) | leaf;
-                oct_off[rk] = base_off + o;
+                oct_off[rk] = base_off + off[leaf];
                 oct_cnt[rk] = c;
             }
         }
     }
+    if (!kInLds) __threadfence();
     __syncthreads();
-    // records out with w3 = rank
+    uint4* dst = kInLds ? out : src;
     for (uint32_t i = t; i < n; i += kBlock) {
-        uint4 r = buf[i];
-        r.w = base_rank + rank[r.w & (kBrickKeys - 1)];
-        out[i] = r;
+        const uint4 x = buf[i];
+        const uint32_t leaf = x.w & (kBrickKeys - 1), lo = off[leaf], c = cnt[leaf];
+        uint32_t before = 0;
+        for (uint32_t q = lo; q < lo + c; ++q) {
+            const uint4 y = buf[q];
+            before += (rec_less(y, x) || (q < i && y.x == x.x && y.y == x.y && y.z == x.z)) ? 1u : 0u;
+        }
+        dst[lo + before] = make_uint4(x.x, x.y, x.z, base_rank + rank[leaf]);
+    }
+    if (!kInLds) {
+        __threadfence();
+        __syncthreads();
+        for (uint32_t i = t; i < n; i += kBlock) out[i] = src[i];
     }
 }
 
@@ -327,36 +332,28 @@ k_brick_wave(const uint4* __restrict__ stage, const uint32_t* __restrict__ brick
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_brick(const uint4* __restrict__ stage, const uint32_t* __restrict__ brick_cnt,
+k_brick(uint4* __restrict__ stage, const uint32_t* __restrict__ brick_cnt,
         const uint32_t* __restrict__ brick_off, const uint32_t* __restrict__ brick_rank,
-        uint32_t n_brick, uint4* __restrict__ frag, uint64_t* __restrict__ oct_key,
+        const uint32_t* __restrict__ list, const uint64_t* __restrict__ list_total,
+        uint4* __restrict__ frag, uint64_t* __restrict__ oct_key,
         uint32_t* __restrict__ oct_off, uint32_t* __restrict__ oct_cnt, uint64_t cap_occ)
 {
     __shared__ uint4 lbuf[kLdsRecs];
     __shared__ uint32_t cnt[kBrickKeys], off[kBrickKeys], cur[kBrickKeys], rank[kBrickKeys],
         tmp[kBrickKeys];
-    __shared__ uint32_t big[kBlock];
-    __shared__ uint32_t n_big;
-    // bricks above the wave kernel's size, found 256 at a time
-    for (uint32_t b0 = blockIdx.x * kBlock; b0 < n_brick; b0 += gridDim.x * kBlock) {
-        if (threadIdx.x == 0) n_big = 0;
-        __syncthreads();
-        const uint32_t bt = b0 + threadIdx.x;
-        if (bt < n_brick && brick_cnt[bt] > (uint32_t)kWaveRecs) big[atomicAdd(&n_big, 1u)] = bt;
-        __syncthreads();
-        const uint32_t nb = n_big;
-        for (uint32_t k = 0; k < nb; ++k) {
-            const uint32_t b = big[k];
-            const uint32_t n = brick_cnt[b];
-            const uint32_t o = brick_off[b];
-            if (n <= (uint32_t)kLdsRecs)
-                brick_sort<true>(lbuf, stage + o, n, cnt, off, cur, rank, tmp, b, o, brick_rank[b],
-                                 frag + o, oct_key, oct_off, oct_cnt, cap_occ);
-            else
-                brick_sort<false>(frag + o, stage + o, n, cnt, off, cur, rank, tmp, b, o,
-                                  brick_rank[b], frag + o, oct_key, oct_off, oct_cnt, cap_occ);
-            __syncthreads();
-        }
+    // bricks above the wave kernel's size, taken from the occupied-brick list
+    const uint32_t nl = (uint32_t)(*list_total >> 32);
+    for (uint32_t li = blockIdx.x; li < nl; li += gridDim.x) {
+        const uint32_t b = list[li];
+        const uint32_t n = brick_cnt[b];
+        if (n <= (uint32_t)kWaveRecs) continue;
+        const uint32_t o = brick_off[b];
+        if (n <= (uint32_t)kLdsRecs)
+            brick_sort<true>(lbuf, stage + o, n, cnt, off, cur, rank, tmp, b, o, brick_rank[b],
+                             frag + o, oct_key, oct_off, oct_cnt, cap_occ);
+        else
+            brick_sort<false>(frag + o, stage + o, n, cnt, off, cur, rank, tmp, b, o,
+                              brick_rank[b], frag + o, oct_key, oct_off, oct_cnt, cap_occ);
         __syncthreads();
     }
 }
@@ -476,9 +473,8 @@ hipError_t compact_launch(const Device& dev, const fhv_lists* L, const fhv_captu
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
-    const uint64_t bmax = (uint64_t)dev.cus * 8;
-    const uint64_t gbig = (n_brick + kBlock - 1) / kBlock;
-    const unsigned gbrick = (unsigned)(gbig < bmax ? gbig : bmax);
+    const uint64_t bmax = (uint64_t)dev.cus * 4;
+    const unsigned gbrick = (unsigned)(n_brick < bmax ? n_brick : bmax);
     ProfScope ps(dev, "compact.brick", s);
     const uint64_t wmax = (uint64_t)dev.cus * 64;
     const unsigned gwave = (unsigned)(n_brick < wmax ? n_brick : wmax);
@@ -487,7 +483,7 @@ hipError_t compact_launch(const Device& dev, const fhv_lists* L, const fhv_captu
         out->oct_key, out->oct_off, out->oct_cnt, out->cap_occ);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     k_brick<<<dim3(gbrick ? gbrick : 1), dim3(kBlock), 0, s>>>(
-        w.stage, w.brick_cnt, w.brick_off, w.brick_rank, (uint32_t)n_brick, (uint4*)out->frag,
+        w.stage, w.brick_cnt, w.brick_off, w.brick_rank, w.list, w.list_total, (uint4*)out->frag,
         out->oct_key, out->oct_off, out->oct_cnt, out->cap_occ);
     return hipGetLastError();
 }

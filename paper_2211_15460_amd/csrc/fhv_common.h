@@ -172,12 +172,13 @@ hipError_t splat_launch(const Device& dev, const fhv_pofa* a, const fhv_capture_
 namespace nn {
 uint64_t param_count(uint32_t levels);
 size_t fill_ws_bytes(uint32_t levels, uint32_t N, uint32_t H, uint32_t W, bool training);
-hipError_t fill(uint32_t levels, const float* th, const uint32_t* rgba, const float* depth, const uint8_t* cov,
-                uint32_t N, uint32_t H, uint32_t W, uint32_t* out, float* residual, void* ws, hipStream_t s);
-hipError_t train_step(uint32_t levels, float* th, float* m, float* v, uint32_t step, float lr,
-                      const uint32_t* rgba, const float* depth, const uint8_t* cov, const uint32_t* tgt,
-                      uint32_t N, uint32_t H, uint32_t W, float* loss, float* grad_out, void* ws,
-                      hipStream_t s);
+hipError_t fill(const Device& dev, uint32_t levels, const float* th, const uint32_t* rgba, const float* depth,
+                const uint8_t* cov, uint32_t N, uint32_t H, uint32_t W, uint32_t* out, float* residual,
+                void* ws, hipStream_t s);
+hipError_t train_step(const Device& dev, uint32_t levels, float* th, float* m, float* v, uint32_t step,
+                      float lr, const uint32_t* rgba, const float* depth, const uint8_t* cov,
+                      const uint32_t* tgt, uint32_t N, uint32_t H, uint32_t W, float* loss, float* grad_out,
+                      void* ws, hipStream_t s);
 }  // namespace nn
 
 // Workspace carving with 256-byte alignment.

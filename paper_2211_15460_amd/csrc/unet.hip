@@ -278,14 +278,22 @@ k_colsum(const uint16_t* __restrict__ m, uint32_t cs, uint32_t P, uint32_t C, ui
     }
 }
 
+// dst[i] = sum over k < splits (in order within each thread's stride, then
+// a fixed tree) of part[k * n + i]; one workgroup per output value.
 __global__ void __launch_bounds__(kBlock)
 k_sum_splits(const float* __restrict__ part, uint32_t splits, uint32_t n, float* __restrict__ dst)
 {
-    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
+    __shared__ float red[kBlock];
+    const uint32_t i = blockIdx.x;
     float s = 0.0f;
-    for (uint32_t k = 0; k < splits; ++k) s += part[(size_t)k * n + i];
-    dst[i] = s;
+    for (uint32_t k = threadIdx.x; k < splits; k += kBlock) s += part[(size_t)k * n + i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dst[i] = red[0];
 }
 
 // Splat images -> bf16 [P][8]: R, G, B, A / 255, depth - 1 (covered), cov, 0, 0.
@@ -499,6 +507,12 @@ namespace nn {
 
 namespace {
 
+thread_local const Device* t_dev = nullptr;   // set at the entry points, for ProfScope
+
+Device no_dev{0, 0, nullptr};
+
+inline const Device& cur_dev() { return t_dev ? *t_dev : no_dev; }
+
 struct Layer {
     int kind;   // 0 = 3x3 conv, 1 = transposed conv, 2 = head
     uint32_t cin, cout, cpad;
@@ -562,7 +576,7 @@ struct Bufs {
     size_t part_elems, hpart_elems;
 };
 
-constexpr uint32_t kWgradTarget = 4096;   // wave tiles per weight-gradient launch
+constexpr uint32_t kWgradTarget = 1024;   // wave tiles per weight-gradient launch
 
 void wgrad_dims(uint32_t P, uint32_t Cin, uint32_t Cout, uint32_t T, uint32_t* splits, uint32_t* per)
 {
@@ -640,6 +654,7 @@ hipError_t conv(const uint16_t* in, uint32_t in_cs, const uint16_t* wt, const fl
     a.mode = (uint32_t)mode;
     a.relu = relu ? 1u : 0u;
     const uint32_t xt = (W + 127) / 128;
+    ProfScope ps(cur_dev(), "fill.conv", s);
     k_conv<<<dim3(N * H * xt, (Cout + 31) / 32, mode == MODE_UP2 ? 4 : 1), dim3(kBlock), 0, s>>>(a);
     return hipGetLastError();
 }
@@ -666,6 +681,7 @@ hipError_t wgrad(const uint16_t* gr, uint32_t g_cs, const uint16_t* x, uint32_t 
     wgrad_dims(P, Cin, Cout, a.T, &splits, &a.per_split);
     a.chunks = (P + 31) / 32;
     if ((size_t)splits * Cout * a.T * Cin > part_elems) return hipErrorInvalidValue;
+    ProfScope ps(cur_dev(), "fill.wgrad", s);
     k_wgrad<<<dim3((Cout / 32) * ((Cin + 31) / 32), a.T, splits), dim3(kWave), 0, s>>>(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -678,11 +694,11 @@ hipError_t bgrad(const uint16_t* m, uint32_t cs, uint32_t P, uint32_t C, float* 
                  hipStream_t s)
 {
     uint32_t splits = (P + 255) / 256;
-    splits = splits > 1024 ? 1024 : splits;
+    splits = splits > 512 ? 512 : splits;
     const uint32_t per = (P + splits - 1) / splits;
     splits = (P + per - 1) / per;
     k_colsum<<<dim3(splits), dim3(kBlock), 0, s>>>(m, cs, P, C, per, part);
-    k_sum_splits<<<blocks(C), dim3(kBlock), 0, s>>>(part, splits, C, dst);
+    k_sum_splits<<<dim3(C), dim3(kBlock), 0, s>>>(part, splits, C, dst);
     return hipGetLastError();
 }
 
@@ -824,6 +840,12 @@ hipError_t backward(const Net& net, const float* th, const Bufs& b, uint32_t N, 
 
 uint64_t param_count(uint32_t levels) { return Net(levels).n_params; }
 
+// Scope that makes the device's profiler visible to the layer helpers.
+struct DevScope {
+    explicit DevScope(const Device& d) { t_dev = &d; }
+    ~DevScope() { t_dev = nullptr; }
+};
+
 size_t fill_ws_bytes(uint32_t levels, uint32_t N, uint32_t H, uint32_t W, bool training)
 {
     Net net(levels);
@@ -831,28 +853,35 @@ size_t fill_ws_bytes(uint32_t levels, uint32_t N, uint32_t H, uint32_t W, bool t
     return carve(net, N, H, W, training, nullptr, &b);
 }
 
-hipError_t fill(uint32_t levels, const float* th, const uint32_t* rgba, const float* depth, const uint8_t* cov,
-                uint32_t N, uint32_t H, uint32_t W, uint32_t* out, float* residual, void* ws, hipStream_t s)
+hipError_t fill(const Device& dev, uint32_t levels, const float* th, const uint32_t* rgba, const float* depth,
+                const uint8_t* cov, uint32_t N, uint32_t H, uint32_t W, uint32_t* out, float* residual,
+                void* ws, hipStream_t s)
 {
+    DevScope dscope(dev);
     Net net(levels);
     Bufs b;
     carve(net, N, H, W, false, (char*)ws, &b);
     const uint32_t P = N * H * W;
-    k_pack_input<<<blocks(P), dim3(kBlock), 0, s>>>(rgba, depth, cov, P, b.x0);
-    FHV_TRY(hipGetLastError());
-    FHV_TRY(prep_weights(net, th, false, b, s));
+    {
+        ProfScope ps(dev, "fill.misc", s);
+        k_pack_input<<<blocks(P), dim3(kBlock), 0, s>>>(rgba, depth, cov, P, b.x0);
+        FHV_TRY(hipGetLastError());
+        FHV_TRY(prep_weights(net, th, false, b, s));
+    }
     const uint16_t* hin = nullptr;
     FHV_TRY(forward(net, th, b, N, H, W, s, &hin));
     const Layer& hd = net.layers[net.head()];
+    ProfScope ps(dev, "fill.misc", s);
     k_head_fill<<<blocks(P), dim3(kBlock), 0, s>>>(hin, th + hd.off_w, th + hd.off_b, rgba, P, out, residual);
     return hipGetLastError();
 }
 
-hipError_t train_step(uint32_t levels, float* th, float* m, float* v, uint32_t step, float lr,
-                      const uint32_t* rgba, const float* depth, const uint8_t* cov, const uint32_t* tgt,
-                      uint32_t N, uint32_t H, uint32_t W, float* loss, float* grad_out, void* ws,
-                      hipStream_t s)
+hipError_t train_step(const Device& dev, uint32_t levels, float* th, float* m, float* v, uint32_t step,
+                      float lr, const uint32_t* rgba, const float* depth, const uint8_t* cov,
+                      const uint32_t* tgt, uint32_t N, uint32_t H, uint32_t W, float* loss, float* grad_out,
+                      void* ws, hipStream_t s)
 {
+    DevScope dscope(dev);
     Net net(levels);
     Bufs b;
     carve(net, N, H, W, true, (char*)ws, &b);
@@ -869,7 +898,7 @@ hipError_t train_step(uint32_t levels, float* th, float* m, float* v, uint32_t s
                                                    b.hpart);
     FHV_TRY(hipGetLastError());
     // head weight and bias gradients, and the loss
-    k_sum_splits<<<blocks(kHeadPart), dim3(kBlock), 0, s>>>(b.hpart, hb, kHeadPart, b.part);
+    k_sum_splits<<<dim3(kHeadPart), dim3(kBlock), 0, s>>>(b.hpart, hb, kHeadPart, b.part);
     FHV_TRY(hipGetLastError());
     FHV_TRY(hipMemcpyAsync(b.grad + hd.off_w, b.part, sizeof(float) * 3 * kBase, hipMemcpyDeviceToDevice, s));
     FHV_TRY(hipMemcpyAsync(b.grad + hd.off_b, b.part + 3 * kBase, sizeof(float) * 3, hipMemcpyDeviceToDevice, s));
