@@ -105,7 +105,7 @@ typedef struct {
 } fhv_mesh;
 
 /* What to capture. PPFL: width, height in [1, 16384]; POFL: levels in
- * [1, 10] (octree depth L). Unused fields are ignored. */
+ * [1, 11] (octree depth L). Unused fields are ignored. */
 typedef struct {
     uint32_t mode;
     uint32_t width;
@@ -118,8 +118,9 @@ typedef struct {
  *       = index of the last fragment inserted for that pixel/octant, or
  *       0xFFFFFFFF. Reset by fhv_capture.
  * pool: uint32 [capacity][4] records, 16-byte aligned; capacity < 2^32 - 1.
- * keys: uint32 [capacity], the pixel or octant key of every pool slot (a
- *       sidecar that lets fhv_compact read the pool linearly).
+ * keys: the pixel or octant key of every pool slot (a sidecar that lets
+ *       fhv_compact read the pool linearly): uint32 [capacity] when n_head
+ *       <= 2^32, else uint64 [capacity].
  * counter: one uint64; after the stream has run, the number of fragments
  *       produced. Reset by fhv_capture. If *counter > capacity the capture
  *       overflowed: the pool holds the first `capacity` fragments that
@@ -131,7 +132,7 @@ typedef struct {
     uint64_t n_head;
     uint32_t* pool;
     uint64_t capacity;
-    uint32_t* keys;
+    void* keys;
     uint64_t* counter;
 } fhv_lists;
 

@@ -263,6 +263,7 @@ typedef struct {
     uint32_t* pool;  /* uint32[4 * cap] */
     uint64_t cap;
     uint64_t counter;
+    uint64_t key_lo, key_hi; /* POFL: only keys in [key_lo, key_hi) are kept */
     /* current triangle */
     uint32_t aux, nrm;
     uint32_t width;  /* PPFL */
@@ -302,7 +303,7 @@ uint64_t orc_capture_ppfl(const float* pos, const uint32_t* rgba, const uint32_t
                           const uint8_t* obj, uint32_t n_tri, uint32_t width, uint32_t height,
                           uint32_t* head, uint32_t* pool, uint64_t cap)
 {
-    lists_t L = {head, pool, cap, 0, 0, 0, width, 0, 0};
+    lists_t L = {head, pool, cap, 0, 0, UINT64_MAX, 0, 0, width, 0, 0};
     for (uint32_t t = 0; t < n_tri; ++t) {
         tri_fx f;
         int64_t q[3][3];
@@ -341,8 +342,9 @@ static void emit_pofl(void* user, int64_t i, int64_t j, const int64_t* a)
     lists_t* L = (lists_t*)user;
     uint32_t px = (uint32_t)a[0], py = (uint32_t)a[1], pz = (uint32_t)a[2];
     uint64_t key = orc_morton3(px >> 8, py >> 8, pz >> 8, L->levels);
+    if (key < L->key_lo || key >= L->key_hi) return;
     uint32_t w0 = (px & 0xFF) | ((py & 0xFF) << 8) | ((pz & 0xFF) << 16) | (L->aux << 24);
-    insert(L, key, w0, rgba_join(a + 3), L->nrm);
+    insert(L, key - L->key_lo, w0, rgba_join(a + 3), L->nrm);
 }
 
 /* Per-octant capture (FHV_POFL) with tangent-space rasterization. Vertices
@@ -352,11 +354,27 @@ static void emit_pofl(void* user, int64_t i, int64_t j, const int64_t* a)
  * units and is anchored at the projection of the grid origin. Each sample's
  * grid position is interpolated from the vertices; its leaf is the top L bits
  * per axis. head holds 8^L entries set to NIL by the caller. */
+uint64_t orc_capture_pofl_range(const float* pos, const uint32_t* rgba, const uint32_t* tri,
+                                const uint8_t* obj, uint32_t n_tri, uint32_t levels, uint64_t key_lo,
+                                uint64_t key_hi, uint32_t* head, uint32_t* pool, uint64_t cap);
+
 uint64_t orc_capture_pofl(const float* pos, const uint32_t* rgba, const uint32_t* tri,
                           const uint8_t* obj, uint32_t n_tri, uint32_t levels,
                           uint32_t* head, uint32_t* pool, uint64_t cap)
 {
-    lists_t L = {head, pool, cap, 0, 0, 0, 0, levels, 1};
+    return orc_capture_pofl_range(pos, rgba, tri, obj, n_tri, levels, 0, (uint64_t)1 << (3 * levels),
+                                  head, pool, cap);
+}
+
+/* Per-octant capture keeping only the fragments whose key lies in
+ * [key_lo, key_hi): the lists of exactly those keys, with head[key - key_lo]
+ * (the octree of a large scene taken one key range at a time). The counter
+ * counts the kept fragments only. */
+uint64_t orc_capture_pofl_range(const float* pos, const uint32_t* rgba, const uint32_t* tri,
+                                const uint8_t* obj, uint32_t n_tri, uint32_t levels, uint64_t key_lo,
+                                uint64_t key_hi, uint32_t* head, uint32_t* pool, uint64_t cap)
+{
+    lists_t L = {head, pool, cap, 0, key_lo, key_hi, 0, 0, 0, levels, 1};
     const int64_t G = (int64_t)1 << (levels + 8);
     const double Gd = (double)G;
     for (uint32_t t = 0; t < n_tri; ++t) {

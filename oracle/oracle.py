@@ -53,6 +53,9 @@ def lib():
         L.orc_capture_pofl.argtypes = [f32p, u32p, u32p, C.c_void_p, C.c_uint32, C.c_uint32,
                                        u32p, u32p, C.c_uint64]
         L.orc_capture_pofl.restype = C.c_uint64
+        L.orc_capture_pofl_range.argtypes = [f32p, u32p, u32p, C.c_void_p, C.c_uint32, C.c_uint32,
+                                             C.c_uint64, C.c_uint64, u32p, u32p, C.c_uint64]
+        L.orc_capture_pofl_range.restype = C.c_uint64
         L.orc_compact.argtypes = [u32p, C.c_uint64, u32p, C.c_uint64, C.c_uint64, u64p, u32p,
                                   u32p, C.c_uint64, u32p]
         L.orc_compact.restype = C.c_uint64
@@ -127,6 +130,17 @@ def capture_pofl(mesh, levels: int, cap: int):
     pool = np.zeros(4 * max(cap, 1), np.uint32)
     cnt = lib().orc_capture_pofl(pos, rgba, tri, _obj_ptr(obj), mesh.tri.shape[0], levels,
                                  head, pool, cap)
+    return head, pool.reshape(-1, 4)[:cap], int(cnt)
+
+
+def capture_pofl_range(mesh, levels: int, key_lo: int, key_hi: int, cap: int):
+    """Per-octant lists of only the keys in [key_lo, key_hi) (head index key
+    - key_lo); the counter counts those fragments only."""
+    pos, rgba, tri, obj = _mesh_arrays(mesh)
+    head = np.full(key_hi - key_lo, NIL, np.uint32)
+    pool = np.zeros(4 * max(cap, 1), np.uint32)
+    cnt = lib().orc_capture_pofl_range(pos, rgba, tri, _obj_ptr(obj), mesh.tri.shape[0], levels,
+                                       key_lo, key_hi, head, pool, cap)
     return head, pool.reshape(-1, 4)[:cap], int(cnt)
 
 
@@ -214,4 +228,4 @@ def psnr_rgb(a: np.ndarray, b: np.ndarray) -> float:
 
 
 __all__ = ["NIL", "build", "lib", "oct_encode", "oct_decode", "tangent_frame", "morton3",
-           "capture_ppfl", "capture_pofl", "compact", "splat", "direct_raster", "psnr_rgb"]
+           "capture_ppfl", "capture_pofl", "capture_pofl_range", "compact", "splat", "direct_raster", "psnr_rgb"]

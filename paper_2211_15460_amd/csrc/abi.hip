@@ -63,7 +63,7 @@ bool desc_ok(const fhv_capture_desc* d)
 {
     if (!d) return false;
     if (d->mode == FHV_PPFL) return d->width >= 1 && d->width <= 16384 && d->height >= 1 && d->height <= 16384;
-    if (d->mode == FHV_POFL) return d->levels >= 1 && d->levels <= 10;
+    if (d->mode == FHV_POFL) return d->levels >= 1 && d->levels <= 11;
     return false;
 }
 

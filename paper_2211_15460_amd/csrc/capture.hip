@@ -206,7 +206,8 @@ k_setup(const float* __restrict__ pos, const uint32_t* __restrict__ rgba,
             r.aux = obj ? (uint32_t)obj[t] : 0u;
             r.A = A;
             r.rA = 1.0 / (double)A;
-            r.pad0 = r.pad1 = 0;
+            r.scene = 0;
+            r.pad1 = 0;
             r.pad2 = 0;
             if (i1 >= i0 && j1 >= j0) {
                 const uint32_t tx = (uint32_t)(i1 - i0) / kTile + 1;
@@ -323,11 +324,12 @@ struct ItemWalk {
 // covered samples of the whole range, reserves that many pool slots with a
 // single atomic add on the counter, and then walks the range again to emit
 // the fragments into consecutive slots.
-template <int kMode>
+template <int kMode, class KeyT>
 __global__ void __launch_bounds__(kBlock)
 k_raster(const TriRec* __restrict__ recs, const uint64_t* __restrict__ incl, uint32_t n_tri,
-         uint32_t width, uint32_t gmax, uint32_t* __restrict__ head, uint4* __restrict__ pool,
-         uint32_t* __restrict__ keys, uint64_t cap, unsigned long long* __restrict__ counter)
+         uint32_t width, uint32_t gmax, uint32_t levels, uint32_t* __restrict__ head,
+         uint4* __restrict__ pool, KeyT* __restrict__ keys, uint64_t cap,
+         unsigned long long* __restrict__ counter)
 {
     const uint64_t total = incl[n_tri - 1];
     const int lane = __lane_id();
@@ -365,7 +367,8 @@ k_raster(const TriRec* __restrict__ recs, const uint64_t* __restrict__ incl, uin
     it.start(n_tri, w0);
     for (uint64_t w = w0; w < w1; w += kBatch) {
         bool has[kBatch];
-        uint32_t key[kBatch], w0r[kBatch], w1r[kBatch], nrm[kBatch];
+        uint64_t key[kBatch];
+        uint32_t w0r[kBatch], w1r[kBatch], nrm[kBatch];
         uint64_t idx[kBatch];
 #pragma unroll
         for (int g = 0; g < kBatch; ++g) {
@@ -384,7 +387,7 @@ k_raster(const TriRec* __restrict__ recs, const uint64_t* __restrict__ incl, uin
             nrm[g] = r.nrm;
             w1r[g] = interp_rgba(sm.e12, sm.e20, sm.e01, r.rgba, r.A, r.rA);
             if (kMode == FHV_PPFL) {
-                key[g] = (uint32_t)sm.j * width + (uint32_t)sm.i;
+                key[g] = (uint64_t)sm.j * width + (uint32_t)sm.i;
                 const uint32_t dz = interp(sm.e12, sm.e20, sm.e01, r.a[0][0], r.a[1][0], r.a[2][0], r.A, r.rA);
                 w0r[g] = dz | (r.aux << 24);
             } else {
@@ -396,7 +399,8 @@ k_raster(const TriRec* __restrict__ recs, const uint64_t* __restrict__ incl, uin
                 gx = gx > gmax ? gmax : gx;
                 gy = gy > gmax ? gmax : gy;
                 gz = gz > gmax ? gmax : gz;
-                key[g] = (spread3(gx >> 8) << 2) | (spread3(gy >> 8) << 1) | spread3(gz >> 8);
+                key[g] = ((uint64_t)r.scene << (3 * levels)) |
+                         (spread3(gx >> 8) << 2) | (spread3(gy >> 8) << 1) | spread3(gz >> 8);
                 w0r[g] = (gx & 0xFFu) | ((gy & 0xFFu) << 8) | ((gz & 0xFFu) << 16) | (r.aux << 24);
             }
         }
@@ -408,7 +412,7 @@ k_raster(const TriRec* __restrict__ recs, const uint64_t* __restrict__ incl, uin
         for (int g = 0; g < kBatch; ++g) {
             if (!has[g]) continue;
             pool[idx[g]] = make_uint4(w0r[g], w1r[g], nrm[g], prev[g]);
-            keys[idx[g]] = key[g];
+            keys[idx[g]] = (KeyT)key[g];
         }
     }
 }
@@ -457,14 +461,19 @@ hipError_t capture_launch(const Device& dev, const fhv_mesh* m, const fhv_captur
     const unsigned grid = (unsigned)(dev.cus * 16);
     const uint32_t gmax = d->mode == FHV_POFL ? (1u << (d->levels + 8)) - 1u : 0u;
     ProfScope ps(dev, "capture.raster", s);
+    const bool wide = L->n_head > (1ull << 32);
     if (d->mode == FHV_PPFL)
-        k_raster<FHV_PPFL><<<dim3(grid), dim3(kBlock), 0, s>>>(
-            recs, incl, m->n_tri, d->width, gmax, L->head, (uint4*)L->pool, L->keys, L->capacity,
-            (unsigned long long*)L->counter);
+        k_raster<FHV_PPFL, uint32_t><<<dim3(grid), dim3(kBlock), 0, s>>>(
+            recs, incl, m->n_tri, d->width, gmax, d->levels, L->head, (uint4*)L->pool,
+            (uint32_t*)L->keys, L->capacity, (unsigned long long*)L->counter);
+    else if (!wide)
+        k_raster<FHV_POFL, uint32_t><<<dim3(grid), dim3(kBlock), 0, s>>>(
+            recs, incl, m->n_tri, d->width, gmax, d->levels, L->head, (uint4*)L->pool,
+            (uint32_t*)L->keys, L->capacity, (unsigned long long*)L->counter);
     else
-        k_raster<FHV_POFL><<<dim3(grid), dim3(kBlock), 0, s>>>(
-            recs, incl, m->n_tri, d->width, gmax, L->head, (uint4*)L->pool, L->keys, L->capacity,
-            (unsigned long long*)L->counter);
+        k_raster<FHV_POFL, uint64_t><<<dim3(grid), dim3(kBlock), 0, s>>>(
+            recs, incl, m->n_tri, d->width, gmax, d->levels, L->head, (uint4*)L->pool,
+            (uint64_t*)L->keys, L->capacity, (unsigned long long*)L->counter);
     return hipGetLastError();
 }
 

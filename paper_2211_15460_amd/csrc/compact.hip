@@ -14,7 +14,8 @@
 //   scan       exclusive sums of both per-brick counts: brick fragment
 //              offsets and brick rank bases; totals = n_frag, n_occ
 //   k_scatter  every pool record to its brick's range of a staging array
-//              (slot within the brick from an atomic cursor), key in w3
+//              (slot within the brick from an atomic cursor), its key's low
+//              9 bits (the key inside the brick) in w3
 //   k_brick_wave / k_brick
 //              per brick: counting sort of its records by key inside LDS,
 //              a per-key insertion sort into canonical order, then the
@@ -36,8 +37,9 @@ __device__ __forceinline__ uint64_t frag_count(const uint64_t* counter, uint64_t
     return c < cap ? c : cap;
 }
 
+template <class KeyT>
 __global__ void __launch_bounds__(kBlock)
-k_hist(const uint32_t* __restrict__ keys, const uint64_t* __restrict__ counter, uint64_t cap,
+k_hist(const KeyT* __restrict__ keys, const uint64_t* __restrict__ counter, uint64_t cap,
        uint32_t* __restrict__ brick_cnt, uint32_t* __restrict__ brick_occ,
        uint32_t* __restrict__ bitmap)
 {
@@ -49,15 +51,16 @@ k_hist(const uint32_t* __restrict__ keys, const uint64_t* __restrict__ counter, 
     const uint64_t Fw = (F + kWave - 1) & ~(uint64_t)(kWave - 1);
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < Fw; i += stride) {
         const bool act = i < F;
-        const uint32_t key = act ? keys[i] : 0u;
-        wave_count_add<false>(brick_cnt, key >> kBrickShift, act);
+        const uint64_t key = act ? (uint64_t)keys[i] : 0u;
+        wave_count_add<false>(brick_cnt, (uint32_t)(key >> kBrickShift), act);
         // key bitmap: lanes hitting the same 32-key word OR their bits
         // together; new bits count as newly occupied keys of the brick
-        const uint32_t word = key >> 5;
+        const uint64_t word = key >> 5;
         uint64_t todo = __ballot(act);
         while (todo) {
             const int leader = __ffsll((unsigned long long)todo) - 1;
-            const uint32_t lw = (uint32_t)__shfl((int)word, leader, kWave);
+            const uint64_t lw = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(word >> 32), leader, kWave) << 32) |
+                                (uint32_t)__shfl((int)(uint32_t)word, leader, kWave);
             const uint64_t m = __ballot(act && word == lw) & todo;
             const uint32_t bits = wave_or(((m >> lane) & 1ull) ? (1u << (key & 31)) : 0u);
             if (lane == leader) {
@@ -70,8 +73,9 @@ k_hist(const uint32_t* __restrict__ keys, const uint64_t* __restrict__ counter, 
     }
 }
 
+template <class KeyT>
 __global__ void __launch_bounds__(kBlock)
-k_scatter(const uint4* __restrict__ pool, const uint32_t* __restrict__ keys,
+k_scatter(const uint4* __restrict__ pool, const KeyT* __restrict__ keys,
           const uint64_t* __restrict__ counter, uint64_t cap, const uint32_t* __restrict__ brick_off,
           uint32_t* __restrict__ brick_cur, uint4* __restrict__ stage)
 {
@@ -80,12 +84,12 @@ k_scatter(const uint4* __restrict__ pool, const uint32_t* __restrict__ keys,
     const uint64_t Fw = (F + kWave - 1) & ~(uint64_t)(kWave - 1);
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < Fw; i += stride) {
         const bool act = i < F;
-        const uint32_t key = act ? keys[i] : 0u;
-        const uint32_t b = key >> kBrickShift;
+        const uint64_t key = act ? (uint64_t)keys[i] : 0u;
+        const uint32_t b = (uint32_t)(key >> kBrickShift);
         const uint32_t slot = wave_count_add<true>(brick_cur, b, act);
         if (!act) continue;
         uint4 r = pool[i];
-        r.w = key;
+        r.w = (uint32_t)key & (kBrickKeys - 1);   // key inside the brick
         stage[brick_off[b] + slot] = r;
     }
 }
@@ -452,8 +456,12 @@ hipError_t compact_launch(const Device& dev, const fhv_lists* L, const fhv_captu
         if (e == hipSuccess) e = fill_u64(w.list_total, 1, 0, s);
         if (e != hipSuccess) return e;
         k_totals<<<dim3(1), dim3(64), 0, s>>>(L->counter, L->capacity, out->n_frag);
-        k_hist<<<dim3(grid), dim3(kBlock), 0, s>>>(L->keys, L->counter, L->capacity, w.brick_cnt,
-                                                   w.brick_occ, w.bitmap);
+        if (L->n_head > (1ull << 32))
+            k_hist<uint64_t><<<dim3(grid), dim3(kBlock), 0, s>>>((const uint64_t*)L->keys, L->counter,
+                                                             L->capacity, w.brick_cnt, w.brick_occ, w.bitmap);
+        else
+            k_hist<uint32_t><<<dim3(grid), dim3(kBlock), 0, s>>>((const uint32_t*)L->keys, L->counter,
+                                                             L->capacity, w.brick_cnt, w.brick_occ, w.bitmap);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
@@ -468,8 +476,12 @@ hipError_t compact_launch(const Device& dev, const fhv_lists* L, const fhv_captu
     if (e != hipSuccess) return e;
     {
         ProfScope ps(dev, "compact.scatter", s);
-        k_scatter<<<dim3(grid), dim3(kBlock), 0, s>>>((const uint4*)L->pool, L->keys, L->counter,
-                                                      L->capacity, w.brick_off, w.brick_cur, w.stage);
+        if (L->n_head > (1ull << 32))
+            k_scatter<uint64_t><<<dim3(grid), dim3(kBlock), 0, s>>>((const uint4*)L->pool,
+                (const uint64_t*)L->keys, L->counter, L->capacity, w.brick_off, w.brick_cur, w.stage);
+        else
+            k_scatter<uint32_t><<<dim3(grid), dim3(kBlock), 0, s>>>((const uint4*)L->pool,
+                (const uint32_t*)L->keys, L->counter, L->capacity, w.brick_off, w.brick_cur, w.stage);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;

@@ -26,7 +26,7 @@ struct alignas(16) TriRec {
     uint32_t tiles_x;        // tiles per bbox row
     uint32_t nrm;            // packed normal
     uint32_t aux;            // object byte
-    uint32_t pad0;
+    uint32_t scene;          // scene of a batch (key space offset scene << 3L)
     uint32_t rgba[3];
     uint32_t pad1;
     int32_t a[3][3];         // PPFL: a[k][0] = depth24; POFL: grid xyz
@@ -95,25 +95,28 @@ __device__ __forceinline__ uint32_t wave_count_add(uint32_t* ctr, uint32_t b, bo
     return slot;
 }
 
-// Spread the low 10 bits of v to every third bit (bit b -> bit 3b).
-__device__ __forceinline__ uint32_t spread3(uint32_t v)
+// Spread the low 21 bits of v to every third bit (bit b -> bit 3b).
+__device__ __forceinline__ uint64_t spread3(uint32_t v32)
 {
-    v &= 0x3FFu;
-    v = (v | (v << 16)) & 0x030000FFu;
-    v = (v | (v << 8)) & 0x0300F00Fu;
-    v = (v | (v << 4)) & 0x030C30C3u;
-    v = (v | (v << 2)) & 0x09249249u;
+    uint64_t v = v32 & 0x1FFFFFull;
+    v = (v | (v << 32)) & 0x1F00000000FFFFull;
+    v = (v | (v << 16)) & 0x1F0000FF0000FFull;
+    v = (v | (v << 8)) & 0x100F00F00F00F00Full;
+    v = (v | (v << 4)) & 0x10C30C30C30C30C3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
     return v;
 }
 
-__device__ __forceinline__ uint32_t compact3(uint32_t v)
+// Inverse of spread3: every third bit of v (bit 3b -> bit b).
+__device__ __forceinline__ uint32_t compact3(uint64_t v)
 {
-    v &= 0x09249249u;
-    v = (v | (v >> 2)) & 0x030C30C3u;
-    v = (v | (v >> 4)) & 0x0300F00Fu;
-    v = (v | (v >> 8)) & 0x030000FFu;
-    v = (v | (v >> 16)) & 0x3FFu;
-    return v;
+    v &= 0x1249249249249249ull;
+    v = (v | (v >> 2)) & 0x10C30C30C30C30C3ull;
+    v = (v | (v >> 4)) & 0x100F00F00F00F00Full;
+    v = (v | (v >> 8)) & 0x1F0000FF0000FFull;
+    v = (v | (v >> 16)) & 0x1F00000000FFFFull;
+    v = (v | (v >> 32)) & 0x1FFFFFull;
+    return (uint32_t)v;
 }
 
 }  // namespace fhv

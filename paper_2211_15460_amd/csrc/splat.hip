@@ -39,8 +39,7 @@ __device__ __forceinline__ void frag_pos(const uint4& r, uint64_t key, uint32_t 
         *y = (float)py + 0.5f;
         *z = (float)(r.x & 0xFFFFFFu);
     } else {
-        const uint32_t k32 = (uint32_t)key;
-        const uint32_t kx = compact3(k32 >> 2), ky = compact3(k32 >> 1), kz = compact3(k32);
+        const uint32_t kx = compact3(key >> 2), ky = compact3(key >> 1), kz = compact3(key);
         *x = (float)((kx << 8) | (r.x & 0xFFu)) + 0.5f;
         *y = (float)((ky << 8) | ((r.x >> 8) & 0xFFu)) + 0.5f;
         *z = (float)((kz << 8) | ((r.x >> 16) & 0xFFu)) + 0.5f;

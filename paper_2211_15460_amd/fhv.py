@@ -166,7 +166,7 @@ def n_head(d: Desc_) -> int:
 class Lists:
     head: torch.Tensor      # int32 [n_head] (uint32 bits)
     pool: torch.Tensor      # int32 [cap, 4]
-    keys: torch.Tensor      # int32 [cap]
+    keys: torch.Tensor      # int32 [cap], or int64 [cap] when n_head > 2^32
     counter: torch.Tensor   # int64 [1]
     capacity: int
 
@@ -176,10 +176,12 @@ class Lists:
                       self.keys.data_ptr(), self.counter.data_ptr())
 
 
-def alloc_lists(d: Desc_, capacity: int, device="cuda") -> Lists:
-    return Lists(torch.empty(n_head(d), dtype=torch.int32, device=device),
+def alloc_lists(d: Desc_, capacity: int, device="cuda", n_head_override: int | None = None) -> Lists:
+    nh = n_head(d) if n_head_override is None else n_head_override
+    kt = torch.int64 if nh > 2 ** 32 else torch.int32
+    return Lists(torch.empty(nh, dtype=torch.int32, device=device),
                  torch.empty((max(capacity, 1), 4), dtype=torch.int32, device=device),
-                 torch.empty(max(capacity, 1), dtype=torch.int32, device=device),
+                 torch.empty(max(capacity, 1), dtype=kt, device=device),
                  torch.zeros(1, dtype=torch.int64, device=device), capacity)
 
 

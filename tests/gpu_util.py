@@ -21,7 +21,9 @@ def run_capture(F, mesh, d, cap):
     F.capture(dm, d, lists)
     torch.cuda.synchronize()
     pool = u32(lists.pool)[:cap] if cap else np.zeros((0, 4), np.uint32)
-    keys = u32(lists.keys)[:cap] if cap else np.zeros(0, np.uint32)
+    kv = lists.keys.detach().cpu().numpy()
+    kv = kv.view(np.uint64) if kv.dtype == np.int64 else kv.view(np.uint32)
+    keys = kv[:cap] if cap else np.zeros(0, np.uint32)
     return u32(lists.head), pool, keys, int(lists.counter.item()), lists
 
 

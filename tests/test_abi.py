@@ -70,7 +70,7 @@ def test_workspace_queries(F):
     p = F.desc(F.FHV_POFL, levels=9)
     assert L.fhv_compact_workspace(C.byref(p), 1000) >= 8 ** 9 // 8
     for bad in (F.desc(7, 1, 1), F.desc(F.FHV_PPFL, 0, 5), F.desc(F.FHV_PPFL, 20000, 5),
-                F.desc(F.FHV_POFL, levels=0), F.desc(F.FHV_POFL, levels=11)):
+                F.desc(F.FHV_POFL, levels=0), F.desc(F.FHV_POFL, levels=12)):
         assert L.fhv_capture_workspace(C.byref(bad), 10) == 0
         assert L.fhv_compact_workspace(C.byref(bad), 10) == 0
 

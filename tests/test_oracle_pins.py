@@ -593,3 +593,17 @@ def test_psnr_closed_forms(orc):
     for d in (1, 3, 17):
         b = a + np.uint32(d * 0x010101)
         assert abs(orc.psnr_rgb(a, b) - 20 * math.log10(255 / d)) < 1e-9
+
+
+def test_range_capture_is_the_restriction_of_the_full_capture(orc):
+    """Capturing one key range gives exactly the lists of those keys."""
+    m = S.cube_scene(4000, seed=12)
+    L = 6
+    head, pool, F = orc.capture_pofl(m, L, 1 << 22)
+    k, recs = walk_lists(head, pool, F)
+    for lo, hi in [(0, 8 ** L), (8 ** L // 8, 3 * 8 ** L // 8), (1000, 1001)]:
+        h2, p2, F2 = orc.capture_pofl_range(m, L, lo, hi, 1 << 22)
+        k2, r2 = walk_lists(h2, p2, F2)
+        sel = (k >= lo) & (k < hi)
+        assert F2 == int(sel.sum())
+        assert np.array_equal(canonical(k2 + np.uint64(lo), r2), canonical(k[sel], recs[sel]))
