@@ -216,6 +216,85 @@ FHV_API fhv_status fhv_splat(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_cap
                      const fhv_view* views, uint32_t n_views, uint64_t* zbuf, uint32_t* rgba,
                      float* depth, uint8_t* cov, fhv_stream stream);
 
+/* Batches (not in the paper): many POFL scenes, each with several views,
+ * through capture, compaction and splat in one call. The scenes share one
+ * key space, key = scene * 8^L + Morton code of the leaf, so one launch per
+ * stage covers every scene and each scene's arrays are one contiguous run
+ * of the table and of frag, in scene order.
+ *
+ * Mesh: the scenes' triangle soups concatenated; tri holds indices into
+ * the concatenated pos/rgba; scene_tri: DEVICE uint32 [n_scenes + 1],
+ * non-decreasing, scene_tri[0] = 0, scene_tri[n_scenes] = n_tri: scene s
+ * owns triangles [scene_tri[s], scene_tri[s+1]). Every scene uses the scene
+ * cube [0,1)^3 and octree depth `levels` (1..11). */
+typedef struct {
+    const float* pos;
+    const uint32_t* rgba;
+    const uint32_t* tri;
+    const uint8_t* obj;
+    const uint32_t* scene_tri;
+    uint32_t n_vert;
+    uint32_t n_tri;
+    uint32_t n_scenes;
+    uint32_t levels;
+} fhv_batch_mesh;
+
+/* Views of a batch: m is a DEVICE float array [n_scenes][n_views][12],
+ * one fhv_view matrix per (scene, view), read when the splat runs (a graph
+ * replay sees the values present at replay time). Every view has the same
+ * width, height (1..16384) and splat_px (1..64); n_views in [1, 32]. */
+typedef struct {
+    const float* m;
+    uint32_t n_views;
+    uint32_t width;
+    uint32_t height;
+    uint32_t splat_px;
+} fhv_batch_views;
+
+/* Kernel launch choices, per context (used by every call on it):
+ * tile_w: raster tile width in samples, 8, 16 or 32 (tiles hold 64 samples:
+ *   8x8, 16x4 or 32x2); raster_wg, splat_wg: workgroups per compute unit of
+ *   the rasterizer and of the splat, 1..64. Results do not depend on them. */
+typedef struct {
+    uint32_t tile_w;
+    uint32_t raster_wg;
+    uint32_t splat_wg;
+} fhv_tuning;
+
+FHV_API fhv_status fhv_get_tuning(fhv_ctx* ctx, fhv_tuning* out);
+FHV_API fhv_status fhv_set_tuning(fhv_ctx* ctx, const fhv_tuning* t);
+
+#define FHV_BATCH_GRAPH 1u /* record the call's launches in a HIP graph once
+                              per distinct argument set, then replay it    */
+#define FHV_BATCH_TUNE 2u  /* before running, time candidate fhv_tuning
+                              values on these inputs (running the stages
+                              many times and waiting for the stream) and
+                              keep the fastest in the context             */
+
+FHV_API size_t fhv_batch_workspace(const fhv_batch_mesh* mesh, const fhv_batch_views* views,
+                                   uint64_t capacity);
+
+/* Capture, compaction and splat of a batch (Sec. 3.2, Sec. 3.3 per scene).
+ * lists: n_head = n_scenes * 8^L (the key space); head may be NULL, then no
+ *   linked lists are built (records keep w3 = 0xFFFFFFFF) and only the
+ *   pool, keys and counter are written; keys are uint64 when n_head > 2^32.
+ *   Overflow as for fhv_capture: after the stream has run, *counter >
+ *   capacity means the arrays and images are incomplete and the call must
+ *   be repeated with capacity >= *counter.
+ * out: arrays as fhv_compact makes them over the whole key space; scene s's
+ *   rows are those with oct_key / 8^L == s.
+ * zbuf, rgba, depth, cov: [n_scenes][n_views][height][width] as for
+ *   fhv_splat; a fragment only reaches its own scene's views.
+ * flags: FHV_BATCH_GRAPH, FHV_BATCH_TUNE. A graph is kept per context for
+ *   each distinct set of pointers, sizes and tuning (at most 8; the oldest
+ *   is dropped); it is recorded on a stream of the context and launched on
+ *   `stream`. Profiling (fhv_profile_begin) does not see graph launches.
+ * Errors: EINVAL (null pointers, sizes, flags), ERANGE, EWORKSPACE. */
+FHV_API fhv_status fhv_batch_run(fhv_ctx* ctx, const fhv_batch_mesh* mesh, const fhv_batch_views* views,
+                                 const fhv_lists* lists, const fhv_pofa* out, uint64_t* zbuf,
+                                 uint32_t* rgba, float* depth, uint8_t* cov, void* ws, size_t ws_bytes,
+                                 uint32_t flags, fhv_stream stream);
+
 /* Learned hole fill (not in the paper; fills what the splat leaves
  * uncovered, where Sec. 3.3 suggests adapting quad sizes or deforming
  * geometry). A U-Net of `levels` (1..4) levels with 32 * 2^l channels on

@@ -53,6 +53,13 @@ void prof_mark(Profiler* p, const char* name, hipStream_t s, bool start)
 struct fhv_ctx {
     fhv::Device dev;
     fhv::Profiler prof;
+    // recorded batch graphs, keyed by the bytes of every argument
+    struct Graph {
+        std::vector<unsigned char> key;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;
+    hipStream_t rec_stream = nullptr;   // stream the graphs are recorded on
 };
 
 namespace {
@@ -87,6 +94,153 @@ fhv_status set_device(fhv_ctx* ctx)
     return hip_status(hipSetDevice(ctx->dev.id));
 }
 
+// ---------------------------------------------------------------- batches
+
+bool batch_shape_ok(const fhv_batch_mesh* m, const fhv_batch_views* v)
+{
+    if (!m || !v) return false;
+    if (m->n_scenes < 1 || m->levels < 1 || m->levels > 11) return false;
+    // key space n_scenes * 8^L up to 2^40 (bricks and bitmap of the
+    // compaction grow with it)
+    if (((uint64_t)m->n_scenes << (3 * m->levels)) > (1ull << 40)) return false;
+    if (v->n_views < 1 || v->n_views > fhv::kMaxViews) return false;
+    if (v->width < 1 || v->width > 16384 || v->height < 1 || v->height > 16384) return false;
+    if (v->splat_px < 1 || v->splat_px > 64) return false;
+    return (uint64_t)m->n_scenes * v->n_views * v->width * v->height < (1ull << 40);
+}
+
+fhv_capture_desc batch_desc(const fhv_batch_mesh* m)
+{
+    fhv_capture_desc d;
+    d.mode = FHV_POFL;
+    d.width = 0;
+    d.height = 0;
+    d.levels = m->levels;
+    return d;
+}
+
+// Workspace: the capture's, then the compaction's (256-byte aligned).
+size_t batch_ws(const fhv_batch_mesh* m, uint64_t capacity, void* ws, void** cap_ws, void** cmp_ws)
+{
+    const fhv_capture_desc d = batch_desc(m);
+    const size_t a = (fhv::capture_ws_bytes(&d, m->n_tri) + 255) & ~(size_t)255;
+    const size_t b = fhv::compact_ws_bytes(&d, (uint64_t)m->n_scenes << (3 * m->levels), capacity);
+    if (cap_ws) *cap_ws = ws;
+    if (cmp_ws) *cmp_ws = ws ? (void*)((char*)ws + a) : nullptr;
+    return a + b;
+}
+
+struct BatchCall {
+    const fhv_batch_mesh* mesh;
+    const fhv_batch_views* views;
+    const fhv_lists* lists;
+    const fhv_pofa* out;
+    uint64_t* zbuf;
+    uint32_t* rgba;
+    float* depth;
+    uint8_t* cov;
+    void* ws;
+};
+
+hipError_t batch_capture(const fhv::Device& dev, const BatchCall& c, hipStream_t s)
+{
+    const fhv_capture_desc d = batch_desc(c.mesh);
+    const fhv_mesh m{c.mesh->pos, c.mesh->rgba, c.mesh->tri, c.mesh->obj, c.mesh->n_vert, c.mesh->n_tri};
+    const fhv::Scenes sc{c.mesh->scene_tri, c.mesh->n_scenes};
+    void* cw = nullptr;
+    batch_ws(c.mesh, c.lists->capacity, c.ws, &cw, nullptr);
+    return fhv::capture_launch(dev, &m, &d, c.lists, cw, s, &sc);
+}
+
+hipError_t batch_compact(const fhv::Device& dev, const BatchCall& c, hipStream_t s)
+{
+    const fhv_capture_desc d = batch_desc(c.mesh);
+    void* mw = nullptr;
+    batch_ws(c.mesh, c.lists->capacity, c.ws, nullptr, &mw);
+    return fhv::compact_launch(dev, c.lists, &d, c.out, mw, s);
+}
+
+hipError_t batch_splat(const fhv::Device& dev, const BatchCall& c, hipStream_t s)
+{
+    const fhv::BatchViews bv{c.views->m, c.mesh->n_scenes, c.views->n_views, c.views->width,
+                             c.views->height, c.views->splat_px};
+    return fhv::splat_batch_launch(dev, c.out, c.mesh->levels, bv, c.zbuf, c.rgba, c.depth, c.cov,
+                                   c.out->cap_frag, s);
+}
+
+hipError_t batch_enqueue(const fhv::Device& dev, const BatchCall& c, hipStream_t s)
+{
+    hipError_t e = batch_capture(dev, c, s);
+    if (e == hipSuccess) e = batch_compact(dev, c, s);
+    if (e == hipSuccess) e = batch_splat(dev, c, s);
+    return e;
+}
+
+// Milliseconds of the best of `reps` runs of fn on stream s.
+template <class Fn>
+hipError_t time_best(Fn fn, int reps, hipStream_t s, hipEvent_t a, hipEvent_t b, float* best)
+{
+    *best = 1e30f;
+    for (int r = 0; r < reps; ++r) {
+        hipError_t e = hipEventRecord(a, s);
+        if (e == hipSuccess) e = fn();
+        if (e == hipSuccess) e = hipEventRecord(b, s);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (e != hipSuccess) return e;
+        *best = ms < *best ? ms : *best;
+    }
+    return hipSuccess;
+}
+
+// Autotuner: on the call's own inputs, time the capture under every raster
+// tile shape and raster grid size, then the splat under every splat grid
+// size, and keep the fastest in the context. Blocks until done; the
+// results do not depend on these choices.
+hipError_t batch_tune(fhv_ctx* ctx, const BatchCall& c, hipStream_t s)
+{
+    fhv::Device d = ctx->dev;
+    d.prof = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) e = batch_enqueue(d, c, s);   // warm-up
+    const uint32_t tiles[3] = {8, 16, 32};
+    const uint32_t grids[4] = {4, 8, 16, 32};
+    fhv::Tuning best = d.tune;
+    float best_ms = 1e30f;
+    for (int ti = 0; ti < 3 && e == hipSuccess; ++ti)
+        for (int gi = 0; gi < 4 && e == hipSuccess; ++gi) {
+            d.tune.tile_w = tiles[ti];
+            d.tune.raster_wg = grids[gi];
+            float ms = 0.0f;
+            e = time_best([&] { return batch_capture(d, c, s); }, 2, s, a, b, &ms);
+            if (e == hipSuccess && ms < best_ms) {
+                best_ms = ms;
+                best.tile_w = tiles[ti];
+                best.raster_wg = grids[gi];
+            }
+        }
+    d.tune = best;
+    if (e == hipSuccess) e = batch_capture(d, c, s);
+    if (e == hipSuccess) e = batch_compact(d, c, s);
+    best_ms = 1e30f;
+    for (int gi = 0; gi < 4 && e == hipSuccess; ++gi) {
+        d.tune.splat_wg = grids[gi];
+        float ms = 0.0f;
+        e = time_best([&] { return batch_splat(d, c, s); }, 2, s, a, b, &ms);
+        if (e == hipSuccess && ms < best_ms) {
+            best_ms = ms;
+            best.splat_wg = grids[gi];
+        }
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (e == hipSuccess) ctx->dev.tune = best;
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -107,6 +261,7 @@ fhv_status fhv_create(fhv_ctx** out, int hip_device)
     c->dev.id = hip_device;
     c->dev.cus = cus > 0 ? cus : 256;
     c->dev.prof = nullptr;
+    c->dev.tune = fhv::Tuning{};
     *out = c;
     return FHV_OK;
 }
@@ -114,6 +269,9 @@ fhv_status fhv_create(fhv_ctx** out, int hip_device)
 fhv_status fhv_destroy(fhv_ctx* ctx)
 {
     if (!ctx) return FHV_OK;
+    (void)hipSetDevice(ctx->dev.id);
+    for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (ctx->rec_stream) (void)hipStreamDestroy(ctx->rec_stream);
     for (auto& r : ctx->prof.recs) {
         if (r.a) (void)hipEventDestroy(r.a);
         if (r.b) (void)hipEventDestroy(r.b);
@@ -300,6 +458,108 @@ fhv_status fhv_fill_train_step(fhv_ctx* ctx, uint32_t levels, float* params, flo
     return hip_status(fhv::nn::train_step(ctx->dev, levels, params, adam_m, adam_v, step, lr, rgba, depth, cov,
                                           target_rgba, n_img, height, width, loss_out, grad_out, ws,
                                           (hipStream_t)stream));
+}
+
+fhv_status fhv_get_tuning(fhv_ctx* ctx, fhv_tuning* out)
+{
+    if (!ctx || !out) return FHV_EINVAL;
+    out->tile_w = ctx->dev.tune.tile_w;
+    out->raster_wg = ctx->dev.tune.raster_wg;
+    out->splat_wg = ctx->dev.tune.splat_wg;
+    return FHV_OK;
+}
+
+fhv_status fhv_set_tuning(fhv_ctx* ctx, const fhv_tuning* t)
+{
+    if (!ctx || !t) return FHV_EINVAL;
+    if (t->tile_w != 8 && t->tile_w != 16 && t->tile_w != 32) return FHV_EINVAL;
+    if (t->raster_wg < 1 || t->raster_wg > 64 || t->splat_wg < 1 || t->splat_wg > 64) return FHV_EINVAL;
+    ctx->dev.tune.tile_w = t->tile_w;
+    ctx->dev.tune.raster_wg = t->raster_wg;
+    ctx->dev.tune.splat_wg = t->splat_wg;
+    return FHV_OK;
+}
+
+size_t fhv_batch_workspace(const fhv_batch_mesh* mesh, const fhv_batch_views* views, uint64_t capacity)
+{
+    if (!batch_shape_ok(mesh, views)) return 0;
+    return batch_ws(mesh, capacity, nullptr, nullptr, nullptr);
+}
+
+fhv_status fhv_batch_run(fhv_ctx* ctx, const fhv_batch_mesh* mesh, const fhv_batch_views* views,
+                         const fhv_lists* lists, const fhv_pofa* out, uint64_t* zbuf, uint32_t* rgba,
+                         float* depth, uint8_t* cov, void* ws, size_t ws_bytes, uint32_t flags,
+                         fhv_stream stream)
+{
+    if (!ctx || !batch_shape_ok(mesh, views) || !lists || !out) return FHV_EINVAL;
+    if (flags & ~(FHV_BATCH_GRAPH | FHV_BATCH_TUNE)) return FHV_EINVAL;
+    if (mesh->n_tri >= (1u << 31)) return FHV_ERANGE;
+    if (mesh->n_tri > 0 && (!mesh->pos || !mesh->rgba || !mesh->tri || mesh->n_vert == 0)) return FHV_EINVAL;
+    if (!mesh->scene_tri || !views->m) return FHV_EINVAL;
+    const uint64_t n_head = (uint64_t)mesh->n_scenes << (3 * mesh->levels);
+    if (lists->n_head != n_head) return FHV_EINVAL;
+    if (!lists->counter || !lists->keys) return FHV_EINVAL;
+    if (lists->capacity >= 0xFFFFFFFFull) return FHV_ERANGE;
+    if (lists->capacity > 0 && !lists->pool) return FHV_EINVAL;
+    if ((uintptr_t)lists->pool & 15) return FHV_EINVAL;
+    if (!out->n_occ || !out->n_frag || out->cap_frag < lists->capacity) return FHV_EINVAL;
+    if (lists->capacity > 0 && !out->frag) return FHV_EINVAL;
+    if ((uintptr_t)out->frag & 15) return FHV_EINVAL;
+    if (out->cap_occ > 0 && (!out->oct_key || !out->oct_off || !out->oct_cnt)) return FHV_EINVAL;
+    if (!zbuf || !rgba || !depth || !cov || ((uintptr_t)zbuf & 15)) return FHV_EINVAL;
+    if (ws_bytes < batch_ws(mesh, lists->capacity, nullptr, nullptr, nullptr)) return FHV_EWORKSPACE;
+    if (!ws) return FHV_EINVAL;
+    fhv_status st = set_device(ctx);
+    if (st != FHV_OK) return st;
+    const hipStream_t s = (hipStream_t)stream;
+    BatchCall call{mesh, views, lists, out, zbuf, rgba, depth, cov, ws};
+    if (flags & FHV_BATCH_TUNE) {
+        if ((st = hip_status(batch_tune(ctx, call, s))) != FHV_OK) return st;
+    }
+    if (!(flags & FHV_BATCH_GRAPH)) return hip_status(batch_enqueue(ctx->dev, call, s));
+
+    // graph: look up by every argument byte and the launch choices
+    std::vector<unsigned char> key;
+    auto put = [&key](const void* p, size_t n) {
+        const unsigned char* b = (const unsigned char*)p;
+        key.insert(key.end(), b, b + n);
+    };
+    put(mesh, sizeof(*mesh));
+    put(views, sizeof(*views));
+    put(lists, sizeof(*lists));
+    put(out, sizeof(*out));
+    const void* ptrs[5] = {zbuf, rgba, depth, cov, ws};
+    put(ptrs, sizeof(ptrs));
+    put(&ws_bytes, sizeof(ws_bytes));
+    put(&ctx->dev.tune, sizeof(ctx->dev.tune));
+    hipGraphExec_t exec = nullptr;
+    for (auto& g : ctx->graphs)
+        if (g.key == key) exec = g.exec;
+    if (!exec) {
+        hipError_t e = hipSuccess;
+        if (!ctx->rec_stream) e = hipStreamCreateWithFlags(&ctx->rec_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_status(e);
+        fhv::Device d = ctx->dev;
+        d.prof = nullptr;   // no event records inside the graph
+        e = hipStreamBeginCapture(ctx->rec_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_status(e);
+        const hipError_t el = batch_enqueue(d, call, ctx->rec_stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(ctx->rec_stream, &g);
+        if (el != hipSuccess || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_status(el != hipSuccess ? el : e);
+        }
+        e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_status(e);
+        if (ctx->graphs.size() >= 8) {
+            (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+            ctx->graphs.erase(ctx->graphs.begin());
+        }
+        ctx->graphs.push_back({key, exec});
+    }
+    return hip_status(hipGraphLaunch(exec, s));
 }
 
 }  // extern "C"

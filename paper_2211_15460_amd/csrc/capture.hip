@@ -7,7 +7,8 @@
 //   k_setup   one thread per triangle: fixed-point vertices (PPFL: viewport
 //             transform; POFL: grid snap, exact integer normal, octahedral
 //             packing, tangent frame of the packed normal, projection),
-//             orientation, sample bounding box, number of 8x8 sample tiles
+//             orientation, sample bounding box, number of sample tiles of
+//             64 samples (8x8, 16x4 or 32x2, a launch choice)
 //   scan      inclusive prefix sum of tiles per triangle
 //   k_raster  work items are (triangle, tile) pairs; a wave takes a
 //             contiguous range of them and processes one tile at a time, one
@@ -18,7 +19,9 @@
 // reserves their slots with one atomic add on the global counter (instead
 // of one increment per fragment; the slots are the same set). Each lane with
 // a slot below the capacity swaps its index into the key's head and stores
-// {w0, rgba, normal, previous head} plus the key sidecar.
+// {w0, rgba, normal, previous head} plus the key sidecar. Without a head
+// array (batches that only want arrays) the exchange is skipped and the
+// link is 0xFFFFFFFF.
 //
 // The fp64 setup relies on IEEE-correct add, mul, div, sqrt and rint and on
 // no contraction into fused multiply-adds (built with -ffp-contract=off):
@@ -95,11 +98,26 @@ __device__ __forceinline__ void sample_range(int64_t lo, int64_t hi, int32_t* i0
 __global__ void __launch_bounds__(kBlock)
 k_setup(const float* __restrict__ pos, const uint32_t* __restrict__ rgba,
         const uint32_t* __restrict__ tri, const uint8_t* __restrict__ obj, uint32_t n_tri,
-        uint32_t mode, uint32_t width, uint32_t height, uint32_t levels,
+        uint32_t mode, uint32_t width, uint32_t height, uint32_t levels, uint32_t tile_shift,
+        const uint32_t* __restrict__ scene_tri, uint32_t n_scenes,
         TriRec* __restrict__ recs, uint64_t* __restrict__ tiles)
 {
     const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= n_tri) return;
+    // scene of a batch: the last s in [0, n_scenes) with scene_tri[s] <= t
+    // (only scene_tri[1 .. n_scenes-1] is read, so the result stays in range)
+    uint32_t scene = 0;
+    if (scene_tri) {
+        uint32_t lo = 0, hi = n_scenes - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (scene_tri[mid] <= t)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        scene = lo;
+    }
     TriRec r;
     int64_t X[3], Y[3];
     int32_t a[3][3];
@@ -206,12 +224,13 @@ k_setup(const float* __restrict__ pos, const uint32_t* __restrict__ rgba,
             r.aux = obj ? (uint32_t)obj[t] : 0u;
             r.A = A;
             r.rA = 1.0 / (double)A;
-            r.scene = 0;
+            r.scene = scene;
             r.pad1 = 0;
             r.pad2 = 0;
             if (i1 >= i0 && j1 >= j0) {
-                const uint32_t tx = (uint32_t)(i1 - i0) / kTile + 1;
-                const uint32_t ty = (uint32_t)(j1 - j0) / kTile + 1;
+                // tiles of (1 << tile_shift) x (64 >> tile_shift) samples
+                const uint32_t tx = ((uint32_t)(i1 - i0) >> tile_shift) + 1;
+                const uint32_t ty = ((uint32_t)(j1 - j0) >> (6 - tile_shift)) + 1;
                 r.tiles_x = tx;
                 n_tiles = (uint64_t)tx * ty;
             } else {
@@ -264,12 +283,12 @@ struct Sample {
     int64_t e01, e12, e20;
 };
 
-__device__ __forceinline__ Sample sample_of(const TriRec& r, uint32_t tile, int lane)
+__device__ __forceinline__ Sample sample_of(const TriRec& r, uint32_t tile, int lane, uint32_t ts)
 {
     Sample s;
     const uint32_t tx = tile % r.tiles_x, ty = tile / r.tiles_x;
-    s.i = r.lo_i + (int32_t)(tx * kTile) + (lane & (kTile - 1));
-    s.j = r.lo_j + (int32_t)(ty * kTile) + (lane >> 3);
+    s.i = r.lo_i + (int32_t)(tx << ts) + (lane & ((1 << ts) - 1));
+    s.j = r.lo_j + (int32_t)(ty << (6 - ts)) + (lane >> ts);
     s.cov = s.i <= r.hi_i && s.j <= r.hi_j;
     s.e01 = s.e12 = s.e20 = 0;
     if (s.cov) {
@@ -327,7 +346,7 @@ struct ItemWalk {
 template <int kMode, class KeyT>
 __global__ void __launch_bounds__(kBlock)
 k_raster(const TriRec* __restrict__ recs, const uint64_t* __restrict__ incl, uint32_t n_tri,
-         uint32_t width, uint32_t gmax, uint32_t levels, uint32_t* __restrict__ head,
+         uint32_t width, uint32_t gmax, uint32_t levels, uint32_t ts, uint32_t* __restrict__ head,
          uint4* __restrict__ pool, KeyT* __restrict__ keys, uint64_t cap,
          unsigned long long* __restrict__ counter)
 {
@@ -357,7 +376,7 @@ k_raster(const TriRec* __restrict__ recs, const uint64_t* __restrict__ incl, uin
         }
 #pragma unroll
         for (int g = 0; g < kBatch; ++g)
-            if (tb[g] != kNil) n_cov += (uint64_t)__popcll(__ballot(sample_of(recs[tb[g]], tile[g], lane).cov));
+            if (tb[g] != kNil) n_cov += (uint64_t)__popcll(__ballot(sample_of(recs[tb[g]], tile[g], lane, ts).cov));
     }
     if (n_cov == 0) return;
     unsigned long long base = 0;
@@ -378,7 +397,7 @@ k_raster(const TriRec* __restrict__ recs, const uint64_t* __restrict__ incl, uin
             if (w + g >= w1) continue;   // wave-uniform
             it.advance(w + g);
             const TriRec& r = recs[it.t];
-            const Sample sm = sample_of(r, (uint32_t)(w + g - it.first), lane);
+            const Sample sm = sample_of(r, (uint32_t)(w + g - it.first), lane, ts);
             const uint64_t mask = __ballot(sm.cov);
             idx[g] = base + (uint64_t)__popcll(mask & lanemask_lt());
             base += (uint64_t)__popcll(mask);
@@ -406,8 +425,10 @@ k_raster(const TriRec* __restrict__ recs, const uint64_t* __restrict__ incl, uin
         }
         uint32_t prev[kBatch];
 #pragma unroll
-        for (int g = 0; g < kBatch; ++g)
-            if (has[g]) prev[g] = atomicExch(head + key[g], (uint32_t)idx[g]);
+        for (int g = 0; g < kBatch; ++g) {
+            prev[g] = kNil;
+            if (head && has[g]) prev[g] = atomicExch(head + key[g], (uint32_t)idx[g]);
+        }
 #pragma unroll
         for (int g = 0; g < kBatch; ++g) {
             if (!has[g]) continue;
@@ -431,25 +452,26 @@ size_t capture_ws_bytes(const fhv_capture_desc* d, uint32_t n_tri)
 }
 
 hipError_t capture_launch(const Device& dev, const fhv_mesh* m, const fhv_capture_desc* d,
-                          const fhv_lists* L, void* ws, hipStream_t s)
+                          const fhv_lists* L, void* ws, hipStream_t s, const Scenes* sc)
 {
     Carver c{(char*)ws, 0};
     TriRec* recs = c.take<TriRec>(m->n_tri);
     uint64_t* tiles = c.take<uint64_t>(m->n_tri);
     uint64_t* incl = c.take<uint64_t>(m->n_tri);
     uint64_t* part = c.take<uint64_t>(scan_partials(m->n_tri));
+    const uint32_t ts = dev.tune.tile_w == 32 ? 5u : (dev.tune.tile_w == 16 ? 4u : 3u);
     hipError_t e;
     {
         ProfScope ps(dev, "capture.reset", s);
-        e = fill_u32(L->head, L->n_head, kNil, s);
+        e = L->head ? fill_u32(L->head, L->n_head, kNil, s) : hipSuccess;
         if (e == hipSuccess) e = fill_u64(L->counter, 1, 0, s);
     }
     if (e != hipSuccess || m->n_tri == 0) return e;
     {
         ProfScope ps(dev, "capture.setup", s);
         k_setup<<<dim3((m->n_tri + kBlock - 1) / kBlock), dim3(kBlock), 0, s>>>(
-            m->pos, m->rgba, m->tri, m->obj, m->n_tri, d->mode, d->width, d->height, d->levels,
-            recs, tiles);
+            m->pos, m->rgba, m->tri, m->obj, m->n_tri, d->mode, d->width, d->height, d->levels, ts,
+            sc ? sc->scene_tri : nullptr, sc ? sc->n_scenes : 1u, recs, tiles);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
@@ -458,21 +480,21 @@ hipError_t capture_launch(const Device& dev, const fhv_mesh* m, const fhv_captur
         e = scan_u64(tiles, incl, m->n_tri, true, part, nullptr, s);
     }
     if (e != hipSuccess) return e;
-    const unsigned grid = (unsigned)(dev.cus * 16);
+    const unsigned grid = (unsigned)(dev.cus * dev.tune.raster_wg);
     const uint32_t gmax = d->mode == FHV_POFL ? (1u << (d->levels + 8)) - 1u : 0u;
     ProfScope ps(dev, "capture.raster", s);
     const bool wide = L->n_head > (1ull << 32);
     if (d->mode == FHV_PPFL)
         k_raster<FHV_PPFL, uint32_t><<<dim3(grid), dim3(kBlock), 0, s>>>(
-            recs, incl, m->n_tri, d->width, gmax, d->levels, L->head, (uint4*)L->pool,
+            recs, incl, m->n_tri, d->width, gmax, d->levels, ts, L->head, (uint4*)L->pool,
             (uint32_t*)L->keys, L->capacity, (unsigned long long*)L->counter);
     else if (!wide)
         k_raster<FHV_POFL, uint32_t><<<dim3(grid), dim3(kBlock), 0, s>>>(
-            recs, incl, m->n_tri, d->width, gmax, d->levels, L->head, (uint4*)L->pool,
+            recs, incl, m->n_tri, d->width, gmax, d->levels, ts, L->head, (uint4*)L->pool,
             (uint32_t*)L->keys, L->capacity, (unsigned long long*)L->counter);
     else
         k_raster<FHV_POFL, uint64_t><<<dim3(grid), dim3(kBlock), 0, s>>>(
-            recs, incl, m->n_tri, d->width, gmax, d->levels, L->head, (uint4*)L->pool,
+            recs, incl, m->n_tri, d->width, gmax, d->levels, ts, L->head, (uint4*)L->pool,
             (uint64_t*)L->keys, L->capacity, (unsigned long long*)L->counter);
     return hipGetLastError();
 }

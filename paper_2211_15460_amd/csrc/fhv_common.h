@@ -12,7 +12,6 @@ namespace fhv {
 constexpr uint32_t kNil = 0xFFFFFFFFu;
 constexpr int kBlock = 256;          // threads per workgroup (4 waves)
 constexpr int kWave = 64;
-constexpr int kTile = 8;             // raster tile: 8 x 8 samples = one wave
 constexpr int kBrickShift = 9;       // compaction bucket: 512 consecutive keys
 constexpr uint32_t kBrickKeys = 1u << kBrickShift;
 constexpr uint32_t kMaxViews = 32;
@@ -126,10 +125,20 @@ namespace fhv {
 
 struct Profiler;  // kernel timing with HIP events, owned by the context
 
+// Launch choices (fhv_tuning): raster tile width (8, 16 or 32 samples; a
+// tile is 64 samples), workgroups per compute unit of the rasterizer and of
+// the splat.
+struct Tuning {
+    uint32_t tile_w = 8;
+    uint32_t raster_wg = 16;
+    uint32_t splat_wg = 16;
+};
+
 struct Device {
     int id;
     int cus;
     Profiler* prof;  // non-null while profiling is on
+    Tuning tune;
 };
 
 void prof_mark(Profiler* p, const char* name, hipStream_t s, bool start);
@@ -160,9 +169,16 @@ hipError_t scan_u32(const uint32_t* in, uint32_t* out, uint64_t n, bool inclusiv
 hipError_t scan_u64(const uint64_t* in, uint64_t* out, uint64_t n, bool inclusive,
                     uint64_t* partial, uint64_t* total, hipStream_t s);
 
+// Scenes of a batch: triangle t belongs to the scene s with
+// scene_tri[s] <= t < scene_tri[s + 1]; its keys are offset by s << 3L.
+struct Scenes {
+    const uint32_t* scene_tri;
+    uint32_t n_scenes;
+};
+
 size_t capture_ws_bytes(const fhv_capture_desc* d, uint32_t n_tri);
 hipError_t capture_launch(const Device& dev, const fhv_mesh* m, const fhv_capture_desc* d,
-                          const fhv_lists* L, void* ws, hipStream_t s);
+                          const fhv_lists* L, void* ws, hipStream_t s, const Scenes* sc = nullptr);
 
 size_t compact_ws_bytes(const fhv_capture_desc* d, uint64_t n_head, uint64_t capacity);
 hipError_t compact_launch(const Device& dev, const fhv_lists* L, const fhv_capture_desc* d,
@@ -171,6 +187,16 @@ hipError_t compact_launch(const Device& dev, const fhv_lists* L, const fhv_captu
 hipError_t splat_launch(const Device& dev, const fhv_pofa* a, const fhv_capture_desc* d,
                         const ViewArgs& va, uint64_t* zbuf, uint32_t* rgba, float* depth,
                         uint8_t* cov, uint64_t max_frag, hipStream_t s);
+
+// Views of a batch: matrices [n_scenes][n_views][12] in device memory.
+struct BatchViews {
+    const float* m;
+    uint32_t n_scenes, n_views, width, height, k;
+};
+
+hipError_t splat_batch_launch(const Device& dev, const fhv_pofa* a, uint32_t levels, const BatchViews& bv,
+                              uint64_t* zbuf, uint32_t* rgba, float* depth, uint8_t* cov,
+                              uint64_t max_frag, hipStream_t s);
 
 namespace nn {
 uint64_t param_count(uint32_t levels);

@@ -144,6 +144,115 @@ k_splat(const uint4* __restrict__ frag, const uint64_t* __restrict__ oct_key,
     }
 }
 
+// Batches: the fragment's scene is the high part of its key (key >> 3L);
+// it draws only into its scene's views, whose matrices are read from device
+// memory [scene][view][12]. When every fragment of a wave belongs to one
+// scene (the usual case: arrays are in key order) the scene index is made
+// wave-uniform so that the matrix reads become scalar loads.
+struct BatchArgs {
+    uint32_t n_scenes, n_views, width, height, k, shift;
+    float c;   // 1/2 - k/2
+};
+
+__device__ __forceinline__ void splat_batch_one(const float* __restrict__ vm, uint32_t scene,
+                                                const BatchArgs& a, float x, float y, float z, uint32_t i,
+                                                unsigned long long* __restrict__ zbuf)
+{
+    const uint64_t plane = (uint64_t)a.width * a.height;
+    const unsigned long long idx = (unsigned long long)i;
+    if (a.k == 1) {
+        for (uint32_t vb = 0; vb < a.n_views; vb += 4) {
+            uint64_t off[4];
+            unsigned long long zk[4], cur[4];
+            bool ok[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t v = vb + j;
+                ok[j] = false;
+                off[j] = 0;
+                zk[j] = 0;
+                if (v < a.n_views) {
+                    const uint64_t pl = (uint64_t)scene * a.n_views + v;
+                    const float* M = vm + pl * 12;
+                    const float sx = ((M[0] * x + M[1] * y) + M[2] * z) + M[3];
+                    const float sy = ((M[4] * x + M[5] * y) + M[6] * z) + M[7];
+                    const float d = ((M[8] * x + M[9] * y) + M[10] * z) + M[11];
+                    const float fx = floorf(sx + a.c), fy = floorf(sy + a.c);
+                    ok[j] = d > 0.0f && fx >= 0.0f && fx < (float)a.width && fy >= 0.0f && fy < (float)a.height;
+                    if (ok[j]) off[j] = pl * plane + (uint64_t)(uint32_t)fy * a.width + (uint32_t)fx;
+                    zk[j] = ((unsigned long long)__float_as_uint(d) << 32) | idx;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) cur[j] = ok[j] ? zbuf[off[j]] : 0ull;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (ok[j] && zk[j] < cur[j]) atomicMin(zbuf + off[j], zk[j]);
+        }
+        return;
+    }
+    for (uint32_t v = 0; v < a.n_views; ++v) {
+        const uint64_t pl = (uint64_t)scene * a.n_views + v;
+        const float* M = vm + pl * 12;
+        const float sx = ((M[0] * x + M[1] * y) + M[2] * z) + M[3];
+        const float sy = ((M[4] * x + M[5] * y) + M[6] * z) + M[7];
+        const float d = ((M[8] * x + M[9] * y) + M[10] * z) + M[11];
+        if (!(d > 0.0f)) continue;
+        const float fx = floorf(sx + a.c), fy = floorf(sy + a.c);
+        if (!(fx > -1073741824.0f && fx < 1073741824.0f)) continue;
+        if (!(fy > -1073741824.0f && fy < 1073741824.0f)) continue;
+        const int32_t k = (int32_t)a.k;
+        int32_t xa = (int32_t)fx, ya = (int32_t)fy;
+        int32_t xb = xa + k, yb = ya + k;   // exclusive
+        xa = xa < 0 ? 0 : xa;
+        ya = ya < 0 ? 0 : ya;
+        xb = xb > (int32_t)a.width ? (int32_t)a.width : xb;
+        yb = yb > (int32_t)a.height ? (int32_t)a.height : yb;
+        const unsigned long long zk = ((unsigned long long)__float_as_uint(d) << 32) | idx;
+        unsigned long long* zb = zbuf + pl * plane;
+        for (int32_t yy = ya; yy < yb; ++yy)
+            for (int32_t xx = xa; xx < xb; ++xx) {
+                unsigned long long* p = zb + (uint64_t)yy * a.width + xx;
+                if (zk < *p) atomicMin(p, zk);
+            }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_splat_batch(const uint4* __restrict__ frag, const uint64_t* __restrict__ oct_key,
+              const uint64_t* __restrict__ n_frag, uint64_t cap_frag, uint64_t cap_occ,
+              const float* __restrict__ vm, BatchArgs a, unsigned long long* __restrict__ zbuf)
+{
+    const uint64_t nf = *n_frag;
+    const uint64_t F = nf < cap_frag ? nf : cap_frag;
+    if (cap_occ == 0) return;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    const uint64_t kmask = (1ull << a.shift) - 1ull;
+    // whole waves iterate together (stride and wave bases are multiples of
+    // 64), so the ballots below see every lane
+    const uint64_t Fw = (F + kWave - 1) & ~(uint64_t)(kWave - 1);
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < Fw; i += stride) {
+        bool act = i < F;
+        const uint4 r = act ? frag[i] : make_uint4(0, 0, 0, 0);
+        act = act && r.w < cap_occ;
+        const uint64_t key = act ? oct_key[r.w] : 0ull;
+        const uint32_t scene = (uint32_t)(key >> a.shift);
+        act = act && scene < a.n_scenes;
+        const uint64_t live = __ballot(act);
+        if (live == 0) continue;
+        float x, y, z;
+        frag_pos<FHV_POFL>(r, key & kmask, 0, &x, &y, &z);
+        const int leader = __ffsll((unsigned long long)live) - 1;
+        const uint32_t s0 = uniform32((uint32_t)__shfl((int)scene, leader, kWave));
+        const bool one_scene = __ballot(act && scene != s0) == 0;
+        if (!act) continue;
+        if (one_scene)
+            splat_batch_one(vm, s0, a, x, y, z, (uint32_t)i, zbuf);
+        else
+            splat_batch_one(vm, scene, a, x, y, z, (uint32_t)i, zbuf);
+    }
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_resolve(const unsigned long long* __restrict__ zbuf, const uint4* __restrict__ frag, uint64_t n,
           uint32_t* __restrict__ rgba, float* __restrict__ depth, uint8_t* __restrict__ cov)
@@ -181,8 +290,9 @@ hipError_t splat_launch(const Device& dev, const fhv_pofa* a, const fhv_capture_
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
+    const uint64_t smax = (uint64_t)dev.cus * dev.tune.splat_wg;
     uint64_t gs = (max_frag + kBlock - 1) / kBlock;
-    gs = gs < 1 ? 1 : (gs > gmax ? gmax : gs);
+    gs = gs < 1 ? 1 : (gs > smax ? smax : gs);
     {
     ProfScope ps(dev, "splat.splat", s);
     if (d->mode == FHV_PPFL)
@@ -194,6 +304,52 @@ hipError_t splat_launch(const Device& dev, const fhv_pofa* a, const fhv_capture_
             (const uint4*)a->frag, a->oct_key, a->n_frag, a->cap_frag, a->cap_occ, d->width, va,
             (unsigned long long*)zbuf);
     e = hipGetLastError();
+    }
+    if (e != hipSuccess) return e;
+    uint64_t gr = (n + kBlock - 1) / kBlock;
+    gr = gr < 1 ? 1 : (gr > gmax ? gmax : gr);
+    ProfScope ps(dev, "splat.resolve", s);
+    k_resolve<<<dim3((unsigned)gr), dim3(kBlock), 0, s>>>((const unsigned long long*)zbuf,
+                                                          (const uint4*)a->frag, n, rgba, depth, cov);
+    return hipGetLastError();
+}
+
+}  // namespace fhv
+
+namespace fhv {
+
+hipError_t splat_batch_launch(const Device& dev, const fhv_pofa* a, uint32_t levels, const BatchViews& bv,
+                              uint64_t* zbuf, uint32_t* rgba, float* depth, uint8_t* cov,
+                              uint64_t max_frag, hipStream_t s)
+{
+    const uint64_t n = (uint64_t)bv.n_scenes * bv.n_views * bv.width * bv.height;
+    const uint64_t gmax = (uint64_t)dev.cus * 16;
+    uint64_t gz = (n / 2 + kBlock - 1) / kBlock;
+    gz = gz < 1 ? 1 : (gz > gmax ? gmax : gz);
+    hipError_t e;
+    {
+        ProfScope ps(dev, "splat.zclear", s);
+        k_zclear<<<dim3((unsigned)gz), dim3(kBlock), 0, s>>>(zbuf, n);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return e;
+    BatchArgs ba;
+    ba.n_scenes = bv.n_scenes;
+    ba.n_views = bv.n_views;
+    ba.width = bv.width;
+    ba.height = bv.height;
+    ba.k = bv.k;
+    ba.shift = 3 * levels;
+    ba.c = 0.5f - 0.5f * (float)bv.k;
+    const uint64_t smax = (uint64_t)dev.cus * dev.tune.splat_wg;
+    uint64_t gs = (max_frag + kBlock - 1) / kBlock;
+    gs = gs < 1 ? 1 : (gs > smax ? smax : gs);
+    {
+        ProfScope ps(dev, "splat.splat", s);
+        k_splat_batch<<<dim3((unsigned)gs), dim3(kBlock), 0, s>>>(
+            (const uint4*)a->frag, a->oct_key, a->n_frag, a->cap_frag, a->cap_occ, bv.m, ba,
+            (unsigned long long*)zbuf);
+        e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
     uint64_t gr = (n + kBlock - 1) / kBlock;

@@ -51,6 +51,24 @@ class View_(C.Structure):
                 ("splat_px", C.c_uint32)]
 
 
+class BatchMesh_(C.Structure):
+    _fields_ = [("pos", C.c_void_p), ("rgba", C.c_void_p), ("tri", C.c_void_p),
+                ("obj", C.c_void_p), ("scene_tri", C.c_void_p), ("n_vert", C.c_uint32),
+                ("n_tri", C.c_uint32), ("n_scenes", C.c_uint32), ("levels", C.c_uint32)]
+
+
+class BatchViews_(C.Structure):
+    _fields_ = [("m", C.c_void_p), ("n_views", C.c_uint32), ("width", C.c_uint32),
+                ("height", C.c_uint32), ("splat_px", C.c_uint32)]
+
+
+class Tuning_(C.Structure):
+    _fields_ = [("tile_w", C.c_uint32), ("raster_wg", C.c_uint32), ("splat_wg", C.c_uint32)]
+
+
+FHV_BATCH_GRAPH, FHV_BATCH_TUNE = 1, 2
+
+
 class KernelStat_(C.Structure):
     _fields_ = [("name", C.c_char_p), ("launches", C.c_uint64), ("total_ms", C.c_double)]
 
@@ -58,7 +76,8 @@ class KernelStat_(C.Structure):
 EXPORTS = ["fhv_create", "fhv_destroy", "fhv_status_str", "fhv_capture_workspace", "fhv_capture",
            "fhv_compact_workspace", "fhv_compact", "fhv_splat", "fhv_profile_begin",
            "fhv_profile_end", "fhv_unet_param_count", "fhv_fill_workspace", "fhv_fill",
-           "fhv_fill_train_step"]
+           "fhv_fill_train_step", "fhv_get_tuning", "fhv_set_tuning", "fhv_batch_workspace",
+           "fhv_batch_run"]
 
 _lib = None
 _ctx: dict[int, C.c_void_p] = {}
@@ -94,10 +113,17 @@ def lib():
                                C.c_size_t, P]
         L.fhv_fill_train_step.argtypes = [P, C.c_uint32, P, P, P, C.c_uint32, C.c_float, P, P, P, P,
                                           C.c_uint32, C.c_uint32, C.c_uint32, P, P, P, C.c_size_t, P]
+        L.fhv_get_tuning.argtypes = [P, C.POINTER(Tuning_)]
+        L.fhv_set_tuning.argtypes = [P, C.POINTER(Tuning_)]
+        L.fhv_batch_workspace.argtypes = [C.POINTER(BatchMesh_), C.POINTER(BatchViews_), C.c_uint64]
+        L.fhv_batch_workspace.restype = C.c_size_t
+        L.fhv_batch_run.argtypes = [P, C.POINTER(BatchMesh_), C.POINTER(BatchViews_), C.POINTER(Lists_),
+                                    C.POINTER(Pofa_), P, P, P, P, P, C.c_size_t, C.c_uint32, P]
         L.fhv_profile_begin.argtypes = [P]
         L.fhv_profile_end.argtypes = [P, C.POINTER(KernelStat_), C.c_uint32, C.POINTER(C.c_uint32)]
         for f in ("fhv_create", "fhv_destroy", "fhv_capture", "fhv_compact", "fhv_splat",
-                  "fhv_profile_begin", "fhv_profile_end", "fhv_fill", "fhv_fill_train_step"):
+                  "fhv_profile_begin", "fhv_profile_end", "fhv_fill", "fhv_fill_train_step",
+                  "fhv_get_tuning", "fhv_set_tuning", "fhv_batch_run"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -164,14 +190,16 @@ def n_head(d: Desc_) -> int:
 
 @dataclass
 class Lists:
-    head: torch.Tensor      # int32 [n_head] (uint32 bits)
+    head: torch.Tensor | None   # int32 [n_head] (uint32 bits); None: no lists (batches)
     pool: torch.Tensor      # int32 [cap, 4]
     keys: torch.Tensor      # int32 [cap], or int64 [cap] when n_head > 2^32
     counter: torch.Tensor   # int64 [1]
     capacity: int
+    key_space: int = 0      # n_head when head is None
 
     def struct(self) -> Lists_:
-        return Lists_(self.head.data_ptr(), self.head.numel(),
+        nh = self.head.numel() if self.head is not None else self.key_space
+        return Lists_(_ptr(self.head), nh,
                       self.pool.data_ptr() if self.capacity else None, self.capacity,
                       self.keys.data_ptr(), self.counter.data_ptr())
 
@@ -343,4 +371,97 @@ def fill_train_step(params: torch.Tensor, m: torch.Tensor | None, v: torch.Tenso
                                      _ptr(rgba), _ptr(depth), _ptr(cov), _ptr(target), N, H, W,
                                      _ptr(loss), _ptr(grad), _ptr(ws), ws.numel(), _stream()),
            "fhv_fill_train_step")
+    return ws
+
+
+# ------------------------------------------------------------------ tuning
+
+def get_tuning() -> dict:
+    t = Tuning_()
+    _check(lib().fhv_get_tuning(ctx(), C.byref(t)), "fhv_get_tuning")
+    return {"tile_w": t.tile_w, "raster_wg": t.raster_wg, "splat_wg": t.splat_wg}
+
+
+def set_tuning(tile_w: int = 8, raster_wg: int = 16, splat_wg: int = 16):
+    t = Tuning_(tile_w, raster_wg, splat_wg)
+    _check(lib().fhv_set_tuning(ctx(), C.byref(t)), "fhv_set_tuning")
+
+
+# ------------------------------------------------------------------ batches
+
+@dataclass
+class DeviceBatch:
+    pos: torch.Tensor        # float32 [nv, 3], all scenes
+    rgba: torch.Tensor       # int32 [nv]
+    tri: torch.Tensor        # int32 [nt, 3], indices into the concatenated vertices
+    obj: torch.Tensor | None
+    scene_tri: torch.Tensor  # int32 [n_scenes + 1] triangle offsets
+    n_scenes: int
+    levels: int
+    tri_off: np.ndarray      # host copy of scene_tri
+
+    def struct(self) -> BatchMesh_:
+        return BatchMesh_(self.pos.data_ptr(), self.rgba.data_ptr(), self.tri.data_ptr(),
+                          _ptr(self.obj), self.scene_tri.data_ptr(), int(self.pos.shape[0]),
+                          int(self.tri.shape[0]), self.n_scenes, self.levels)
+
+
+def to_device_batch(meshes, levels: int, device="cuda") -> DeviceBatch:
+    """Concatenate host meshes (scenes.Mesh) into one batch on the device."""
+    pos, rgba, tri, obj = [], [], [], []
+    nv = 0
+    offs = [0]
+    for m in meshes:
+        pos.append(np.asarray(m.pos, np.float32))
+        rgba.append(np.asarray(m.rgba, np.uint32))
+        tri.append(np.asarray(m.tri, np.uint64) + nv)
+        obj.append(np.zeros(m.tri.shape[0], np.uint8) if m.obj is None else np.asarray(m.obj, np.uint8))
+        nv += m.pos.shape[0]
+        offs.append(offs[-1] + m.tri.shape[0])
+    assert nv < 2 ** 32 and offs[-1] < 2 ** 31
+    cat = lambda xs, dt: np.ascontiguousarray(np.concatenate(xs).astype(dt))
+    t = lambda a: torch.from_numpy(a).to(device)
+    off = np.array(offs, np.uint32)
+    return DeviceBatch(t(cat(pos, np.float32)), t(cat(rgba, np.uint32).view(np.int32)),
+                       t(cat(tri, np.uint32).view(np.int32)), t(cat(obj, np.uint8)),
+                       t(off.view(np.int32)), len(meshes), levels, off)
+
+
+def batch_view_matrices(views_per_scene, device="cuda") -> torch.Tensor:
+    """float32 [n_scenes, n_views, 12] device tensor of view matrices."""
+    m = np.stack([np.stack([np.asarray(v.m, np.float32).reshape(12) for v in vs]) for vs in views_per_scene])
+    return torch.from_numpy(np.ascontiguousarray(m)).to(device)
+
+
+def alloc_batch_lists(b: DeviceBatch, capacity: int, link: bool = False, device="cuda") -> Lists:
+    """Pool, keys and counter for a batch; head array only when link=True."""
+    ks = b.n_scenes * 8 ** b.levels
+    kt = torch.int64 if ks > 2 ** 32 else torch.int32
+    head = torch.empty(ks, dtype=torch.int32, device=device) if link else None
+    return Lists(head, torch.empty((max(capacity, 1), 4), dtype=torch.int32, device=device),
+                 torch.empty(max(capacity, 1), dtype=kt, device=device),
+                 torch.zeros(1, dtype=torch.int64, device=device), capacity, ks)
+
+
+def batch_workspace(b: DeviceBatch, vstruct: BatchViews_, capacity: int) -> int:
+    ms = b.struct()
+    return int(lib().fhv_batch_workspace(C.byref(ms), C.byref(vstruct), capacity))
+
+
+def batch_run(b: DeviceBatch, vm: torch.Tensor, width: int, height: int, splat_px: int, lists: Lists,
+              out: Pofa, img: Images, ws: torch.Tensor | None = None, flags: int = 0) -> torch.Tensor:
+    """fhv_batch_run; img tensors are [n_scenes * n_views, H, W]. Returns the
+    workspace tensor for reuse."""
+    n_views = int(vm.shape[1])
+    vs = BatchViews_(vm.data_ptr(), n_views, width, height, splat_px)
+    ms = b.struct()
+    need = int(lib().fhv_batch_workspace(C.byref(ms), C.byref(vs), lists.capacity))
+    if need == 0:
+        raise FhvError("fhv_batch_workspace: invalid batch shape")
+    ws = _ws(ws, need, b.pos.device)
+    ls = lists.struct()
+    ps = out.struct()
+    _check(lib().fhv_batch_run(ctx(), C.byref(ms), C.byref(vs), C.byref(ls), C.byref(ps), _ptr(img.zbuf),
+                               _ptr(img.rgba), _ptr(img.depth), _ptr(img.cov), _ptr(ws), ws.numel(), flags,
+                               _stream()), "fhv_batch_run")
     return ws

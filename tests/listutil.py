@@ -7,13 +7,15 @@ import numpy as np
 NIL = 0xFFFFFFFF
 
 
-def walk_lists(head: np.ndarray, pool: np.ndarray, counter: int, return_index: bool = False):
+def walk_lists(head: np.ndarray, pool: np.ndarray, counter: int, return_index: bool = False,
+               partial: bool = False):
     """Follow every list from its head (vectorised over lists).
 
     Returns (keys, recs): for every list member its head key and its 16-byte
     record, in walk order (and the pool indices when return_index). Raises AssertionError if an index is out of range,
     a pool slot is reached twice, or the walk does not visit exactly
-    min(counter, cap) slots."""
+    min(counter, cap) slots (with partial=True, head covers only some of the
+    keys and each slot is visited at most once)."""
     cap = pool.shape[0]
     F = min(counter, cap)
     keys_all = np.nonzero(head != NIL)[0].astype(np.uint64)
@@ -31,7 +33,10 @@ def walk_lists(head: np.ndarray, pool: np.ndarray, counter: int, return_index: b
         keys_all, cur = keys_all[live], nxt[live]
         steps += 1
         assert steps <= F + 1, "cycle in a list"
-    assert np.all(seen == 1), "pool slot not in exactly one list"
+    if partial:
+        assert np.all(seen <= 1), "pool slot in more than one list"
+    else:
+        assert np.all(seen == 1), "pool slot not in exactly one list"
     if not out_k:
         e = (np.zeros(0, np.uint64), np.zeros((0, 4), np.uint32))
         return e + (np.zeros(0, np.int64),) if return_index else e

@@ -84,3 +84,20 @@ def test_bad_arguments_rejected_before_launch(F):
     assert L.fhv_compact(None, C.byref(ls), C.byref(d), None, None, 0, None) == -1
     assert L.fhv_splat(None, None, C.byref(d), None, 0, None, None, None, None, None) == -1
     assert L.fhv_create(None, 0) == -1
+
+
+def test_batch_workspace_shapes(F):
+    bm = F.BatchMesh_(None, None, None, None, None, 1000, 5000, 4, 9)
+    bv = F.BatchViews_(None, 8, 1280, 720, 1)
+    assert L_ws(F, bm, bv, 1 << 20) > (1 << 20) * 16
+    for bad_m, bad_v in (((0, 9), (8, 1280, 720, 1)), ((4, 0), (8, 1280, 720, 1)), ((4, 12), (8, 1280, 720, 1)),
+                         ((1 << 20, 9), (8, 1280, 720, 1)), ((4, 9), (0, 1280, 720, 1)),
+                         ((4, 9), (33, 1280, 720, 1)), ((4, 9), (8, 0, 720, 1)), ((4, 9), (8, 1280, 720, 0)),
+                         ((4, 9), (8, 1280, 720, 65))):
+        m = F.BatchMesh_(None, None, None, None, None, 1000, 5000, *bad_m)
+        v = F.BatchViews_(None, *bad_v)
+        assert L_ws(F, m, v, 1000) == 0
+
+
+def L_ws(F, m, v, cap):
+    return F.lib().fhv_batch_workspace(C.byref(m), C.byref(v), cap)
