@@ -15,7 +15,11 @@ throughput and its PSNR gain over the plain splat (a short training run on
 separate scenes, evaluated on held-out views), and the CPU oracle timed on
 one host core beside it.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload pofl200k|batch64|large5m]
+
+The other workloads (a batch of 64 scenes through one graph per step; one
+5M-triangle scene at octree depth 11 with 16 4K views) print a line of the
+same form for their own configuration.
 """
 from __future__ import annotations
 
@@ -53,16 +57,19 @@ def host_info():
     return {"nproc": os.cpu_count(), "cpu": model or platform.processor()}
 
 
-def algorithmic_bytes(F: int, n_occ: int, n_tri: int, n_head: int, n_views: int, pix: int) -> dict:
+def algorithmic_bytes(F: int, n_occ: int, n_tri: int, n_head: int, n_views: int, pix: int,
+                      key_bytes: int = 4, link: bool = True) -> dict:
     """Bytes each kernel scope must move at minimum, per launch (one step).
 
-    capture.reset    4 per head entry written
+    capture.reset    4 per head entry written (8 for the counter alone when
+                     no lists are linked)
     capture.setup    3 x (12 + 4) vertex bytes + 12 index bytes + 128 record
                      + 8 tile count per triangle
-    capture.raster   per fragment: 16 record + 4 key written, 8 for the head
-                     exchange (read + write of 4); 128 per triangle record
-    compact.hist     4 per fragment key read
-    compact.scatter  per fragment: 16 record + 4 key read, 16 staged record
+    capture.raster   per fragment: 16 record + key (4, or 8 beyond 2^32
+                     keys) written, 8 for the head exchange (read + write
+                     of 4) when linking; 128 per triangle record
+    compact.hist     one key read per fragment
+    compact.scatter  per fragment: 16 record + key read, 16 staged record
                      written
     compact.brick    per fragment 16 read + 16 written; 16 per table row
     splat.zclear     8 per z-buffer pixel
@@ -72,12 +79,12 @@ def algorithmic_bytes(F: int, n_occ: int, n_tri: int, n_head: int, n_views: int,
     """
     n_brick = (n_head + 511) // 512
     return {
-        "capture.reset": 4 * n_head,
+        "capture.reset": 4 * n_head if link else 8,
         "capture.setup": n_tri * (3 * 16 + 12 + 128 + 8),
-        "capture.raster": F * (16 + 4 + 8) + 128 * n_tri,
-        "compact.hist": 4 * F,
+        "capture.raster": F * (16 + key_bytes + (8 if link else 0)) + 128 * n_tri,
+        "compact.hist": key_bytes * F,
         "compact.scan": 2 * 2 * 4 * n_brick,
-        "compact.scatter": F * (16 + 4 + 16),
+        "compact.scatter": F * (16 + key_bytes + 16),
         "compact.brick": F * 32 + 16 * n_occ,
         "splat.zclear": 8 * n_views * pix,
         "splat.splat": 16 * F + 8 * n_occ,
@@ -207,11 +214,233 @@ def cpu_baseline(mesh, views, min_seconds: float = 10.0):
                       f"{t_all:.1f} s on one core, {dt:.3f} s per step"}
 
 
+def kernel_table(prof: dict, algo: dict) -> dict:
+    kernels = {}
+    for name, (launches, tot) in prof.items():
+        avg = tot / max(launches, 1)
+        b = algo.get(name, 0)
+        kernels[name] = {"avg_ms": round(avg, 5), "launches": launches, "algo_bytes": b,
+                         "gbs": round(b / (avg * 1e-3) / 1e9, 1) if avg > 0 and b else None}
+    return kernels
+
+
+def hbm_roofline(kernels: dict) -> dict:
+    """Roofline entry of the kernel scope with the largest total time; HBM
+    bytes from counters are not taken for this workload (null)."""
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+    dk = kernels[dom]
+    return {"bound": "hbm", "kernel": dom, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": dk["gbs"] / HBM_PEAK_GBS if dk["gbs"] else None, "traffic": None}
+
+
+def timed(torch, fn, steps: int) -> float:
+    """Milliseconds per call of fn over `steps` calls, HIP events on the
+    current stream."""
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(steps):
+        fn()
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps
+
+
+def bench_batch64(args, torch, fhv, scenes):
+    """64 scenes (triangle counts log-uniform in [1e3, 5e5]) at octree depth
+    9, 8 views each at 1280x720 (45 degrees apart): capture, compaction and
+    splat of the whole batch per step, through fhv_batch_run. The launch
+    choices are autotuned on the batch first; the timed steps replay the
+    recorded graph (eager launches are timed and profiled separately)."""
+    import numpy as np
+    L, V, W, H = 9, 8, 1280, 720
+    meshes = scenes.batched_scenes(SEED, 64)
+    n_tri = sum(m.tri.shape[0] for m in meshes)
+    b = fhv.to_device_batch(meshes, L)
+    views = [[scenes.cube_view(45.0 * v, L, W, H) for v in range(V)] for _ in meshes]
+    vm = fhv.batch_view_matrices(views)
+    k = views[0][0].splat_px
+    img = fhv.alloc_images(len(meshes) * V, W, H)
+    probe, probe_pofa = fhv.alloc_batch_lists(b, 1 << 16), fhv.alloc_pofa(1 << 16)
+    fhv.batch_run(b, vm, W, H, k, probe, probe_pofa, img)
+    torch.cuda.synchronize()
+    F = int(probe.counter.item())
+    del probe, probe_pofa
+    cap = ((F >> 20) + 1) << 20
+    lists, pofa = fhv.alloc_batch_lists(b, cap), fhv.alloc_pofa(cap)
+    ws = fhv.batch_run(b, vm, W, H, k, lists, pofa, img, flags=fhv.FHV_BATCH_TUNE)
+    tuning = fhv.get_tuning()
+    eager = lambda: fhv.batch_run(b, vm, W, H, k, lists, pofa, img, ws=ws)
+    graph = lambda: fhv.batch_run(b, vm, W, H, k, lists, pofa, img, ws=ws, flags=fhv.FHV_BATCH_GRAPH)
+    for _ in range(args.warmup):
+        eager()
+    fhv.profile_begin()
+    ms_eager = timed(torch, eager, args.steps)
+    prof = fhv.profile_end()
+    for _ in range(args.warmup):
+        graph()
+    t0 = time.perf_counter()
+    ms_graph = timed(torch, graph, args.steps)
+    wall = time.perf_counter() - t0
+    assert int(lists.counter.item()) == F
+    n_occ = int(pofa.n_occ.item())
+    n_views = len(meshes) * V
+    algo = algorithmic_bytes(F, n_occ, n_tri, len(meshes) * 8 ** L, n_views, W * H, key_bytes=8,
+                             link=False)
+    kernels = kernel_table(prof, algo)
+    for kk in kernels.values():
+        kk["launches_per_step"] = kk["launches"] / args.steps
+    out = {
+        "metric": "fragments captured/s; 1080p novel views/s; learned-fill vs plain-splat PSNR",
+        "value": F / (ms_graph * 1e-3), "unit": "fragments/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_graph, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "batched: 64 procedural scenes (seed 0), triangle counts log-uniform in "
+                               "[1e3, 5e5], octree depth 9, 8 views each at 1280x720, one graph per step",
+                   "scenes": len(meshes), "n_tri": n_tri, "levels": L, "fragments": F,
+                   "occupied_octants": n_occ, "views": n_views, "view_size": [W, H]},
+        "scenes_per_s": len(meshes) / (ms_graph * 1e-3),
+        "views_per_s_720p": n_views / (ms_graph * 1e-3),
+        "ms_per_step_eager": ms_eager,
+        "graph_saves_ms": ms_eager - ms_graph,
+        "tuning": tuning,
+        "kernels": kernels,
+        "roofline": hbm_roofline(kernels),
+        "wall_s_timed": wall,
+        "host": host_info(),
+        "device": torch.cuda.get_device_name(0),
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.lib()
+        n_s, n_f, t_all = 0, 0, 0.0
+        for m, vs in zip(meshes, views):
+            t1 = time.perf_counter()
+            head, pool, Fs = oracle.capture_pofl(m, L, 32 << 20)
+            r = oracle.compact(head, pool, Fs)
+            oracle.splat(1, r["key"], r["frag"], vs, levels=L)
+            t_all += time.perf_counter() - t1
+            n_s, n_f = n_s + 1, n_f + Fs
+            del head, pool, r
+            if t_all >= 10.0:
+                break
+        out["cpu_baseline"] = {"value": n_f / t_all, "unit": "fragments/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the first {n_s} scenes of the batch, each captured, compacted "
+                                         f"and splatted into its 8 views ({n_f} fragments, {t_all:.1f} s "
+                                         "on one core)"}
+    return out
+
+
+def bench_large5m(args, torch, fhv, scenes):
+    """One 5M-triangle scene (20,000 objects) at octree depth 11 (2048^3
+    leaves, 64-bit keys), about 0.9e9 fragments; 16 views at 3840x2160,
+    22.5 degrees apart. Each step: capture, compaction, splat of the 16
+    views."""
+    import numpy as np
+    L, V, W, H = 11, 16, 3840, 2160
+    mesh = scenes.large_scene(SEED)
+    views = [scenes.cube_view(22.5 * v, L, W, H) for v in range(V)]
+    d = fhv.desc(fhv.FHV_POFL, levels=L)
+    dm = fhv.to_device(mesh)
+    head = torch.empty(8 ** L, dtype=torch.int32, device="cuda")
+    probe = fhv.Lists(head, torch.empty((1 << 16, 4), dtype=torch.int32, device="cuda"),
+                      torch.empty(1 << 16, dtype=torch.int64, device="cuda"),
+                      torch.zeros(1, dtype=torch.int64, device="cuda"), 1 << 16)
+    fhv.capture(dm, d, probe)
+    torch.cuda.synchronize()
+    F = int(probe.counter.item())
+    del probe
+    cap = ((F >> 20) + 1) << 20
+    lists = fhv.Lists(head, torch.empty((cap, 4), dtype=torch.int32, device="cuda"),
+                      torch.empty(cap, dtype=torch.int64, device="cuda"),
+                      torch.zeros(1, dtype=torch.int64, device="cuda"), cap)
+    pofa = fhv.alloc_pofa(cap)
+    imgs = fhv.alloc_images(V, W, H)
+    ws_c = torch.empty(fhv.capture_workspace(d, mesh.n_tri), dtype=torch.uint8, device="cuda")
+    ws_k = torch.empty(fhv.compact_workspace(d, cap), dtype=torch.uint8, device="cuda")
+    vs = fhv.views_struct(views)
+
+    def step():
+        fhv.capture(dm, d, lists, ws_c)
+        fhv.compact(lists, d, pofa, ws_k)
+        fhv.splat(pofa, d, views, imgs, vs)
+
+    for _ in range(args.warmup):
+        step()
+    fhv.profile_begin()
+    t0 = time.perf_counter()
+    ms = timed(torch, step, args.steps)
+    wall = time.perf_counter() - t0
+    prof = fhv.profile_end()
+    assert int(lists.counter.item()) == F
+    n_occ = int(pofa.n_occ.item())
+    algo = algorithmic_bytes(F, n_occ, mesh.n_tri, 8 ** L, V, W * H, key_bytes=8)
+    kernels = kernel_table(prof, algo)
+    stage = lambda pre: sum(kernels[k]["avg_ms"] * kernels[k]["launches"] / args.steps
+                            for k in kernels if k.startswith(pre))
+    cs_bytes = sum(algo[k] for k in algo if k.startswith(("compact.", "splat.")))
+    out = {
+        "metric": "fragments captured/s; 1080p novel views/s; learned-fill vs plain-splat PSNR",
+        "value": F / (ms * 1e-3), "unit": "fragments/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "large pofa: 5M-tri procedural scene (seed 0, 20k objects), octree depth 11, "
+                               "16 x 3840x2160 splats 22.5 deg apart",
+                   "n_tri": mesh.n_tri, "levels": L, "fragments": F, "occupied_octants": n_occ,
+                   "views": V, "view_size": [W, H]},
+        "views_per_s_4k": V / (ms * 1e-3),
+        "stage_ms": {"capture": stage("capture."), "compact": stage("compact."), "splat": stage("splat.")},
+        "compact_gbs": sum(algo[k] for k in algo if k.startswith("compact.")) / (stage("compact.") * 1e-3) / 1e9,
+        "compact_splat_hbm_frac": cs_bytes / ((stage("compact.") + stage("splat.")) * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "kernels": kernels,
+        "roofline": hbm_roofline(kernels),
+        "wall_s_timed": wall,
+        "host": host_info(),
+        "device": torch.cuda.get_device_name(0),
+    }
+    if not args.no_cpu_baseline:
+        # the oracle cannot hold 8^11 list heads: it captures the keys of one
+        # level-3 sub-cube (8^8 keys) from the triangles whose snapped
+        # bounding box meets that sub-cube, and compacts them
+        import oracle
+        oracle.lib()
+        G = 2 ** (L + 8)
+        sh = L + 8 - 3
+        g = np.minimum(np.floor(mesh.pos.astype(np.float64) * G), G - 1).astype(np.int64)
+        tg = g[mesh.tri]                                   # [nt, 3, 3]
+        lo_c, hi_c = tg.min(axis=1) >> sh, tg.max(axis=1) >> sh
+        top = g[mesh.tri[0, 0]] >> sh
+        sel = np.all((lo_c <= top) & (hi_c >= top), axis=1)
+        sub = scenes.Mesh(mesh.pos, mesh.rgba, mesh.tri[sel], mesh.obj[sel])
+        span = 8 ** (L - 3)
+        key_lo = oracle.morton3(int(top[0]), int(top[1]), int(top[2]), 3) * span
+        n, t_all = 0, 0.0
+        while t_all < 10.0:
+            t1 = time.perf_counter()
+            oh, op, Fs = oracle.capture_pofl_range(sub, L, key_lo, key_lo + span, 64 << 20)
+            oracle.compact(oh, op, Fs)
+            t_all += time.perf_counter() - t1
+            n += 1
+        out["cpu_baseline"] = {"value": Fs * n / t_all, "unit": "fragments/s", "cores": 1, "kind": "oracle",
+                               "sample": f"capture and compaction of one level-3 sub-cube (8^8 keys, {Fs} "
+                                         f"fragments) from the {int(sel.sum())} triangles meeting it, {n} "
+                                         f"runs, {t_all:.1f} s on one core"}
+    return out
+
+
+WORKLOADS = {"pofl200k": None, "batch64": bench_batch64, "large5m": bench_large5m}
+DEFAULT_STEPS = {"pofl200k": (50, 5), "batch64": (10, 2), "large5m": (4, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="pofl200k",
+                    help="pofl200k (default): 200k triangles, depth 9, 3 x 1080p views + fill; "
+                         "batch64: 64 scenes x 8 views at 720p in one graph; "
+                         "large5m: 5M triangles, depth 11, 16 x 4K views")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-train", action="store_true", help="skip the learned-fill training report")
     ap.add_argument("--copy-mib", type=int, default=256,
@@ -222,11 +451,17 @@ def main():
         print("bench.py measures one GPU: this path runs on a single MI355X; "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    ds, dw = DEFAULT_STEPS[args.workload]
+    args.steps = ds if args.steps is None else args.steps
+    args.warmup = dw if args.warmup is None else args.warmup
 
     import torch
     from paper_2211_15460_amd import fhv, scenes
 
     torch.cuda.set_device(0)
+    if WORKLOADS[args.workload] is not None:
+        print(json.dumps(WORKLOADS[args.workload](args, torch, fhv, scenes)), flush=True)
+        return
     mesh = scenes.pofl_scene(SEED, N_TRI)
     views = [scenes.cube_view(th, LEVELS, W_OUT, H_OUT) for th in THETAS]
     d = fhv.desc(fhv.FHV_POFL, levels=LEVELS)

@@ -330,6 +330,12 @@ def pofl_scene(seed: int = 0, n_tri: int = 200_000) -> Mesh:
     return cube_scene(n_tri, seed)
 
 
+def large_scene(seed: int = 0) -> Mesh:
+    """5M triangles in 20,000 objects (octree depth 11): object scales
+    log-uniform in [0.012, 0.046] give about 0.9e9 fragments."""
+    return cube_scene(5_000_000, seed, scale_range=(0.012, 0.046), n_objects=20_000)
+
+
 def batched_scenes(seed: int = 0, n_scenes: int = 64) -> list[Mesh]:
     """n_scenes procedural scenes with triangle counts log-uniform in [1e3, 5e5]."""
     rng = SplitMix64(seed ^ 0x5CE7E5)

@@ -134,3 +134,100 @@ def test_splat_decodes_keys_above_32_bits(F, orc):
     assert ocov.sum() > 0
     assert np.array_equal(img.cov.cpu().numpy(), ocov)
     assert np.array_equal(u32(img.rgba), orgba)
+
+
+def subcube_triangles(mesh, levels, top):
+    """Triangles whose snapped bounding box meets level-3 sub-cube `top`
+    (integer xyz): no other triangle can put a fragment there, since
+    interpolated positions stay within the vertices' range per axis."""
+    G = 2 ** (levels + 8)
+    sh = levels + 8 - 3
+    g = np.minimum(np.floor(mesh.pos.astype(np.float64) * G), G - 1).astype(np.int64)
+    tg = g[mesh.tri]
+    lo, hi = tg.min(axis=1) >> sh, tg.max(axis=1) >> sh
+    sel = np.all((lo <= top) & (hi >= top), axis=1)
+    return S.Mesh(mesh.pos, mesh.rgba, mesh.tri[sel], mesh.obj[sel]), g
+
+
+@pytest.mark.slow
+def test_large_scene_full_size(F, orc):
+    """The 5M-triangle depth-11 workload at full size (about 0.9e9
+    fragments): invariants over the whole result on the device, records and
+    table rows of two level-3 sub-cubes bit for bit against the oracle, and
+    two of the 16 4K views checked against the oracle's splat of those
+    sub-cubes' fragments (a pixel they cover is covered, never farther than
+    their nearest fragment, and identical where the winner is one of
+    them)."""
+    import torch
+    L = 11
+    mesh = S.large_scene(0)
+    d = F.desc(F.FHV_POFL, levels=L)
+    dm = F.to_device(mesh)
+    head = torch.empty(8 ** L, dtype=torch.int32, device="cuda")
+    mk = lambda cap: F.Lists(head, torch.empty((max(cap, 1), 4), dtype=torch.int32, device="cuda"),
+                             torch.empty(max(cap, 1), dtype=torch.int64, device="cuda"),
+                             torch.zeros(1, dtype=torch.int64, device="cuda"), cap)
+    probe = mk(1 << 16)
+    F.capture(dm, d, probe)
+    torch.cuda.synchronize()
+    Fn = int(probe.counter.item())
+    del probe
+    print(f"large scene: {mesh.n_tri} triangles, {Fn} fragments", flush=True)
+    assert 5e8 < Fn < 2 ** 32 - 1
+    lists = mk(Fn)
+    F.capture(dm, d, lists)
+    pofa = F.alloc_pofa(Fn)
+    F.compact(lists, d, pofa)
+    views = [S.cube_view(22.5 * v, L, 3840, 2160) for v in range(16)]
+    img = F.splat(pofa, d, views)
+    torch.cuda.synchronize()
+    assert int(lists.counter.item()) == Fn
+    n_occ = int(pofa.n_occ.item())
+    tk = pofa.oct_key[:n_occ]
+    tc = pofa.oct_cnt[:n_occ].to(torch.int64) & 0xFFFFFFFF
+    to = pofa.oct_off[:n_occ].to(torch.int64) & 0xFFFFFFFF
+    assert int(tc.sum()) == Fn and int(pofa.n_frag.item()) == Fn
+    assert bool((tk[1:] > tk[:-1]).all()) and int(tk[0]) >= 0 and int(tk[-1]) < 8 ** L
+    assert torch.equal(to, torch.cumsum(tc, 0) - tc)
+    rank = torch.repeat_interleave(torch.arange(n_occ, device="cuda"), tc)
+    assert torch.equal(pofa.frag[:Fn, 3].to(torch.int64) & 0xFFFFFFFF, rank)
+    del rank
+    keys = lists.keys[:Fn]
+    assert int(keys.sum()) == int((tk * tc).sum())
+    assert int((keys * keys).sum()) == int((tk * tk * tc).sum())     # both wrap mod 2^64
+    print("invariants hold", flush=True)
+
+    span = 8 ** (L - 3)
+    zb = img.zbuf.cpu().numpy().view(np.uint64)
+    n_mine = 0
+    for v in (0, mesh.n_vert // 2):
+        g0 = np.minimum(np.floor(mesh.pos[v].astype(np.float64) * 2 ** (L + 8)), 2 ** (L + 8) - 1).astype(np.int64)
+        top = g0 >> (L + 8 - 3)
+        sub, _ = subcube_triangles(mesh, L, top)
+        lo = orc.morton3(int(top[0]), int(top[1]), int(top[2]), 3) * span
+        oh, op, oF = orc.capture_pofl_range(sub, L, lo, lo + span, 1 << 24)
+        assert 0 < oF <= 1 << 24
+        o = orc.compact(oh, op, oF)
+        rows = torch.nonzero((tk >= lo) & (tk < lo + span)).flatten()
+        r0 = int(rows[0])
+        assert rows.numel() == o["key"].size and int(rows[-1]) == r0 + rows.numel() - 1
+        assert np.array_equal(u64(tk[rows]) - np.uint64(lo), o["key"])
+        assert np.array_equal(tc[rows].cpu().numpy().astype(np.uint32), o["cnt"])
+        f0 = int(to[r0])
+        seg = u32(pofa.frag[f0:f0 + oF])
+        assert np.array_equal(seg[:, :3], o["frag"][:, :3])
+        assert np.array_equal(seg[:, 3], o["frag"][:, 3] + np.uint32(r0))
+        print(f"sub-cube {top.tolist()}: {oF} fragments from {sub.tri.shape[0]} triangles match", flush=True)
+        for vi in (0, 5):
+            orgba, odepth, ocov = orc.splat(1, o["key"] + np.uint64(lo), o["frag"], [views[vi]], levels=L)
+            cov = ocov[0] > 0
+            gz = zb[vi]
+            assert np.all(img.cov[vi].cpu().numpy()[cov] == 1)
+            gd = (gz >> np.uint64(32)).astype(np.uint32).view(np.float32)
+            assert np.all(gd[cov] <= odepth[0][cov])
+            gid = (gz & np.uint64(0xFFFFFFFF)).astype(np.int64)
+            mine = cov & (gid >= f0) & (gid < f0 + oF)
+            n_mine += int(mine.sum())
+            assert np.array_equal(gd[mine].view(np.uint32), odepth[0][mine].view(np.uint32))
+            assert np.array_equal(u32(img.rgba[vi])[mine], orgba[0][mine])
+    assert n_mine > 0      # some checked pixel is won by a sub-cube fragment
