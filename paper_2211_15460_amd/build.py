@@ -22,6 +22,10 @@ FLAGS = [
     # no packed fp32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-fvisibility=hidden", "-Wall", "-Wno-unused-result",
+    # matrix-core results in ordinary vector registers: keeps the loop-carried
+    # accumulators of the convolution kernels in place instead of copying
+    # them between register files every iteration
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
 ]
 
 

@@ -71,68 +71,156 @@ struct ConvArgs {
     uint32_t Cin, Cout, T, mode, relu;
 };
 
-// Wave tile 32 pixels x 32 channels (2 x 2 MFMA 16x16x32), workgroup = 4
-// waves along x: 128 pixels of one row x 32 output channels.
+// Buffer resource over `bytes` bytes at p (raw, unswizzled): loads at an
+// offset at or beyond `bytes` return zeros, which is how out-of-image taps
+// and channels past the end read as zero padding without branches.
+constexpr uint32_t kOob = 0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ u32x4 bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+}
+
+// Wave tile (16 MI) pixels of one row x (16 NJ) output channels, MI x NJ
+// MFMA 16x16x32 tiles; a workgroup is 4 waves side by side along the row.
+// The K loop runs over (tap, 32-channel chunk) pairs. Per tap, the source
+// row is wave-uniform and becomes a buffer resource (empty when the row is
+// outside the image); per lane only the column offset and its validity
+// change. The operands of the next chunk are loaded before the matrix
+// products of the current one. kSmall: 8 input channels, where a 32-wide
+// K chunk spans four taps (one per lane group).
+template <int kMode, int MI, int NJ, bool kSmall>
 __global__ void __launch_bounds__(kBlock) k_conv(ConvArgs a)
 {
+    constexpr int WX = 16 * MI;
     const int lane = __lane_id(), wv = threadIdx.x / kWave;
     const int g = lane >> 4, l16 = lane & 15;
-    const uint32_t xtiles = (a.W + 127) / 128;
+    const uint32_t xtiles = (a.W + 4 * WX - 1) / (4 * WX);
     const uint32_t row = blockIdx.x / xtiles;
-    const uint32_t x0 = (blockIdx.x % xtiles) * 128 + wv * 32;
+    const uint32_t x0 = (blockIdx.x % xtiles) * (4 * WX) + wv * WX;
     if (x0 >= a.W) return;   // whole wave past the row end
     const uint32_t n = row / a.H, y = row % a.H;
-    const uint32_t co0 = blockIdx.y * 32;
+    const uint32_t co0 = blockIdx.y * (16 * NJ);
     const uint32_t tapz = blockIdx.z;   // UP2: output sub-position
     const uint32_t K = a.T * a.Cin;
-    const uint16_t* wt = a.wt + (a.mode == MODE_UP2 ? (size_t)tapz * a.Cout * a.Cin : 0);
-    const uint32_t nchunk = (K + 31) / 32;
-    floatx4 acc[2][2];
+    const uint16_t* wt = a.wt + (kMode == MODE_UP2 ? (size_t)tapz * a.Cout * a.Cin : 0);
+    const __amdgpu_buffer_rsrc_t wr = rsrc(wt, a.Cout * K * 2);
+    const uint32_t nc = a.Cin >> 5;
+    const uint32_t total = kSmall ? (K + 31) / 32 : a.T * nc;
+    const uint32_t pix_b = a.in_cs * 2;   // bytes per input pixel
+    uint32_t wo[NJ];                      // weight row offsets (bytes)
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < NJ; ++j) {
+        const uint32_t co = co0 + 16 * j + l16;
+        wo[j] = co < a.Cout ? (co * K + g * 8) * 2 : kOob;
+    }
+    // input rows of the grid the operand is read from
+    const uint32_t in_w = kMode == MODE_GATHER4 ? 2 * a.W : a.W;
+    const uint32_t in_h = kMode == MODE_GATHER4 ? 2 * a.H : a.H;
+    uint32_t xo[MI];   // per-lane column offsets (bytes) before the tap shift
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (uint32_t c = 0; c < nchunk; ++c) {
-        const uint32_t k = c * 32 + g * 8;
-        const bool kok = k < K;
-        const uint32_t tap = kok ? k / a.Cin : 0, ci = kok ? k % a.Cin : 0;
-        u32x4 av[2], bv[2];
+    for (int i = 0; i < MI; ++i) {
+        const uint32_t x = x0 + 16 * i + l16;
+        xo[i] = (kMode == MODE_GATHER4 ? 2 * x : x) * pix_b + g * 16;
+    }
+    uint32_t ltap = 0, lcc = 0;   // next (tap, chunk) to load
+    auto load = [&](u32x4 (&av)[MI], u32x4 (&bv)[NJ]) {
+        if (kSmall) {
+            // 8 channels: lane group g reads tap 4 * chunk + g, all channels
+            const uint32_t k = lcc * 32 + g * 8;
+            const bool kok = k < K;
+            const uint32_t tap = kok ? k >> 3 : 0;
+            const uint32_t dy = (tap * 11) >> 5, dx = tap - 3 * dy;   // tap / 3, tap % 3 for tap < 9
+            const int ys = (int)y + (int)dy - 1;
+            const bool rok = kok && ys >= 0 && ys < (int)a.H;
+            const uint16_t* rp = a.in + ((size_t)n * a.H + (uint32_t)(rok ? ys : 0)) * a.W * a.in_cs;
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const uint32_t x = x0 + 16 * i + l16;
-            bool ok = kok && x < a.W;
-            size_t src = 0;
-            if (a.mode == MODE_SAME3) {
-                const int ys = (int)y + (int)(tap / 3) - 1, xs = (int)x + (int)(tap % 3) - 1;
-                ok = ok && ys >= 0 && ys < (int)a.H && xs >= 0 && xs < (int)a.W;
-                src = ((size_t)n * a.H + (uint32_t)ys) * a.W + (uint32_t)xs;
-            } else if (a.mode == MODE_GATHER4) {
-                const uint32_t ys = 2 * y + (tap >> 1), xs = 2 * x + (tap & 1);
-                src = ((size_t)n * 2 * a.H + ys) * (2 * (size_t)a.W) + xs;
-            } else {
-                src = (size_t)row * a.W + x;
+            for (int i = 0; i < MI; ++i) {
+                const int xs = (int)(x0 + 16 * i + l16) + (int)dx - 1;
+                const bool ok = rok && xs >= 0 && xs < (int)a.W;
+                av[i] = ok ? *(const u32x4*)(rp + (uint32_t)xs * a.in_cs) : u32x4{0u, 0u, 0u, 0u};
             }
-            av[i] = ok ? *(const u32x4*)(a.in + src * a.in_cs + ci) : u32x4{0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) bv[j] = bload(wr, kok ? wo[j] - g * 16 + k * 2 : kOob, 0);
+            ++lcc;
+            return;
+        }
+        const uint32_t tap = ltap, cb = lcc * 64;   // chunk byte offset
+        if (++lcc == nc) {
+            lcc = 0;
+            ++ltap;
+        }
+        uint32_t ys, dxb = 0;
+        bool rok = true;
+        uint32_t lo_ok = 0, hi_ok = 0;   // which shifted columns stay inside
+        if (kMode == MODE_SAME3) {
+            const uint32_t dy = (tap * 11) >> 5, dx = tap - 3 * dy;
+            const int yy = (int)y + (int)dy - 1;
+            rok = yy >= 0 && yy < (int)a.H;
+            ys = rok ? (uint32_t)yy : 0;
+            dxb = dx * pix_b;
+            lo_ok = dx == 0;
+            hi_ok = dx == 2;
+        } else if (kMode == MODE_GATHER4) {
+            ys = 2 * y + (tap >> 1);
+            dxb = (tap & 1) * pix_b;
+        } else {
+            ys = y;
+        }
+        rok = rok && ys < in_h;
+        const size_t rbase = ((size_t)n * in_h + (rok ? ys : 0)) * in_w * a.in_cs;
+        const __amdgpu_buffer_rsrc_t ir = rsrc(a.in + rbase, rok ? in_w * pix_b : 0u);
+#pragma unroll
+        for (int i = 0; i < MI; ++i) {
+            const uint32_t x = x0 + 16 * i + l16;
+            bool ok = x < a.W;
+            if (kMode == MODE_SAME3) {
+                // column x + dx - 1: invalid left of 0 (dx = 0, x = 0) and
+                // right of W - 1 (dx = 2, x = W - 1)
+                ok = ok && !(lo_ok && x == 0) && !(hi_ok && x + 1 >= a.W);
+            }
+            const uint32_t off = kMode == MODE_SAME3 ? xo[i] + dxb - pix_b : xo[i] + dxb;
+            av[i] = bload(ir, ok ? off : kOob, cb);
         }
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const uint32_t co = co0 + 16 * j + l16;
-            bv[j] = (kok && co < a.Cout) ? *(const u32x4*)(wt + (size_t)co * K + k) : u32x4{0u, 0u, 0u, 0u};
-        }
+        for (int j = 0; j < NJ; ++j) bv[j] = bload(wr, wo[j], (tap * a.Cin) * 2 + cb);
+    };
+    floatx4 acc[MI][NJ];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < NJ; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    auto mma = [&](const u32x4 (&av)[MI], const u32x4 (&bv)[NJ]) {
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                     __builtin_bit_cast(bf16x8, av[i]), __builtin_bit_cast(bf16x8, bv[j]), acc[i][j], 0, 0, 0);
+    };
+    // Loads run one chunk ahead without conditions: the one past the end
+    // reads in-range memory or zeros (buffer range checks) and is not used.
+    u32x4 a0[MI], b0[NJ], a1[MI], b1[NJ];
+    load(a0, b0);
+    for (uint32_t it = 0; it + 2 <= total; it += 2) {
+        load(a1, b1);
+        mma(a0, b0);
+        load(a0, b0);
+        mma(a1, b1);
     }
+    if (total & 1) mma(a0, b0);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < NJ; ++j) {
         const uint32_t co = co0 + 16 * j + l16;
         if (co >= a.Cout) continue;
         const float b = a.bias ? a.bias[co] : 0.0f;
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < MI; ++i)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const uint32_t x = x0 + 16 * i + 4 * g + r;
@@ -140,11 +228,133 @@ __global__ void __launch_bounds__(kBlock) k_conv(ConvArgs a)
                 float v = acc[i][j][r] + b;
                 if (a.relu) v = v > 0.0f ? v : 0.0f;
                 size_t dst;
-                if (a.mode == MODE_UP2)
+                if (kMode == MODE_UP2)
                     dst = ((size_t)n * 2 * a.H + 2 * y + (tapz >> 1)) * (2 * (size_t)a.W) + 2 * x + (tapz & 1);
                 else
                     dst = (size_t)row * a.W + x;
                 a.out[dst * a.out_cs + co] = f2bf(v);
+            }
+    }
+}
+
+// 3x3 convolution (stride 1, zero padding 1) with Cin a multiple of 32.
+// A workgroup computes 2 output rows x 128 pixels x (16 NJ) channels; its
+// four waves take 64 pixels of one row each (4 x NJ MFMA tiles). Per
+// 32-channel chunk the input halo (4 rows x 130 pixels x 32 channels) is
+// staged once in LDS, zero outside the image, and every tap reads its A
+// operands from there; pixels are padded to 40 bf16 (80 B) so that 16
+// consecutive pixels at one channel offset fall in distinct LDS banks.
+// Weights (shared by every workgroup) are read through the caches, one tap
+// ahead. The next chunk's halo is loaded into registers while the current
+// one is in use.
+template <int NJ>
+__global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
+{
+    constexpr int R = 2, TX = 128, HP = TX + 2, RP = R + 2, PITCH = 40;
+    constexpr int UNITS = RP * HP * 4;                 // 16-byte units of the halo
+    constexpr int UPT = (UNITS + kBlock - 1) / kBlock;
+    __shared__ __attribute__((aligned(16))) uint16_t tile[RP * HP * PITCH];
+    const int lane = __lane_id(), wv = threadIdx.x / kWave;
+    const int g = lane >> 4, l16 = lane & 15;
+    const uint32_t xtiles = (a.W + TX - 1) / TX, ytiles = (a.H + R - 1) / R;
+    const uint32_t n = blockIdx.x / (xtiles * ytiles);
+    const uint32_t rem = blockIdx.x % (xtiles * ytiles);
+    const uint32_t y0 = (rem / xtiles) * R, x0 = (rem % xtiles) * TX;
+    const uint32_t wr = (uint32_t)wv >> 1, wx = ((uint32_t)wv & 1u) * 64u;
+    const uint32_t co0 = blockIdx.y * (16 * NJ);
+    const uint32_t Cin = a.Cin, K = 9 * Cin, nc = Cin >> 5;
+    // input rows y0-1 .. y0+2 of image n, as far as they exist
+    const uint32_t r_first = y0 > 0 ? y0 - 1 : 0;
+    const uint32_t r_last = y0 + R < a.H ? y0 + R : a.H - 1;
+    const uint32_t row_b = a.W * a.in_cs * 2;
+    const __amdgpu_buffer_rsrc_t ir =
+        rsrc(a.in + ((size_t)n * a.H + r_first) * a.W * a.in_cs, (r_last - r_first + 1) * row_b);
+    const __amdgpu_buffer_rsrc_t wrs = rsrc(a.wt, a.Cout * K * 2);
+    uint32_t wo[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const uint32_t co = co0 + 16 * j + l16;
+        wo[j] = co < a.Cout ? (co * K + g * 8) * 2 : kOob;
+    }
+    // staging offsets (bytes, before the chunk offset) of this thread's units
+    uint32_t so[UPT];
+#pragma unroll
+    for (int u = 0; u < UPT; ++u) {
+        const uint32_t idx = threadIdx.x + u * kBlock;
+        const uint32_t r = idx / (HP * 4), px = (idx % (HP * 4)) >> 2, q = idx & 3;
+        const int ys = (int)y0 + (int)r - 1, xs = (int)x0 + (int)px - 1;
+        const bool ok = idx < (uint32_t)UNITS && ys >= 0 && ys < (int)a.H && xs >= 0 && xs < (int)a.W;
+        so[u] = ok ? ((uint32_t)ys - r_first) * row_b + (uint32_t)xs * a.in_cs * 2 + q * 16 : kOob;
+    }
+    u32x4 st[UPT];
+    auto gload = [&](uint32_t cc) {
+#pragma unroll
+        for (int u = 0; u < UPT; ++u) st[u] = bload(ir, so[u], cc * 64);
+    };
+    auto lds_put = [&]() {
+#pragma unroll
+        for (int u = 0; u < UPT; ++u) {
+            const uint32_t idx = threadIdx.x + u * kBlock;
+            if (idx < (uint32_t)UNITS) {
+                const uint32_t r = idx / (HP * 4), px = (idx % (HP * 4)) >> 2, q = idx & 3;
+                *(u32x4*)&tile[(r * HP + px) * PITCH + q * 8] = st[u];
+            }
+        }
+    };
+    floatx4 acc[4][NJ];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    gload(0);
+    lds_put();
+    __syncthreads();
+    for (uint32_t cc = 0; cc < nc; ++cc) {
+        if (cc + 1 < nc) gload(cc + 1);
+        u32x4 bv[2][NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) bv[0][j] = bload(wrs, wo[j], cc * 64);
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int cur = tap & 1;
+            if (tap + 1 < 9) {
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) bv[cur ^ 1][j] = bload(wrs, wo[j], ((tap + 1) * Cin + cc * 32) * 2);
+            }
+            const int dy = tap / 3, dx = tap % 3;
+            u32x4 av[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                av[i] = *(const u32x4*)&tile[((wr + dy) * HP + wx + 16 * i + l16 + dx) * PITCH + g * 8];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < NJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(bf16x8, av[i]), __builtin_bit_cast(bf16x8, bv[cur][j]), acc[i][j], 0, 0, 0);
+        }
+        if (cc + 1 < nc) {
+            __syncthreads();
+            lds_put();
+            __syncthreads();
+        }
+    }
+    const uint32_t y = y0 + wr;
+    if (y >= a.H) return;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const uint32_t co = co0 + 16 * j + l16;
+        if (co >= a.Cout) continue;
+        const float b = a.bias ? a.bias[co] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint32_t x = x0 + wx + 16 * i + 4 * g + r;
+                if (x >= a.W) continue;
+                float v = acc[i][j][r] + b;
+                if (a.relu) v = v > 0.0f ? v : 0.0f;
+                a.out[(((size_t)n * a.H + y) * a.W + x) * a.out_cs + co] = f2bf(v);
             }
     }
 }
@@ -653,9 +863,33 @@ hipError_t conv(const uint16_t* in, uint32_t in_cs, const uint16_t* wt, const fl
     a.T = mode == MODE_SAME3 ? 9 : (mode == MODE_GATHER4 ? 4 : 1);
     a.mode = (uint32_t)mode;
     a.relu = relu ? 1u : 0u;
-    const uint32_t xt = (W + 127) / 128;
+    const unsigned gz = mode == MODE_UP2 ? 4 : 1;
     ProfScope ps(cur_dev(), "fill.conv", s);
-    k_conv<<<dim3(N * H * xt, (Cout + 31) / 32, mode == MODE_UP2 ? 4 : 1), dim3(kBlock), 0, s>>>(a);
+    const dim3 blk(kBlock);
+    const uint32_t rows = N * H;
+    if (Cin == 8) {
+        if (mode != MODE_SAME3) return hipErrorInvalidValue;
+        k_conv<MODE_SAME3, 2, 2, true><<<dim3(rows * ((W + 127) / 128), (Cout + 31) / 32, gz), blk, 0, s>>>(a);
+        return hipGetLastError();
+    }
+    if (Cin % 32 != 0) return hipErrorInvalidValue;
+    const dim3 g32(rows * ((W + 255) / 256), (Cout + 31) / 32, gz), g64(rows * ((W + 255) / 256), (Cout + 63) / 64, gz);
+    const bool narrow = Cout <= 32;
+    const unsigned tiles3 = (unsigned)(N * ((H + 1) / 2) * ((W + 127) / 128));
+    switch (mode) {
+    case MODE_SAME3:
+        if (narrow) k_conv3<2><<<dim3(tiles3, (Cout + 31) / 32), blk, 0, s>>>(a);
+        else k_conv3<4><<<dim3(tiles3, (Cout + 63) / 64), blk, 0, s>>>(a);
+        break;
+    case MODE_UP2:
+        if (narrow) k_conv<MODE_UP2, 4, 2, false><<<g32, blk, 0, s>>>(a);
+        else k_conv<MODE_UP2, 4, 4, false><<<g64, blk, 0, s>>>(a);
+        break;
+    default:
+        if (narrow) k_conv<MODE_GATHER4, 4, 2, false><<<g32, blk, 0, s>>>(a);
+        else k_conv<MODE_GATHER4, 4, 4, false><<<g64, blk, 0, s>>>(a);
+        break;
+    }
     return hipGetLastError();
 }
 
