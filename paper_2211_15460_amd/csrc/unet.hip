@@ -86,6 +86,43 @@ __device__ __forceinline__ u32x4 bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, 
     return __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
 }
 
+// Epilogue of a wave's (16 MI)-pixel x (16 NJ)-channel result tile: bias,
+// ReLU and bf16 rounding, then a pass through the wave's own LDS region
+// (pixel-major, pitch 16 NJ + 8) so that each lane stores whole 16-byte
+// runs of 8 channels of one pixel. dst(p) is the first output channel of
+// the tile's pixel p, or null when that pixel is outside the output.
+template <int MI, int NJ, class Dst>
+__device__ __forceinline__ void store_tile(uint16_t* __restrict__ lds, const floatx4 (&acc)[MI][NJ],
+                                           const float* __restrict__ bias, uint32_t co0, uint32_t Cout,
+                                           bool relu, Dst dst)
+{
+    constexpr int P = 16 * NJ + 8, CH = 2 * NJ;
+    const int lane = __lane_id(), g = lane >> 4, l16 = lane & 15;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const uint32_t co = co0 + 16 * j + l16;
+        const float b = (bias && co < Cout) ? bias[co] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float v = acc[i][j][r] + b;
+                if (relu) v = v > 0.0f ? v : 0.0f;
+                lds[(16 * i + 4 * g + r) * P + 16 * j + l16] = f2bf(v);
+            }
+    }
+    // the wave reads back what its own lanes wrote
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int t = 0; t < (16 * MI * CH) / kWave; ++t) {
+        const int id = lane + kWave * t, px = id / CH, q = id % CH;
+        const u32x4 v = *(const u32x4*)&lds[px * P + q * 8];
+        uint16_t* d = dst(px);
+        if (d && co0 + 8 * q < Cout) *(u32x4*)(d + 8 * q) = v;
+    }
+}
+
 // Wave tile (16 MI) pixels of one row x (16 NJ) output channels, MI x NJ
 // MFMA 16x16x32 tiles; a workgroup is 4 waves side by side along the row.
 // The K loop runs over (tap, 32-channel chunk) pairs. Per tap, the source
@@ -98,6 +135,7 @@ template <int kMode, int MI, int NJ, bool kSmall>
 __global__ void __launch_bounds__(kBlock) k_conv(ConvArgs a)
 {
     constexpr int WX = 16 * MI;
+    __shared__ __attribute__((aligned(16))) uint16_t epi[kBlock / kWave][16 * MI * (16 * NJ + 8)];
     const int lane = __lane_id(), wv = threadIdx.x / kWave;
     const int g = lane >> 4, l16 = lane & 15;
     const uint32_t xtiles = (a.W + 4 * WX - 1) / (4 * WX);
@@ -214,27 +252,16 @@ __global__ void __launch_bounds__(kBlock) k_conv(ConvArgs a)
         mma(a1, b1);
     }
     if (total & 1) mma(a0, b0);
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        const uint32_t co = co0 + 16 * j + l16;
-        if (co >= a.Cout) continue;
-        const float b = a.bias ? a.bias[co] : 0.0f;
-#pragma unroll
-        for (int i = 0; i < MI; ++i)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const uint32_t x = x0 + 16 * i + 4 * g + r;
-                if (x >= a.W) continue;
-                float v = acc[i][j][r] + b;
-                if (a.relu) v = v > 0.0f ? v : 0.0f;
-                size_t dst;
-                if (kMode == MODE_UP2)
-                    dst = ((size_t)n * 2 * a.H + 2 * y + (tapz >> 1)) * (2 * (size_t)a.W) + 2 * x + (tapz & 1);
-                else
-                    dst = (size_t)row * a.W + x;
-                a.out[dst * a.out_cs + co] = f2bf(v);
-            }
-    }
+    store_tile<MI, NJ>(epi[wv], acc, a.bias, co0, a.Cout, a.relu != 0, [&](int px) -> uint16_t* {
+        const uint32_t x = x0 + px;
+        if (x >= a.W) return nullptr;
+        size_t dst;
+        if (kMode == MODE_UP2)
+            dst = ((size_t)n * 2 * a.H + 2 * y + (tapz >> 1)) * (2 * (size_t)a.W) + 2 * x + (tapz & 1);
+        else
+            dst = (size_t)row * a.W + x;
+        return a.out + dst * a.out_cs + co0;
+    });
 }
 
 // 3x3 convolution (stride 1, zero padding 1) with Cin a multiple of 32.
@@ -339,24 +366,17 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
             __syncthreads();
         }
     }
+    // the halo tile is free once every wave is done with it; each wave then
+    // uses its own part of it for the epilogue
+    static_assert(4 * 64 * (16 * NJ + 8) <= RP * HP * PITCH, "epilogue fits the halo tile");
+    __syncthreads();
     const uint32_t y = y0 + wr;
-    if (y >= a.H) return;
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        const uint32_t co = co0 + 16 * j + l16;
-        if (co >= a.Cout) continue;
-        const float b = a.bias ? a.bias[co] : 0.0f;
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const uint32_t x = x0 + wx + 16 * i + 4 * g + r;
-                if (x >= a.W) continue;
-                float v = acc[i][j][r] + b;
-                if (a.relu) v = v > 0.0f ? v : 0.0f;
-                a.out[(((size_t)n * a.H + y) * a.W + x) * a.out_cs + co] = f2bf(v);
-            }
-    }
+    store_tile<4, NJ>(tile + wv * 64 * (16 * NJ + 8), acc, a.bias, co0, a.Cout, a.relu != 0,
+                      [&](int px) -> uint16_t* {
+                          const uint32_t x = x0 + wx + px;
+                          if (y >= a.H || x >= a.W) return nullptr;
+                          return a.out + (((size_t)n * a.H + y) * a.W + x) * a.out_cs + co0;
+                      });
 }
 
 struct WgradArgs {
@@ -530,22 +550,41 @@ __global__ void __launch_bounds__(kBlock)
 k_maxpool(const uint16_t* __restrict__ in, uint32_t in_cs, uint32_t N, uint32_t H, uint32_t W,
           uint32_t C, uint16_t* __restrict__ out)
 {
-    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x, tot = (size_t)N * H * W * C;
+    // one thread per 8 channels of one pooled pixel (C is a multiple of 8)
+    const uint32_t G = C >> 3;
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x, tot = (size_t)N * H * W * G;
     if (i >= tot) return;
-    const uint32_t c = (uint32_t)(i % C);
-    const size_t p = i / C;
+    const uint32_t c = (uint32_t)(i % G) * 8;
+    const size_t p = i / G;
     const uint32_t x = (uint32_t)(p % W), y = (uint32_t)((p / W) % H), n = (uint32_t)(p / ((size_t)W * H));
-    float m = -INFINITY;
-    uint16_t best = 0;
+    u32x4 v[4];
+#pragma unroll
     for (int k = 0; k < 4; ++k) {
         const size_t s = ((size_t)n * 2 * H + 2 * y + (k >> 1)) * (2 * (size_t)W) + 2 * x + (k & 1);
-        const uint16_t v = in[s * in_cs + c];
-        if (bf2f(v) > m) {
-            m = bf2f(v);
-            best = v;
-        }
+        v[k] = *(const u32x4*)(in + s * in_cs + c);
     }
-    out[p * C + c] = best;
+    u32x4 o;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        uint32_t word = 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            // first window position holding the largest value
+            float m = -INFINITY;
+            uint32_t best = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t b = (v[k][w] >> (16 * h)) & 0xFFFFu;
+                if (bf2f((uint16_t)b) > m) {
+                    m = bf2f((uint16_t)b);
+                    best = b;
+                }
+            }
+            word |= best << (16 * h);
+        }
+        o[w] = word;
+    }
+    *(u32x4*)(out + p * C + c) = o;
 }
 
 // Gradient w.r.t. the pooled tensor's source: the pooled gradient goes to
@@ -973,7 +1012,7 @@ hipError_t forward(const Net& net, const float* th, const Bufs& b, uint32_t N, u
         const uint32_t o1_cs = l + 1 < L ? 2 * Cl : Cl;
         FHV_TRY(conv(b.e0[l], Cl, b.wt + a1.wf_off, th + a1.off_b, o1, o1_cs, N, Hl, Wl, Cl, Cl, MODE_SAME3, true, s));
         if (l + 1 < L) {
-            k_maxpool<<<blocks((size_t)N * (Hl / 2) * (Wl / 2) * Cl), dim3(kBlock), 0, s>>>(
+            k_maxpool<<<blocks((size_t)N * (Hl / 2) * (Wl / 2) * (Cl / 8)), dim3(kBlock), 0, s>>>(
                 o1, o1_cs, N, Hl / 2, Wl / 2, Cl, b.pool[l]);
             FHV_TRY(hipGetLastError());
             h = b.pool[l];
