@@ -92,13 +92,13 @@ def algorithmic_bytes(F: int, n_occ: int, n_tri: int, n_head: int, n_views: int,
     }
 
 
-# kernels behind each timed scope (POFL mode)
+# kernel-name prefixes behind each timed scope (POFL mode)
 SCOPE_KERNELS = {
-    "fill.conv": ["k_conv"],
-    "capture.reset": ["k_fill_u32"], "capture.setup": ["k_setup"], "capture.raster": ["k_raster<1>"],
-    "compact.hist": ["k_hist"], "compact.scatter": ["k_scatter"],
-    "compact.brick": ["k_brick_wave", "k_brick"], "splat.zclear": ["k_zclear"],
-    "splat.splat": ["k_splat<1>"], "splat.resolve": ["k_resolve"],
+    "fill.conv": ("k_conv",),
+    "capture.setup": ("k_setup",), "capture.raster": ("k_raster",),
+    "compact.hist": ("k_hist",), "compact.scatter": ("k_scatter",),
+    "compact.brick": ("k_brick_wave", "k_brick"), "splat.zclear": ("k_zclear",),
+    "splat.splat": ("k_splat",), "splat.resolve": ("k_resolve",),
 }
 
 
@@ -112,20 +112,77 @@ def src_digest() -> str:
     return h.hexdigest()
 
 
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
+
+
 def measured_traffic(scope: str):
     """HBM bytes per launch of a scope from the committed rocprofv3 counter
     summary (profiles/traffic.json), or None when the kernels have changed
     since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path) or scope not in SCOPE_KERNELS:
+    if not os.path.exists(TRAFFIC_JSON):
         return None
-    t = json.load(open(path))
-    if t.get("src_sha256") != src_digest():
+    t = json.load(open(TRAFFIC_JSON))
+    if t.get("src_sha256") != src_digest() or scope not in t.get("scopes", {}):
         return None
-    ks = t["kernels"]
-    if not all(k in ks for k in SCOPE_KERNELS[scope]):
-        return None
-    return sum(ks[k]["read_bytes"] + ks[k]["write_bytes"] for k in SCOPE_KERNELS[scope])
+    sc = t["scopes"][scope]
+    return sc["read_bytes"] + sc["write_bytes"]
+
+
+def _scope_of(kernel: str):
+    for scope, prefixes in SCOPE_KERNELS.items():
+        if any(kernel.startswith(p) for p in prefixes):
+            return scope
+    return None
+
+
+def traffic_from(fetch_dir: str, write_dir: str, copy_mib: int) -> dict:
+    """Per-scope HBM bytes per launch from two rocprofv3 --pmc runs of this
+    benchmark (FETCH_SIZE, then WRITE_SIZE; --output-format csv), each
+    calibrated by what the counter reads for the plain device copy of
+    copy_mib MiB that the benchmark runs first. Uses the dispatches of the
+    last step (from the last triangle setup on); run with --no-train."""
+    import csv
+    import glob
+    import re
+
+    def load(d, counter):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not f:
+            raise SystemExit(f"no counter_collection.csv under {d}")
+        per = {}
+        for r in csv.DictReader(open(f[0])):
+            if r["Counter_Name"] != counter:
+                continue
+            did = int(r["Dispatch_Id"])
+            name = re.sub(r"^void ", "", r["Kernel_Name"])
+            name = re.sub(r"^(fhv::)?(nn::)?(\(anonymous namespace\)::)?", "", name)
+            nm, v = per.get(did, (name, 0.0))
+            per[did] = (nm, v + float(r["Counter_Value"]))
+        return [per[k] for k in sorted(per)]
+
+    out = {"src_sha256": src_digest(), "calibration": {}, "scopes": {}}
+    for counter, d, key in (("FETCH_SIZE", fetch_dir, "read_bytes"), ("WRITE_SIZE", write_dir, "write_bytes")):
+        rows = load(d, counter)
+        copies = [v for n, v in rows if "copyBuffer" in n or "copy" in n.lower()]
+        if not copies:
+            raise SystemExit("the calibration copy is missing from the trace")
+        scale = copy_mib * 1024.0 / max(copies[0], 1e-9)
+        out["calibration"][counter] = {"copy_kib": copies[0], "bytes_per_kib": scale * 1024.0}
+        last = max(i for i, (n, _) in enumerate(rows) if n.startswith("k_setup"))
+        start = last
+        while start > 0 and rows[start - 1][0].startswith(("k_fill_u32", "k_fill_u64")):
+            start -= 1
+        acc = {}
+        for n, v in rows[start:]:
+            sc = _scope_of(n)
+            if sc is None:
+                continue
+            b, c = acc.get(sc, (0.0, 0))
+            acc[sc] = (b + v * scale * 1024.0, c + 1)
+        for sc, (b, c) in acc.items():
+            ent = out["scopes"].setdefault(sc, {"launches_per_step": c})
+            ent[key] = b / c
+    return out
 
 
 def unet_flops_per_pixel(levels: int = 4, training: bool = False) -> float:
@@ -446,7 +503,15 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=256,
                     help="size of a plain device copy run once before the steps, so that "
                          "hardware byte counters can be calibrated against a known size")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic.json from two rocprofv3 --pmc runs of this "
+                         "benchmark (FETCH_SIZE, WRITE_SIZE; csv output) and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        t = traffic_from(args.traffic_from[0], args.traffic_from[1], args.copy_mib)
+        json.dump(t, open(TRAFFIC_JSON, "w"), indent=1)
+        print(json.dumps(t["scopes"]))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this path runs on a single MI355X; "
               "run with --gpus 1", file=sys.stderr)

@@ -139,12 +139,15 @@ __global__ void __launch_bounds__(kBlock) k_conv(ConvArgs a)
     const int lane = __lane_id(), wv = threadIdx.x / kWave;
     const int g = lane >> 4, l16 = lane & 15;
     const uint32_t xtiles = (a.W + 4 * WX - 1) / (4 * WX);
-    const uint32_t row = blockIdx.x / xtiles;
-    const uint32_t x0 = (blockIdx.x % xtiles) * (4 * WX) + wv * WX;
+    // UP2: the four output sub-positions of a tile are adjacent workgroups,
+    // so they share the input tile in cache and write neighbouring pixels
+    const uint32_t tapz = kMode == MODE_UP2 ? (blockIdx.x & 3u) : 0u;
+    const uint32_t bx = kMode == MODE_UP2 ? (blockIdx.x >> 2) : blockIdx.x;
+    const uint32_t row = bx / xtiles;
+    const uint32_t x0 = (bx % xtiles) * (4 * WX) + wv * WX;
     if (x0 >= a.W) return;   // whole wave past the row end
     const uint32_t n = row / a.H, y = row % a.H;
     const uint32_t co0 = blockIdx.y * (16 * NJ);
-    const uint32_t tapz = blockIdx.z;   // UP2: output sub-position
     const uint32_t K = a.T * a.Cin;
     const uint16_t* wt = a.wt + (kMode == MODE_UP2 ? (size_t)tapz * a.Cout * a.Cin : 0);
     const __amdgpu_buffer_rsrc_t wr = rsrc(wt, a.Cout * K * 2);
@@ -267,20 +270,23 @@ __global__ void __launch_bounds__(kBlock) k_conv(ConvArgs a)
 // 3x3 convolution (stride 1, zero padding 1) with Cin a multiple of 32.
 // A workgroup computes 2 output rows x 128 pixels x (16 NJ) channels; its
 // four waves take 64 pixels of one row each (4 x NJ MFMA tiles). Per
-// 32-channel chunk the input halo (4 rows x 130 pixels x 32 channels) is
-// staged once in LDS, zero outside the image, and every tap reads its A
-// operands from there; pixels are padded to 40 bf16 (80 B) so that 16
-// consecutive pixels at one channel offset fall in distinct LDS banks.
-// Weights (shared by every workgroup) are read through the caches, one tap
-// ahead. The next chunk's halo is loaded into registers while the current
-// one is in use.
+// 32-channel chunk, the input halo (4 rows x 130 pixels, zero outside the
+// image) and the chunk's weights of all nine taps are staged in LDS, so the
+// tap loop reads only LDS: the next tap's operands are read while the
+// current tap's matrix products run, and the next chunk's halo and weights
+// are loaded into registers meanwhile. Rows of 32 channels are padded to
+// 40 bf16 (80 B): 16 consecutive rows at one channel offset then fall in
+// distinct LDS banks.
 template <int NJ>
 __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
 {
-    constexpr int R = 2, TX = 128, HP = TX + 2, RP = R + 2, PITCH = 40;
-    constexpr int UNITS = RP * HP * 4;                 // 16-byte units of the halo
-    constexpr int UPT = (UNITS + kBlock - 1) / kBlock;
-    __shared__ __attribute__((aligned(16))) uint16_t tile[RP * HP * PITCH];
+    constexpr int R = 2, TX = 128, HP = TX + 2, RP = R + 2, PITCH = 40, TN = 16 * NJ;
+    constexpr int HU = RP * HP * 4, WU = 9 * TN * 4;     // 16-byte units: halo, weights
+    constexpr int HPT = (HU + kBlock - 1) / kBlock, WPT = (WU + kBlock - 1) / kBlock;
+    constexpr int HALO = RP * HP * PITCH;                // bf16 elements
+    __shared__ __attribute__((aligned(16))) uint16_t lds[HALO + 9 * TN * PITCH];
+    uint16_t* const tile = lds;
+    uint16_t* const wts = lds + HALO;
     const int lane = __lane_id(), wv = threadIdx.x / kWave;
     const int g = lane >> 4, l16 = lane & 15;
     const uint32_t xtiles = (a.W + TX - 1) / TX, ytiles = (a.H + R - 1) / R;
@@ -288,7 +294,7 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
     const uint32_t rem = blockIdx.x % (xtiles * ytiles);
     const uint32_t y0 = (rem / xtiles) * R, x0 = (rem % xtiles) * TX;
     const uint32_t wr = (uint32_t)wv >> 1, wx = ((uint32_t)wv & 1u) * 64u;
-    const uint32_t co0 = blockIdx.y * (16 * NJ);
+    const uint32_t co0 = blockIdx.y * TN;
     const uint32_t Cin = a.Cin, K = 9 * Cin, nc = Cin >> 5;
     // input rows y0-1 .. y0+2 of image n, as far as they exist
     const uint32_t r_first = y0 > 0 ? y0 - 1 : 0;
@@ -297,36 +303,48 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
     const __amdgpu_buffer_rsrc_t ir =
         rsrc(a.in + ((size_t)n * a.H + r_first) * a.W * a.in_cs, (r_last - r_first + 1) * row_b);
     const __amdgpu_buffer_rsrc_t wrs = rsrc(a.wt, a.Cout * K * 2);
-    uint32_t wo[NJ];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        const uint32_t co = co0 + 16 * j + l16;
-        wo[j] = co < a.Cout ? (co * K + g * 8) * 2 : kOob;
-    }
-    // staging offsets (bytes, before the chunk offset) of this thread's units
-    uint32_t so[UPT];
-#pragma unroll
-    for (int u = 0; u < UPT; ++u) {
+    // staging units of this thread (16 bytes each): global byte offsets
+    // (out-of-range offsets read zeros) and LDS element offsets, recomputed
+    // per chunk to keep registers for the operands
+    auto halo_unit = [&](int u, uint32_t* go, uint32_t* lo) {
         const uint32_t idx = threadIdx.x + u * kBlock;
         const uint32_t r = idx / (HP * 4), px = (idx % (HP * 4)) >> 2, q = idx & 3;
         const int ys = (int)y0 + (int)r - 1, xs = (int)x0 + (int)px - 1;
-        const bool ok = idx < (uint32_t)UNITS && ys >= 0 && ys < (int)a.H && xs >= 0 && xs < (int)a.W;
-        so[u] = ok ? ((uint32_t)ys - r_first) * row_b + (uint32_t)xs * a.in_cs * 2 + q * 16 : kOob;
-    }
-    u32x4 st[UPT];
+        const bool ok = idx < (uint32_t)HU && ys >= 0 && ys < (int)a.H && xs >= 0 && xs < (int)a.W;
+        *go = ok ? ((uint32_t)ys - r_first) * row_b + (uint32_t)xs * a.in_cs * 2 + q * 16 : kOob;
+        *lo = (r * HP + px) * PITCH + q * 8;
+        return idx < (uint32_t)HU;
+    };
+    auto wt_unit = [&](int u, uint32_t* go, uint32_t* lo) {
+        const uint32_t idx = threadIdx.x + u * kBlock;
+        const uint32_t tap = idx / (TN * 4), co = (idx % (TN * 4)) >> 2, q = idx & 3;
+        const bool ok = idx < (uint32_t)WU && co0 + co < a.Cout;
+        *go = ok ? ((co0 + co) * K + tap * Cin + q * 8) * 2 : kOob;
+        *lo = (tap * TN + co) * PITCH + q * 8;
+        return idx < (uint32_t)WU;
+    };
+    u32x4 hst[HPT], wst[WPT];
     auto gload = [&](uint32_t cc) {
+        uint32_t go, lo;
 #pragma unroll
-        for (int u = 0; u < UPT; ++u) st[u] = bload(ir, so[u], cc * 64);
+        for (int u = 0; u < HPT; ++u) {
+            halo_unit(u, &go, &lo);
+            hst[u] = bload(ir, go, cc * 64);
+        }
+#pragma unroll
+        for (int u = 0; u < WPT; ++u) {
+            wt_unit(u, &go, &lo);
+            wst[u] = bload(wrs, go, cc * 64);
+        }
     };
     auto lds_put = [&]() {
+        uint32_t go, lo;
 #pragma unroll
-        for (int u = 0; u < UPT; ++u) {
-            const uint32_t idx = threadIdx.x + u * kBlock;
-            if (idx < (uint32_t)UNITS) {
-                const uint32_t r = idx / (HP * 4), px = (idx % (HP * 4)) >> 2, q = idx & 3;
-                *(u32x4*)&tile[(r * HP + px) * PITCH + q * 8] = st[u];
-            }
-        }
+        for (int u = 0; u < HPT; ++u)
+            if (halo_unit(u, &go, &lo)) *(u32x4*)&tile[lo] = hst[u];
+#pragma unroll
+        for (int u = 0; u < WPT; ++u)
+            if (wt_unit(u, &go, &lo)) *(u32x4*)&wts[lo] = wst[u];
     };
     floatx4 acc[4][NJ];
 #pragma unroll
@@ -338,27 +356,29 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
     __syncthreads();
     for (uint32_t cc = 0; cc < nc; ++cc) {
         if (cc + 1 < nc) gload(cc + 1);
-        u32x4 bv[2][NJ];
+        u32x4 av[2][4], bv[2][NJ];
+        auto rd = [&](int tap, u32x4 (&A)[4], u32x4 (&B)[NJ]) {
+            const int dy = tap / 3, dx = tap % 3;
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) bv[0][j] = bload(wrs, wo[j], cc * 64);
+            for (int i = 0; i < 4; ++i)
+                A[i] = *(const u32x4*)&tile[((wr + dy) * HP + wx + 16 * i + l16 + dx) * PITCH + g * 8];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) B[j] = *(const u32x4*)&wts[(tap * TN + 16 * j + l16) * PITCH + g * 8];
+        };
+        rd(0, av[0], bv[0]);
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
             const int cur = tap & 1;
-            if (tap + 1 < 9) {
-#pragma unroll
-                for (int j = 0; j < NJ; ++j) bv[cur ^ 1][j] = bload(wrs, wo[j], ((tap + 1) * Cin + cc * 32) * 2);
-            }
-            const int dy = tap / 3, dx = tap % 3;
-            u32x4 av[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                av[i] = *(const u32x4*)&tile[((wr + dy) * HP + wx + 16 * i + l16 + dx) * PITCH + g * 8];
+            if (tap + 1 < 9) rd(tap + 1, av[cur ^ 1], bv[cur ^ 1]);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < NJ; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        __builtin_bit_cast(bf16x8, av[i]), __builtin_bit_cast(bf16x8, bv[cur][j]), acc[i][j], 0, 0, 0);
+                        __builtin_bit_cast(bf16x8, av[cur][i]), __builtin_bit_cast(bf16x8, bv[cur][j]), acc[i][j], 0, 0,
+                        0);
+            __builtin_amdgcn_sched_barrier(0);
         }
         if (cc + 1 < nc) {
             __syncthreads();
@@ -366,9 +386,9 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
             __syncthreads();
         }
     }
-    // the halo tile is free once every wave is done with it; each wave then
-    // uses its own part of it for the epilogue
-    static_assert(4 * 64 * (16 * NJ + 8) <= RP * HP * PITCH, "epilogue fits the halo tile");
+    // the staged tiles are free once every wave is done with them; each wave
+    // then uses its own part for the epilogue
+    static_assert(4 * 64 * (16 * NJ + 8) <= HALO, "epilogue fits the halo tile");
     __syncthreads();
     const uint32_t y = y0 + wr;
     store_tile<4, NJ>(tile + wv * 64 * (16 * NJ + 8), acc, a.bias, co0, a.Cout, a.relu != 0,
@@ -902,7 +922,7 @@ hipError_t conv(const uint16_t* in, uint32_t in_cs, const uint16_t* wt, const fl
     a.T = mode == MODE_SAME3 ? 9 : (mode == MODE_GATHER4 ? 4 : 1);
     a.mode = (uint32_t)mode;
     a.relu = relu ? 1u : 0u;
-    const unsigned gz = mode == MODE_UP2 ? 4 : 1;
+    const unsigned gz = 1, up = mode == MODE_UP2 ? 4 : 1;
     ProfScope ps(cur_dev(), "fill.conv", s);
     const dim3 blk(kBlock);
     const uint32_t rows = N * H;
@@ -912,7 +932,8 @@ hipError_t conv(const uint16_t* in, uint32_t in_cs, const uint16_t* wt, const fl
         return hipGetLastError();
     }
     if (Cin % 32 != 0) return hipErrorInvalidValue;
-    const dim3 g32(rows * ((W + 255) / 256), (Cout + 31) / 32, gz), g64(rows * ((W + 255) / 256), (Cout + 63) / 64, gz);
+    const dim3 g32(rows * ((W + 255) / 256) * up, (Cout + 31) / 32, gz),
+        g64(rows * ((W + 255) / 256) * up, (Cout + 63) / 64, gz);
     const bool narrow = Cout <= 32;
     const unsigned tiles3 = (unsigned)(N * ((H + 1) / 2) * ((W + 127) / 128));
     switch (mode) {
