@@ -280,7 +280,10 @@ __global__ void __launch_bounds__(kBlock) k_conv(ConvArgs a)
 template <int NJ>
 __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
 {
-    constexpr int R = 2, TX = 128, HP = TX + 2, RP = R + 2, PITCH = 40, TN = 16 * NJ;
+    constexpr int R = 2, TX = 128, HP = TX + 2, RP = R + 2, TN = 16 * NJ, PITCH = 40;
+    // element offset of 16-byte chunk q of staged row `row` (a pixel of the
+    // halo or an output channel of the weights)
+    auto loff = [](uint32_t row, uint32_t q) -> uint32_t { return row * PITCH + q * 8; };
     constexpr int HU = RP * HP * 4, WU = 9 * TN * 4;     // 16-byte units: halo, weights
     constexpr int HPT = (HU + kBlock - 1) / kBlock, WPT = (WU + kBlock - 1) / kBlock;
     constexpr int HALO = RP * HP * PITCH;                // bf16 elements
@@ -312,7 +315,7 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
         const int ys = (int)y0 + (int)r - 1, xs = (int)x0 + (int)px - 1;
         const bool ok = idx < (uint32_t)HU && ys >= 0 && ys < (int)a.H && xs >= 0 && xs < (int)a.W;
         *go = ok ? ((uint32_t)ys - r_first) * row_b + (uint32_t)xs * a.in_cs * 2 + q * 16 : kOob;
-        *lo = (r * HP + px) * PITCH + q * 8;
+        *lo = loff(r * HP + px, q);
         return idx < (uint32_t)HU;
     };
     auto wt_unit = [&](int u, uint32_t* go, uint32_t* lo) {
@@ -320,7 +323,7 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
         const uint32_t tap = idx / (TN * 4), co = (idx % (TN * 4)) >> 2, q = idx & 3;
         const bool ok = idx < (uint32_t)WU && co0 + co < a.Cout;
         *go = ok ? ((co0 + co) * K + tap * Cin + q * 8) * 2 : kOob;
-        *lo = (tap * TN + co) * PITCH + q * 8;
+        *lo = loff(tap * TN + co, q);
         return idx < (uint32_t)WU;
     };
     u32x4 hst[HPT], wst[WPT];
@@ -361,9 +364,9 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
             const int dy = tap / 3, dx = tap % 3;
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                A[i] = *(const u32x4*)&tile[((wr + dy) * HP + wx + 16 * i + l16 + dx) * PITCH + g * 8];
+                A[i] = *(const u32x4*)&tile[loff((wr + dy) * HP + wx + 16 * i + l16 + dx, g)];
 #pragma unroll
-            for (int j = 0; j < NJ; ++j) B[j] = *(const u32x4*)&wts[(tap * TN + 16 * j + l16) * PITCH + g * 8];
+            for (int j = 0; j < NJ; ++j) B[j] = *(const u32x4*)&wts[loff(tap * TN + 16 * j + l16, g)];
         };
         rd(0, av[0], bv[0]);
 #pragma unroll
@@ -388,10 +391,10 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
     }
     // the staged tiles are free once every wave is done with them; each wave
     // then uses its own part for the epilogue
-    static_assert(4 * 64 * (16 * NJ + 8) <= HALO, "epilogue fits the halo tile");
+    static_assert(4 * 64 * (16 * NJ + 8) <= HALO + 9 * TN * PITCH, "epilogue fits the staging area");
     __syncthreads();
     const uint32_t y = y0 + wr;
-    store_tile<4, NJ>(tile + wv * 64 * (16 * NJ + 8), acc, a.bias, co0, a.Cout, a.relu != 0,
+    store_tile<4, NJ>(lds + wv * 64 * (16 * NJ + 8), acc, a.bias, co0, a.Cout, a.relu != 0,
                       [&](int px) -> uint16_t* {
                           const uint32_t x = x0 + wx + px;
                           if (y >= a.H || x >= a.W) return nullptr;
