@@ -268,19 +268,23 @@ __global__ void __launch_bounds__(kBlock) k_conv(ConvArgs a)
 }
 
 // 3x3 convolution (stride 1, zero padding 1) with Cin a multiple of 32.
-// A workgroup computes 2 output rows x 128 pixels x (16 NJ) channels; its
-// four waves take 64 pixels of one row each (4 x NJ MFMA tiles). Per
-// 32-channel chunk, the input halo (4 rows x 130 pixels, zero outside the
+// A workgroup computes 2 output rows x TX pixels x (16 NJ) channels; its
+// four waves take 64 pixels of one row each and, when TX = 64, half of the
+// channels (4 x NJ or 4 x NJ/2 MFMA tiles). TX = 64 halves the halo so that
+// two workgroups share a compute unit's LDS and hide each other's loads. Per
+// 32-channel chunk, the input halo (4 rows x TX+2 pixels, zero outside the
 // image) and the chunk's weights of all nine taps are staged in LDS, so the
 // tap loop reads only LDS: the next tap's operands are read while the
 // current tap's matrix products run, and the next chunk's halo and weights
 // are loaded into registers meanwhile. Rows of 32 channels are padded to
 // 40 bf16 (80 B): 16 consecutive rows at one channel offset then fall in
 // distinct LDS banks.
-template <int NJ>
+template <int NJ, int TX>
 __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
 {
-    constexpr int R = 2, TX = 128, HP = TX + 2, RP = R + 2, TN = 16 * NJ, PITCH = 40;
+    constexpr int R = 2, HP = TX + 2, RP = R + 2, TN = 16 * NJ, PITCH = 40;
+    constexpr int NW = TX == 128 ? NJ : NJ / 2;          // MFMA column tiles per wave
+    static_assert(TX == 128 || (TX == 64 && NJ % 2 == 0), "tile shape");
     // element offset of 16-byte chunk q of staged row `row` (a pixel of the
     // halo or an output channel of the weights)
     auto loff = [](uint32_t row, uint32_t q) -> uint32_t { return row * PITCH + q * 8; };
@@ -296,7 +300,9 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
     const uint32_t n = blockIdx.x / (xtiles * ytiles);
     const uint32_t rem = blockIdx.x % (xtiles * ytiles);
     const uint32_t y0 = (rem / xtiles) * R, x0 = (rem % xtiles) * TX;
-    const uint32_t wr = (uint32_t)wv >> 1, wx = ((uint32_t)wv & 1u) * 64u;
+    const uint32_t wr = (uint32_t)wv >> 1;
+    const uint32_t wx = TX == 128 ? ((uint32_t)wv & 1u) * 64u : 0u;
+    const uint32_t wco = TX == 128 ? 0u : ((uint32_t)wv & 1u) * (16u * NW);   // wave's channel offset in the tile
     const uint32_t co0 = blockIdx.y * TN;
     const uint32_t Cin = a.Cin, K = 9 * Cin, nc = Cin >> 5;
     // input rows y0-1 .. y0+2 of image n, as far as they exist
@@ -349,24 +355,24 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
         for (int u = 0; u < WPT; ++u)
             if (wt_unit(u, &go, &lo)) *(u32x4*)&wts[lo] = wst[u];
     };
-    floatx4 acc[4][NJ];
+    floatx4 acc[4][NW];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < NW; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
     gload(0);
     lds_put();
     __syncthreads();
     for (uint32_t cc = 0; cc < nc; ++cc) {
         if (cc + 1 < nc) gload(cc + 1);
-        u32x4 av[2][4], bv[2][NJ];
-        auto rd = [&](int tap, u32x4 (&A)[4], u32x4 (&B)[NJ]) {
+        u32x4 av[2][4], bv[2][NW];
+        auto rd = [&](int tap, u32x4 (&A)[4], u32x4 (&B)[NW]) {
             const int dy = tap / 3, dx = tap % 3;
 #pragma unroll
             for (int i = 0; i < 4; ++i)
                 A[i] = *(const u32x4*)&tile[loff((wr + dy) * HP + wx + 16 * i + l16 + dx, g)];
 #pragma unroll
-            for (int j = 0; j < NJ; ++j) B[j] = *(const u32x4*)&wts[loff(tap * TN + 16 * j + l16, g)];
+            for (int j = 0; j < NW; ++j) B[j] = *(const u32x4*)&wts[loff(tap * TN + wco + 16 * j + l16, g)];
         };
         rd(0, av[0], bv[0]);
 #pragma unroll
@@ -377,7 +383,7 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < NJ; ++j)
+                for (int j = 0; j < NW; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                         __builtin_bit_cast(bf16x8, av[cur][i]), __builtin_bit_cast(bf16x8, bv[cur][j]), acc[i][j], 0, 0,
                         0);
@@ -391,14 +397,14 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
     }
     // the staged tiles are free once every wave is done with them; each wave
     // then uses its own part for the epilogue
-    static_assert(4 * 64 * (16 * NJ + 8) <= HALO + 9 * TN * PITCH, "epilogue fits the staging area");
+    static_assert(4 * 64 * (16 * NW + 8) <= HALO + 9 * TN * PITCH, "epilogue fits the staging area");
     __syncthreads();
     const uint32_t y = y0 + wr;
-    store_tile<4, NJ>(lds + wv * 64 * (16 * NJ + 8), acc, a.bias, co0, a.Cout, a.relu != 0,
+    store_tile<4, NW>(lds + wv * 64 * (16 * NW + 8), acc, a.bias, co0 + wco, a.Cout, a.relu != 0,
                       [&](int px) -> uint16_t* {
                           const uint32_t x = x0 + wx + px;
                           if (y >= a.H || x >= a.W) return nullptr;
-                          return a.out + (((size_t)n * a.H + y) * a.W + x) * a.out_cs + co0;
+                          return a.out + (((size_t)n * a.H + y) * a.W + x) * a.out_cs + co0 + wco;
                       });
 }
 
@@ -938,11 +944,11 @@ hipError_t conv(const uint16_t* in, uint32_t in_cs, const uint16_t* wt, const fl
     const dim3 g32(rows * ((W + 255) / 256) * up, (Cout + 31) / 32, gz),
         g64(rows * ((W + 255) / 256) * up, (Cout + 63) / 64, gz);
     const bool narrow = Cout <= 32;
-    const unsigned tiles3 = (unsigned)(N * ((H + 1) / 2) * ((W + 127) / 128));
+    const unsigned rows2 = (unsigned)(N * ((H + 1) / 2));
     switch (mode) {
     case MODE_SAME3:
-        if (narrow) k_conv3<2><<<dim3(tiles3, (Cout + 31) / 32), blk, 0, s>>>(a);
-        else k_conv3<4><<<dim3(tiles3, (Cout + 63) / 64), blk, 0, s>>>(a);
+        if (narrow) k_conv3<2, 128><<<dim3(rows2 * ((W + 127) / 128), (Cout + 31) / 32), blk, 0, s>>>(a);
+        else k_conv3<4, 64><<<dim3(rows2 * ((W + 63) / 64), (Cout + 63) / 64), blk, 0, s>>>(a);
         break;
     case MODE_UP2:
         if (narrow) k_conv<MODE_UP2, 4, 2, false><<<g32, blk, 0, s>>>(a);
