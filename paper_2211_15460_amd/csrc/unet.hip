@@ -69,6 +69,8 @@ struct ConvArgs {
     uint32_t in_cs, out_cs;   // elements per pixel
     uint32_t N, H, W;     // row grid: output grid (SAME3, GATHER4), input grid (UP2)
     uint32_t Cin, Cout, T, mode, relu;
+    uint16_t* pool;       // 3x3 only, or null: also write the 2x2 max pool of the output
+    uint32_t pool_cs;     // elements per pooled pixel
 };
 
 // Buffer resource over `bytes` bytes at p (raw, unswizzled): loads at an
@@ -398,14 +400,54 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
     // the staged tiles are free once every wave is done with them; each wave
     // then uses its own part for the epilogue
     static_assert(4 * 64 * (16 * NW + 8) <= HALO + 9 * TN * PITCH, "epilogue fits the staging area");
+    constexpr int EP = 16 * NW + 8;   // epilogue pitch (bf16 per pixel)
     __syncthreads();
     const uint32_t y = y0 + wr;
-    store_tile<4, NW>(lds + wv * 64 * (16 * NW + 8), acc, a.bias, co0 + wco, a.Cout, a.relu != 0,
+    store_tile<4, NW>(lds + wv * 64 * EP, acc, a.bias, co0 + wco, a.Cout, a.relu != 0,
                       [&](int px) -> uint16_t* {
                           const uint32_t x = x0 + wx + px;
                           if (y >= a.H || x >= a.W) return nullptr;
                           return a.out + (((size_t)n * a.H + y) * a.W + x) * a.out_cs + co0 + wco;
                       });
+    if (!a.pool) return;
+    // 2x2 max pool of the two output rows (even H and W, y0 even): waves
+    // 2 r + s hold row r; one thread per pooled pixel and 8 channels, the
+    // first largest of the window in (0,0), (0,1), (1,0), (1,1) order
+    __syncthreads();
+    constexpr int PCH = TN / 8;   // 16-byte channel runs per pooled pixel
+    static_assert((TX / 2) * PCH == kBlock, "one pooled run per thread");
+    const uint32_t p2 = threadIdx.x / PCH, q = threadIdx.x % PCH;
+    const uint32_t xs = x0 + 2 * p2;
+    if (xs >= a.W || co0 + 8 * q >= a.Cout) return;
+    u32x4 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t r = k >> 1, px = 2 * p2 + (k & 1);              // within the tile
+        const uint32_t w = TX == 128 ? 2 * r + px / 64 : 2 * r + (8 * q) / (16 * NW);
+        const uint32_t col = TX == 128 ? (8 * q) : (8 * q) % (16 * NW);
+        v[k] = *(const u32x4*)&lds[w * 64 * EP + (px % 64) * EP + col];
+    }
+    u32x4 o;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        uint32_t word = 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            float m = -INFINITY;
+            uint32_t best = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t b = (v[k][c] >> (16 * h)) & 0xFFFFu;
+                if (bf2f((uint16_t)b) > m) {
+                    m = bf2f((uint16_t)b);
+                    best = b;
+                }
+            }
+            word |= best << (16 * h);
+        }
+        o[c] = word;
+    }
+    *(u32x4*)(a.pool + (((size_t)n * (a.H / 2) + y0 / 2) * (a.W / 2) + xs / 2) * a.pool_cs + co0 + 8 * q) = o;
 }
 
 struct WgradArgs {
@@ -572,48 +614,6 @@ k_pack_input(const uint32_t* __restrict__ rgba, const float* __restrict__ depth,
     u32x4 w;
     for (int k = 0; k < 4; ++k) w[k] = (uint32_t)v[2 * k] | ((uint32_t)v[2 * k + 1] << 16);
     *(u32x4*)(out + (size_t)p * 8) = w;
-}
-
-// 2x2 max pool: out[n,y,x,c] (H, W = output size) from in (2H x 2W).
-__global__ void __launch_bounds__(kBlock)
-k_maxpool(const uint16_t* __restrict__ in, uint32_t in_cs, uint32_t N, uint32_t H, uint32_t W,
-          uint32_t C, uint16_t* __restrict__ out)
-{
-    // one thread per 8 channels of one pooled pixel (C is a multiple of 8)
-    const uint32_t G = C >> 3;
-    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x, tot = (size_t)N * H * W * G;
-    if (i >= tot) return;
-    const uint32_t c = (uint32_t)(i % G) * 8;
-    const size_t p = i / G;
-    const uint32_t x = (uint32_t)(p % W), y = (uint32_t)((p / W) % H), n = (uint32_t)(p / ((size_t)W * H));
-    u32x4 v[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const size_t s = ((size_t)n * 2 * H + 2 * y + (k >> 1)) * (2 * (size_t)W) + 2 * x + (k & 1);
-        v[k] = *(const u32x4*)(in + s * in_cs + c);
-    }
-    u32x4 o;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        uint32_t word = 0;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            // first window position holding the largest value
-            float m = -INFINITY;
-            uint32_t best = 0;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint32_t b = (v[k][w] >> (16 * h)) & 0xFFFFu;
-                if (bf2f((uint16_t)b) > m) {
-                    m = bf2f((uint16_t)b);
-                    best = b;
-                }
-            }
-            word |= best << (16 * h);
-        }
-        o[w] = word;
-    }
-    *(u32x4*)(out + p * C + c) = o;
 }
 
 // Gradient w.r.t. the pooled tensor's source: the pooled gradient goes to
@@ -914,9 +914,14 @@ unsigned blocks(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 hipError_t conv(const uint16_t* in, uint32_t in_cs, const uint16_t* wt, const float* bias, uint16_t* out,
                 uint32_t out_cs, uint32_t N, uint32_t H, uint32_t W, uint32_t Cin, uint32_t Cout,
-                int mode, bool relu, hipStream_t s)
+                int mode, bool relu, hipStream_t s, uint16_t* pool = nullptr, uint32_t pool_cs = 0)
 {
     ConvArgs a;
+    a.pool = pool;
+    a.pool_cs = pool_cs;
+    // the fused pool needs a 3x3 layer on the staged path, even sizes
+    if (pool && (mode != MODE_SAME3 || Cin % 32 != 0 || (H & 1) || (W & 1) || Cout % 8 != 0))
+        return hipErrorInvalidValue;
     a.in = in;
     a.wt = wt;
     a.bias = bias;
@@ -1040,11 +1045,11 @@ hipError_t forward(const Net& net, const float* th, const Bufs& b, uint32_t N, u
         FHV_TRY(conv(h, h_cs, b.wt + a0.wf_off, th + a0.off_b, b.e0[l], Cl, N, Hl, Wl, cin, Cl, MODE_SAME3, true, s));
         uint16_t* o1 = l + 1 < L ? b.cat[l] + Cl : b.elast;
         const uint32_t o1_cs = l + 1 < L ? 2 * Cl : Cl;
-        FHV_TRY(conv(b.e0[l], Cl, b.wt + a1.wf_off, th + a1.off_b, o1, o1_cs, N, Hl, Wl, Cl, Cl, MODE_SAME3, true, s));
+        // the second convolution of a level above the last also writes its
+        // 2x2 max pool (fused into its epilogue)
+        FHV_TRY(conv(b.e0[l], Cl, b.wt + a1.wf_off, th + a1.off_b, o1, o1_cs, N, Hl, Wl, Cl, Cl, MODE_SAME3, true, s,
+                     l + 1 < L ? b.pool[l] : nullptr, Cl));
         if (l + 1 < L) {
-            k_maxpool<<<blocks((size_t)N * (Hl / 2) * (Wl / 2) * (Cl / 8)), dim3(kBlock), 0, s>>>(
-                o1, o1_cs, N, Hl / 2, Wl / 2, Cl, b.pool[l]);
-            FHV_TRY(hipGetLastError());
             h = b.pool[l];
             h_cs = Cl;
             cin = Cl;
