@@ -163,11 +163,13 @@ def traffic_from(fetch_dir: str, write_dir: str, copy_mib: int) -> dict:
     out = {"src_sha256": src_digest(), "calibration": {}, "scopes": {}}
     for counter, d, key in (("FETCH_SIZE", fetch_dir, "read_bytes"), ("WRITE_SIZE", write_dir, "write_bytes")):
         rows = load(d, counter)
-        copies = [v for n, v in rows if "copyBuffer" in n or "copy" in n.lower()]
+        # the calibration copy is the largest device copy of the run
+        copies = [v for n, v in rows if "copy" in n.lower()]
         if not copies:
             raise SystemExit("the calibration copy is missing from the trace")
-        scale = copy_mib * 1024.0 / max(copies[0], 1e-9)
-        out["calibration"][counter] = {"copy_kib": copies[0], "bytes_per_kib": scale * 1024.0}
+        big = max(copies)
+        scale = copy_mib * 1024.0 / max(big, 1e-9)
+        out["calibration"][counter] = {"copy_kib": big, "bytes_per_kib": scale * 1024.0}
         last = max(i for i, (n, _) in enumerate(rows) if n.startswith("k_setup"))
         start = last
         while start > 0 and rows[start - 1][0].startswith(("k_fill_u32", "k_fill_u64")):
