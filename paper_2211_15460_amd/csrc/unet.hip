@@ -281,19 +281,26 @@ __global__ void __launch_bounds__(kBlock) k_conv(ConvArgs a)
 // are loaded into registers meanwhile. Rows of 32 channels are padded to
 // 40 bf16 (80 B): 16 consecutive rows at one channel offset then fall in
 // distinct LDS banks.
-template <int NJ, int TX>
+//
+// kUp: the same structure for the 2x2 stride-2 transposed convolution,
+// which is a 1x1 convolution onto 4 Cout columns (sub-position, channel):
+// one tap, no halo, and the epilogue scatters each 32-column group to its
+// sub-position of the doubled grid.
+template <int NJ, int TX, bool kUp>
 __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
 {
-    constexpr int R = 2, HP = TX + 2, RP = R + 2, TN = 16 * NJ, PITCH = 40;
+    constexpr int T = kUp ? 1 : 9, PAD = kUp ? 0 : 1;
+    constexpr int R = 2, HP = TX + 2 * PAD, RP = R + 2 * PAD, TN = 16 * NJ, PITCH = 40;
     constexpr int NW = TX == 128 ? NJ : NJ / 2;          // MFMA column tiles per wave
     static_assert(TX == 128 || (TX == 64 && NJ % 2 == 0), "tile shape");
     // element offset of 16-byte chunk q of staged row `row` (a pixel of the
     // halo or an output channel of the weights)
     auto loff = [](uint32_t row, uint32_t q) -> uint32_t { return row * PITCH + q * 8; };
-    constexpr int HU = RP * HP * 4, WU = 9 * TN * 4;     // 16-byte units: halo, weights
+    constexpr int HU = RP * HP * 4, WU = T * TN * 4;     // 16-byte units: halo, weights
     constexpr int HPT = (HU + kBlock - 1) / kBlock, WPT = (WU + kBlock - 1) / kBlock;
     constexpr int HALO = RP * HP * PITCH;                // bf16 elements
-    __shared__ __attribute__((aligned(16))) uint16_t lds[HALO + 9 * TN * PITCH];
+    constexpr int STAGE = HALO + T * TN * PITCH, EPI = 4 * 64 * (16 * NW + 8);
+    __shared__ __attribute__((aligned(16))) uint16_t lds[STAGE > EPI ? STAGE : EPI];
     uint16_t* const tile = lds;
     uint16_t* const wts = lds + HALO;
     const int lane = __lane_id(), wv = threadIdx.x / kWave;
@@ -306,21 +313,22 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
     const uint32_t wx = TX == 128 ? ((uint32_t)wv & 1u) * 64u : 0u;
     const uint32_t wco = TX == 128 ? 0u : ((uint32_t)wv & 1u) * (16u * NW);   // wave's channel offset in the tile
     const uint32_t co0 = blockIdx.y * TN;
-    const uint32_t Cin = a.Cin, K = 9 * Cin, nc = Cin >> 5;
-    // input rows y0-1 .. y0+2 of image n, as far as they exist
-    const uint32_t r_first = y0 > 0 ? y0 - 1 : 0;
-    const uint32_t r_last = y0 + R < a.H ? y0 + R : a.H - 1;
+    const uint32_t Cin = a.Cin, K = T * Cin, nc = Cin >> 5;
+    const uint32_t Cg = kUp ? 4 * a.Cout : a.Cout;   // GEMM columns
+    // input rows y0-PAD .. y0+R-1+PAD of image n, as far as they exist
+    const uint32_t r_first = y0 >= (uint32_t)PAD ? y0 - PAD : 0;
+    const uint32_t r_last = y0 + R - 1 + PAD < a.H ? y0 + R - 1 + PAD : a.H - 1;
     const uint32_t row_b = a.W * a.in_cs * 2;
     const __amdgpu_buffer_rsrc_t ir =
         rsrc(a.in + ((size_t)n * a.H + r_first) * a.W * a.in_cs, (r_last - r_first + 1) * row_b);
-    const __amdgpu_buffer_rsrc_t wrs = rsrc(a.wt, a.Cout * K * 2);
+    const __amdgpu_buffer_rsrc_t wrs = rsrc(a.wt, Cg * K * 2);
     // staging units of this thread (16 bytes each): global byte offsets
     // (out-of-range offsets read zeros) and LDS element offsets, recomputed
     // per chunk to keep registers for the operands
     auto halo_unit = [&](int u, uint32_t* go, uint32_t* lo) {
         const uint32_t idx = threadIdx.x + u * kBlock;
         const uint32_t r = idx / (HP * 4), px = (idx % (HP * 4)) >> 2, q = idx & 3;
-        const int ys = (int)y0 + (int)r - 1, xs = (int)x0 + (int)px - 1;
+        const int ys = (int)y0 + (int)r - PAD, xs = (int)x0 + (int)px - PAD;
         const bool ok = idx < (uint32_t)HU && ys >= 0 && ys < (int)a.H && xs >= 0 && xs < (int)a.W;
         *go = ok ? ((uint32_t)ys - r_first) * row_b + (uint32_t)xs * a.in_cs * 2 + q * 16 : kOob;
         *lo = loff(r * HP + px, q);
@@ -329,7 +337,7 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
     auto wt_unit = [&](int u, uint32_t* go, uint32_t* lo) {
         const uint32_t idx = threadIdx.x + u * kBlock;
         const uint32_t tap = idx / (TN * 4), co = (idx % (TN * 4)) >> 2, q = idx & 3;
-        const bool ok = idx < (uint32_t)WU && co0 + co < a.Cout;
+        const bool ok = idx < (uint32_t)WU && co0 + co < Cg;
         *go = ok ? ((co0 + co) * K + tap * Cin + q * 8) * 2 : kOob;
         *lo = loff(tap * TN + co, q);
         return idx < (uint32_t)WU;
@@ -378,9 +386,9 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
         };
         rd(0, av[0], bv[0]);
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
+        for (int tap = 0; tap < T; ++tap) {
             const int cur = tap & 1;
-            if (tap + 1 < 9) rd(tap + 1, av[cur ^ 1], bv[cur ^ 1]);
+            if (tap + 1 < T) rd(tap + 1, av[cur ^ 1], bv[cur ^ 1]);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int i = 0; i < 4; ++i)
@@ -399,10 +407,21 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
     }
     // the staged tiles are free once every wave is done with them; each wave
     // then uses its own part for the epilogue
-    static_assert(4 * 64 * (16 * NW + 8) <= HALO + 9 * TN * PITCH, "epilogue fits the staging area");
     constexpr int EP = 16 * NW + 8;   // epilogue pitch (bf16 per pixel)
     __syncthreads();
     const uint32_t y = y0 + wr;
+    if (kUp) {
+        // a wave's 32 columns are one sub-position (Cout is a multiple of 32)
+        const uint32_t cw = co0 + wco, tz = cw / a.Cout, cb = cw % a.Cout;
+        store_tile<4, NW>(lds + wv * 64 * EP, acc, a.bias, cb, cw < Cg ? a.Cout : 0u, a.relu != 0,
+                          [&](int px) -> uint16_t* {
+                              const uint32_t x = x0 + wx + px;
+                              if (y >= a.H || x >= a.W) return nullptr;
+                              return a.out + (((size_t)n * 2 * a.H + 2 * y + (tz >> 1)) * (2 * (size_t)a.W) + 2 * x +
+                                              (tz & 1)) * a.out_cs + cb;
+                          });
+        return;
+    }
     store_tile<4, NW>(lds + wv * 64 * EP, acc, a.bias, co0 + wco, a.Cout, a.relu != 0,
                       [&](int px) -> uint16_t* {
                           const uint32_t x = x0 + wx + px;
@@ -952,10 +971,14 @@ hipError_t conv(const uint16_t* in, uint32_t in_cs, const uint16_t* wt, const fl
     const unsigned rows2 = (unsigned)(N * ((H + 1) / 2));
     switch (mode) {
     case MODE_SAME3:
-        if (narrow) k_conv3<2, 128><<<dim3(rows2 * ((W + 127) / 128), (Cout + 31) / 32), blk, 0, s>>>(a);
-        else k_conv3<4, 64><<<dim3(rows2 * ((W + 63) / 64), (Cout + 63) / 64), blk, 0, s>>>(a);
+        if (narrow) k_conv3<2, 128, false><<<dim3(rows2 * ((W + 127) / 128), (Cout + 31) / 32), blk, 0, s>>>(a);
+        else k_conv3<4, 64, false><<<dim3(rows2 * ((W + 63) / 64), (Cout + 63) / 64), blk, 0, s>>>(a);
         break;
     case MODE_UP2:
+        if (Cout % 32 == 0) {
+            k_conv3<4, 64, true><<<dim3(rows2 * ((W + 63) / 64), (4 * Cout + 63) / 64), blk, 0, s>>>(a);
+            break;
+        }
         if (narrow) k_conv<MODE_UP2, 4, 2, false><<<g32, blk, 0, s>>>(a);
         else k_conv<MODE_UP2, 4, 4, false><<<g64, blk, 0, s>>>(a);
         break;
