@@ -286,13 +286,20 @@ __global__ void __launch_bounds__(kBlock) k_conv(ConvArgs a)
 // which is a 1x1 convolution onto 4 Cout columns (sub-position, channel):
 // one tap, no halo, and the epilogue scatters each 32-column group to its
 // sub-position of the doubled grid.
-template <int NJ, int TX, bool kUp>
+//
+// R = 4 (with TX = 64): four output rows, one per wave, all channels of the
+// tile per wave; the halo of 6 rows for 4 output rows re-reads less of the
+// input than 4 rows for 2, which matters for the memory-bound full-size
+// layers.
+template <int NJ, int TX, bool kUp, int R = 2>
 __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
 {
     constexpr int T = kUp ? 1 : 9, PAD = kUp ? 0 : 1;
-    constexpr int R = 2, HP = TX + 2 * PAD, RP = R + 2 * PAD, TN = 16 * NJ, PITCH = 40;
-    constexpr int NW = TX == 128 ? NJ : NJ / 2;          // MFMA column tiles per wave
-    static_assert(TX == 128 || (TX == 64 && NJ % 2 == 0), "tile shape");
+    constexpr int HP = TX + 2 * PAD, RP = R + 2 * PAD, TN = 16 * NJ, PITCH = 40;
+    // waves: R = 4 -> one row each; TX = 128 -> (row, 64-pixel half);
+    // TX = 64 -> (row, half of the channels)
+    constexpr int NW = (R == 4 || TX == 128) ? NJ : NJ / 2;   // MFMA column tiles per wave
+    static_assert((R == 2 && (TX == 128 || (TX == 64 && NJ % 2 == 0))) || (R == 4 && TX == 64), "tile shape");
     // element offset of 16-byte chunk q of staged row `row` (a pixel of the
     // halo or an output channel of the weights)
     auto loff = [](uint32_t row, uint32_t q) -> uint32_t { return row * PITCH + q * 8; };
@@ -309,9 +316,9 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
     const uint32_t n = blockIdx.x / (xtiles * ytiles);
     const uint32_t rem = blockIdx.x % (xtiles * ytiles);
     const uint32_t y0 = (rem / xtiles) * R, x0 = (rem % xtiles) * TX;
-    const uint32_t wr = (uint32_t)wv >> 1;
-    const uint32_t wx = TX == 128 ? ((uint32_t)wv & 1u) * 64u : 0u;
-    const uint32_t wco = TX == 128 ? 0u : ((uint32_t)wv & 1u) * (16u * NW);   // wave's channel offset in the tile
+    const uint32_t wr = R == 4 ? (uint32_t)wv : (uint32_t)wv >> 1;
+    const uint32_t wx = (R == 2 && TX == 128) ? ((uint32_t)wv & 1u) * 64u : 0u;
+    const uint32_t wco = (R == 2 && TX == 64) ? ((uint32_t)wv & 1u) * (16u * NW) : 0u;   // wave's channel offset
     const uint32_t co0 = blockIdx.y * TN;
     const uint32_t Cin = a.Cin, K = T * Cin, nc = Cin >> 5;
     const uint32_t Cg = kUp ? 4 * a.Cout : a.Cout;   // GEMM columns
@@ -429,21 +436,21 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
                           return a.out + (((size_t)n * a.H + y) * a.W + x) * a.out_cs + co0 + wco;
                       });
     if (!a.pool) return;
-    // 2x2 max pool of the two output rows (even H and W, y0 even): waves
-    // 2 r + s hold row r; one thread per pooled pixel and 8 channels, the
+    // 2x2 max pool of the output rows (even H and W, y0 even), from the
+    // waves' epilogue tiles; one thread per pooled pixel and 8 channels, the
     // first largest of the window in (0,0), (0,1), (1,0), (1,1) order
     __syncthreads();
     constexpr int PCH = TN / 8;   // 16-byte channel runs per pooled pixel
-    static_assert((TX / 2) * PCH == kBlock, "one pooled run per thread");
-    const uint32_t p2 = threadIdx.x / PCH, q = threadIdx.x % PCH;
-    const uint32_t xs = x0 + 2 * p2;
-    if (xs >= a.W || co0 + 8 * q >= a.Cout) return;
+    static_assert((TX / 2) * (R / 2) * PCH == kBlock, "one pooled run per thread");
+    const uint32_t q = threadIdx.x % PCH, p2 = (threadIdx.x / PCH) % (TX / 2), pr = threadIdx.x / (PCH * (TX / 2));
+    const uint32_t xs = x0 + 2 * p2, ys = y0 + 2 * pr;
+    if (xs >= a.W || ys >= a.H || co0 + 8 * q >= a.Cout) return;
     u32x4 v[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const uint32_t r = k >> 1, px = 2 * p2 + (k & 1);              // within the tile
-        const uint32_t w = TX == 128 ? 2 * r + px / 64 : 2 * r + (8 * q) / (16 * NW);
-        const uint32_t col = TX == 128 ? (8 * q) : (8 * q) % (16 * NW);
+        const uint32_t r = 2 * pr + (k >> 1), px = 2 * p2 + (k & 1);   // within the tile
+        const uint32_t w = R == 4 ? r : (TX == 128 ? 2 * r + px / 64 : 2 * r + (8 * q) / (16 * NW));
+        const uint32_t col = (R == 2 && TX == 64) ? (8 * q) % (16 * NW) : 8 * q;
         v[k] = *(const u32x4*)&lds[w * 64 * EP + (px % 64) * EP + col];
     }
     u32x4 o;
@@ -466,7 +473,7 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
         }
         o[c] = word;
     }
-    *(u32x4*)(a.pool + (((size_t)n * (a.H / 2) + y0 / 2) * (a.W / 2) + xs / 2) * a.pool_cs + co0 + 8 * q) = o;
+    *(u32x4*)(a.pool + (((size_t)n * (a.H / 2) + ys / 2) * (a.W / 2) + xs / 2) * a.pool_cs + co0 + 8 * q) = o;
 }
 
 struct WgradArgs {
@@ -971,7 +978,8 @@ hipError_t conv(const uint16_t* in, uint32_t in_cs, const uint16_t* wt, const fl
     const unsigned rows2 = (unsigned)(N * ((H + 1) / 2));
     switch (mode) {
     case MODE_SAME3:
-        if (narrow) k_conv3<2, 128, false><<<dim3(rows2 * ((W + 127) / 128), (Cout + 31) / 32), blk, 0, s>>>(a);
+        if (narrow)
+            k_conv3<2, 64, false, 4><<<dim3(N * ((H + 3) / 4) * ((W + 63) / 64), (Cout + 31) / 32), blk, 0, s>>>(a);
         else k_conv3<4, 64, false><<<dim3(rows2 * ((W + 63) / 64), (Cout + 63) / 64), blk, 0, s>>>(a);
         break;
     case MODE_UP2:
