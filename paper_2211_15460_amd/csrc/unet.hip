@@ -307,55 +307,68 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
     constexpr int HPT = (HU + kBlock - 1) / kBlock, WPT = (WU + kBlock - 1) / kBlock;
     constexpr int HALO = RP * HP * PITCH;                // bf16 elements
     constexpr int STAGE = HALO + T * TN * PITCH, EPI = 4 * 64 * (16 * NW + 8);
+    constexpr int EP = 16 * NW + 8;                      // epilogue pitch (bf16 per pixel)
     __shared__ __attribute__((aligned(16))) uint16_t lds[STAGE > EPI ? STAGE : EPI];
     uint16_t* const tile = lds;
     uint16_t* const wts = lds + HALO;
     const int lane = __lane_id(), wv = threadIdx.x / kWave;
     const int g = lane >> 4, l16 = lane & 15;
     const uint32_t xtiles = (a.W + TX - 1) / TX, ytiles = (a.H + R - 1) / R;
-    const uint32_t n = blockIdx.x / (xtiles * ytiles);
-    const uint32_t rem = blockIdx.x % (xtiles * ytiles);
-    const uint32_t y0 = (rem / xtiles) * R, x0 = (rem % xtiles) * TX;
+    const uint32_t n_tiles = a.N * ytiles * xtiles;
     const uint32_t wr = R == 4 ? (uint32_t)wv : (uint32_t)wv >> 1;
     const uint32_t wx = (R == 2 && TX == 128) ? ((uint32_t)wv & 1u) * 64u : 0u;
     const uint32_t wco = (R == 2 && TX == 64) ? ((uint32_t)wv & 1u) * (16u * NW) : 0u;   // wave's channel offset
     const uint32_t co0 = blockIdx.y * TN;
     const uint32_t Cin = a.Cin, K = T * Cin, nc = Cin >> 5;
     const uint32_t Cg = kUp ? 4 * a.Cout : a.Cout;   // GEMM columns
-    // input rows y0-PAD .. y0+R-1+PAD of image n, as far as they exist
-    const uint32_t r_first = y0 >= (uint32_t)PAD ? y0 - PAD : 0;
-    const uint32_t r_last = y0 + R - 1 + PAD < a.H ? y0 + R - 1 + PAD : a.H - 1;
     const uint32_t row_b = a.W * a.in_cs * 2;
-    const __amdgpu_buffer_rsrc_t ir =
-        rsrc(a.in + ((size_t)n * a.H + r_first) * a.W * a.in_cs, (r_last - r_first + 1) * row_b);
     const __amdgpu_buffer_rsrc_t wrs = rsrc(a.wt, Cg * K * 2);
+    // Workgroups are persistent: a workgroup takes tiles blockIdx.x,
+    // blockIdx.x + gridDim.x, ... and every (tile, chunk) unit's operands are
+    // loaded while the previous unit is computed (across tiles too).
+    struct Geo {
+        uint32_t n, y0, x0, r_first;
+        __amdgpu_buffer_rsrc_t ir;
+    };
+    auto geo = [&](uint32_t t) {
+        Geo q;
+        q.n = t / (xtiles * ytiles);
+        const uint32_t rem = t % (xtiles * ytiles);
+        q.y0 = (rem / xtiles) * R;
+        q.x0 = (rem % xtiles) * TX;
+        // input rows y0-PAD .. y0+R-1+PAD of image n, as far as they exist
+        q.r_first = q.y0 >= (uint32_t)PAD ? q.y0 - PAD : 0;
+        const uint32_t r_last = q.y0 + R - 1 + PAD < a.H ? q.y0 + R - 1 + PAD : a.H - 1;
+        q.ir = rsrc(a.in + ((size_t)q.n * a.H + q.r_first) * a.W * a.in_cs, (r_last - q.r_first + 1) * row_b);
+        return q;
+    };
     // staging units of this thread (16 bytes each): global byte offsets
     // (out-of-range offsets read zeros) and LDS element offsets, recomputed
-    // per chunk to keep registers for the operands
-    auto halo_unit = [&](int u, uint32_t* go, uint32_t* lo) {
+    // per unit to keep registers for the operands
+    auto halo_unit = [&](const Geo& q, int u, uint32_t* go, uint32_t* lo) {
         const uint32_t idx = threadIdx.x + u * kBlock;
-        const uint32_t r = idx / (HP * 4), px = (idx % (HP * 4)) >> 2, q = idx & 3;
-        const int ys = (int)y0 + (int)r - PAD, xs = (int)x0 + (int)px - PAD;
+        const uint32_t r = idx / (HP * 4), px = (idx % (HP * 4)) >> 2, c = idx & 3;
+        const int ys = (int)q.y0 + (int)r - PAD, xs = (int)q.x0 + (int)px - PAD;
         const bool ok = idx < (uint32_t)HU && ys >= 0 && ys < (int)a.H && xs >= 0 && xs < (int)a.W;
-        *go = ok ? ((uint32_t)ys - r_first) * row_b + (uint32_t)xs * a.in_cs * 2 + q * 16 : kOob;
-        *lo = loff(r * HP + px, q);
+        *go = ok ? ((uint32_t)ys - q.r_first) * row_b + (uint32_t)xs * a.in_cs * 2 + c * 16 : kOob;
+        *lo = loff(r * HP + px, c);
         return idx < (uint32_t)HU;
     };
     auto wt_unit = [&](int u, uint32_t* go, uint32_t* lo) {
         const uint32_t idx = threadIdx.x + u * kBlock;
-        const uint32_t tap = idx / (TN * 4), co = (idx % (TN * 4)) >> 2, q = idx & 3;
+        const uint32_t tap = idx / (TN * 4), co = (idx % (TN * 4)) >> 2, c = idx & 3;
         const bool ok = idx < (uint32_t)WU && co0 + co < Cg;
-        *go = ok ? ((co0 + co) * K + tap * Cin + q * 8) * 2 : kOob;
-        *lo = loff(tap * TN + co, q);
+        *go = ok ? ((co0 + co) * K + tap * Cin + c * 8) * 2 : kOob;
+        *lo = loff(tap * TN + co, c);
         return idx < (uint32_t)WU;
     };
     u32x4 hst[HPT], wst[WPT];
-    auto gload = [&](uint32_t cc) {
+    auto gload = [&](const Geo& q, uint32_t cc) {
         uint32_t go, lo;
 #pragma unroll
         for (int u = 0; u < HPT; ++u) {
-            halo_unit(u, &go, &lo);
-            hst[u] = bload(ir, go, cc * 64);
+            halo_unit(q, u, &go, &lo);
+            hst[u] = bload(q.ir, go, cc * 64);
         }
 #pragma unroll
         for (int u = 0; u < WPT; ++u) {
@@ -363,11 +376,11 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
             wst[u] = bload(wrs, go, cc * 64);
         }
     };
-    auto lds_put = [&]() {
+    auto lds_put = [&](const Geo& q) {
         uint32_t go, lo;
 #pragma unroll
         for (int u = 0; u < HPT; ++u)
-            if (halo_unit(u, &go, &lo)) *(u32x4*)&tile[lo] = hst[u];
+            if (halo_unit(q, u, &go, &lo)) *(u32x4*)&tile[lo] = hst[u];
 #pragma unroll
         for (int u = 0; u < WPT; ++u)
             if (wt_unit(u, &go, &lo)) *(u32x4*)&wts[lo] = wst[u];
@@ -377,11 +390,7 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < NW; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    gload(0);
-    lds_put();
-    __syncthreads();
-    for (uint32_t cc = 0; cc < nc; ++cc) {
-        if (cc + 1 < nc) gload(cc + 1);
+    auto compute = [&]() {
         u32x4 av[2][4], bv[2][NW];
         auto rd = [&](int tap, u32x4 (&A)[4], u32x4 (&B)[NW]) {
             const int dy = tap / 3, dx = tap % 3;
@@ -406,74 +415,104 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
                         0);
             __builtin_amdgcn_sched_barrier(0);
         }
-        if (cc + 1 < nc) {
-            __syncthreads();
-            lds_put();
-            __syncthreads();
+    };
+    // Epilogue of tile q (the staging area is free: every wave has passed the
+    // barrier before it); each wave uses its own part of the LDS.
+    auto epilogue = [&](const Geo& q) {
+        const uint32_t y = q.y0 + wr;
+        if (kUp) {
+            // a wave's 32 columns are one sub-position (Cout is a multiple of 32)
+            const uint32_t cw = co0 + wco, tz = cw / a.Cout, cb = cw % a.Cout;
+            store_tile<4, NW>(lds + wv * 64 * EP, acc, a.bias, cb, cw < Cg ? a.Cout : 0u, a.relu != 0,
+                              [&](int px) -> uint16_t* {
+                                  const uint32_t x = q.x0 + wx + px;
+                                  if (y >= a.H || x >= a.W) return nullptr;
+                                  return a.out + (((size_t)q.n * 2 * a.H + 2 * y + (tz >> 1)) * (2 * (size_t)a.W) +
+                                                  2 * x + (tz & 1)) * a.out_cs + cb;
+                              });
+            return;
         }
-    }
-    // the staged tiles are free once every wave is done with them; each wave
-    // then uses its own part for the epilogue
-    constexpr int EP = 16 * NW + 8;   // epilogue pitch (bf16 per pixel)
-    __syncthreads();
-    const uint32_t y = y0 + wr;
-    if (kUp) {
-        // a wave's 32 columns are one sub-position (Cout is a multiple of 32)
-        const uint32_t cw = co0 + wco, tz = cw / a.Cout, cb = cw % a.Cout;
-        store_tile<4, NW>(lds + wv * 64 * EP, acc, a.bias, cb, cw < Cg ? a.Cout : 0u, a.relu != 0,
+        store_tile<4, NW>(lds + wv * 64 * EP, acc, a.bias, co0 + wco, a.Cout, a.relu != 0,
                           [&](int px) -> uint16_t* {
-                              const uint32_t x = x0 + wx + px;
+                              const uint32_t x = q.x0 + wx + px;
                               if (y >= a.H || x >= a.W) return nullptr;
-                              return a.out + (((size_t)n * 2 * a.H + 2 * y + (tz >> 1)) * (2 * (size_t)a.W) + 2 * x +
-                                              (tz & 1)) * a.out_cs + cb;
+                              return a.out + (((size_t)q.n * a.H + y) * a.W + x) * a.out_cs + co0 + wco;
                           });
-        return;
-    }
-    store_tile<4, NW>(lds + wv * 64 * EP, acc, a.bias, co0 + wco, a.Cout, a.relu != 0,
-                      [&](int px) -> uint16_t* {
-                          const uint32_t x = x0 + wx + px;
-                          if (y >= a.H || x >= a.W) return nullptr;
-                          return a.out + (((size_t)n * a.H + y) * a.W + x) * a.out_cs + co0 + wco;
-                      });
-    if (!a.pool) return;
-    // 2x2 max pool of the output rows (even H and W, y0 even), from the
-    // waves' epilogue tiles; one thread per pooled pixel and 8 channels, the
-    // first largest of the window in (0,0), (0,1), (1,0), (1,1) order
-    __syncthreads();
-    constexpr int PCH = TN / 8;   // 16-byte channel runs per pooled pixel
-    static_assert((TX / 2) * (R / 2) * PCH == kBlock, "one pooled run per thread");
-    const uint32_t q = threadIdx.x % PCH, p2 = (threadIdx.x / PCH) % (TX / 2), pr = threadIdx.x / (PCH * (TX / 2));
-    const uint32_t xs = x0 + 2 * p2, ys = y0 + 2 * pr;
-    if (xs >= a.W || ys >= a.H || co0 + 8 * q >= a.Cout) return;
-    u32x4 v[4];
+        if (!a.pool) return;
+        // 2x2 max pool of the output rows (even H and W, y0 even), from the
+        // waves' epilogue tiles; one thread per pooled pixel and 8 channels,
+        // the first largest of the window in (0,0), (0,1), (1,0), (1,1) order
+        __syncthreads();
+        constexpr int PCH = TN / 8;   // 16-byte channel runs per pooled pixel
+        static_assert((TX / 2) * (R / 2) * PCH == kBlock, "one pooled run per thread");
+        const uint32_t c8 = threadIdx.x % PCH, p2 = (threadIdx.x / PCH) % (TX / 2), pr = threadIdx.x / (PCH * (TX / 2));
+        const uint32_t xs = q.x0 + 2 * p2, ys = q.y0 + 2 * pr;
+        if (xs >= a.W || ys >= a.H || co0 + 8 * c8 >= a.Cout) return;
+        u32x4 v[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint32_t r = 2 * pr + (k >> 1), px = 2 * p2 + (k & 1);   // within the tile
-        const uint32_t w = R == 4 ? r : (TX == 128 ? 2 * r + px / 64 : 2 * r + (8 * q) / (16 * NW));
-        const uint32_t col = (R == 2 && TX == 64) ? (8 * q) % (16 * NW) : 8 * q;
-        v[k] = *(const u32x4*)&lds[w * 64 * EP + (px % 64) * EP + col];
-    }
-    u32x4 o;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        uint32_t word = 0;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            float m = -INFINITY;
-            uint32_t best = 0;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint32_t b = (v[k][c] >> (16 * h)) & 0xFFFFu;
-                if (bf2f((uint16_t)b) > m) {
-                    m = bf2f((uint16_t)b);
-                    best = b;
-                }
-            }
-            word |= best << (16 * h);
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t r = 2 * pr + (k >> 1), px = 2 * p2 + (k & 1);   // within the tile
+            const uint32_t w = R == 4 ? r : (TX == 128 ? 2 * r + px / 64 : 2 * r + (8 * c8) / (16 * NW));
+            const uint32_t col = (R == 2 && TX == 64) ? (8 * c8) % (16 * NW) : 8 * c8;
+            v[k] = *(const u32x4*)&lds[w * 64 * EP + (px % 64) * EP + col];
         }
-        o[c] = word;
+        u32x4 o;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            uint32_t word = 0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                float m = -INFINITY;
+                uint32_t best = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t b = (v[k][c] >> (16 * h)) & 0xFFFFu;
+                    if (bf2f((uint16_t)b) > m) {
+                        m = bf2f((uint16_t)b);
+                        best = b;
+                    }
+                }
+                word |= best << (16 * h);
+            }
+            o[c] = word;
+        }
+        *(u32x4*)(a.pool + (((size_t)q.n * (a.H / 2) + ys / 2) * (a.W / 2) + xs / 2) * a.pool_cs + co0 + 8 * c8) = o;
+    };
+
+    uint32_t t = blockIdx.x, cc = 0;
+    if (t >= n_tiles) return;   // whole workgroup
+    Geo cur = geo(t);
+    gload(cur, 0);
+    lds_put(cur);
+    __syncthreads();
+    for (;;) {
+        // the next unit: next chunk, or the first chunk of the next tile
+        uint32_t nt = t, ncc = cc + 1;
+        if (ncc == nc) {
+            ncc = 0;
+            nt = t + gridDim.x;
+        }
+        const bool more = nt < n_tiles;
+        Geo nxt = cur;
+        if (nt != t && more) nxt = geo(nt);
+        if (more) gload(nxt, ncc);
+        compute();
+        __syncthreads();   // staged operands no longer needed
+        if (cc + 1 == nc) {
+            epilogue(cur);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < NW; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+            __syncthreads();   // epilogue reads of the LDS done
+        }
+        if (!more) break;
+        lds_put(nxt);
+        __syncthreads();
+        t = nt;
+        cc = ncc;
+        cur = nxt;
     }
-    *(u32x4*)(a.pool + (((size_t)n * (a.H / 2) + ys / 2) * (a.W / 2) + xs / 2) * a.pool_cs + co0 + 8 * q) = o;
 }
 
 struct WgradArgs {
@@ -975,16 +1014,26 @@ hipError_t conv(const uint16_t* in, uint32_t in_cs, const uint16_t* wt, const fl
     const dim3 g32(rows * ((W + 255) / 256) * up, (Cout + 31) / 32, gz),
         g64(rows * ((W + 255) / 256) * up, (Cout + 63) / 64, gz);
     const bool narrow = Cout <= 32;
-    const unsigned rows2 = (unsigned)(N * ((H + 1) / 2));
+    // staged kernel: with one 32-channel chunk per tile a workgroup has
+    // nothing to load ahead within its tile, so workgroups are made
+    // persistent (two per compute unit, as LDS and registers allow) and load
+    // the next tile during the current one; otherwise one workgroup per tile
+    const auto pgrid = [&](uint32_t tiles, uint32_t cols) {
+        if (Cin > 32) return dim3(tiles, cols);
+        const uint32_t want = (uint32_t)cur_dev().cus * 2 / cols;
+        return dim3(std::max(1u, std::min(tiles, want)), cols);
+    };
+    const uint32_t rows2 = N * ((H + 1) / 2);
     switch (mode) {
     case MODE_SAME3:
         if (narrow)
-            k_conv3<2, 64, false, 4><<<dim3(N * ((H + 3) / 4) * ((W + 63) / 64), (Cout + 31) / 32), blk, 0, s>>>(a);
-        else k_conv3<4, 64, false><<<dim3(rows2 * ((W + 63) / 64), (Cout + 63) / 64), blk, 0, s>>>(a);
+            k_conv3<2, 64, false, 4><<<pgrid(N * ((H + 3) / 4) * ((W + 63) / 64), (Cout + 31) / 32), blk, 0, s>>>(a);
+        else
+            k_conv3<4, 64, false><<<pgrid(rows2 * ((W + 63) / 64), (Cout + 63) / 64), blk, 0, s>>>(a);
         break;
     case MODE_UP2:
         if (Cout % 32 == 0) {
-            k_conv3<4, 64, true><<<dim3(rows2 * ((W + 63) / 64), (4 * Cout + 63) / 64), blk, 0, s>>>(a);
+            k_conv3<4, 64, true><<<pgrid(rows2 * ((W + 63) / 64), (4 * Cout + 63) / 64), blk, 0, s>>>(a);
             break;
         }
         if (narrow) k_conv<MODE_UP2, 4, 2, false><<<g32, blk, 0, s>>>(a);
