@@ -19,19 +19,24 @@
 // concatenation costs nothing.
 //
 // Kernels
-//   k_conv        implicit GEMM on MFMA 16x16x32 bf16: rows = pixels of a
-//                 grid, K = taps x input channels, N = output channels; three
-//                 addressing modes: 3x3 same-size (forward, and input
-//                 gradient with flipped transposed weights), 2x2 stride-2 up
-//                 (transposed conv forward), 2x2 gather from the doubled grid
-//                 (transposed conv input gradient). Fused bias, ReLU, bf16.
+//   k_conv3       implicit GEMM on MFMA 16x16x32 bf16 with the input halo and
+//                 the weights staged in LDS per 32-channel chunk: 3x3 same-size
+//                 convolutions (forward, and input gradients with flipped
+//                 transposed weights) and the 2x2 stride-2 transposed
+//                 convolution as a 1x1 product onto (sub-position, channel)
+//                 columns. Fused bias, ReLU, bf16 rounding; optionally the
+//                 encoder's 2x2 max pool and, for the last layer in inference,
+//                 the 1x1 head with the filled image.
+//   k_conv        the remaining shapes (8 input channels; gathered input
+//                 gradient of the transposed convolution), operands through
+//                 buffer resources
 //   k_wgrad       weight gradients: GEMM over pixels, both operands staged
 //                 through LDS transposed (pixels contiguous), split over
 //                 pixel ranges with fp32 partials and a fixed-order reduction
 //   k_colsum      bias gradients, same split / reduce scheme
-//   elementwise   input packing, max pool and its gradient (plus the skip
-//                 gradient), ReLU gradient, head with residual and loss,
-//                 Adam, weight conversion to bf16 layouts
+//   elementwise   input packing, max-pool gradient (plus the skip gradient),
+//                 ReLU gradient, head with loss in training, Adam, weight
+//                 conversion to bf16 layouts
 #include <math.h>
 #include <string.h>
 
@@ -71,6 +76,14 @@ struct ConvArgs {
     uint32_t Cin, Cout, T, mode, relu;
     uint16_t* pool;       // 3x3 only, or null: also write the 2x2 max pool of the output
     uint32_t pool_cs;     // elements per pooled pixel
+    // 3x3 with 32 output channels only, or null: apply the 1x1 head to the
+    // (bf16) output and write the filled image (and the residual, if asked);
+    // the convolution's own output is then not stored
+    const float* head_w;  // [3][32]
+    const float* head_b;  // [3]
+    const uint32_t* head_rgba;
+    uint32_t* head_out;
+    float* head_res;
 };
 
 // Buffer resource over `bytes` bytes at p (raw, unswizzled): loads at an
@@ -291,7 +304,7 @@ __global__ void __launch_bounds__(kBlock) k_conv(ConvArgs a)
 // tile per wave; the halo of 6 rows for 4 output rows re-reads less of the
 // input than 4 rows for 2, which matters for the memory-bound full-size
 // layers.
-template <int NJ, int TX, bool kUp, int R = 2>
+template <int NJ, int TX, bool kUp, int R = 2, bool kHead = false>
 __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
 {
     constexpr int T = kUp ? 1 : 9, PAD = kUp ? 0 : 1;
@@ -432,12 +445,46 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
                               });
             return;
         }
+        constexpr bool fuse_head = kHead;   // wave = 64 pixels x all 32 channels
+        static_assert(!kHead || (NW == 2 && R == 4), "head fusion needs whole 32-channel pixel rows per wave");
         store_tile<4, NW>(lds + wv * 64 * EP, acc, a.bias, co0 + wco, a.Cout, a.relu != 0,
                           [&](int px) -> uint16_t* {
                               const uint32_t x = q.x0 + wx + px;
-                              if (y >= a.H || x >= a.W) return nullptr;
+                              if (fuse_head || y >= a.H || x >= a.W) return nullptr;
                               return a.out + (((size_t)q.n * a.H + y) * a.W + x) * a.out_cs + co0 + wco;
                           });
+        if (fuse_head) {
+            // one lane per pixel of the wave's row: residual = W h + b over
+            // the 32 bf16 channels, added to the splat colour, clamped,
+            // rounded half up; alpha 255
+            const uint32_t x = q.x0 + wx + (uint32_t)lane;
+            if (y < a.H && x < a.W) {
+                const uint16_t* hp = lds + wv * 64 * EP + lane * EP;
+                float r[3] = {a.head_b[0], a.head_b[1], a.head_b[2]};
+#pragma unroll 1
+                for (int c4 = 0; c4 < 4; ++c4) {
+                    const u32x4 hv = *(const u32x4*)(hp + 8 * c4);
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const int c = 8 * c4 + e;
+                        const float v = bf2f((uint16_t)(hv[e >> 1] >> (16 * (e & 1))));
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) r[k] += a.head_w[k * 32 + c] * v;
+                    }
+                }
+                const size_t p = ((size_t)q.n * a.H + y) * a.W + x;
+                const uint32_t sp = a.head_rgba[p];
+                uint32_t o = 0xFF000000u;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    float v = (float)((sp >> (8 * k)) & 0xFFu) / 255.0f + r[k];
+                    v = v < 0.0f ? 0.0f : (v > 1.0f ? 1.0f : v);
+                    o |= (uint32_t)floorf(v * 255.0f + 0.5f) << (8 * k);
+                    if (a.head_res) a.head_res[p * 3 + k] = r[k];
+                }
+                a.head_out[p] = o;
+            }
+        }
         if (!a.pool) return;
         // 2x2 max pool of the output rows (even H and W, y0 even), from the
         // waves' epilogue tiles; one thread per pooled pixel and 8 channels,
@@ -724,32 +771,6 @@ k_relu_bwd(const uint16_t* __restrict__ dy, uint32_t dy_cs, const uint16_t* __re
     dz[i] = bf2f(y[p * y_cs + c]) > 0.0f ? dy[p * dy_cs + c] : (uint16_t)0;
 }
 
-// Head: residual[p][k] = b[k] + sum_c W[k][c] x[p][c] (fp32). Inference writes
-// the filled image (clamp(rgb / 255 + residual) rounded half up, alpha 255)
-// and optionally the residual.
-__global__ void __launch_bounds__(kBlock)
-k_head_fill(const uint16_t* __restrict__ x, const float* __restrict__ w, const float* __restrict__ b,
-            const uint32_t* __restrict__ rgba, uint32_t P, uint32_t* __restrict__ out,
-            float* __restrict__ residual)
-{
-    const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
-    if (p >= P) return;
-    float r[3] = {b[0], b[1], b[2]};
-    for (int c = 0; c < kBase; ++c) {
-        const float v = bf2f(x[(size_t)p * kBase + c]);
-        for (int k = 0; k < 3; ++k) r[k] += w[k * kBase + c] * v;
-    }
-    const uint32_t s = rgba[p];
-    uint32_t o = 0xFF000000u;
-    for (int k = 0; k < 3; ++k) {
-        float v = (float)((s >> (8 * k)) & 0xFFu) / 255.0f + r[k];
-        v = v < 0.0f ? 0.0f : (v > 1.0f ? 1.0f : v);
-        o |= (uint32_t)floorf(v * 255.0f + 0.5f) << (8 * k);
-        if (residual) residual[(size_t)p * 3 + k] = r[k];
-    }
-    out[p] = o;
-}
-
 // Head in training: loss = mean over 3P of (rgb / 255 + residual - t / 255)^2.
 // Writes dX (bf16 [P][32]) and per-block partial sums: [blocks][32*3 dW, 3 db, 1 loss].
 constexpr int kHeadPart = kBase * 3 + 3 + 1;
@@ -977,13 +998,30 @@ size_t carve(const Net& net, uint32_t N, uint32_t H, uint32_t W, bool training, 
 
 unsigned blocks(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// Head applied in the epilogue of the network's last convolution (inference).
+struct HeadFuse {
+    const float* w;
+    const float* b;
+    const uint32_t* rgba;
+    uint32_t* out;
+    float* res;
+};
+
 hipError_t conv(const uint16_t* in, uint32_t in_cs, const uint16_t* wt, const float* bias, uint16_t* out,
                 uint32_t out_cs, uint32_t N, uint32_t H, uint32_t W, uint32_t Cin, uint32_t Cout,
-                int mode, bool relu, hipStream_t s, uint16_t* pool = nullptr, uint32_t pool_cs = 0)
+                int mode, bool relu, hipStream_t s, uint16_t* pool = nullptr, uint32_t pool_cs = 0,
+                const HeadFuse* hf = nullptr)
 {
     ConvArgs a;
     a.pool = pool;
     a.pool_cs = pool_cs;
+    a.head_w = hf ? hf->w : nullptr;
+    a.head_b = hf ? hf->b : nullptr;
+    a.head_rgba = hf ? hf->rgba : nullptr;
+    a.head_out = hf ? hf->out : nullptr;
+    a.head_res = hf ? hf->res : nullptr;
+    // the fused head needs the 32-channel 3x3 path
+    if (hf && (mode != MODE_SAME3 || Cin != 32 || Cout != 32)) return hipErrorInvalidValue;
     // the fused pool needs a 3x3 layer on the staged path, even sizes
     if (pool && (mode != MODE_SAME3 || Cin % 32 != 0 || (H & 1) || (W & 1) || Cout % 8 != 0))
         return hipErrorInvalidValue;
@@ -1026,7 +1064,9 @@ hipError_t conv(const uint16_t* in, uint32_t in_cs, const uint16_t* wt, const fl
     const uint32_t rows2 = N * ((H + 1) / 2);
     switch (mode) {
     case MODE_SAME3:
-        if (narrow)
+        if (narrow && hf)
+            k_conv3<2, 64, false, 4, true><<<pgrid(N * ((H + 3) / 4) * ((W + 63) / 64), (Cout + 31) / 32), blk, 0, s>>>(a);
+        else if (narrow)
             k_conv3<2, 64, false, 4><<<pgrid(N * ((H + 3) / 4) * ((W + 63) / 64), (Cout + 31) / 32), blk, 0, s>>>(a);
         else
             k_conv3<4, 64, false><<<pgrid(rows2 * ((W + 63) / 64), (Cout + 63) / 64), blk, 0, s>>>(a);
@@ -1113,7 +1153,7 @@ hipError_t prep_weights(const Net& net, const float* th, bool training, const Bu
 
 // Forward pass up to the head input; returns it (P0 x 32, row stride 32).
 hipError_t forward(const Net& net, const float* th, const Bufs& b, uint32_t N, uint32_t H, uint32_t W,
-                   hipStream_t s, const uint16_t** head_in)
+                   hipStream_t s, const uint16_t** head_in, const HeadFuse* hf = nullptr)
 {
     const uint32_t L = net.L;
     const uint16_t* h = b.x0;
@@ -1128,7 +1168,7 @@ hipError_t forward(const Net& net, const float* th, const Bufs& b, uint32_t N, u
         // the second convolution of a level above the last also writes its
         // 2x2 max pool (fused into its epilogue)
         FHV_TRY(conv(b.e0[l], Cl, b.wt + a1.wf_off, th + a1.off_b, o1, o1_cs, N, Hl, Wl, Cl, Cl, MODE_SAME3, true, s,
-                     l + 1 < L ? b.pool[l] : nullptr, Cl));
+                     l + 1 < L ? b.pool[l] : nullptr, Cl, L == 1 ? hf : nullptr));
         if (l + 1 < L) {
             h = b.pool[l];
             h_cs = Cl;
@@ -1147,7 +1187,7 @@ hipError_t forward(const Net& net, const float* th, const Bufs& b, uint32_t N, u
         FHV_TRY(conv(b.cat[l], 2 * Cl, b.wt + c0.wf_off, th + c0.off_b, b.d0[l], Cl, N, Hl, Wl, 2 * Cl, Cl,
                      MODE_SAME3, true, s));
         FHV_TRY(conv(b.d0[l], Cl, b.wt + c1.wf_off, th + c1.off_b, b.d1[l], Cl, N, Hl, Wl, Cl, Cl,
-                     MODE_SAME3, true, s));
+                     MODE_SAME3, true, s, nullptr, 0, l == 0 ? hf : nullptr));
         h = b.d1[l];
         h_cs = Cl;
     }
@@ -1256,12 +1296,11 @@ hipError_t fill(const Device& dev, uint32_t levels, const float* th, const uint3
         FHV_TRY(hipGetLastError());
         FHV_TRY(prep_weights(net, th, false, b, s));
     }
-    const uint16_t* hin = nullptr;
-    FHV_TRY(forward(net, th, b, N, H, W, s, &hin));
+    // the head runs in the epilogue of the last convolution
     const Layer& hd = net.layers[net.head()];
-    ProfScope ps(dev, "fill.misc", s);
-    k_head_fill<<<blocks(P), dim3(kBlock), 0, s>>>(hin, th + hd.off_w, th + hd.off_b, rgba, P, out, residual);
-    return hipGetLastError();
+    const HeadFuse hf{th + hd.off_w, th + hd.off_b, rgba, out, residual};
+    const uint16_t* hin = nullptr;
+    return forward(net, th, b, N, H, W, s, &hin, &hf);
 }
 
 hipError_t train_step(const Device& dev, uint32_t levels, float* th, float* m, float* v, uint32_t step,
