@@ -70,7 +70,10 @@ def params_for(seed, levels):
 
 
 @pytest.mark.parametrize("levels,N,H,W", [(1, 1, 8, 16), (2, 2, 16, 24), (3, 1, 24, 40), (4, 2, 16, 24),
-                                          (4, 1, 8, 8)])
+                                          (4, 1, 8, 8),
+                                          # ragged tiles: rows not a multiple of 4, several
+                                          # 64-pixel column tiles with a partial last one
+                                          (1, 1, 13, 70), (2, 1, 18, 130), (3, 2, 20, 132)])
 def test_forward_parity(F, levels, N, H, W):
     th = params_for(levels, levels)
     rgba, depth, cov, _ = splat_batch(levels, N, H, W)
@@ -89,7 +92,7 @@ def test_forward_parity(F, levels, N, H, W):
     assert d.max() <= 1 and (d > 0).mean() < 1e-3
 
 
-@pytest.mark.parametrize("levels,N,H,W", [(1, 1, 8, 16), (2, 2, 16, 24), (4, 2, 16, 16)])
+@pytest.mark.parametrize("levels,N,H,W", [(1, 1, 8, 16), (2, 2, 16, 24), (4, 2, 16, 16), (2, 1, 18, 130)])
 def test_gradient_parity(F, levels, N, H, W):
     import torch
     th = params_for(7 + levels, levels)
