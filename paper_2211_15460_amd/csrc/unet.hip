@@ -491,39 +491,44 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
         // the first largest of the window in (0,0), (0,1), (1,0), (1,1) order
         __syncthreads();
         constexpr int PCH = TN / 8;   // 16-byte channel runs per pooled pixel
-        static_assert((TX / 2) * (R / 2) * PCH == kBlock, "one pooled run per thread");
-        const uint32_t c8 = threadIdx.x % PCH, p2 = (threadIdx.x / PCH) % (TX / 2), pr = threadIdx.x / (PCH * (TX / 2));
-        const uint32_t xs = q.x0 + 2 * p2, ys = q.y0 + 2 * pr;
-        if (xs >= a.W || ys >= a.H || co0 + 8 * c8 >= a.Cout) return;
-        u32x4 v[4];
+        constexpr int RUNS = (TX / 2) * (R / 2) * PCH;
+        static_assert(RUNS % kBlock == 0, "whole passes over the pooled runs");
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t r = 2 * pr + (k >> 1), px = 2 * p2 + (k & 1);   // within the tile
-            const uint32_t w = R == 4 ? r : (TX == 128 ? 2 * r + px / 64 : 2 * r + (8 * c8) / (16 * NW));
-            const uint32_t col = (R == 2 && TX == 64) ? (8 * c8) % (16 * NW) : 8 * c8;
-            v[k] = *(const u32x4*)&lds[w * 64 * EP + (px % 64) * EP + col];
-        }
-        u32x4 o;
+        for (int it = 0; it < RUNS / kBlock; ++it) {
+            const uint32_t run = threadIdx.x + it * kBlock;
+            const uint32_t c8 = run % PCH, p2 = (run / PCH) % (TX / 2), pr = run / (PCH * (TX / 2));
+            const uint32_t xs = q.x0 + 2 * p2, ys = q.y0 + 2 * pr;
+            if (xs >= a.W || ys >= a.H || co0 + 8 * c8 >= a.Cout) continue;
+            u32x4 v[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            uint32_t word = 0;
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                float m = -INFINITY;
-                uint32_t best = 0;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const uint32_t b = (v[k][c] >> (16 * h)) & 0xFFFFu;
-                    if (bf2f((uint16_t)b) > m) {
-                        m = bf2f((uint16_t)b);
-                        best = b;
-                    }
-                }
-                word |= best << (16 * h);
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t r = 2 * pr + (k >> 1), px = 2 * p2 + (k & 1);   // within the tile
+                const uint32_t w = R == 4 ? r : (TX == 128 ? 2 * r + px / 64 : 2 * r + (8 * c8) / (16 * NW));
+                const uint32_t col = (R == 2 && TX == 64) ? (8 * c8) % (16 * NW) : 8 * c8;
+                v[k] = *(const u32x4*)&lds[w * 64 * EP + (px % 64) * EP + col];
             }
-            o[c] = word;
+            u32x4 o;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                uint32_t word = 0;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    float m = -INFINITY;
+                    uint32_t best = 0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const uint32_t bb = (v[k][c] >> (16 * h)) & 0xFFFFu;
+                        if (bf2f((uint16_t)bb) > m) {
+                            m = bf2f((uint16_t)bb);
+                            best = bb;
+                        }
+                    }
+                    word |= best << (16 * h);
+                }
+                o[c] = word;
+            }
+            *(u32x4*)(a.pool + (((size_t)q.n * (a.H / 2) + ys / 2) * (a.W / 2) + xs / 2) * a.pool_cs + co0 + 8 * c8) = o;
         }
-        *(u32x4*)(a.pool + (((size_t)q.n * (a.H / 2) + ys / 2) * (a.W / 2) + xs / 2) * a.pool_cs + co0 + 8 * c8) = o;
     };
 
     uint32_t t = blockIdx.x, cc = 0;
