@@ -198,15 +198,18 @@ __device__ __forceinline__ void wave_lds_sync()
 }
 
 constexpr int kWaveRecs = 1024;            // records per wave-sized brick
-constexpr int kPerLane = kWaveRecs / kWave;  // 16
+constexpr int kSmallRecs = 256;            // bricks up to this size take the smaller variant
 constexpr int kKeysPerLane = kBrickKeys / kWave;  // 8
 
-// One wave per brick of at most kWaveRecs records, with no workgroup
-// barriers (one-wave workgroups): records held in registers (16 per lane) are counted per key in
+// One wave per brick of kLo < n <= kRecs records, with no workgroup
+// barriers (one-wave workgroups; the variant for small bricks needs less
+// LDS and fewer registers, so more of them share a compute unit): records
+// held in registers (kRecs / 64 per lane) are counted per key in
 // LDS, the 512 counts scanned across the wave (8 consecutive keys per lane),
 // the records grouped by key in LDS through cursors, and every record
 // written straight to its final slot: its key's offset plus its rank inside
 // the key's run in canonical order, with w3 = the key's table rank.
+template <int kRecs, int kLo>
 __global__ void __launch_bounds__(kWave)
 k_brick_wave(const uint4* __restrict__ stage, const uint32_t* __restrict__ brick_cnt,
              const uint32_t* __restrict__ brick_off, const uint32_t* __restrict__ brick_rank,
@@ -214,14 +217,15 @@ k_brick_wave(const uint4* __restrict__ stage, const uint32_t* __restrict__ brick
              uint4* __restrict__ frag, uint64_t* __restrict__ oct_key,
              uint32_t* __restrict__ oct_off, uint32_t* __restrict__ oct_cnt, uint64_t cap_occ)
 {
-    __shared__ uint4 buf[kWaveRecs];
+    constexpr int kPerLane = kRecs / kWave;
+    __shared__ uint4 buf[kRecs];
     __shared__ uint32_t off[kBrickKeys], rank[kBrickKeys], cur[kBrickKeys];
     const int lane = __lane_id();
     const uint32_t nl = (uint32_t)(*list_total >> 32);
     for (uint32_t li = blockIdx.x; li < nl; li += gridDim.x) {
         const uint32_t b = list[li];
         const uint32_t n = brick_cnt[b];
-        if (n == 0 || n > (uint32_t)kWaveRecs) continue;
+        if (n <= (uint32_t)kLo || n > (uint32_t)kRecs) continue;
         const uint32_t o = brick_off[b], base_rank = brick_rank[b];
         uint4 r[kPerLane];
 #pragma unroll
@@ -490,7 +494,11 @@ hipError_t compact_launch(const Device& dev, const fhv_lists* L, const fhv_captu
     ProfScope ps(dev, "compact.brick", s);
     const uint64_t wmax = (uint64_t)dev.cus * 64;
     const unsigned gwave = (unsigned)(n_brick < wmax ? n_brick : wmax);
-    k_brick_wave<<<dim3(gwave ? gwave : 1), dim3(kWave), 0, s>>>(
+    k_brick_wave<kSmallRecs, 0><<<dim3(gwave ? gwave : 1), dim3(kWave), 0, s>>>(
+        w.stage, w.brick_cnt, w.brick_off, w.brick_rank, w.list, w.list_total, (uint4*)out->frag,
+        out->oct_key, out->oct_off, out->oct_cnt, out->cap_occ);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_brick_wave<kWaveRecs, kSmallRecs><<<dim3(gwave ? gwave : 1), dim3(kWave), 0, s>>>(
         w.stage, w.brick_cnt, w.brick_off, w.brick_rank, w.list, w.list_total, (uint4*)out->frag,
         out->oct_key, out->oct_off, out->oct_cnt, out->cap_occ);
     if ((e = hipGetLastError()) != hipSuccess) return e;
