@@ -115,6 +115,17 @@ def src_digest() -> str:
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
 
 
+def measured_scope(scope: str):
+    """(scope's counter figures, calibration) from profiles/traffic.json, or
+    (None, None) when the kernels have changed since they were taken."""
+    if not os.path.exists(TRAFFIC_JSON):
+        return None, None
+    t = json.load(open(TRAFFIC_JSON))
+    if t.get("src_sha256") != src_digest():
+        return None, None
+    return t.get("scopes", {}).get(scope), t.get("calibration", {})
+
+
 def measured_traffic(scope: str):
     """HBM bytes per launch of a scope from the committed rocprofv3 counter
     summary (profiles/traffic.json), or None when the kernels have changed
@@ -135,12 +146,18 @@ def _scope_of(kernel: str):
     return None
 
 
-def traffic_from(fetch_dir: str, write_dir: str, copy_mib: int) -> dict:
+def traffic_from(fetch_dir: str, write_dir: str, copy_mib: int, atomic_dir: str | None = None) -> dict:
     """Per-scope HBM bytes per launch from two rocprofv3 --pmc runs of this
     benchmark (FETCH_SIZE, then WRITE_SIZE; --output-format csv), each
     calibrated by what the counter reads for the plain device copy of
     copy_mib MiB that the benchmark runs first. Uses the dispatches of the
-    last step (from the last triangle setup on); run with --no-train."""
+    last step (from the last triangle setup on); run with --no-train.
+
+    With atomic_dir (a third run, counter TCC_ATOMIC_sum, with the ceiling
+    probes on), each scope also gets the memory-side atomic requests per
+    launch, and the calibration the requests per atomic operation of the
+    probes: one per 128-byte line ("sparse", the add probe on HBM lines) and
+    one per 8-byte word ("dense", the minimum probe on HBM words)."""
     import csv
     import glob
     import re
@@ -151,7 +168,7 @@ def traffic_from(fetch_dir: str, write_dir: str, copy_mib: int) -> dict:
             raise SystemExit(f"no counter_collection.csv under {d}")
         per = {}
         for r in csv.DictReader(open(f[0])):
-            if r["Counter_Name"] != counter:
+            if r["Counter_Name"] not in (counter, counter + "_sum"):
                 continue
             did = int(r["Dispatch_Id"])
             name = re.sub(r"^void ", "", r["Kernel_Name"])
@@ -164,7 +181,7 @@ def traffic_from(fetch_dir: str, write_dir: str, copy_mib: int) -> dict:
     for counter, d, key in (("FETCH_SIZE", fetch_dir, "read_bytes"), ("WRITE_SIZE", write_dir, "write_bytes")):
         rows = load(d, counter)
         # the calibration copy is the largest device copy of the run
-        copies = [v for n, v in rows if "copy" in n.lower()]
+        copies = [v for n, v in rows if n.startswith("__amd_rocclr_copyBuffer")]
         if not copies:
             raise SystemExit("the calibration copy is missing from the trace")
         big = max(copies)
@@ -184,6 +201,28 @@ def traffic_from(fetch_dir: str, write_dir: str, copy_mib: int) -> dict:
         for sc, (b, c) in acc.items():
             ent = out["scopes"].setdefault(sc, {"launches_per_step": c})
             ent[key] = b / c
+    if atomic_dir:
+        rows = load(atomic_dir, "TCC_ATOMIC")
+        add = [v for n, v in rows if n.startswith("k_probe_atomic<1")]
+        mn = [v for n, v in rows if n.startswith("k_probe_atomic<3")]
+        if len(add) < 6 or len(mn) < 18:
+            raise SystemExit("the ceiling probes are missing from the atomic-counter run")
+        # probe order per operation: hbm, llc, dense_hbm, dense_llc, one
+        # warm-up and five timed launches each (see ceilings())
+        sparse_ops, dense_ops = (2 << 30) // 128, (2 << 30) // 8
+        out["calibration"]["TCC_ATOMIC"] = {
+            "requests_per_op_sparse": sum(add[1:6]) / 5 / sparse_ops,
+            "requests_per_op_dense": sum(mn[13:18]) / 5 / dense_ops}
+        last = max(i for i, (n, _) in enumerate(rows) if n.startswith("k_setup"))
+        acc = {}
+        for n, v in rows[last:]:
+            sc = _scope_of(n)
+            if sc is None:
+                continue
+            b, c = acc.get(sc, (0.0, 0))
+            acc[sc] = (b + v, c + 1)
+        for sc, (b, c) in acc.items():
+            out["scopes"].setdefault(sc, {"launches_per_step": c})["atomic_requests"] = b / c
     return out
 
 
@@ -207,12 +246,13 @@ def unet_flops_per_pixel(levels: int = 4, training: bool = False) -> float:
     return 3 * fwd - first if training else fwd
 
 
-def learned_fill_report(torch, fhv, scenes, train_steps: int = 600):
+def learned_fill_report(torch, fhv, scenes, train_steps: int = 600, eval_seeds: int = 10):
     """Train the fill on splats of separate scenes (octree depth 8, 1080p,
     random orbit angles) against reference renders of the same views (the
     library's per-pixel capture of the triangles, nearest fragment kept),
-    then compare PSNR of fill and plain splat on a held-out scene at 30 and
-    60 degrees. Returns the report and the trained model."""
+    then compare PSNR of fill and plain splat on held-out scenes (seeds
+    0..eval_seeds-1, which no training scene uses) at 30 and 60 degrees.
+    Returns the report and the trained model."""
     import numpy as np
     from paper_2211_15460_amd import learned_fill as LF
     L, W, H = 8, 1920, 1080
@@ -240,15 +280,20 @@ def learned_fill_report(torch, fhv, scenes, train_steps: int = 600):
     res = {"train_steps": train_steps, "batch": "8 x 256 x 256", "train_ms_per_step": ms,
            "train_tflops": unet_flops_per_pixel(4, True) * 8 * 256 * 256 / (ms * 1e-3) / 1e12,
            "octree_levels": L, "eval": []}
-    mesh = LF.training_scene(0)
-    for th in (30.0, 60.0):
-        v = scenes.cube_view(th, L, W, H)
-        img, _ = LF.render_splats(mesh, L, [v])
-        ref = LF.reference_render(mesh, L, v)
-        out = model.fill(img)
-        res["eval"].append({"theta": th, "psnr_splat_db": LF.psnr_rgb(img.rgba, ref),
-                            "psnr_fill_db": LF.psnr_rgb(out, ref)})
-    res["margin_db"] = min(e["psnr_fill_db"] - e["psnr_splat_db"] for e in res["eval"])
+    for seed in range(eval_seeds):
+        mesh = LF.training_scene(seed)
+        for th in (30.0, 60.0):
+            v = scenes.cube_view(th, L, W, H)
+            img, _ = LF.render_splats(mesh, L, [v])
+            ref = LF.reference_render(mesh, L, v)
+            out = model.fill(img)
+            res["eval"].append({"seed": seed, "theta": th, "psnr_splat_db": LF.psnr_rgb(img.rgba, ref),
+                                "psnr_fill_db": LF.psnr_rgb(out, ref)})
+    gain = np.array([e["psnr_fill_db"] - e["psnr_splat_db"] for e in res["eval"]])
+    res["margin_db"] = float(gain.min())
+    res["gain_db"] = {"mean": float(gain.mean()), "std": float(gain.std()), "min": float(gain.min()),
+                      "max": float(gain.max()), "n": int(gain.size),
+                      "over": f"held-out scenes of seeds 0..{eval_seeds - 1} at 30 and 60 degrees"}
     res["reference"] = "library per-pixel capture of the triangles in the view, nearest fragment"
     return res, model
 
@@ -290,6 +335,86 @@ def hbm_roofline(kernels: dict) -> dict:
     dk = kernels[dom]
     return {"bound": "hbm", "kernel": dom, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": dk["gbs"] / HBM_PEAK_GBS if dk["gbs"] else None, "traffic": None}
+
+
+def ceilings(torch, fhv, reps: int = 5) -> dict:
+    """Measured ceilings beside the vendor peaks (fhv_probe): plain copy
+    bandwidth over 2 GiB, and the rate of uncontended device-scope atomics
+    on a 2 GiB buffer (lines in HBM, one pass) and a 64 MiB one (lines held
+    by the last-level cache, 32 passes): one atomic per 128-byte line
+    ("sparse", as list-head exchanges land), or on every 8-byte word
+    ("dense", as neighbouring pixels of a z-buffer do). Each figure is the
+    mean of `reps` launches after one warm-up, from HIP events on the launch
+    stream; buffers are reset before every launch, outside the timing."""
+    big = torch.empty(2 << 30, dtype=torch.uint8, device="cuda")
+    small = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    cases = [("copy", fhv.FHV_PROBE_COPY, big, 128, 1, "probe.copy")]
+    for op, kind, scope in (("add_u32", fhv.FHV_PROBE_ADD_U32, "probe.add_u32"),
+                            ("exch_u32", fhv.FHV_PROBE_EXCH_U32, "probe.exch_u32"),
+                            ("min_u64", fhv.FHV_PROBE_MIN_U64, "probe.min_u64")):
+        cases.append((op + ".hbm", kind, big, 128, 1, scope))
+        cases.append((op + ".llc", kind, small, 128, 32, scope))
+        if kind != fhv.FHV_PROBE_EXCH_U32:
+            cases.append((op + ".dense_hbm", kind, big, 8, 1, scope))
+            cases.append((op + ".dense_llc", kind, small, 8, 32, scope))
+    res = {}
+    for name, kind, buf, line, passes, scope in cases:
+        tot = 0.0
+        for r in range(reps + 1):
+            buf.fill_(0xFF)
+            torch.cuda.synchronize()
+            fhv.profile_begin()
+            fhv.probe(kind, buf, line, passes)
+            prof = fhv.profile_end()
+            if r > 0:
+                tot += prof[scope][1]
+        ms = tot / reps
+        if kind == fhv.FHV_PROBE_COPY:
+            res["copy_gbs"] = buf.numel() / (ms * 1e-3) / 1e9
+        else:
+            res.setdefault("atomics_g_per_s", {})[name] = buf.numel() // line * passes / (ms * 1e-3) / 1e9
+    del big, small
+    res["note"] = ("copy: GB/s read+written over 2 GiB; atomics: G ops/s; hbm = 2 GiB buffer, one pass; "
+                   "llc = 64 MiB buffer, 32 passes; one atomic per 128-B line, or per 8-B word (dense); "
+                   "exch returns its value")
+    return res
+
+
+def add_ceilings(args, out: dict, torch, fhv, kernels: dict, n_exch: int | None, counters: bool = False):
+    """Adds the measured ceilings, the streaming kernels' fraction of the
+    measured copy bandwidth and, when the capture keeps list heads, the
+    raster's head exchanges (one returning u32 atomic per fragment, on a head
+    array in HBM) against the measured exchange rate. `counters`: the
+    committed counter figures were taken on this workload, so the splat's
+    measured atomic requests are reported too."""
+    if args.no_ceilings:
+        return
+    ceil = ceilings(torch, fhv)
+    out["ceilings"] = ceil
+    out["copy_frac"] = {k: kernels[k]["gbs"] / ceil["copy_gbs"] for k in kernels
+                        if k in ("compact.scatter", "splat.zclear", "splat.resolve", "capture.reset")
+                        and kernels[k].get("gbs")}
+    r_ms = kernels.get("capture.raster", {}).get("avg_ms")
+    if n_exch and r_ms:
+        rate = n_exch / (r_ms * 1e-3) / 1e9
+        peak = ceil["atomics_g_per_s"]["exch_u32.hbm"]
+        out["atomic_roofline"] = {"kernel": "capture.raster", "achieved": rate, "peak": peak,
+                                  "unit": "G atomics/s", "frac": rate / peak,
+                                  "what": "list-head exchanges, one per fragment, against the measured rate "
+                                          "of uncontended returning u32 exchanges on HBM lines"}
+    # the splat's z-buffer minima are data dependent (a pixel already
+    # holding a nearer fragment is skipped): their memory-side requests come
+    # from the committed counter run, compared with the probes' request rates
+    sc, cal = measured_scope("splat.splat") if counters else (None, None)
+    s_ms = kernels.get("splat.splat", {}).get("avg_ms")
+    if sc and "atomic_requests" in sc and "TCC_ATOMIC" in (cal or {}) and s_ms:
+        c = cal["TCC_ATOMIC"]
+        a = ceil["atomics_g_per_s"]
+        rate = sc["atomic_requests"] / (s_ms * 1e-3) / 1e9
+        peaks = {"min_u64.llc": a["min_u64.llc"] * c["requests_per_op_sparse"],
+                 "min_u64.dense_llc": a["min_u64.dense_llc"] * c["requests_per_op_dense"]}
+        out["splat_atomics"] = {"requests_per_launch": sc["atomic_requests"], "achieved_g_per_s": rate,
+                                "probe_requests_g_per_s": peaks, "unit": "G memory-side atomic requests/s"}
 
 
 def timed(torch, fn, steps: int) -> float:
@@ -369,6 +494,7 @@ def bench_batch64(args, torch, fhv, scenes):
         "host": host_info(),
         "device": torch.cuda.get_device_name(0),
     }
+    add_ceilings(args, out, torch, fhv, kernels, None)     # a batch keeps no list heads
     if not args.no_cpu_baseline:
         import oracle
         oracle.lib()
@@ -387,6 +513,78 @@ def bench_batch64(args, torch, fhv, scenes):
                                "sample": f"the first {n_s} scenes of the batch, each captured, compacted "
                                          f"and splatted into its 8 views ({n_f} fragments, {t_all:.1f} s "
                                          "on one core)"}
+    return out
+
+
+def bench_ppfl64(args, torch, fhv, scenes):
+    """The per-pixel case: 64 random clip-space triangles captured into
+    per-pixel fragment lists at 128x128 (pool of 2^18 records), compacted
+    into per-pixel arrays and splatted at 30 degrees into one 128x128 view.
+    About 80k fragments: a latency-bound correctness configuration, timed
+    for completeness (the roofline entry is the dominant kernel's, with no
+    claim of being near it)."""
+    Wc = Hc = 128
+    cap = 1 << 18
+    mesh = scenes.ppfl_plain(SEED)
+    views = [scenes.ppfl_view(30.0, Wc, Hc)]
+    d = fhv.desc(fhv.FHV_PPFL, Wc, Hc)
+    dm = fhv.to_device(mesh)
+    lists = fhv.alloc_lists(d, cap)
+    pofa = fhv.alloc_pofa(cap)
+    imgs = fhv.alloc_images(1, Wc, Hc)
+    ws_c = torch.empty(fhv.capture_workspace(d, mesh.n_tri), dtype=torch.uint8, device="cuda")
+    ws_k = torch.empty(fhv.compact_workspace(d, cap), dtype=torch.uint8, device="cuda")
+    vs = fhv.views_struct(views)
+
+    def step():
+        fhv.capture(dm, d, lists, ws_c)
+        fhv.compact(lists, d, pofa, ws_k)
+        fhv.splat(pofa, d, views, imgs, vs)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    F = int(lists.counter.item())
+    assert 0 < F <= cap
+    fhv.profile_begin()
+    t0 = time.perf_counter()
+    ms = timed(torch, step, args.steps)
+    wall = time.perf_counter() - t0
+    prof = fhv.profile_end()
+    n_occ = int(pofa.n_occ.item())
+    algo = algorithmic_bytes(F, n_occ, mesh.n_tri, Wc * Hc, 1, Wc * Hc)
+    kernels = kernel_table(prof, algo)
+    stage = lambda pre: sum(kernels[k]["avg_ms"] * kernels[k]["launches"] / args.steps
+                            for k in kernels if k.startswith(pre))
+    out = {
+        "metric": "fragments captured/s; 1080p novel views/s; learned-fill vs plain-splat PSNR",
+        "value": F / (ms * 1e-3), "unit": "fragments/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "ppfl plain: 64 random clip-space triangles (seed 0), 128x128 per-pixel "
+                               "lists, pool 2^18, one 128x128 splat at 30 deg",
+                   "n_tri": mesh.n_tri, "fragments": F, "occupied_pixels": n_occ, "views": 1,
+                   "view_size": [Wc, Hc]},
+        "stage_ms": {"capture": stage("capture."), "compact": stage("compact."), "splat": stage("splat.")},
+        "kernels": kernels,
+        "roofline": hbm_roofline(kernels),
+        "wall_s_timed": wall,
+        "host": host_info(),
+        "device": torch.cuda.get_device_name(0),
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.lib()
+        n, t_all = 0, 0.0
+        while t_all < 10.0:
+            t1 = time.perf_counter()
+            oh, op, Fs = oracle.capture_ppfl(mesh, Wc, Hc, cap)
+            r = oracle.compact(oh, op, Fs)
+            oracle.splat(0, r["key"], r["frag"], views, width_cap=Wc)
+            t_all += time.perf_counter() - t1
+            n += 1
+        out["cpu_baseline"] = {"value": Fs * n / t_all, "unit": "fragments/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the whole step ({Fs} fragments), {n} runs, {t_all:.1f} s on one core"}
     return out
 
 
@@ -457,6 +655,7 @@ def bench_large5m(args, torch, fhv, scenes):
         "host": host_info(),
         "device": torch.cuda.get_device_name(0),
     }
+    add_ceilings(args, out, torch, fhv, kernels, F)
     if not args.no_cpu_baseline:
         # the oracle cannot hold 8^11 list heads: it captures the keys of one
         # level-3 sub-cube (8^8 keys) from the triangles whose snapped
@@ -487,8 +686,8 @@ def bench_large5m(args, torch, fhv, scenes):
     return out
 
 
-WORKLOADS = {"pofl200k": None, "batch64": bench_batch64, "large5m": bench_large5m}
-DEFAULT_STEPS = {"pofl200k": (50, 5), "batch64": (10, 2), "large5m": (4, 1)}
+WORKLOADS = {"pofl200k": None, "batch64": bench_batch64, "large5m": bench_large5m, "ppfl64": bench_ppfl64}
+DEFAULT_STEPS = {"pofl200k": (50, 5), "batch64": (10, 2), "large5m": (4, 1), "ppfl64": (200, 20)}
 
 
 def main():
@@ -499,18 +698,24 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="pofl200k",
                     help="pofl200k (default): 200k triangles, depth 9, 3 x 1080p views + fill; "
                          "batch64: 64 scenes x 8 views at 720p in one graph; "
-                         "large5m: 5M triangles, depth 11, 16 x 4K views")
+                         "large5m: 5M triangles, depth 11, 16 x 4K views; "
+                         "ppfl64: 64 triangles, per-pixel lists at 128x128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-train", action="store_true", help="skip the learned-fill training report")
+    ap.add_argument("--no-ceilings", action="store_true",
+                    help="skip the measured copy and atomic ceilings (fhv_probe)")
     ap.add_argument("--copy-mib", type=int, default=256,
                     help="size of a plain device copy run once before the steps, so that "
                          "hardware byte counters can be calibrated against a known size")
-    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
-                    help="write profiles/traffic.json from two rocprofv3 --pmc runs of this "
-                         "benchmark (FETCH_SIZE, WRITE_SIZE; csv output) and exit")
+    ap.add_argument("--traffic-from", nargs="+", metavar="DIR",
+                    help="write profiles/traffic.json from rocprofv3 --pmc runs of this benchmark "
+                         "(FETCH_SIZE dir, WRITE_SIZE dir[, TCC_ATOMIC_sum dir]; csv output) and exit")
     args = ap.parse_args()
     if args.traffic_from:
-        t = traffic_from(args.traffic_from[0], args.traffic_from[1], args.copy_mib)
+        if len(args.traffic_from) not in (2, 3):
+            raise SystemExit("--traffic-from takes two or three directories")
+        t = traffic_from(*args.traffic_from[:2], args.copy_mib,
+                         args.traffic_from[2] if len(args.traffic_from) == 3 else None)
         json.dump(t, open(TRAFFIC_JSON, "w"), indent=1)
         print(json.dumps(t["scopes"]))
         return
@@ -644,6 +849,7 @@ def main():
         "host": host_info(),
         "device": torch.cuda.get_device_name(0),
     }
+    add_ceilings(args, out, torch, fhv, kernels, F, counters=True)
     if not args.no_train:
         out["learned_fill"], _ = learned_fill_report(torch, fhv, scenes)
     if not args.no_cpu_baseline:

@@ -355,6 +355,31 @@ FHV_API fhv_status fhv_profile_begin(fhv_ctx* ctx);
 FHV_API fhv_status fhv_profile_end(fhv_ctx* ctx, fhv_kernel_stat* out, uint32_t cap,
                                    uint32_t* n_out);
 
+/* Measurement probes: the ceilings against which the capture, compaction
+ * and splat kernels are measured (roofline of memory-side atomics and of
+ * HBM copies). Not an operation of the method.
+ *   FHV_PROBE_COPY      second half of buf <- first half, 16-byte vector
+ *                       loads and stores (bytes a multiple of 32)
+ *   FHV_PROBE_ADD_U32   per line of `line` bytes and per pass: atomic add of
+ *                       1 to the line's first u32, result unused
+ *   FHV_PROBE_EXCH_U32  atomic exchange of the line's first u32 with
+ *                       pass + 1, result used (each thread writes the sum of
+ *                       what it received into the line's second u32)
+ *   FHV_PROBE_MIN_U64   atomic minimum of the line's first u64 with
+ *                       ((passes - pass) << 32 | line index), result unused
+ * Lines are uncontended: one atomic per line per pass. `buf` is a device
+ * pointer owned by the caller, 16-byte aligned; `line` is a power of two in
+ * [8, 4096] (atomic probes), `passes` in [1, 1024]; FHV_EINVAL otherwise.
+ * Launches on `stream`; timed by fhv_profile_begin/end as "probe.copy",
+ * "probe.add_u32", "probe.exch_u32", "probe.min_u64". */
+#define FHV_PROBE_COPY 0u
+#define FHV_PROBE_ADD_U32 1u
+#define FHV_PROBE_EXCH_U32 2u
+#define FHV_PROBE_MIN_U64 3u
+
+FHV_API fhv_status fhv_probe(fhv_ctx* ctx, uint32_t kind, void* buf, uint64_t bytes, uint32_t line,
+                             uint32_t passes, fhv_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -407,6 +407,21 @@ fhv_status fhv_splat(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_capture_des
                                         arrays->cap_frag, (hipStream_t)stream));
 }
 
+fhv_status fhv_probe(fhv_ctx* ctx, uint32_t kind, void* buf, uint64_t bytes, uint32_t line,
+                     uint32_t passes, fhv_stream stream)
+{
+    if (!ctx || !buf || ((uintptr_t)buf & 15) || kind > FHV_PROBE_MIN_U64) return FHV_EINVAL;
+    if (kind == FHV_PROBE_COPY) {
+        if (bytes < 32 || bytes % 32 != 0) return FHV_EINVAL;
+    } else {
+        if (line < 8 || line > 4096 || (line & (line - 1)) || bytes < line) return FHV_EINVAL;
+        if (passes < 1 || passes > 1024) return FHV_EINVAL;
+    }
+    fhv_status st = set_device(ctx);
+    if (st != FHV_OK) return st;
+    return hip_status(fhv::probe_launch(ctx->dev, kind, buf, bytes, line, passes, (hipStream_t)stream));
+}
+
 static bool fill_dims_ok(uint32_t levels, uint32_t n, uint32_t h, uint32_t w)
 {
     if (levels < 1 || levels > 4 || n == 0 || h == 0 || w == 0) return false;

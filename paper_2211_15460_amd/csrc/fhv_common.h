@@ -198,6 +198,11 @@ hipError_t splat_batch_launch(const Device& dev, const fhv_pofa* a, uint32_t lev
                               uint64_t* zbuf, uint32_t* rgba, float* depth, uint8_t* cov,
                               uint64_t max_frag, hipStream_t s);
 
+// Measurement probes (fhv_probe): copy over the buffer's two halves, or
+// one atomic per line and pass.
+hipError_t probe_launch(const Device& dev, uint32_t kind, void* buf, uint64_t bytes, uint32_t line,
+                        uint32_t passes, hipStream_t s);
+
 namespace nn {
 uint64_t param_count(uint32_t levels);
 size_t fill_ws_bytes(uint32_t levels, uint32_t N, uint32_t H, uint32_t W, bool training);

@@ -292,8 +292,9 @@ __global__ void __launch_bounds__(kBlock) k_conv(ConvArgs a)
 // tap loop reads only LDS: the next tap's operands are read while the
 // current tap's matrix products run, and the next chunk's halo and weights
 // are loaded into registers meanwhile. Rows of 32 channels are padded to
-// 40 bf16 (80 B): 16 consecutive rows at one channel offset then fall in
-// distinct LDS banks.
+// 48 bf16 (96 B): the 16-byte reads of 16 consecutive rows at 4 channel
+// offsets (one MFMA operand) then run at the LDS's full rate, which rows of
+// 64 or 80 bytes do not (bank conflicts; measured on gfx950).
 //
 // kUp: the same structure for the 2x2 stride-2 transposed convolution,
 // which is a 1x1 convolution onto 4 Cout columns (sub-position, channel):
@@ -308,7 +309,7 @@ template <int NJ, int TX, bool kUp, int R = 2, bool kHead = false>
 __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
 {
     constexpr int T = kUp ? 1 : 9, PAD = kUp ? 0 : 1;
-    constexpr int HP = TX + 2 * PAD, RP = R + 2 * PAD, TN = 16 * NJ, PITCH = 40;
+    constexpr int HP = TX + 2 * PAD, RP = R + 2 * PAD, TN = 16 * NJ, PITCH = 48;
     // waves: R = 4 -> one row each; TX = 128 -> (row, 64-pixel half);
     // TX = 64 -> (row, half of the channels)
     constexpr int NW = (R == 4 || TX == 128) ? NJ : NJ / 2;   // MFMA column tiles per wave

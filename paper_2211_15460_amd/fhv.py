@@ -77,7 +77,7 @@ EXPORTS = ["fhv_create", "fhv_destroy", "fhv_status_str", "fhv_capture_workspace
            "fhv_compact_workspace", "fhv_compact", "fhv_splat", "fhv_profile_begin",
            "fhv_profile_end", "fhv_unet_param_count", "fhv_fill_workspace", "fhv_fill",
            "fhv_fill_train_step", "fhv_get_tuning", "fhv_set_tuning", "fhv_batch_workspace",
-           "fhv_batch_run"]
+           "fhv_batch_run", "fhv_probe"]
 
 _lib = None
 _ctx: dict[int, C.c_void_p] = {}
@@ -119,11 +119,12 @@ def lib():
         L.fhv_batch_workspace.restype = C.c_size_t
         L.fhv_batch_run.argtypes = [P, C.POINTER(BatchMesh_), C.POINTER(BatchViews_), C.POINTER(Lists_),
                                     C.POINTER(Pofa_), P, P, P, P, P, C.c_size_t, C.c_uint32, P]
+        L.fhv_probe.argtypes = [P, C.c_uint32, P, C.c_uint64, C.c_uint32, C.c_uint32, P]
         L.fhv_profile_begin.argtypes = [P]
         L.fhv_profile_end.argtypes = [P, C.POINTER(KernelStat_), C.c_uint32, C.POINTER(C.c_uint32)]
         for f in ("fhv_create", "fhv_destroy", "fhv_capture", "fhv_compact", "fhv_splat",
                   "fhv_profile_begin", "fhv_profile_end", "fhv_fill", "fhv_fill_train_step",
-                  "fhv_get_tuning", "fhv_set_tuning", "fhv_batch_run"):
+                  "fhv_get_tuning", "fhv_set_tuning", "fhv_batch_run", "fhv_probe"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -329,6 +330,17 @@ def profile_end() -> dict[str, tuple[int, float]]:
     _check(lib().fhv_profile_end(ctx(), arr, 64, C.byref(n)), "fhv_profile_end")
     return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms))
             for i in range(min(n.value, 64))}
+
+
+FHV_PROBE_COPY, FHV_PROBE_ADD_U32, FHV_PROBE_EXCH_U32, FHV_PROBE_MIN_U64 = 0, 1, 2, 3
+
+
+def probe(kind: int, buf: torch.Tensor, line: int = 128, passes: int = 1):
+    """One ceiling probe over `buf` (device tensor, any dtype) on torch's
+    current stream: a copy of its first half onto its second, or one
+    atomic per `line`-byte line and pass."""
+    nbytes = buf.numel() * buf.element_size()
+    _check(lib().fhv_probe(ctx(), kind, _ptr(buf), nbytes, line, passes, _stream()), "fhv_probe")
 
 
 # ------------------------------------------------------------------ learned fill

@@ -101,3 +101,8 @@ def test_batch_workspace_shapes(F):
 
 def L_ws(F, m, v, cap):
     return F.lib().fhv_batch_workspace(C.byref(m), C.byref(v), cap)
+
+
+def test_probe_rejects_missing_context(F):
+    L = F.lib()
+    assert L.fhv_probe(None, 0, None, 4096, 128, 1, None) == -1
