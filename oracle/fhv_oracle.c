@@ -30,6 +30,15 @@
  *                             novel view, covers at least one pixel, and the
  *                             nearest fragment wins (deferred-shading
  *                             emulation).
+ *   ray casting               Sec. 3.3 evaluation by ray casting: per output
+ *                             pixel, every fragment the pixel's ray meets,
+ *                             ordered from the viewer outward, composited
+ *                             front to back with its alpha ("R/T"), or the
+ *                             nearest one alone ("R"); accumulation stops at
+ *                             a transmittance threshold. Written as its
+ *                             definition (gather, sort, composite); the
+ *                             octree traversal that finds the fragments is
+ *                             the GPU's business.
  *   direct raster             Sec. 3.2 rasterization of the triangles
  *                             themselves in the novel view with a depth test;
  *                             the reference image for the splat.
@@ -563,6 +572,91 @@ void orc_splat(int mode, uint32_t width_cap, uint32_t levels, const uint64_t* oc
         }
         base += (size_t)W * H;
     }
+}
+
+/* ------------------------------------------------------------ ray casting */
+
+static int cmp_u64(const void* a, const void* b)
+{
+    uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* Ray casting of the per-octant arrays into one view (Sec. 3.3, evaluation
+ * by ray casting). The view is orthographic (the matrix m as in orc_splat):
+ * the ray of pixel (x, y) meets fragment i when i projects into that pixel,
+ * floor(s) = (x, y) per axis, with depth s2 > 0 (the one-pixel footprint of
+ * the splat). The fragments a pixel's ray meets are ordered by (depth bits,
+ * index) and composited front to back in fp32, each operation in the order
+ * written:
+ *   a = A / 255 (mode 1; mode 0 takes a = 1), w = T * a,
+ *   C_c = C_c + w * (c / 255) for c = R, G, B, T = T * (1 - a),
+ * starting from C = 0, T = 1 and stopping after the fragment that leaves
+ * T < tau or T = 0 (later fragments add exact zeros). Output per pixel: (C_r, C_g, C_b, 1 - T), zero where no fragment
+ * is met. out: float [H][W][4]. Returns the largest number of fragments
+ * met by one pixel. */
+uint64_t orc_raycast(uint32_t levels, const uint64_t* oct_key, const uint32_t* frag, uint64_t n_frag,
+                     const float* m, uint32_t W, uint32_t H, int mode, float tau, float* out)
+{
+    size_t np = (size_t)W * H;
+    uint64_t* cnt = (uint64_t*)calloc(np + 1, sizeof(uint64_t));
+    int64_t* pix = (int64_t*)malloc((n_frag ? n_frag : 1) * sizeof(int64_t));
+    uint64_t* key = (uint64_t*)malloc((n_frag ? n_frag : 1) * sizeof(uint64_t));
+    /* every fragment's pixel (or none) and sort key */
+    for (uint64_t i = 0; i < n_frag; ++i) {
+        const uint32_t* r = frag + 4 * i;
+        float p[3], s[3];
+        pix[i] = -1;
+        frag_pos(1, 0, levels, oct_key[r[3]], r[0], p);
+        for (int row = 0; row < 3; ++row) {
+            float a = m[4 * row + 0] * p[0];
+            float b = m[4 * row + 1] * p[1];
+            float e = m[4 * row + 2] * p[2];
+            s[row] = ((a + b) + e) + m[4 * row + 3];
+        }
+        if (!(s[2] > 0.0f)) continue;
+        float fx = floorf(s[0]), fy = floorf(s[1]);
+        if (!(fx >= 0.0f && fx < (float)W && fy >= 0.0f && fy < (float)H)) continue;
+        pix[i] = (int64_t)fy * W + (int64_t)fx;
+        key[i] = ((uint64_t)f32_bits(s[2]) << 32) | (uint32_t)i;
+        cnt[pix[i] + 1] += 1;
+    }
+    /* group by pixel (counting sort), then order each group */
+    for (size_t q = 0; q < np; ++q) cnt[q + 1] += cnt[q];
+    uint64_t* list = (uint64_t*)malloc((cnt[np] ? cnt[np] : 1) * sizeof(uint64_t));
+    uint64_t* fill = (uint64_t*)malloc((np ? np : 1) * sizeof(uint64_t));
+    memcpy(fill, cnt, np * sizeof(uint64_t));
+    for (uint64_t i = 0; i < n_frag; ++i)
+        if (pix[i] >= 0) list[fill[pix[i]]++] = key[i];
+    uint64_t deepest = 0;
+    for (size_t q = 0; q < np; ++q) {
+        uint64_t b = cnt[q], n = cnt[q + 1] - b;
+        float* o = out + 4 * q;
+        o[0] = o[1] = o[2] = o[3] = 0.0f;
+        if (n == 0) continue;
+        if (n > deepest) deepest = n;
+        qsort(list + b, n, sizeof(uint64_t), cmp_u64);
+        float c[3] = {0.0f, 0.0f, 0.0f}, t = 1.0f;
+        for (uint64_t j = 0; j < n; ++j) {
+            uint32_t id = (uint32_t)(list[b + j] & 0xFFFFFFFFu);
+            uint32_t rgba = frag[4 * (size_t)id + 1];
+            float a = mode == 1 ? (float)(rgba >> 24) / 255.0f : 1.0f;
+            float w = t * a;
+            for (int k = 0; k < 3; ++k) c[k] = c[k] + w * ((float)((rgba >> (8 * k)) & 0xFFu) / 255.0f);
+            t = t * (1.0f - a);
+            if (t < tau || t == 0.0f) break;
+        }
+        o[0] = c[0];
+        o[1] = c[1];
+        o[2] = c[2];
+        o[3] = 1.0f - t;
+    }
+    free(cnt);
+    free(pix);
+    free(key);
+    free(list);
+    free(fill);
+    return deepest;
 }
 
 /* ------------------------------------------------------------ direct raster */

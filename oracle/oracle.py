@@ -65,6 +65,9 @@ def lib():
                                         u32p, C.c_uint32, f32p, C.c_uint32, C.c_uint32, u64p, u32p,
                                         f32p, u8p]
         L.orc_psnr_rgb.argtypes = [u32p, u32p, C.c_uint64]
+        L.orc_raycast.argtypes = [C.c_uint32, u64p, u32p, C.c_uint64, f32p, C.c_uint32, C.c_uint32, C.c_int,
+                                  C.c_float, f32p]
+        L.orc_raycast.restype = C.c_uint64
         L.orc_psnr_rgb.restype = C.c_double
     return _lib
 
@@ -203,6 +206,32 @@ def splat(mode: int, keys: np.ndarray, frag: np.ndarray, views, width_cap: int =
     return rgba.reshape(V, H, W), depth.reshape(V, H, W), cov.reshape(V, H, W)
 
 
+def raycast(keys: np.ndarray, frag: np.ndarray, views, levels: int, mode: int = 1, tau: float = 0.0):
+    """Ray casting of per-octant arrays (Sec. 3.3): per pixel, the fragments
+    its ray meets, nearest first, composited front to back with their alpha
+    (mode 1, "R/T") or the nearest alone (mode 0, "R"), stopping once the
+    transmittance falls below tau. Returns (float32 [V,H,W,4] premultiplied
+    RGB and coverage, largest number of fragments met by one pixel)."""
+    W, H = views[0].width, views[0].height
+    assert all(v.width == W and v.height == H for v in views)
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    if keys.size == 0:
+        keys = np.zeros(1, np.uint64)
+    fr = np.ascontiguousarray(frag, dtype=np.uint32).reshape(-1)
+    n = fr.size // 4
+    if fr.size == 0:
+        fr = np.zeros(4, np.uint32)
+    out = np.zeros((len(views), H, W, 4), np.float32)
+    deepest = 0
+    for v, view in enumerate(views):
+        o = np.zeros((H, W, 4), np.float32)
+        d = lib().orc_raycast(levels, keys, fr, n, np.ascontiguousarray(view.m.astype(np.float32).reshape(12)),
+                              W, H, mode, float(tau), o)
+        out[v] = o
+        deepest = max(deepest, int(d))
+    return out, deepest
+
+
 def direct_raster(mode: int, mesh, view, width_cap: int = 0, height_cap: int = 0, levels: int = 0):
     """Depth-tested rasterization of the triangles into one view: the
     reference image for a novel-view reconstruction. Returns (rgba, depth,
@@ -228,4 +257,5 @@ def psnr_rgb(a: np.ndarray, b: np.ndarray) -> float:
 
 
 __all__ = ["NIL", "build", "lib", "oct_encode", "oct_decode", "tangent_frame", "morton3",
-           "capture_ppfl", "capture_pofl", "capture_pofl_range", "compact", "splat", "direct_raster", "psnr_rgb"]
+           "capture_ppfl", "capture_pofl", "capture_pofl_range", "compact", "splat", "raycast", "direct_raster",
+           "psnr_rgb"]
