@@ -216,6 +216,35 @@ FHV_API fhv_status fhv_splat(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_cap
                      const fhv_view* views, uint32_t n_views, uint64_t* zbuf, uint32_t* rgba,
                      float* depth, uint8_t* cov, fhv_stream stream);
 
+/* Ray casting (Sec. 3.3, evaluation by ray casting) of POFL per-octant
+ * arrays into orthographic views. The ray of pixel (x, y) meets array
+ * fragment i when i projects into that pixel, floor(s) = (x, y) per axis,
+ * with depth > 0 (the splat's one-pixel footprint). The fragments a ray
+ * meets are ordered by (fp32 depth bits, i) and composited front to back in
+ * fp32, each operation in this order and without fused multiply-adds:
+ *   a = A/255 (FHV_RAY_BLEND) or 1 (FHV_RAY_NEAREST), w = T*a,
+ *   C_c = C_c + w*(c/255) for c = R, G, B, T = T*(1 - a),
+ * from C = 0, T = 1, stopping after the fragment that leaves T < tau or
+ * T = 0. FHV_RAY_NEAREST is simple ray casting ("R": the nearest fragment,
+ * opaque); FHV_RAY_BLEND resolves transparency ("R/T"). The walk descends
+ * the octree from the root through occupied octants only, rebuilding every
+ * level's occupancy from the table on each call (Sec. 3.1: coarser levels
+ * store the occupancy of their children).
+ * desc: FHV_POFL with levels in [1, 10] (ERANGE above). views: host array
+ * of n_views in [1, 32] entries sharing width, height in [1, 16384], each
+ * with splat_px = 1. rgba: float [n_views][height][width][4] (premultiplied
+ * R, G, B and 1 - T; zero where no fragment is met), device, 16-byte
+ * aligned. ws: fhv_raycast_workspace(desc) bytes, device, caller-owned.
+ * Errors: EINVAL (null pointers, mode, NaN tau, views of different sizes,
+ * splat_px other than 1, PPFL desc), ERANGE, EWORKSPACE. */
+#define FHV_RAY_NEAREST 0u
+#define FHV_RAY_BLEND 1u
+
+FHV_API size_t fhv_raycast_workspace(const fhv_capture_desc* desc);
+FHV_API fhv_status fhv_raycast(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_capture_desc* desc,
+                               const fhv_view* views, uint32_t n_views, uint32_t mode, float tau,
+                               float* rgba, void* ws, size_t ws_bytes, fhv_stream stream);
+
 /* Batches (not in the paper): many POFL scenes, each with several views,
  * through capture, compaction and splat in one call. The scenes share one
  * key space, key = scene * 8^L + Morton code of the leaf, so one launch per

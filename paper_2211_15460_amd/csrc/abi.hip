@@ -422,6 +422,42 @@ fhv_status fhv_probe(fhv_ctx* ctx, uint32_t kind, void* buf, uint64_t bytes, uin
     return hip_status(fhv::probe_launch(ctx->dev, kind, buf, bytes, line, passes, (hipStream_t)stream));
 }
 
+size_t fhv_raycast_workspace(const fhv_capture_desc* desc)
+{
+    if (!desc_ok(desc) || desc->mode != FHV_POFL) return 0;
+    return fhv::raycast_ws_bytes(desc->levels);
+}
+
+fhv_status fhv_raycast(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_capture_desc* desc,
+                       const fhv_view* views, uint32_t n_views, uint32_t mode, float tau, float* rgba,
+                       void* ws, size_t ws_bytes, fhv_stream stream)
+{
+    if (!ctx || !arrays || !desc_ok(desc) || !views || !rgba || !ws) return FHV_EINVAL;
+    if (desc->mode != FHV_POFL || mode > FHV_RAY_BLEND || tau != tau) return FHV_EINVAL;
+    if (desc->levels > fhv::kMaxRayLevels) return FHV_ERANGE;
+    if (n_views == 0 || n_views > fhv::kMaxViews) return FHV_ERANGE;
+    if (!arrays->n_occ) return FHV_EINVAL;
+    if (arrays->cap_occ > 0 && (!arrays->oct_key || !arrays->oct_off || !arrays->oct_cnt)) return FHV_EINVAL;
+    if (arrays->cap_frag > 0 && !arrays->frag) return FHV_EINVAL;
+    if (arrays->cap_frag >= 0xFFFFFFFFull) return FHV_ERANGE;
+    if (((uintptr_t)arrays->frag & 15) || ((uintptr_t)rgba & 15)) return FHV_EINVAL;
+    fhv::RayViews rv;
+    rv.n_views = n_views;
+    rv.width = views[0].width;
+    rv.height = views[0].height;
+    if (rv.width < 1 || rv.width > 16384 || rv.height < 1 || rv.height > 16384) return FHV_ERANGE;
+    for (uint32_t v = 0; v < n_views; ++v) {
+        if (views[v].width != rv.width || views[v].height != rv.height) return FHV_EINVAL;
+        if (views[v].splat_px != 1) return FHV_EINVAL;
+        memcpy(rv.m[v], views[v].m, sizeof(rv.m[v]));
+    }
+    if (ws_bytes < fhv::raycast_ws_bytes(desc->levels)) return FHV_EWORKSPACE;
+    fhv_status st = set_device(ctx);
+    if (st != FHV_OK) return st;
+    return hip_status(fhv::raycast_launch(ctx->dev, arrays, desc->levels, rv, mode, tau, rgba, ws,
+                                          (hipStream_t)stream));
+}
+
 static bool fill_dims_ok(uint32_t levels, uint32_t n, uint32_t h, uint32_t w)
 {
     if (levels < 1 || levels > 4 || n == 0 || h == 0 || w == 0) return false;

@@ -198,6 +198,17 @@ hipError_t splat_batch_launch(const Device& dev, const fhv_pofa* a, uint32_t lev
                               uint64_t* zbuf, uint32_t* rgba, float* depth, uint8_t* cov,
                               uint64_t max_frag, hipStream_t s);
 
+// Ray casting of per-octant arrays (fhv_raycast): octree depth up to
+// kMaxRayLevels (Morton codes of octants fit 32 bits).
+constexpr uint32_t kMaxRayLevels = 10;
+struct RayViews {
+    float m[kMaxViews][12];
+    uint32_t n_views, width, height;
+};
+size_t raycast_ws_bytes(uint32_t levels);
+hipError_t raycast_launch(const Device& dev, const fhv_pofa* p, uint32_t levels, const RayViews& rv,
+                          uint32_t mode, float tau, float* out, void* ws, hipStream_t s);
+
 // Measurement probes (fhv_probe): copy over the buffer's two halves, or
 // one atomic per line and pass.
 hipError_t probe_launch(const Device& dev, uint32_t kind, void* buf, uint64_t bytes, uint32_t line,

@@ -77,7 +77,7 @@ EXPORTS = ["fhv_create", "fhv_destroy", "fhv_status_str", "fhv_capture_workspace
            "fhv_compact_workspace", "fhv_compact", "fhv_splat", "fhv_profile_begin",
            "fhv_profile_end", "fhv_unet_param_count", "fhv_fill_workspace", "fhv_fill",
            "fhv_fill_train_step", "fhv_get_tuning", "fhv_set_tuning", "fhv_batch_workspace",
-           "fhv_batch_run", "fhv_probe"]
+           "fhv_batch_run", "fhv_probe", "fhv_raycast_workspace", "fhv_raycast"]
 
 _lib = None
 _ctx: dict[int, C.c_void_p] = {}
@@ -120,11 +120,15 @@ def lib():
         L.fhv_batch_run.argtypes = [P, C.POINTER(BatchMesh_), C.POINTER(BatchViews_), C.POINTER(Lists_),
                                     C.POINTER(Pofa_), P, P, P, P, P, C.c_size_t, C.c_uint32, P]
         L.fhv_probe.argtypes = [P, C.c_uint32, P, C.c_uint64, C.c_uint32, C.c_uint32, P]
+        L.fhv_raycast_workspace.argtypes = [C.POINTER(Desc_)]
+        L.fhv_raycast_workspace.restype = C.c_size_t
+        L.fhv_raycast.argtypes = [P, C.POINTER(Pofa_), C.POINTER(Desc_), C.POINTER(View_), C.c_uint32, C.c_uint32,
+                                  C.c_float, P, P, C.c_size_t, P]
         L.fhv_profile_begin.argtypes = [P]
         L.fhv_profile_end.argtypes = [P, C.POINTER(KernelStat_), C.c_uint32, C.POINTER(C.c_uint32)]
         for f in ("fhv_create", "fhv_destroy", "fhv_capture", "fhv_compact", "fhv_splat",
                   "fhv_profile_begin", "fhv_profile_end", "fhv_fill", "fhv_fill_train_step",
-                  "fhv_get_tuning", "fhv_set_tuning", "fhv_batch_run", "fhv_probe"):
+                  "fhv_get_tuning", "fhv_set_tuning", "fhv_batch_run", "fhv_probe", "fhv_raycast"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -313,6 +317,35 @@ def splat(arrays: Pofa, d: Desc_, views, out: Images | None = None, vstruct=None
         _check(lib().fhv_splat(ctx(), C.byref(ps), C.byref(d), arr, len(vs),
                                _ptr(out.zbuf[v0:]), _ptr(out.rgba[v0:]), _ptr(out.depth[v0:]),
                                _ptr(out.cov[v0:]), _stream()), "fhv_splat")
+    return out
+
+
+FHV_RAY_NEAREST, FHV_RAY_BLEND = 0, 1
+
+
+def raycast_workspace(d: Desc_) -> int:
+    return int(lib().fhv_raycast_workspace(C.byref(d)))
+
+
+def raycast(arrays: Pofa, d: Desc_, views, mode: int = FHV_RAY_BLEND, tau: float = 0.0,
+            out: torch.Tensor | None = None, ws: torch.Tensor | None = None, vstruct=None) -> torch.Tensor:
+    """fhv_raycast of all views (at most 32 per call; more are split).
+    Returns float32 [V, H, W, 4]: premultiplied R, G, B and 1 - T."""
+    W, H = views[0].width, views[0].height
+    dev = arrays.frag.device
+    if out is None:
+        out = torch.empty((len(views), H, W, 4), dtype=torch.float32, device=dev)
+    need = raycast_workspace(d)
+    if need == 0:
+        raise FhvError("fhv_raycast_workspace: unsupported descriptor")
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    ps = arrays.struct()
+    for v0 in range(0, len(views), 32):
+        vs = views[v0:v0 + 32]
+        arr = vstruct if (vstruct is not None and len(views) <= 32) else views_struct(vs)
+        _check(lib().fhv_raycast(ctx(), C.byref(ps), C.byref(d), arr, len(vs), mode, float(tau),
+                                 _ptr(out[v0:]), _ptr(ws), ws.numel(), _stream()), "fhv_raycast")
     return out
 
 
