@@ -99,6 +99,7 @@ SCOPE_KERNELS = {
     "compact.hist": ("k_hist",), "compact.scatter": ("k_scatter",),
     "compact.brick": ("k_brick_wave", "k_brick"), "splat.zclear": ("k_zclear",),
     "splat.splat": ("k_splat",), "splat.resolve": ("k_resolve",),
+    "ray.occupancy": ("k_occ_build",), "ray.cast": ("k_raycast",),
 }
 
 
@@ -296,6 +297,52 @@ def learned_fill_report(torch, fhv, scenes, train_steps: int = 600, eval_seeds: 
                       "over": f"held-out scenes of seeds 0..{eval_seeds - 1} at 30 and 60 degrees"}
     res["reference"] = "library per-pixel capture of the triangles in the view, nearest fragment"
     return res, model
+
+
+def raycast_report(torch, fhv, scenes, mesh, views, reps: int = 10) -> dict:
+    """Ray casting (Sec. 3.3) of the step's scene into the same views:
+    simple ray casting (R, nearest fragment) and ray casting with
+    transparency (R/T, front to back until the transmittance is below
+    1/256). The scene's own colours are opaque, so both run on the same
+    scene with a seeded random alpha per vertex. Each figure is the mean of
+    `reps` calls after two warm-ups (HIP events around the library's
+    launches); a call rebuilds the octree's occupancy levels from the table
+    and then casts one ray per pixel of every view."""
+    import numpy as np
+    rng = np.random.default_rng(7)
+    alpha = rng.integers(0, 256, mesh.rgba.size, dtype=np.uint32)
+    amesh = scenes.Mesh(mesh.pos, (mesh.rgba & 0x00FFFFFF) | (alpha << 24), mesh.tri, mesh.obj)
+    d = fhv.desc(fhv.FHV_POFL, levels=LEVELS)
+    dm = fhv.to_device(amesh)
+    probe = fhv.alloc_lists(d, 1 << 16)
+    fhv.capture(dm, d, probe)
+    torch.cuda.synchronize()
+    F = int(probe.counter.item())
+    del probe
+    lists = fhv.alloc_lists(d, F)
+    fhv.capture(dm, d, lists)
+    pofa = fhv.alloc_pofa(F)
+    fhv.compact(lists, d, pofa)
+    del lists
+    W, H = views[0].width, views[0].height
+    out = torch.empty((len(views), H, W, 4), dtype=torch.float32, device="cuda")
+    ws = torch.empty(fhv.raycast_workspace(d), dtype=torch.uint8, device="cuda")
+    vs = fhv.views_struct(views)
+    res = {"views": len(views), "view_size": [W, H], "fragments": F, "levels": LEVELS, "tau_rt": 1.0 / 256}
+    for mode, tau, name in ((fhv.FHV_RAY_NEAREST, 0.0, "R"), (fhv.FHV_RAY_BLEND, 1.0 / 256, "RT")):
+        for _ in range(2):
+            fhv.raycast(pofa, d, views, mode, tau, out, ws, vs)
+        torch.cuda.synchronize()
+        fhv.profile_begin()
+        for _ in range(reps):
+            fhv.raycast(pofa, d, views, mode, tau, out, ws, vs)
+        prof = fhv.profile_end()
+        occ = prof["ray.occupancy"][1] / reps
+        cast = prof["ray.cast"][1] / reps
+        res[name] = {"ms_per_call": occ + cast, "occupancy_ms": occ, "cast_ms": cast,
+                     "views_per_s": len(views) / ((occ + cast) * 1e-3),
+                     "rays_per_s": len(views) * W * H / (cast * 1e-3)}
+    return res
 
 
 def cpu_baseline(mesh, views, min_seconds: float = 10.0):
@@ -702,6 +749,7 @@ def main():
                          "ppfl64: 64 triangles, per-pixel lists at 128x128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-train", action="store_true", help="skip the learned-fill training report")
+    ap.add_argument("--no-raycast", action="store_true", help="skip the ray casting report")
     ap.add_argument("--no-ceilings", action="store_true",
                     help="skip the measured copy and atomic ceilings (fhv_probe)")
     ap.add_argument("--copy-mib", type=int, default=256,
@@ -850,6 +898,8 @@ def main():
         "device": torch.cuda.get_device_name(0),
     }
     add_ceilings(args, out, torch, fhv, kernels, F, counters=True)
+    if not args.no_raycast:
+        out["raycast"] = raycast_report(torch, fhv, scenes, mesh, views)
     if not args.no_train:
         out["learned_fill"], _ = learned_fill_report(torch, fhv, scenes)
     if not args.no_cpu_baseline:

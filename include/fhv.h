@@ -230,6 +230,7 @@ FHV_API fhv_status fhv_splat(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_cap
  * the octree from the root through occupied octants only, rebuilding every
  * level's occupancy from the table on each call (Sec. 3.1: coarser levels
  * store the occupancy of their children).
+ * Fragments whose table row was not stored (rank >= cap_occ) are not met.
  * desc: FHV_POFL with levels in [1, 10] (ERANGE above). views: host array
  * of n_views in [1, 32] entries sharing width, height in [1, 16384], each
  * with splat_px = 1. rgba: float [n_views][height][width][4] (premultiplied
