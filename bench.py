@@ -443,12 +443,28 @@ def add_ceilings(args, out: dict, torch, fhv, kernels: dict, n_exch: int | None,
                         and kernels[k].get("gbs")}
     r_ms = kernels.get("capture.raster", {}).get("avg_ms")
     if n_exch and r_ms:
-        rate = n_exch / (r_ms * 1e-3) / 1e9
-        peak = ceil["atomics_g_per_s"]["exch_u32.hbm"]
-        out["atomic_roofline"] = {"kernel": "capture.raster", "achieved": rate, "peak": peak,
-                                  "unit": "G atomics/s", "frac": rate / peak,
-                                  "what": "list-head exchanges, one per fragment, against the measured rate "
-                                          "of uncontended returning u32 exchanges on HBM lines"}
+        # one exchange per fragment; samples next to each other in a tile
+        # often hit one 64-byte line and share a memory-side request, so the
+        # request count (from the committed counters, when they were taken
+        # on this workload) is what meets the ceiling
+        ops = n_exch / (r_ms * 1e-3) / 1e9
+        peak = ceil["atomics_g_per_s"]["exch_u32.hbm"]     # one request per exchange there
+        sc, cal = measured_scope("capture.raster") if counters else (None, None)
+        if sc and sc.get("atomic_requests"):
+            req = sc["atomic_requests"] / (r_ms * 1e-3) / 1e9
+            out["atomic_roofline"] = {"kernel": "capture.raster", "achieved": req, "peak": peak,
+                                      "unit": "G memory-side atomic requests/s", "frac": req / peak,
+                                      "exchanges_g_per_s": ops,
+                                      "what": "the raster's memory-side atomic requests (list-head exchanges "
+                                              "and counters, from the counter run) against the measured rate "
+                                              "of uncontended returning u32 exchanges, one request each"}
+        else:
+            out["atomic_roofline"] = {"kernel": "capture.raster", "achieved": None, "peak": peak,
+                                      "unit": "G memory-side atomic requests/s", "frac": None,
+                                      "exchanges_g_per_s": ops,
+                                      "what": "requests not counted for this workload; exchanges per second "
+                                              "exceed the one-request-per-exchange rate where samples share "
+                                              "lines"}
     # the splat's z-buffer minima are data dependent (a pixel already
     # holding a nearer fragment is skipped): their memory-side requests come
     # from the committed counter run, compared with the probes' request rates
