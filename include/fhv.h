@@ -105,12 +105,32 @@ typedef struct {
 } fhv_mesh;
 
 /* What to capture. PPFL: width, height in [1, 16384]; POFL: levels in
- * [1, 11] (octree depth L). Unused fields are ignored. */
+ * [1, 11] (octree depth L). Unused fields are ignored.
+ * projection (POFL only; PPFL requires 0): the plane each triangle is
+ * rasterized in (Sec. 3.2, Fig. 7 and 8, Table 2). Every variant samples its
+ * plane on a lattice of 2^7 grid units anchored at the projected grid origin
+ * and interpolates the sample's 3D grid position, colour and flat normal:
+ *   FHV_PROJ_NORMAL      the triangle's own plane (tangent frame of its packed
+ *                        normal; "1-Pass/Normal", the default)
+ *   FHV_PROJ_VIEW        the x-y plane (seen along z, the capture view;
+ *                        "1-Pass/View")
+ *   FHV_PROJ_AXES_3PASS  the y-z, z-x and x-y planes in three passes over the
+ *                        triangles ("3-Pass/1-Way")
+ *   FHV_PROJ_AXES_1PASS  the same three planes, three projected copies of
+ *                        every triangle in one pass ("1-Pass/3-Way"; the same
+ *                        fragments as 3-Pass/1-Way, in another order)
+ * A triangle seen edge-on in a plane yields no fragments there. */
+#define FHV_PROJ_NORMAL 0u
+#define FHV_PROJ_VIEW 1u
+#define FHV_PROJ_AXES_3PASS 2u
+#define FHV_PROJ_AXES_1PASS 3u
+
 typedef struct {
     uint32_t mode;
     uint32_t width;
     uint32_t height;
     uint32_t levels;
+    uint32_t projection;
 } fhv_capture_desc;
 
 /* Fragment lists (Sec. 3.1, Fig. 3 and Fig. 5).

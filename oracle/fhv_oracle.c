@@ -363,16 +363,17 @@ static void emit_pofl(void* user, int64_t i, int64_t j, const int64_t* a)
  * units and is anchored at the projection of the grid origin. Each sample's
  * grid position is interpolated from the vertices; its leaf is the top L bits
  * per axis. head holds 8^L entries set to NIL by the caller. */
-uint64_t orc_capture_pofl_range(const float* pos, const uint32_t* rgba, const uint32_t* tri,
-                                const uint8_t* obj, uint32_t n_tri, uint32_t levels, uint64_t key_lo,
-                                uint64_t key_hi, uint32_t* head, uint32_t* pool, uint64_t cap);
+uint64_t orc_capture_pofl_proj(const float* pos, const uint32_t* rgba, const uint32_t* tri,
+                               const uint8_t* obj, uint32_t n_tri, uint32_t levels, uint32_t proj,
+                               uint64_t key_lo, uint64_t key_hi, uint32_t* head, uint32_t* pool,
+                               uint64_t cap);
 
 uint64_t orc_capture_pofl(const float* pos, const uint32_t* rgba, const uint32_t* tri,
                           const uint8_t* obj, uint32_t n_tri, uint32_t levels,
                           uint32_t* head, uint32_t* pool, uint64_t cap)
 {
-    return orc_capture_pofl_range(pos, rgba, tri, obj, n_tri, levels, 0, (uint64_t)1 << (3 * levels),
-                                  head, pool, cap);
+    return orc_capture_pofl_proj(pos, rgba, tri, obj, n_tri, levels, 0, 0, (uint64_t)1 << (3 * levels),
+                                 head, pool, cap);
 }
 
 /* Per-octant capture keeping only the fragments whose key lies in
@@ -382,6 +383,23 @@ uint64_t orc_capture_pofl(const float* pos, const uint32_t* rgba, const uint32_t
 uint64_t orc_capture_pofl_range(const float* pos, const uint32_t* rgba, const uint32_t* tri,
                                 const uint8_t* obj, uint32_t n_tri, uint32_t levels, uint64_t key_lo,
                                 uint64_t key_hi, uint32_t* head, uint32_t* pool, uint64_t cap)
+{
+    return orc_capture_pofl_proj(pos, rgba, tri, obj, n_tri, levels, 0, key_lo, key_hi, head, pool, cap);
+}
+
+/* The capture with a choice of rasterization plane (Sec. 3.2, Figs. 7-8,
+ * Table 2): proj 0 the triangle's own plane ("1-Pass/Normal", above);
+ * 1 the x-y plane, seen along z ("1-Pass/View"); 2 and 3 the y-z, z-x and
+ * x-y planes, every triangle rasterized once in each ("3-Pass/1-Way" and
+ * "1-Pass/3-Way" capture the same fragments; only their order differs, and
+ * the order is not part of the result). In an axis plane the sample
+ * coordinates are two of the grid coordinates, in cyclic order after the
+ * axis, scaled to the lattice of 2^7 grid units; a triangle seen edge-on
+ * there has zero area and no fragments. */
+uint64_t orc_capture_pofl_proj(const float* pos, const uint32_t* rgba, const uint32_t* tri,
+                               const uint8_t* obj, uint32_t n_tri, uint32_t levels, uint32_t proj,
+                               uint64_t key_lo, uint64_t key_hi, uint32_t* head, uint32_t* pool,
+                               uint64_t cap)
 {
     lists_t L = {head, pool, cap, 0, key_lo, key_hi, 0, 0, 0, levels, 1};
     const int64_t G = (int64_t)1 << (levels + 8);
@@ -405,26 +423,41 @@ uint64_t orc_capture_pofl_range(const float* pos, const uint32_t* rgba, const ui
         int64_t nx = uy * vz - uz * vy, ny = uz * vx - ux * vz, nz = ux * vy - uy * vx;
         if (nx == 0 && ny == 0 && nz == 0) continue; /* degenerate: no fragments */
         uint32_t nrm = orc_oct_encode(nx, ny, nz);
-        double n[3], tt[3], bb[3];
-        oct_decode64(nrm, n);
-        onb(n, tt, bb);
+        L.nrm = nrm;
+        L.aux = obj ? obj[t] : 0;
         tri_fx f;
         f.n_attr = 7;
         for (int k = 0; k < 3; ++k) {
-            double px = (double)P[k][0], py = (double)P[k][1], pz = (double)P[k][2];
-            double u = px * tt[0] + py * tt[1] + pz * tt[2];
-            double v = px * bb[0] + py * bb[1] + pz * bb[2];
-            /* 2^7 grid units per sample = 256 sub-sample units: scale by 2 */
-            f.x[k] = (int64_t)rint(2.0 * u);
-            f.y[k] = (int64_t)rint(2.0 * v);
             f.attr[k][0] = P[k][0];
             f.attr[k][1] = P[k][1];
             f.attr[k][2] = P[k][2];
             rgba_split(rgba[tri[3 * t + k]], &f.attr[k][3]);
         }
-        L.nrm = nrm;
-        L.aux = obj ? obj[t] : 0;
-        raster_tri(&f, INT64_MIN / 4, INT64_MAX / 4, INT64_MIN / 4, INT64_MAX / 4, emit_pofl, &L);
+        if (proj == 0) {
+            double n[3], tt[3], bb[3];
+            oct_decode64(nrm, n);
+            onb(n, tt, bb);
+            for (int k = 0; k < 3; ++k) {
+                double px = (double)P[k][0], py = (double)P[k][1], pz = (double)P[k][2];
+                double u = px * tt[0] + py * tt[1] + pz * tt[2];
+                double v = px * bb[0] + py * bb[1] + pz * bb[2];
+                /* 2^7 grid units per sample = 256 sub-sample units: scale by 2 */
+                f.x[k] = (int64_t)rint(2.0 * u);
+                f.y[k] = (int64_t)rint(2.0 * v);
+            }
+            raster_tri(&f, INT64_MIN / 4, INT64_MAX / 4, INT64_MIN / 4, INT64_MAX / 4, emit_pofl, &L);
+            continue;
+        }
+        /* axis planes: seen along z only (View), or along x, y and z */
+        for (int axis = 0; axis < 3; ++axis) {
+            if (proj == 1 && axis != 2) continue;
+            int cu = (axis + 1) % 3, cv = (axis + 2) % 3;
+            for (int k = 0; k < 3; ++k) {
+                f.x[k] = 2 * P[k][cu];
+                f.y[k] = 2 * P[k][cv];
+            }
+            raster_tri(&f, INT64_MIN / 4, INT64_MAX / 4, INT64_MIN / 4, INT64_MAX / 4, emit_pofl, &L);
+        }
     }
     return L.counter;
 }

@@ -65,6 +65,9 @@ def lib():
                                         u32p, C.c_uint32, f32p, C.c_uint32, C.c_uint32, u64p, u32p,
                                         f32p, u8p]
         L.orc_psnr_rgb.argtypes = [u32p, u32p, C.c_uint64]
+        L.orc_capture_pofl_proj.argtypes = [f32p, u32p, u32p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32,
+                                            C.c_uint64, C.c_uint64, u32p, u32p, C.c_uint64]
+        L.orc_capture_pofl_proj.restype = C.c_uint64
         L.orc_raycast.argtypes = [C.c_uint32, u64p, u32p, C.c_uint64, f32p, C.c_uint32, C.c_uint32, C.c_int,
                                   C.c_float, f32p]
         L.orc_raycast.restype = C.c_uint64
@@ -123,16 +126,19 @@ def capture_ppfl(mesh, width: int, height: int, cap: int):
     return head, pool.reshape(-1, 4)[:cap], int(cnt)
 
 
-def capture_pofl(mesh, levels: int, cap: int):
+def capture_pofl(mesh, levels: int, cap: int, projection: int = 0):
     """Per-octant fragment lists with tangent-space rasterization
-    (Sec. 3.1 octree layout, Sec. 3.2 FHV_POFL, Fig. 8).
+    (Sec. 3.1 octree layout, Sec. 3.2 FHV_POFL, Fig. 8), or with the
+    rasterization plane of another capture variant (Table 2): 1 the x-y plane
+    ("1-Pass/View"), 2 or 3 all three axis planes ("3-Pass/1-Way",
+    "1-Pass/3-Way").
 
     Returns (head uint32[8^L], pool uint32[cap, 4], counter)."""
     pos, rgba, tri, obj = _mesh_arrays(mesh)
     head = np.full(8 ** levels, NIL, np.uint32)
     pool = np.zeros(4 * max(cap, 1), np.uint32)
-    cnt = lib().orc_capture_pofl(pos, rgba, tri, _obj_ptr(obj), mesh.tri.shape[0], levels,
-                                 head, pool, cap)
+    cnt = lib().orc_capture_pofl_proj(pos, rgba, tri, _obj_ptr(obj), mesh.tri.shape[0], levels, projection,
+                                      0, 8 ** levels, head, pool, cap)
     return head, pool.reshape(-1, 4)[:cap], int(cnt)
 
 

@@ -69,8 +69,9 @@ fhv_status hip_status(hipError_t e) { return e == hipSuccess ? FHV_OK : FHV_EHIP
 bool desc_ok(const fhv_capture_desc* d)
 {
     if (!d) return false;
-    if (d->mode == FHV_PPFL) return d->width >= 1 && d->width <= 16384 && d->height >= 1 && d->height <= 16384;
-    if (d->mode == FHV_POFL) return d->levels >= 1 && d->levels <= 11;
+    if (d->mode == FHV_PPFL)
+        return d->width >= 1 && d->width <= 16384 && d->height >= 1 && d->height <= 16384 && d->projection == 0;
+    if (d->mode == FHV_POFL) return d->levels >= 1 && d->levels <= 11 && d->projection <= FHV_PROJ_AXES_1PASS;
     return false;
 }
 
@@ -116,6 +117,7 @@ fhv_capture_desc batch_desc(const fhv_batch_mesh* m)
     d.width = 0;
     d.height = 0;
     d.levels = m->levels;
+    d.projection = FHV_PROJ_NORMAL;
     return d;
 }
 
@@ -342,6 +344,8 @@ fhv_status fhv_capture(fhv_ctx* ctx, const fhv_mesh* mesh, const fhv_capture_des
                        const fhv_lists* lists, void* ws, size_t ws_bytes, fhv_stream stream)
 {
     if (!ctx || !mesh || !desc_ok(desc)) return FHV_EINVAL;
+    if (desc->mode == FHV_POFL && desc->projection == FHV_PROJ_AXES_1PASS && mesh->n_tri > 0x55555555u)
+        return FHV_ERANGE;   // three setup records per triangle
     fhv_status st = check_lists(lists, desc);
     if (st != FHV_OK) return st;
     if (mesh->n_tri > 0 && (!mesh->pos || !mesh->rgba || !mesh->tri || mesh->n_vert == 0))

@@ -95,15 +95,21 @@ __device__ __forceinline__ void sample_range(int64_t lo, int64_t hi, int32_t* i0
     *i1 = (int32_t)((hi - 128) >> 8);
 }
 
+// Setup record `tr` of n_rec: triangle tr / copies. POFL projection: the
+// tangent frame (FHV_PROJ_NORMAL), or an axis plane: `axis` (2: x-y, 0: y-z,
+// 1: z-x), or with three copies per triangle the copy's own (tr mod 3).
 __global__ void __launch_bounds__(kBlock)
 k_setup(const float* __restrict__ pos, const uint32_t* __restrict__ rgba,
-        const uint32_t* __restrict__ tri, const uint8_t* __restrict__ obj, uint32_t n_tri,
+        const uint32_t* __restrict__ tri, const uint8_t* __restrict__ obj, uint32_t n_rec,
         uint32_t mode, uint32_t width, uint32_t height, uint32_t levels, uint32_t tile_shift,
+        uint32_t proj, uint32_t axis, uint32_t copies,
         const uint32_t* __restrict__ scene_tri, uint32_t n_scenes,
         TriRec* __restrict__ recs, uint64_t* __restrict__ tiles)
 {
-    const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= n_tri) return;
+    const uint32_t tr = blockIdx.x * kBlock + threadIdx.x;
+    if (tr >= n_rec) return;
+    const uint32_t t = tr / copies;
+    if (copies == 3) axis = tr % 3;
     // scene of a batch: the last s in [0, n_scenes) with scene_tri[s] <= t
     // (only scene_tri[1 .. n_scenes-1] is read, so the result stays in range)
     uint32_t scene = 0;
@@ -172,14 +178,24 @@ k_setup(const float* __restrict__ pos, const uint32_t* __restrict__ rgba,
                 skip = true;
             } else {
                 nrm = oct_pack(nx, ny, nz);
-                double tt[3], bb[3];
-                tangent_frame(nrm, tt, bb);
-                for (int k = 0; k < 3; ++k) {
-                    const double px = (double)a[k][0], py = (double)a[k][1], pz = (double)a[k][2];
-                    const double u = px * tt[0] + py * tt[1] + pz * tt[2];
-                    const double v = px * bb[0] + py * bb[1] + pz * bb[2];
-                    X[k] = (int64_t)rint(2.0 * u);
-                    Y[k] = (int64_t)rint(2.0 * v);
+                if (proj == FHV_PROJ_NORMAL) {
+                    double tt[3], bb[3];
+                    tangent_frame(nrm, tt, bb);
+                    for (int k = 0; k < 3; ++k) {
+                        const double px = (double)a[k][0], py = (double)a[k][1], pz = (double)a[k][2];
+                        const double u = px * tt[0] + py * tt[1] + pz * tt[2];
+                        const double v = px * bb[0] + py * bb[1] + pz * bb[2];
+                        X[k] = (int64_t)rint(2.0 * u);
+                        Y[k] = (int64_t)rint(2.0 * v);
+                    }
+                } else {
+                    // axis plane: (u, v) = two grid coordinates in cyclic
+                    // order after the axis, exact integers
+                    const int cu = (int)((axis + 1) % 3), cv = (int)((axis + 2) % 3);
+                    for (int k = 0; k < 3; ++k) {
+                        X[k] = 2 * (int64_t)a[k][cu];
+                        Y[k] = 2 * (int64_t)a[k][cv];
+                    }
                 }
             }
         }
@@ -236,10 +252,10 @@ k_setup(const float* __restrict__ pos, const uint32_t* __restrict__ rgba,
             } else {
                 r.tiles_x = 0;
             }
-            recs[t] = r;
+            recs[tr] = r;
         }
     }
-    tiles[t] = n_tiles;
+    tiles[tr] = n_tiles;
 }
 
 // floor((w0 a0 + w1 a1 + w2 a2 + floor(A/2)) / A) for non-negative weights
@@ -440,25 +456,33 @@ k_raster(const TriRec* __restrict__ recs, const uint64_t* __restrict__ incl, uin
 
 }  // namespace
 
+// Setup records per pass: three projected copies of every triangle for
+// FHV_PROJ_AXES_1PASS, one otherwise.
+static uint64_t records_of(const fhv_capture_desc* d, uint32_t n_tri)
+{
+    return d->mode == FHV_POFL && d->projection == FHV_PROJ_AXES_1PASS ? 3ull * n_tri : (uint64_t)n_tri;
+}
+
 size_t capture_ws_bytes(const fhv_capture_desc* d, uint32_t n_tri)
 {
-    (void)d;
+    const uint64_t n = records_of(d, n_tri);
     Carver c{nullptr, 0};
-    c.take<TriRec>(n_tri);
-    c.take<uint64_t>(n_tri);
-    c.take<uint64_t>(n_tri);
-    c.take<uint64_t>(scan_partials(n_tri));
+    c.take<TriRec>(n);
+    c.take<uint64_t>(n);
+    c.take<uint64_t>(n);
+    c.take<uint64_t>(scan_partials(n));
     return c.off + 256;
 }
 
 hipError_t capture_launch(const Device& dev, const fhv_mesh* m, const fhv_capture_desc* d,
                           const fhv_lists* L, void* ws, hipStream_t s, const Scenes* sc)
 {
+    const uint64_t n_rec = records_of(d, m->n_tri);
     Carver c{(char*)ws, 0};
-    TriRec* recs = c.take<TriRec>(m->n_tri);
-    uint64_t* tiles = c.take<uint64_t>(m->n_tri);
-    uint64_t* incl = c.take<uint64_t>(m->n_tri);
-    uint64_t* part = c.take<uint64_t>(scan_partials(m->n_tri));
+    TriRec* recs = c.take<TriRec>(n_rec);
+    uint64_t* tiles = c.take<uint64_t>(n_rec);
+    uint64_t* incl = c.take<uint64_t>(n_rec);
+    uint64_t* part = c.take<uint64_t>(scan_partials(n_rec));
     const uint32_t ts = dev.tune.tile_w == 32 ? 5u : (dev.tune.tile_w == 16 ? 4u : 3u);
     hipError_t e;
     {
@@ -467,36 +491,46 @@ hipError_t capture_launch(const Device& dev, const fhv_mesh* m, const fhv_captur
         if (e == hipSuccess) e = fill_u64(L->counter, 1, 0, s);
     }
     if (e != hipSuccess || m->n_tri == 0) return e;
-    {
-        ProfScope ps(dev, "capture.setup", s);
-        k_setup<<<dim3((m->n_tri + kBlock - 1) / kBlock), dim3(kBlock), 0, s>>>(
-            m->pos, m->rgba, m->tri, m->obj, m->n_tri, d->mode, d->width, d->height, d->levels, ts,
-            sc ? sc->scene_tri : nullptr, sc ? sc->n_scenes : 1u, recs, tiles);
-        e = hipGetLastError();
-    }
-    if (e != hipSuccess) return e;
-    {
-        ProfScope ps(dev, "capture.scan", s);
-        e = scan_u64(tiles, incl, m->n_tri, true, part, nullptr, s);
-    }
-    if (e != hipSuccess) return e;
+    const uint32_t proj = d->mode == FHV_POFL ? d->projection : FHV_PROJ_NORMAL;
+    const uint32_t copies = proj == FHV_PROJ_AXES_1PASS ? 3u : 1u;
+    // passes and the axis plane of each: three for 3-Pass/1-Way (y-z, z-x,
+    // x-y), one otherwise (x-y for 1-Pass/View)
+    const uint32_t passes = proj == FHV_PROJ_AXES_3PASS ? 3u : 1u;
     const unsigned grid = (unsigned)(dev.cus * dev.tune.raster_wg);
     const uint32_t gmax = d->mode == FHV_POFL ? (1u << (d->levels + 8)) - 1u : 0u;
-    ProfScope ps(dev, "capture.raster", s);
     const bool wide = L->n_head > (1ull << 32);
-    if (d->mode == FHV_PPFL)
-        k_raster<FHV_PPFL, uint32_t><<<dim3(grid), dim3(kBlock), 0, s>>>(
-            recs, incl, m->n_tri, d->width, gmax, d->levels, ts, L->head, (uint4*)L->pool,
-            (uint32_t*)L->keys, L->capacity, (unsigned long long*)L->counter);
-    else if (!wide)
-        k_raster<FHV_POFL, uint32_t><<<dim3(grid), dim3(kBlock), 0, s>>>(
-            recs, incl, m->n_tri, d->width, gmax, d->levels, ts, L->head, (uint4*)L->pool,
-            (uint32_t*)L->keys, L->capacity, (unsigned long long*)L->counter);
-    else
-        k_raster<FHV_POFL, uint64_t><<<dim3(grid), dim3(kBlock), 0, s>>>(
-            recs, incl, m->n_tri, d->width, gmax, d->levels, ts, L->head, (uint4*)L->pool,
-            (uint64_t*)L->keys, L->capacity, (unsigned long long*)L->counter);
-    return hipGetLastError();
+    for (uint32_t pass = 0; pass < passes; ++pass) {
+        const uint32_t axis = passes == 3 ? pass : 2u;
+        {
+            ProfScope ps(dev, "capture.setup", s);
+            k_setup<<<dim3((unsigned)((n_rec + kBlock - 1) / kBlock)), dim3(kBlock), 0, s>>>(
+                m->pos, m->rgba, m->tri, m->obj, (uint32_t)n_rec, d->mode, d->width, d->height, d->levels, ts,
+                proj, axis, copies, sc ? sc->scene_tri : nullptr, sc ? sc->n_scenes : 1u, recs, tiles);
+            e = hipGetLastError();
+        }
+        if (e != hipSuccess) return e;
+        {
+            ProfScope ps(dev, "capture.scan", s);
+            e = scan_u64(tiles, incl, n_rec, true, part, nullptr, s);
+        }
+        if (e != hipSuccess) return e;
+        ProfScope ps(dev, "capture.raster", s);
+        if (d->mode == FHV_PPFL)
+            k_raster<FHV_PPFL, uint32_t><<<dim3(grid), dim3(kBlock), 0, s>>>(
+                recs, incl, (uint32_t)n_rec, d->width, gmax, d->levels, ts, L->head, (uint4*)L->pool,
+                (uint32_t*)L->keys, L->capacity, (unsigned long long*)L->counter);
+        else if (!wide)
+            k_raster<FHV_POFL, uint32_t><<<dim3(grid), dim3(kBlock), 0, s>>>(
+                recs, incl, (uint32_t)n_rec, d->width, gmax, d->levels, ts, L->head, (uint4*)L->pool,
+                (uint32_t*)L->keys, L->capacity, (unsigned long long*)L->counter);
+        else
+            k_raster<FHV_POFL, uint64_t><<<dim3(grid), dim3(kBlock), 0, s>>>(
+                recs, incl, (uint32_t)n_rec, d->width, gmax, d->levels, ts, L->head, (uint4*)L->pool,
+                (uint64_t*)L->keys, L->capacity, (unsigned long long*)L->counter);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace fhv

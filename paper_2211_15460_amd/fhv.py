@@ -32,7 +32,7 @@ class Mesh_(C.Structure):
 
 class Desc_(C.Structure):
     _fields_ = [("mode", C.c_uint32), ("width", C.c_uint32), ("height", C.c_uint32),
-                ("levels", C.c_uint32)]
+                ("levels", C.c_uint32), ("projection", C.c_uint32)]
 
 
 class Lists_(C.Structure):
@@ -183,8 +183,11 @@ def to_device(mesh, device="cuda") -> DeviceMesh:
     return DeviceMesh(pos, rgba, tri, obj)
 
 
-def desc(mode: int, width: int = 0, height: int = 0, levels: int = 0) -> Desc_:
-    return Desc_(mode, width, height, levels)
+FHV_PROJ_NORMAL, FHV_PROJ_VIEW, FHV_PROJ_AXES_3PASS, FHV_PROJ_AXES_1PASS = 0, 1, 2, 3
+
+
+def desc(mode: int, width: int = 0, height: int = 0, levels: int = 0, projection: int = 0) -> Desc_:
+    return Desc_(mode, width, height, levels, projection)
 
 
 def n_head(d: Desc_) -> int:
