@@ -345,6 +345,42 @@ def raycast_report(torch, fhv, scenes, mesh, views, reps: int = 10) -> dict:
     return res
 
 
+def capture_variants_report(torch, fhv, mesh, reps: int = 10) -> dict:
+    """The capture variants of Table 2 on the step's scene (octree depth 9):
+    fragments captured and capture time (list reset, setup, scan and raster,
+    summed over the passes) for 1-Pass/Normal (the step's own), 1-Pass/View,
+    3-Pass/1-Way and 1-Pass/3-Way; means of `reps` captures after one
+    warm-up, HIP events around the library's launches."""
+    dm = fhv.to_device(mesh)
+    names = {fhv.FHV_PROJ_NORMAL: "1-Pass/Normal", fhv.FHV_PROJ_VIEW: "1-Pass/View",
+             fhv.FHV_PROJ_AXES_3PASS: "3-Pass/1-Way", fhv.FHV_PROJ_AXES_1PASS: "1-Pass/3-Way"}
+    res = {}
+    for proj, name in names.items():
+        d = fhv.desc(fhv.FHV_POFL, levels=LEVELS, projection=proj)
+        probe = fhv.alloc_lists(d, 1 << 16)
+        fhv.capture(dm, d, probe)
+        torch.cuda.synchronize()
+        F = int(probe.counter.item())
+        del probe
+        lists = fhv.alloc_lists(d, F)
+        ws = torch.empty(fhv.capture_workspace(d, mesh.n_tri), dtype=torch.uint8, device="cuda")
+        fhv.capture(dm, d, lists, ws)
+        torch.cuda.synchronize()
+        fhv.profile_begin()
+        for _ in range(reps):
+            fhv.capture(dm, d, lists, ws)
+        prof = fhv.profile_end()
+        ms = sum(t for k, (n, t) in prof.items() if k.startswith("capture.")) / reps
+        res[name] = {"fragments": F, "capture_ms": ms, "fragments_per_s": F / (ms * 1e-3),
+                     "raster_launches": prof["capture.raster"][0] // reps}
+        del lists, ws
+    base = res["1-Pass/Normal"]
+    for name, r in res.items():
+        r["fragments_vs_normal"] = r["fragments"] / base["fragments"]
+        r["time_vs_normal"] = r["capture_ms"] / base["capture_ms"]
+    return res
+
+
 def cpu_baseline(mesh, views, min_seconds: float = 10.0):
     """The CPU oracle, single-threaded, on the same workload: full steps
     (capture, compaction, three splats) repeated for at least min_seconds."""
@@ -766,6 +802,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-train", action="store_true", help="skip the learned-fill training report")
     ap.add_argument("--no-raycast", action="store_true", help="skip the ray casting report")
+    ap.add_argument("--no-variants", action="store_true", help="skip the capture-variant report")
     ap.add_argument("--no-ceilings", action="store_true",
                     help="skip the measured copy and atomic ceilings (fhv_probe)")
     ap.add_argument("--copy-mib", type=int, default=256,
@@ -916,6 +953,8 @@ def main():
     add_ceilings(args, out, torch, fhv, kernels, F, counters=True)
     if not args.no_raycast:
         out["raycast"] = raycast_report(torch, fhv, scenes, mesh, views)
+    if not args.no_variants:
+        out["capture_variants"] = capture_variants_report(torch, fhv, mesh)
     if not args.no_train:
         out["learned_fill"], _ = learned_fill_report(torch, fhv, scenes)
     if not args.no_cpu_baseline:
