@@ -204,6 +204,24 @@ FHV_API size_t fhv_compact_workspace(const fhv_capture_desc* desc, uint64_t capa
 FHV_API fhv_status fhv_compact(fhv_ctx* ctx, const fhv_lists* lists, const fhv_capture_desc* desc,
                        const fhv_pofa* out, void* ws, size_t ws_bytes, fhv_stream stream);
 
+/* POFL per-octant arrays straight from the triangles, created the way the
+ * paper creates FHV_POFA (Sec. 3.2): a first rasterization counts the
+ * fragments of every octant, a prefix sum in Morton order turns the counts
+ * into offsets, and a second rasterization stores every fragment at its
+ * octant's next free slot; no lists and no pool. The result is the one
+ * fhv_compact makes from fhv_capture's lists (the same table, offsets,
+ * counts and records in the same canonical in-octant order), bit for bit.
+ * out: as for fhv_compact; cap_frag must be >= 1 and < 2^32 - 1. If the
+ * scene has more than cap_frag fragments, *n_frag is set to their number,
+ * *n_occ to 0 and nothing else is written (allocate and call again, as
+ * after an overflowed capture). ws: fhv_capture_arrays_workspace(desc,
+ * n_tri, out->cap_frag) bytes, device, caller-owned.
+ * Errors: EINVAL (null pointers, PPFL desc, misaligned frag), ERANGE,
+ * EWORKSPACE. */
+FHV_API size_t fhv_capture_arrays_workspace(const fhv_capture_desc* desc, uint32_t n_tri, uint64_t capacity);
+FHV_API fhv_status fhv_capture_arrays(fhv_ctx* ctx, const fhv_mesh* mesh, const fhv_capture_desc* desc,
+                                      const fhv_pofa* out, void* ws, size_t ws_bytes, fhv_stream stream);
+
 /* One novel view (host struct, passed by value inside a host array).
  * m: row-major fp32 3x4 matrix taking a fragment position to (screen x,
  * screen y, depth) with screen units of pixels, y up, and depth > 0

@@ -426,6 +426,30 @@ fhv_status fhv_probe(fhv_ctx* ctx, uint32_t kind, void* buf, uint64_t bytes, uin
     return hip_status(fhv::probe_launch(ctx->dev, kind, buf, bytes, line, passes, (hipStream_t)stream));
 }
 
+size_t fhv_capture_arrays_workspace(const fhv_capture_desc* desc, uint32_t n_tri, uint64_t capacity)
+{
+    if (!desc_ok(desc) || desc->mode != FHV_POFL || capacity == 0 || capacity >= 0xFFFFFFFFull) return 0;
+    if (desc->projection == FHV_PROJ_AXES_1PASS && n_tri > 0x55555555u) return 0;
+    return fhv::capture_arrays_ws_bytes(desc, n_tri, capacity);
+}
+
+fhv_status fhv_capture_arrays(fhv_ctx* ctx, const fhv_mesh* mesh, const fhv_capture_desc* desc,
+                              const fhv_pofa* out, void* ws, size_t ws_bytes, fhv_stream stream)
+{
+    if (!ctx || !mesh || !desc_ok(desc) || !out || !ws) return FHV_EINVAL;
+    if (desc->mode != FHV_POFL) return FHV_EINVAL;
+    if (mesh->n_tri > 0 && (!mesh->pos || !mesh->rgba || !mesh->tri)) return FHV_EINVAL;
+    if (!out->n_occ || !out->n_frag || !out->frag || !out->oct_key || !out->oct_off || !out->oct_cnt)
+        return FHV_EINVAL;
+    if (out->cap_frag == 0 || out->cap_frag >= 0xFFFFFFFFull || out->cap_occ == 0) return FHV_ERANGE;
+    if ((uintptr_t)out->frag & 15) return FHV_EINVAL;
+    if (desc->projection == FHV_PROJ_AXES_1PASS && mesh->n_tri > 0x55555555u) return FHV_ERANGE;
+    if (ws_bytes < fhv::capture_arrays_ws_bytes(desc, mesh->n_tri, out->cap_frag)) return FHV_EWORKSPACE;
+    fhv_status st = set_device(ctx);
+    if (st != FHV_OK) return st;
+    return hip_status(fhv::capture_arrays_launch(ctx->dev, mesh, desc, out, ws, (hipStream_t)stream));
+}
+
 size_t fhv_raycast_workspace(const fhv_capture_desc* desc)
 {
     if (!desc_ok(desc) || desc->mode != FHV_POFL) return 0;

@@ -359,12 +359,16 @@ struct ItemWalk {
 // covered samples of the whole range, reserves that many pool slots with a
 // single atomic add on the counter, and then walks the range again to emit
 // the fragments into consecutive slots.
-template <int kMode, class KeyT>
+//
+// kAct (two-pass capture into arrays, lists and pool unused): kActCount
+// adds every fragment to its brick's histogram, kActInsert stores it in its
+// brick's staging range with the key's low bits in w3.
+template <int kMode, class KeyT, int kAct = kActList>
 __global__ void __launch_bounds__(kBlock)
 k_raster(const TriRec* __restrict__ recs, const uint64_t* __restrict__ incl, uint32_t n_tri,
          uint32_t width, uint32_t gmax, uint32_t levels, uint32_t ts, uint32_t* __restrict__ head,
          uint4* __restrict__ pool, KeyT* __restrict__ keys, uint64_t cap,
-         unsigned long long* __restrict__ counter)
+         unsigned long long* __restrict__ counter, BrickSink bs)
 {
     const uint64_t total = incl[n_tri - 1];
     const int lane = __lane_id();
@@ -374,9 +378,12 @@ k_raster(const TriRec* __restrict__ recs, const uint64_t* __restrict__ incl, uin
     const uint64_t w0 = wid * per;
     const uint64_t w1 = w0 + per < total ? w0 + per : total;
     if (w0 >= w1) return;
+    if (kAct == kActInsert && *bs.skip) return;
 
     ItemWalk it{incl, 0, 0, 0};
     constexpr int kBatch = 4;   // tiles per step; their memory operations overlap
+    unsigned long long base = 0;
+    if (kAct == kActList) {
     it.start(n_tri, w0);
     uint64_t n_cov = 0;
     for (uint64_t w = w0; w < w1; w += kBatch) {
@@ -395,9 +402,9 @@ k_raster(const TriRec* __restrict__ recs, const uint64_t* __restrict__ incl, uin
             if (tb[g] != kNil) n_cov += (uint64_t)__popcll(__ballot(sample_of(recs[tb[g]], tile[g], lane, ts).cov));
     }
     if (n_cov == 0) return;
-    unsigned long long base = 0;
     if (lane == 0) base = atomicAdd(counter, (unsigned long long)n_cov);
     base = __shfl(base, 0, kWave);
+    }
 
     it.start(n_tri, w0);
     for (uint64_t w = w0; w < w1; w += kBatch) {
@@ -414,10 +421,14 @@ k_raster(const TriRec* __restrict__ recs, const uint64_t* __restrict__ incl, uin
             it.advance(w + g);
             const TriRec& r = recs[it.t];
             const Sample sm = sample_of(r, (uint32_t)(w + g - it.first), lane, ts);
-            const uint64_t mask = __ballot(sm.cov);
-            idx[g] = base + (uint64_t)__popcll(mask & lanemask_lt());
-            base += (uint64_t)__popcll(mask);
-            has[g] = sm.cov && idx[g] < cap;
+            if (kAct == kActList) {
+                const uint64_t mask = __ballot(sm.cov);
+                idx[g] = base + (uint64_t)__popcll(mask & lanemask_lt());
+                base += (uint64_t)__popcll(mask);
+                has[g] = sm.cov && idx[g] < cap;
+            } else {
+                has[g] = sm.cov;
+            }
             if (!has[g]) continue;
             nrm[g] = r.nrm;
             w1r[g] = interp_rgba(sm.e12, sm.e20, sm.e01, r.rgba, r.A, r.rA);
@@ -438,6 +449,24 @@ k_raster(const TriRec* __restrict__ recs, const uint64_t* __restrict__ incl, uin
                          (spread3(gx >> 8) << 2) | (spread3(gy >> 8) << 1) | spread3(gz >> 8);
                 w0r[g] = (gx & 0xFFu) | ((gy & 0xFFu) << 8) | ((gz & 0xFFu) << 16) | (r.aux << 24);
             }
+        }
+        if (kAct == kActCount) {
+#pragma unroll
+            for (int g = 0; g < kBatch; ++g)
+                if (w + g < w1) wave_hist(key[g], has[g], bs.cnt, bs.occ, bs.bitmap);   // wave-uniform
+            continue;
+        }
+        if (kAct == kActInsert) {
+#pragma unroll
+            for (int g = 0; g < kBatch; ++g) {
+                if (w + g >= w1) continue;   // wave-uniform
+                const uint32_t b = (uint32_t)(key[g] >> kBrickShift);
+                const uint32_t slot = wave_count_add<true>(bs.cur, b, has[g]);
+                if (has[g])
+                    bs.stage[bs.off[b] + slot] =
+                        make_uint4(w0r[g], w1r[g], nrm[g], (uint32_t)key[g] & (kBrickKeys - 1));
+            }
+            continue;
         }
         uint32_t prev[kBatch];
 #pragma unroll
@@ -474,6 +503,63 @@ size_t capture_ws_bytes(const fhv_capture_desc* d, uint32_t n_tri)
     return c.off + 256;
 }
 
+// Setup of pass `pass` (of one, or three for 3-Pass/1-Way) and the
+// inclusive scan of its tiles per record.
+static hipError_t setup_pass(const Device& dev, const fhv_mesh* m, const fhv_capture_desc* d, uint32_t pass,
+                             const Scenes* sc, TriRec* recs, uint64_t* tiles, uint64_t* incl, uint64_t* part,
+                             const char* setup_name, const char* scan_name, hipStream_t s)
+{
+    const uint64_t n_rec = records_of(d, m->n_tri);
+    const uint32_t ts = dev.tune.tile_w == 32 ? 5u : (dev.tune.tile_w == 16 ? 4u : 3u);
+    const uint32_t proj = d->mode == FHV_POFL ? d->projection : FHV_PROJ_NORMAL;
+    const uint32_t copies = proj == FHV_PROJ_AXES_1PASS ? 3u : 1u;
+    // the axis plane of the pass: y-z, z-x, x-y for 3-Pass/1-Way, x-y for
+    // 1-Pass/View
+    const uint32_t axis = proj == FHV_PROJ_AXES_3PASS ? pass : 2u;
+    hipError_t e;
+    {
+        ProfScope ps(dev, setup_name, s);
+        k_setup<<<dim3((unsigned)((n_rec + kBlock - 1) / kBlock)), dim3(kBlock), 0, s>>>(
+            m->pos, m->rgba, m->tri, m->obj, (uint32_t)n_rec, d->mode, d->width, d->height, d->levels, ts, proj,
+            axis, copies, sc ? sc->scene_tri : nullptr, sc ? sc->n_scenes : 1u, recs, tiles);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return e;
+    ProfScope ps(dev, scan_name, s);
+    return scan_u64(tiles, incl, n_rec, true, part, nullptr, s);
+}
+
+hipError_t capture_bricks_launch(const Device& dev, const fhv_mesh* m, const fhv_capture_desc* d, void* ws,
+                                 int act, const BrickSink& bs, hipStream_t s)
+{
+    const uint64_t n_rec = records_of(d, m->n_tri);
+    Carver c{(char*)ws, 0};
+    TriRec* recs = c.take<TriRec>(n_rec);
+    uint64_t* tiles = c.take<uint64_t>(n_rec);
+    uint64_t* incl = c.take<uint64_t>(n_rec);
+    uint64_t* part = c.take<uint64_t>(scan_partials(n_rec));
+    if (m->n_tri == 0) return hipSuccess;
+    const uint32_t ts = dev.tune.tile_w == 32 ? 5u : (dev.tune.tile_w == 16 ? 4u : 3u);
+    const uint32_t passes = d->projection == FHV_PROJ_AXES_3PASS ? 3u : 1u;
+    const unsigned grid = (unsigned)(dev.cus * dev.tune.raster_wg);
+    const uint32_t gmax = (1u << (d->levels + 8)) - 1u;
+    const char* name = act == kActCount ? "arrays.count" : "arrays.insert";
+    for (uint32_t pass = 0; pass < passes; ++pass) {
+        hipError_t e = setup_pass(dev, m, d, pass, nullptr, recs, tiles, incl, part, "arrays.setup", "arrays.scan", s);
+        if (e != hipSuccess) return e;
+        ProfScope ps(dev, name, s);
+        if (act == kActCount)
+            k_raster<FHV_POFL, uint32_t, kActCount><<<dim3(grid), dim3(kBlock), 0, s>>>(
+                recs, incl, (uint32_t)n_rec, 0u, gmax, d->levels, ts, nullptr, nullptr, nullptr, 0, nullptr, bs);
+        else
+            k_raster<FHV_POFL, uint32_t, kActInsert><<<dim3(grid), dim3(kBlock), 0, s>>>(
+                recs, incl, (uint32_t)n_rec, 0u, gmax, d->levels, ts, nullptr, nullptr, nullptr, 0, nullptr, bs);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t capture_launch(const Device& dev, const fhv_mesh* m, const fhv_capture_desc* d,
                           const fhv_lists* L, void* ws, hipStream_t s, const Scenes* sc)
 {
@@ -491,42 +577,27 @@ hipError_t capture_launch(const Device& dev, const fhv_mesh* m, const fhv_captur
         if (e == hipSuccess) e = fill_u64(L->counter, 1, 0, s);
     }
     if (e != hipSuccess || m->n_tri == 0) return e;
-    const uint32_t proj = d->mode == FHV_POFL ? d->projection : FHV_PROJ_NORMAL;
-    const uint32_t copies = proj == FHV_PROJ_AXES_1PASS ? 3u : 1u;
-    // passes and the axis plane of each: three for 3-Pass/1-Way (y-z, z-x,
-    // x-y), one otherwise (x-y for 1-Pass/View)
-    const uint32_t passes = proj == FHV_PROJ_AXES_3PASS ? 3u : 1u;
+    // three passes for 3-Pass/1-Way, one otherwise
+    const uint32_t passes = d->mode == FHV_POFL && d->projection == FHV_PROJ_AXES_3PASS ? 3u : 1u;
     const unsigned grid = (unsigned)(dev.cus * dev.tune.raster_wg);
     const uint32_t gmax = d->mode == FHV_POFL ? (1u << (d->levels + 8)) - 1u : 0u;
     const bool wide = L->n_head > (1ull << 32);
     for (uint32_t pass = 0; pass < passes; ++pass) {
-        const uint32_t axis = passes == 3 ? pass : 2u;
-        {
-            ProfScope ps(dev, "capture.setup", s);
-            k_setup<<<dim3((unsigned)((n_rec + kBlock - 1) / kBlock)), dim3(kBlock), 0, s>>>(
-                m->pos, m->rgba, m->tri, m->obj, (uint32_t)n_rec, d->mode, d->width, d->height, d->levels, ts,
-                proj, axis, copies, sc ? sc->scene_tri : nullptr, sc ? sc->n_scenes : 1u, recs, tiles);
-            e = hipGetLastError();
-        }
-        if (e != hipSuccess) return e;
-        {
-            ProfScope ps(dev, "capture.scan", s);
-            e = scan_u64(tiles, incl, n_rec, true, part, nullptr, s);
-        }
+        e = setup_pass(dev, m, d, pass, sc, recs, tiles, incl, part, "capture.setup", "capture.scan", s);
         if (e != hipSuccess) return e;
         ProfScope ps(dev, "capture.raster", s);
         if (d->mode == FHV_PPFL)
             k_raster<FHV_PPFL, uint32_t><<<dim3(grid), dim3(kBlock), 0, s>>>(
                 recs, incl, (uint32_t)n_rec, d->width, gmax, d->levels, ts, L->head, (uint4*)L->pool,
-                (uint32_t*)L->keys, L->capacity, (unsigned long long*)L->counter);
+                (uint32_t*)L->keys, L->capacity, (unsigned long long*)L->counter, BrickSink{});
         else if (!wide)
             k_raster<FHV_POFL, uint32_t><<<dim3(grid), dim3(kBlock), 0, s>>>(
                 recs, incl, (uint32_t)n_rec, d->width, gmax, d->levels, ts, L->head, (uint4*)L->pool,
-                (uint32_t*)L->keys, L->capacity, (unsigned long long*)L->counter);
+                (uint32_t*)L->keys, L->capacity, (unsigned long long*)L->counter, BrickSink{});
         else
             k_raster<FHV_POFL, uint64_t><<<dim3(grid), dim3(kBlock), 0, s>>>(
                 recs, incl, (uint32_t)n_rec, d->width, gmax, d->levels, ts, L->head, (uint4*)L->pool,
-                (uint64_t*)L->keys, L->capacity, (unsigned long long*)L->counter);
+                (uint64_t*)L->keys, L->capacity, (unsigned long long*)L->counter, BrickSink{});
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -45,31 +45,13 @@ k_hist(const KeyT* __restrict__ keys, const uint64_t* __restrict__ counter, uint
 {
     const uint64_t F = frag_count(counter, cap);
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    const int lane = __lane_id();
     // the loop bound is rounded up to whole waves so that every lane of a
     // wave takes part in the wave-wide aggregation
     const uint64_t Fw = (F + kWave - 1) & ~(uint64_t)(kWave - 1);
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < Fw; i += stride) {
         const bool act = i < F;
         const uint64_t key = act ? (uint64_t)keys[i] : 0u;
-        wave_count_add<false>(brick_cnt, (uint32_t)(key >> kBrickShift), act);
-        // key bitmap: lanes hitting the same 32-key word OR their bits
-        // together; new bits count as newly occupied keys of the brick
-        const uint64_t word = key >> 5;
-        uint64_t todo = __ballot(act);
-        while (todo) {
-            const int leader = __ffsll((unsigned long long)todo) - 1;
-            const uint64_t lw = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(word >> 32), leader, kWave) << 32) |
-                                (uint32_t)__shfl((int)(uint32_t)word, leader, kWave);
-            const uint64_t m = __ballot(act && word == lw) & todo;
-            const uint32_t bits = wave_or(((m >> lane) & 1ull) ? (1u << (key & 31)) : 0u);
-            if (lane == leader) {
-                const uint32_t old = atomicOr(bitmap + lw, bits);
-                const uint32_t fresh = (uint32_t)__popc(bits & ~old);
-                if (fresh) atomicAdd(brick_occ + (lw >> (kBrickShift - 5)), fresh);
-            }
-            todo &= ~m;
-        }
+        wave_hist(key, act, brick_cnt, brick_occ, bitmap);
     }
 }
 
@@ -444,6 +426,9 @@ size_t compact_ws_bytes(const fhv_capture_desc* d, uint64_t n_head, uint64_t cap
     return b;
 }
 
+static hipError_t brick_sorts(const Device& dev, const CompactWs& w, const fhv_pofa* out, uint64_t n_brick,
+                              const char* name, hipStream_t s);
+
 hipError_t compact_launch(const Device& dev, const fhv_lists* L, const fhv_capture_desc* d,
                           const fhv_pofa* out, void* ws, hipStream_t s)
 {
@@ -489,9 +474,17 @@ hipError_t compact_launch(const Device& dev, const fhv_lists* L, const fhv_captu
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
+    return brick_sorts(dev, w, out, n_brick, "compact.brick", s);
+}
+
+// Per-brick sorts of the staging array into the output arrays.
+static hipError_t brick_sorts(const Device& dev, const CompactWs& w, const fhv_pofa* out, uint64_t n_brick,
+                              const char* name, hipStream_t s)
+{
+    hipError_t e;
     const uint64_t bmax = (uint64_t)dev.cus * 4;
     const unsigned gbrick = (unsigned)(n_brick < bmax ? n_brick : bmax);
-    ProfScope ps(dev, "compact.brick", s);
+    ProfScope ps(dev, name, s);
     const uint64_t wmax = (uint64_t)dev.cus * 64;
     const unsigned gwave = (unsigned)(n_brick < wmax ? n_brick : wmax);
     k_brick_wave<kSmallRecs, 0><<<dim3(gwave ? gwave : 1), dim3(kWave), 0, s>>>(
@@ -506,6 +499,70 @@ hipError_t compact_launch(const Device& dev, const fhv_lists* L, const fhv_captu
         w.stage, w.brick_cnt, w.brick_off, w.brick_rank, w.list, w.list_total, (uint4*)out->frag,
         out->oct_key, out->oct_off, out->oct_cnt, out->cap_occ);
     return hipGetLastError();
+}
+
+// Two-pass capture into arrays: after the count pass and the scans, the
+// fragment total decides whether the arrays hold them; if not, only the
+// counts are reported and the insert pass and the sorts do nothing.
+__global__ void k_arrays_check(uint64_t* __restrict__ list_total, uint64_t capacity, uint64_t* __restrict__ n_frag,
+                               uint64_t* __restrict__ n_occ, uint32_t* __restrict__ skip)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const uint64_t total = *list_total & 0xFFFFFFFFull;
+    *n_frag = total;
+    if (total > capacity) {
+        *skip = 1u;
+        *list_total = total;   // no occupied bricks left to sort
+        *n_occ = 0;
+    } else {
+        *skip = 0u;
+    }
+}
+
+size_t capture_arrays_ws_bytes(const fhv_capture_desc* d, uint32_t n_tri, uint64_t capacity)
+{
+    const size_t cap_b = (capture_ws_bytes(d, n_tri) + 255) & ~(size_t)255;
+    size_t b = 0;
+    carve_compact(nullptr, 1ull << (3 * d->levels), capacity, &b);
+    return cap_b + ((b + 255) & ~(size_t)255) + 256;
+}
+
+hipError_t capture_arrays_launch(const Device& dev, const fhv_mesh* m, const fhv_capture_desc* d,
+                                 const fhv_pofa* out, void* ws, hipStream_t s)
+{
+    const uint64_t n_head = 1ull << (3 * d->levels);
+    const uint64_t n_brick = (n_head + kBrickKeys - 1) / kBrickKeys;
+    const size_t cap_b = (capture_ws_bytes(d, m->n_tri) + 255) & ~(size_t)255;
+    size_t cmp_b = 0;
+    CompactWs w = carve_compact((char*)ws + cap_b, n_head, out->cap_frag, &cmp_b);
+    uint32_t* skip = (uint32_t*)((char*)ws + cap_b + ((cmp_b + 255) & ~(size_t)255));
+    hipError_t e;
+    {
+        ProfScope ps(dev, "arrays.reset", s);
+        e = fill_u32(w.brick_cnt, 3 * n_brick + (n_head + 31) / 32, 0u, s);
+        if (e == hipSuccess) e = fill_u64(w.list_total, 1, 0, s);
+        if (e == hipSuccess) e = fill_u32(skip, 1, 0u, s);
+    }
+    if (e != hipSuccess) return e;
+    BrickSink bs{w.brick_cnt, w.brick_occ, w.bitmap, w.brick_off, w.brick_cur, w.stage, skip};
+    e = capture_bricks_launch(dev, m, d, ws, kActCount, bs, s);
+    if (e != hipSuccess) return e;
+    {
+        ProfScope ps(dev, "arrays.scan", s);
+        e = scan<uint64_t>(LoadBrick{w.brick_cnt}, StoreBrick{w.brick_off, w.list}, n_brick, w.part,
+                           w.list_total, s);
+        if (e == hipSuccess)
+            e = scan<uint64_t>(LoadOcc{w.brick_occ}, StoreRank{w.brick_rank}, n_brick, w.part,
+                               (uint64_t*)out->n_occ, s);
+        if (e == hipSuccess) {
+            k_arrays_check<<<dim3(1), dim3(64), 0, s>>>(w.list_total, out->cap_frag, out->n_frag, out->n_occ, skip);
+            e = hipGetLastError();
+        }
+    }
+    if (e != hipSuccess) return e;
+    e = capture_bricks_launch(dev, m, d, ws, kActInsert, bs, s);
+    if (e != hipSuccess) return e;
+    return brick_sorts(dev, w, out, n_brick, "arrays.brick", s);
 }
 
 }  // namespace fhv

@@ -94,6 +94,33 @@ __device__ __forceinline__ uint32_t wave_count_add(uint32_t* ctr, uint32_t b, bo
     return slot;
 }
 
+// Per-brick histogram of keys (compaction buckets of kBrickKeys keys):
+// every active lane adds 1 to brick_cnt[key >> kBrickShift] and sets the
+// key's bit in `bitmap`; a bit set for the first time counts the key in
+// brick_occ. Lanes with the same brick or bitmap word share one atomic.
+// Must be called by all lanes of the wave.
+__device__ __forceinline__ void wave_hist(uint64_t key, bool act, uint32_t* brick_cnt, uint32_t* brick_occ,
+                                          uint32_t* bitmap)
+{
+    const int lane = __lane_id();
+    wave_count_add<false>(brick_cnt, (uint32_t)(key >> kBrickShift), act);
+    const uint64_t word = key >> 5;
+    uint64_t todo = __ballot(act);
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const uint64_t lw = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(word >> 32), leader, kWave) << 32) |
+                            (uint32_t)__shfl((int)(uint32_t)word, leader, kWave);
+        const uint64_t m = __ballot(act && word == lw) & todo;
+        const uint32_t bits = wave_or(((m >> lane) & 1ull) ? (1u << (key & 31)) : 0u);
+        if (lane == leader) {
+            const uint32_t old = atomicOr(bitmap + lw, bits);
+            const uint32_t fresh = (uint32_t)__popc(bits & ~old);
+            if (fresh) atomicAdd(brick_occ + (lw >> (kBrickShift - 5)), fresh);
+        }
+        todo &= ~m;
+    }
+}
+
 // Spread the low 21 bits of v to every third bit (bit b -> bit 3b).
 __device__ __forceinline__ uint64_t spread3(uint32_t v32)
 {
@@ -197,6 +224,23 @@ struct BatchViews {
 hipError_t splat_batch_launch(const Device& dev, const fhv_pofa* a, uint32_t levels, const BatchViews& bv,
                               uint64_t* zbuf, uint32_t* rgba, float* depth, uint8_t* cov,
                               uint64_t max_frag, hipStream_t s);
+
+// Two-pass capture straight into per-octant arrays (fhv_capture_arrays):
+// the rasterizer counts fragments per brick (kActCount) or stores each at its
+// brick's next free staging slot (kActInsert) instead of appending to lists.
+enum RasterAct { kActList = 0, kActCount = 1, kActInsert = 2 };
+struct BrickSink {
+    uint32_t *cnt, *occ, *bitmap;   // kActCount: per-brick counts, distinct keys, key bitmap
+    const uint32_t* off;            // kActInsert: brick offsets in the staging array
+    uint32_t* cur;                  //             per-brick slot cursors (zeroed)
+    uint4* stage;                   //             staging records, w3 = key within the brick
+    const uint32_t* skip;           //             non-zero: the arrays are too small, store nothing
+};
+hipError_t capture_bricks_launch(const Device& dev, const fhv_mesh* m, const fhv_capture_desc* d, void* ws,
+                                 int act, const BrickSink& bs, hipStream_t s);
+size_t capture_arrays_ws_bytes(const fhv_capture_desc* d, uint32_t n_tri, uint64_t capacity);
+hipError_t capture_arrays_launch(const Device& dev, const fhv_mesh* m, const fhv_capture_desc* d,
+                                 const fhv_pofa* out, void* ws, hipStream_t s);
 
 // Ray casting of per-octant arrays (fhv_raycast): octree depth up to
 // kMaxRayLevels (Morton codes of octants fit 32 bits).

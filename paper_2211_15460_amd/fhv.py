@@ -77,7 +77,8 @@ EXPORTS = ["fhv_create", "fhv_destroy", "fhv_status_str", "fhv_capture_workspace
            "fhv_compact_workspace", "fhv_compact", "fhv_splat", "fhv_profile_begin",
            "fhv_profile_end", "fhv_unet_param_count", "fhv_fill_workspace", "fhv_fill",
            "fhv_fill_train_step", "fhv_get_tuning", "fhv_set_tuning", "fhv_batch_workspace",
-           "fhv_batch_run", "fhv_probe", "fhv_raycast_workspace", "fhv_raycast"]
+           "fhv_batch_run", "fhv_probe", "fhv_raycast_workspace", "fhv_raycast", "fhv_capture_arrays_workspace",
+           "fhv_capture_arrays"]
 
 _lib = None
 _ctx: dict[int, C.c_void_p] = {}
@@ -120,6 +121,9 @@ def lib():
         L.fhv_batch_run.argtypes = [P, C.POINTER(BatchMesh_), C.POINTER(BatchViews_), C.POINTER(Lists_),
                                     C.POINTER(Pofa_), P, P, P, P, P, C.c_size_t, C.c_uint32, P]
         L.fhv_probe.argtypes = [P, C.c_uint32, P, C.c_uint64, C.c_uint32, C.c_uint32, P]
+        L.fhv_capture_arrays_workspace.argtypes = [C.POINTER(Desc_), C.c_uint32, C.c_uint64]
+        L.fhv_capture_arrays_workspace.restype = C.c_size_t
+        L.fhv_capture_arrays.argtypes = [P, C.POINTER(Mesh_), C.POINTER(Desc_), C.POINTER(Pofa_), P, C.c_size_t, P]
         L.fhv_raycast_workspace.argtypes = [C.POINTER(Desc_)]
         L.fhv_raycast_workspace.restype = C.c_size_t
         L.fhv_raycast.argtypes = [P, C.POINTER(Pofa_), C.POINTER(Desc_), C.POINTER(View_), C.c_uint32, C.c_uint32,
@@ -128,7 +132,7 @@ def lib():
         L.fhv_profile_end.argtypes = [P, C.POINTER(KernelStat_), C.c_uint32, C.POINTER(C.c_uint32)]
         for f in ("fhv_create", "fhv_destroy", "fhv_capture", "fhv_compact", "fhv_splat",
                   "fhv_profile_begin", "fhv_profile_end", "fhv_fill", "fhv_fill_train_step",
-                  "fhv_get_tuning", "fhv_set_tuning", "fhv_batch_run", "fhv_probe", "fhv_raycast"):
+                  "fhv_get_tuning", "fhv_set_tuning", "fhv_batch_run", "fhv_probe", "fhv_raycast", "fhv_capture_arrays"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -265,6 +269,26 @@ def alloc_pofa(cap_frag: int, cap_occ: int | None = None, device="cuda") -> Pofa
                 torch.empty((max(cap_frag, 1), 4), dtype=torch.int32, device=device),
                 torch.zeros(1, dtype=torch.int64, device=device),
                 torch.zeros(1, dtype=torch.int64, device=device), cap_occ, cap_frag)
+
+
+def capture_arrays_workspace(d: Desc_, n_tri: int, capacity: int) -> int:
+    return int(lib().fhv_capture_arrays_workspace(C.byref(d), n_tri, capacity))
+
+
+def capture_arrays(m: DeviceMesh, d: Desc_, out: Pofa, ws: torch.Tensor | None = None) -> Pofa:
+    """fhv_capture_arrays: per-octant arrays straight from the triangles
+    (two rasterization passes, no lists); returns `out`."""
+    need = capture_arrays_workspace(d, m.n_tri, out.cap_frag)
+    if need == 0:
+        raise FhvError("fhv_capture_arrays_workspace: unsupported arguments")
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=m.pos.device)
+    mesh = Mesh_(m.pos.data_ptr(), m.rgba.data_ptr(), m.tri.data_ptr(),
+                 None if m.obj is None else m.obj.data_ptr(), m.n_vert, m.n_tri)
+    ps = out.struct()
+    _check(lib().fhv_capture_arrays(ctx(), C.byref(mesh), C.byref(d), C.byref(ps), _ptr(ws), ws.numel(),
+                                    _stream()), "fhv_capture_arrays")
+    return out
 
 
 def compact_workspace(d: Desc_, capacity: int) -> int:
