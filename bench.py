@@ -381,6 +381,34 @@ def capture_variants_report(torch, fhv, mesh, reps: int = 10) -> dict:
     return res
 
 
+def arrays_report(torch, fhv, mesh, reps: int = 10) -> dict:
+    """The paper's way of creating the per-octant arrays (Sec. 3.2: count
+    pass, scan, insert pass; fhv_capture_arrays) against the step's lists
+    then compaction (fhv_capture + fhv_compact), on the step's scene; means
+    of `reps` calls after one warm-up, HIP events around the library's
+    launches. Both give the same arrays."""
+    d = fhv.desc(fhv.FHV_POFL, levels=LEVELS)
+    dm = fhv.to_device(mesh)
+    probe = fhv.alloc_lists(d, 1 << 16)
+    fhv.capture(dm, d, probe)
+    torch.cuda.synchronize()
+    F = int(probe.counter.item())
+    del probe
+    out = fhv.alloc_pofa(F)
+    ws = torch.empty(fhv.capture_arrays_workspace(d, mesh.n_tri, F), dtype=torch.uint8, device="cuda")
+    fhv.capture_arrays(dm, d, out, ws)
+    torch.cuda.synchronize()
+    assert int(out.n_frag.item()) == F
+    fhv.profile_begin()
+    for _ in range(reps):
+        fhv.capture_arrays(dm, d, out, ws)
+    prof = fhv.profile_end()
+    per = {k: t / reps for k, (n, t) in prof.items() if k.startswith("arrays.")}
+    return {"two_pass_ms": sum(per.values()), "stages_ms": per, "fragments": F,
+            "what": "count rasterization, scans, insert rasterization, per-brick sort; compare with "
+                    "stage_ms capture + compact (lists, then compaction)"}
+
+
 def cpu_baseline(mesh, views, min_seconds: float = 10.0):
     """The CPU oracle, single-threaded, on the same workload: full steps
     (capture, compaction, three splats) repeated for at least min_seconds."""
@@ -955,6 +983,7 @@ def main():
         out["raycast"] = raycast_report(torch, fhv, scenes, mesh, views)
     if not args.no_variants:
         out["capture_variants"] = capture_variants_report(torch, fhv, mesh)
+        out["pofa_two_pass"] = arrays_report(torch, fhv, mesh)
     if not args.no_train:
         out["learned_fill"], _ = learned_fill_report(torch, fhv, scenes)
     if not args.no_cpu_baseline:

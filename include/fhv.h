@@ -284,6 +284,33 @@ FHV_API fhv_status fhv_raycast(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_c
                                const fhv_view* views, uint32_t n_views, uint32_t mode, float tau,
                                float* rgba, void* ws, size_t ws_bytes, fhv_stream stream);
 
+/* Shading of the splat's nearest fragments (Sec. 5: a local illumination
+ * model per fragment, Phong 1975 / Blinn 1977). Per pixel of a splat's
+ * z-buffer holding a fragment: n = its packed normal unfolded from the
+ * octahedron, (int16 x, int16 y)/32767 with z = (1 - |x|) - |y| and, when
+ * z < 0, (x, y) = ((1 - |y|) s(x), (1 - |x|) s(y)), s(0) = +1, normalised by
+ * sqrt((x^2 + y^2) + z^2); flipped when n.v < 0 (no culling at capture);
+ * d = max(n.l, 0), s = (n.l > 0 ? max(n.h, 0) : 0)^(2^shine) by repeated
+ * squaring; out = albedo/255 * (ka + kd d) + ks s per channel, alpha 1; fp32,
+ * dot products as (x0 y0 + x1 y1) + x2 y2, no fused multiply-adds. Pixels
+ * without a fragment get 0.
+ * l, v, h: unit light, viewer and half vectors (world), given per view.
+ * zbuf: the uint64 [n_views][height][width] z-buffer of fhv_splat with the
+ * same arrays; rgba: float [n_views][height][width][4], device, 16-byte
+ * aligned. lights: host array of n_views in [1, 32]; shine <= 16.
+ * Errors: EINVAL (null pointers, shine above 16), ERANGE. */
+typedef struct {
+    float l[3];
+    float v[3];
+    float h[3];
+    float ka, kd, ks;
+    uint32_t shine;
+} fhv_light;
+
+FHV_API fhv_status fhv_shade(fhv_ctx* ctx, const fhv_pofa* arrays, const uint64_t* zbuf, uint32_t n_views,
+                             uint32_t width, uint32_t height, const fhv_light* lights, float* rgba,
+                             fhv_stream stream);
+
 /* Batches (not in the paper): many POFL scenes, each with several views,
  * through capture, compaction and splat in one call. The scenes share one
  * key space, key = scene * 8^L + Morton code of the leaf, so one launch per

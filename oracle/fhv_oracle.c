@@ -39,6 +39,9 @@
  *                             definition (gather, sort, composite); the
  *                             octree traversal that finds the fragments is
  *                             the GPU's business.
+ *   shading                   Sec. 5: a local illumination model per
+ *                             fragment (Blinn-Phong) applied to the splat's
+ *                             nearest fragments, from their packed normals.
  *   direct raster             Sec. 3.2 rasterization of the triangles
  *                             themselves in the novel view with a depth test;
  *                             the reference image for the splat.
@@ -690,6 +693,68 @@ uint64_t orc_raycast(uint32_t levels, const uint64_t* oct_key, const uint32_t* f
     free(list);
     free(fill);
     return deepest;
+}
+
+/* ------------------------------------------------------------ shading */
+
+/* Blinn-Phong shading of the splat's winners (Sec. 5: a local illumination
+ * model per fragment, Phong 1975 / Blinn 1977), fp32, each operation in the
+ * order written:
+ *   normal: p = (int16 x, int16 y) / 32767, z = (1 - |px|) - |py|; when
+ *   z < 0 the octahedron's lower half unfolds, (px, py) = ((1 - |py|) s(px),
+ *   (1 - |px|) s(py)) with s(0) = +1; n = (px, py, z) / sqrt((px^2 + py^2) +
+ *   z^2);
+ *   two-sided: if n.V < 0 the normal is flipped (n.X = (nx Xx + ny Xy) + nz Xz);
+ *   d = max(n.L, 0), s = (n.L > 0 ? max(n.H, 0) : 0) squared `shine`
+ *   times (exponent 2^shine), c = albedo (R, G, B / 255):
+ *   out = c * (ka + kd * d) + ks * s, alpha 1; empty pixels stay 0.
+ * light: per view L[3], V[3], H[3] (unit light, viewer and half vectors,
+ * given), ka, kd, ks, and shine as a float. zbuf: the splat's
+ * [V][H][W] keys (depth bits << 32 | index, ~0 empty). out: [V][H][W][4]. */
+void orc_shade(const uint32_t* frag, const uint64_t* zbuf, uint64_t n_pix_per_view, uint32_t n_views,
+               const float* light, float* out)
+{
+    for (uint32_t v = 0; v < n_views; ++v) {
+        const float* P = light + 13 * v;
+        const float *Lv = P, *Vv = P + 3, *Hv = P + 6;
+        const float ka = P[9], kd = P[10], ks = P[11];
+        const int shine = (int)P[12];
+        for (uint64_t q = 0; q < n_pix_per_view; ++q) {
+            const uint64_t z = zbuf[v * n_pix_per_view + q];
+            float* o = out + 4 * (v * n_pix_per_view + q);
+            o[0] = o[1] = o[2] = o[3] = 0.0f;
+            if (z == ~(uint64_t)0) continue;
+            const uint32_t* r = frag + 4 * (size_t)(uint32_t)z;
+            const uint32_t w2 = r[2], c = r[1];
+            float px = (float)(int16_t)(w2 & 0xFFFF) / 32767.0f;
+            float py = (float)(int16_t)(w2 >> 16) / 32767.0f;
+            const float nz = (1.0f - fabsf(px)) - fabsf(py);
+            if (nz < 0.0f) {
+                const float tx = (1.0f - fabsf(py)) * (px >= 0.0f ? 1.0f : -1.0f);
+                const float ty = (1.0f - fabsf(px)) * (py >= 0.0f ? 1.0f : -1.0f);
+                px = tx;
+                py = ty;
+            }
+            const float len = sqrtf((px * px + py * py) + nz * nz);
+            float n[3] = {px / len, py / len, nz / len};
+            const float ndv = (n[0] * Vv[0] + n[1] * Vv[1]) + n[2] * Vv[2];
+            if (ndv < 0.0f) {
+                n[0] = -n[0];
+                n[1] = -n[1];
+                n[2] = -n[2];
+            }
+            const float ndl = (n[0] * Lv[0] + n[1] * Lv[1]) + n[2] * Lv[2];
+            const float ndh = (n[0] * Hv[0] + n[1] * Hv[1]) + n[2] * Hv[2];
+            const float d = ndl > 0.0f ? ndl : 0.0f;
+            float sp = (ndl > 0.0f && ndh > 0.0f) ? ndh : 0.0f;
+            for (int k = 0; k < shine; ++k) sp = sp * sp;
+            for (int k = 0; k < 3; ++k) {
+                const float al = (float)((c >> (8 * k)) & 0xFFu) / 255.0f;
+                o[k] = al * (ka + kd * d) + ks * sp;
+            }
+            o[3] = 1.0f;
+        }
+    }
 }
 
 /* ------------------------------------------------------------ direct raster */

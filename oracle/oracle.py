@@ -68,6 +68,7 @@ def lib():
         L.orc_capture_pofl_proj.argtypes = [f32p, u32p, u32p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32,
                                             C.c_uint64, C.c_uint64, u32p, u32p, C.c_uint64]
         L.orc_capture_pofl_proj.restype = C.c_uint64
+        L.orc_shade.argtypes = [u32p, u64p, C.c_uint64, C.c_uint32, f32p, f32p]
         L.orc_raycast.argtypes = [C.c_uint32, u64p, u32p, C.c_uint64, f32p, C.c_uint32, C.c_uint32, C.c_int,
                                   C.c_float, f32p]
         L.orc_raycast.restype = C.c_uint64
@@ -189,10 +190,11 @@ def _views_arrays(views):
 
 
 def splat(mode: int, keys: np.ndarray, frag: np.ndarray, views, width_cap: int = 0,
-          levels: int = 0):
+          levels: int = 0, return_zbuf: bool = False):
     """Point splat with nearest-fragment resolve (Sec. 3.3).
 
-    Returns (rgba uint32[V,H,W], depth float32[V,H,W], cov uint8[V,H,W]); all
+    Returns (rgba uint32[V,H,W], depth float32[V,H,W], cov uint8[V,H,W]),
+    and the z-buffer of winners (uint64 [V,H,W]) when return_zbuf; all
     views must share one size."""
     W, H = views[0].width, views[0].height
     assert all(v.width == W and v.height == H for v in views)
@@ -209,6 +211,8 @@ def splat(mode: int, keys: np.ndarray, frag: np.ndarray, views, width_cap: int =
     if fr.size == 0:
         fr = np.zeros(4, np.uint32)
     lib().orc_splat(mode, width_cap, levels, keys, fr, frag.shape[0], m, whk, V, z, rgba, depth, cov)
+    if return_zbuf:
+        return rgba.reshape(V, H, W), depth.reshape(V, H, W), cov.reshape(V, H, W), z.reshape(V, H, W)
     return rgba.reshape(V, H, W), depth.reshape(V, H, W), cov.reshape(V, H, W)
 
 
@@ -238,6 +242,22 @@ def raycast(keys: np.ndarray, frag: np.ndarray, views, levels: int, mode: int = 
     return out, deepest
 
 
+def shade(frag: np.ndarray, zbuf: np.ndarray, lights: np.ndarray) -> np.ndarray:
+    """Blinn-Phong shading of a splat's winners (Sec. 5). zbuf: uint64
+    [V, H, W] splat keys; lights: float32 [V, 13] = L, V, H (unit vectors),
+    ka, kd, ks, shine (exponent 2^shine). Returns float32 [V, H, W, 4]."""
+    zb = np.ascontiguousarray(zbuf, dtype=np.uint64)
+    V = zb.shape[0]
+    npix = zb.size // V
+    fr = np.ascontiguousarray(frag, dtype=np.uint32).reshape(-1)
+    if fr.size == 0:
+        fr = np.zeros(4, np.uint32)
+    out = np.zeros(zb.shape + (4,), np.float32)
+    lib().orc_shade(fr, zb.reshape(-1), npix, V, np.ascontiguousarray(lights, np.float32).reshape(-1),
+                    out.reshape(-1))
+    return out
+
+
 def direct_raster(mode: int, mesh, view, width_cap: int = 0, height_cap: int = 0, levels: int = 0):
     """Depth-tested rasterization of the triangles into one view: the
     reference image for a novel-view reconstruction. Returns (rgba, depth,
@@ -263,5 +283,5 @@ def psnr_rgb(a: np.ndarray, b: np.ndarray) -> float:
 
 
 __all__ = ["NIL", "build", "lib", "oct_encode", "oct_decode", "tangent_frame", "morton3",
-           "capture_ppfl", "capture_pofl", "capture_pofl_range", "compact", "splat", "raycast", "direct_raster",
+           "capture_ppfl", "capture_pofl", "capture_pofl_range", "compact", "splat", "raycast", "shade", "direct_raster",
            "psnr_rgb"]

@@ -450,6 +450,34 @@ fhv_status fhv_capture_arrays(fhv_ctx* ctx, const fhv_mesh* mesh, const fhv_capt
     return hip_status(fhv::capture_arrays_launch(ctx->dev, mesh, desc, out, ws, (hipStream_t)stream));
 }
 
+fhv_status fhv_shade(fhv_ctx* ctx, const fhv_pofa* arrays, const uint64_t* zbuf, uint32_t n_views,
+                     uint32_t width, uint32_t height, const fhv_light* lights, float* rgba, fhv_stream stream)
+{
+    if (!ctx || !arrays || !zbuf || !lights || !rgba) return FHV_EINVAL;
+    if (n_views == 0 || n_views > fhv::kMaxViews) return FHV_ERANGE;
+    if (width < 1 || width > 16384 || height < 1 || height > 16384) return FHV_ERANGE;
+    if (arrays->cap_frag > 0 && !arrays->frag) return FHV_EINVAL;
+    if (((uintptr_t)rgba & 15) || ((uintptr_t)zbuf & 7)) return FHV_EINVAL;
+    fhv::ShadeArgs a;
+    memset(&a, 0, sizeof(a));
+    for (uint32_t v = 0; v < n_views; ++v) {
+        if (lights[v].shine > 16) return FHV_EINVAL;
+        for (int k = 0; k < 3; ++k) {
+            a.l[v][k] = lights[v].l[k];
+            a.v[v][k] = lights[v].v[k];
+            a.h[v][k] = lights[v].h[k];
+        }
+        a.ka[v] = lights[v].ka;
+        a.kd[v] = lights[v].kd;
+        a.ks[v] = lights[v].ks;
+        a.shine[v] = lights[v].shine;
+    }
+    fhv_status st = set_device(ctx);
+    if (st != FHV_OK) return st;
+    return hip_status(fhv::shade_launch(ctx->dev, arrays, zbuf, n_views, (uint64_t)width * height, a, rgba,
+                                        (hipStream_t)stream));
+}
+
 size_t fhv_raycast_workspace(const fhv_capture_desc* desc)
 {
     if (!desc_ok(desc) || desc->mode != FHV_POFL) return 0;

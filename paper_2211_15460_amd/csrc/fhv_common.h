@@ -242,6 +242,16 @@ size_t capture_arrays_ws_bytes(const fhv_capture_desc* d, uint32_t n_tri, uint64
 hipError_t capture_arrays_launch(const Device& dev, const fhv_mesh* m, const fhv_capture_desc* d,
                                  const fhv_pofa* out, void* ws, hipStream_t s);
 
+// Shading of splat winners (fhv_shade): per view the light, viewer and half
+// vectors and the material terms.
+struct ShadeArgs {
+    float l[kMaxViews][3], v[kMaxViews][3], h[kMaxViews][3];
+    float ka[kMaxViews], kd[kMaxViews], ks[kMaxViews];
+    uint32_t shine[kMaxViews];
+};
+hipError_t shade_launch(const Device& dev, const fhv_pofa* p, const uint64_t* zbuf, uint32_t n_views,
+                        uint64_t n_pix, const ShadeArgs& a, float* out, hipStream_t s);
+
 // Ray casting of per-octant arrays (fhv_raycast): octree depth up to
 // kMaxRayLevels (Morton codes of octants fit 32 bits).
 constexpr uint32_t kMaxRayLevels = 10;

@@ -35,6 +35,11 @@ class Desc_(C.Structure):
                 ("levels", C.c_uint32), ("projection", C.c_uint32)]
 
 
+class Light_(C.Structure):
+    _fields_ = [("l", C.c_float * 3), ("v", C.c_float * 3), ("h", C.c_float * 3), ("ka", C.c_float),
+                ("kd", C.c_float), ("ks", C.c_float), ("shine", C.c_uint32)]
+
+
 class Lists_(C.Structure):
     _fields_ = [("head", C.c_void_p), ("n_head", C.c_uint64), ("pool", C.c_void_p),
                 ("capacity", C.c_uint64), ("keys", C.c_void_p), ("counter", C.c_void_p)]
@@ -78,7 +83,7 @@ EXPORTS = ["fhv_create", "fhv_destroy", "fhv_status_str", "fhv_capture_workspace
            "fhv_profile_end", "fhv_unet_param_count", "fhv_fill_workspace", "fhv_fill",
            "fhv_fill_train_step", "fhv_get_tuning", "fhv_set_tuning", "fhv_batch_workspace",
            "fhv_batch_run", "fhv_probe", "fhv_raycast_workspace", "fhv_raycast", "fhv_capture_arrays_workspace",
-           "fhv_capture_arrays"]
+           "fhv_capture_arrays", "fhv_shade"]
 
 _lib = None
 _ctx: dict[int, C.c_void_p] = {}
@@ -124,6 +129,8 @@ def lib():
         L.fhv_capture_arrays_workspace.argtypes = [C.POINTER(Desc_), C.c_uint32, C.c_uint64]
         L.fhv_capture_arrays_workspace.restype = C.c_size_t
         L.fhv_capture_arrays.argtypes = [P, C.POINTER(Mesh_), C.POINTER(Desc_), C.POINTER(Pofa_), P, C.c_size_t, P]
+        L.fhv_shade.argtypes = [P, C.POINTER(Pofa_), P, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(Light_),
+                                P, P]
         L.fhv_raycast_workspace.argtypes = [C.POINTER(Desc_)]
         L.fhv_raycast_workspace.restype = C.c_size_t
         L.fhv_raycast.argtypes = [P, C.POINTER(Pofa_), C.POINTER(Desc_), C.POINTER(View_), C.c_uint32, C.c_uint32,
@@ -132,7 +139,7 @@ def lib():
         L.fhv_profile_end.argtypes = [P, C.POINTER(KernelStat_), C.c_uint32, C.POINTER(C.c_uint32)]
         for f in ("fhv_create", "fhv_destroy", "fhv_capture", "fhv_compact", "fhv_splat",
                   "fhv_profile_begin", "fhv_profile_end", "fhv_fill", "fhv_fill_train_step",
-                  "fhv_get_tuning", "fhv_set_tuning", "fhv_batch_run", "fhv_probe", "fhv_raycast", "fhv_capture_arrays"):
+                  "fhv_get_tuning", "fhv_set_tuning", "fhv_batch_run", "fhv_probe", "fhv_raycast", "fhv_capture_arrays", "fhv_shade"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -344,6 +351,37 @@ def splat(arrays: Pofa, d: Desc_, views, out: Images | None = None, vstruct=None
         _check(lib().fhv_splat(ctx(), C.byref(ps), C.byref(d), arr, len(vs),
                                _ptr(out.zbuf[v0:]), _ptr(out.rgba[v0:]), _ptr(out.depth[v0:]),
                                _ptr(out.cov[v0:]), _stream()), "fhv_splat")
+    return out
+
+
+def light_vectors(view, light_dir, ka: float = 0.2, kd: float = 0.7, ks: float = 0.3, shine: int = 5):
+    """[13] float32 light record for a view: unit light direction (towards
+    the light), unit viewer direction (towards the viewer: minus the view's
+    depth axis), their half vector, ka, kd, ks, shine (exponent 2^shine)."""
+    m = np.asarray(view.m, np.float64).reshape(3, 4)
+    vv = -m[2, :3] / np.linalg.norm(m[2, :3])
+    ll = np.asarray(light_dir, np.float64)
+    ll = ll / np.linalg.norm(ll)
+    hh = (ll + vv) / np.linalg.norm(ll + vv)
+    return np.concatenate([ll, vv, hh, [ka, kd, ks, float(shine)]]).astype(np.float32)
+
+
+def shade(arrays: Pofa, images: Images, lights) -> torch.Tensor:
+    """fhv_shade of a splat's z-buffers (images from fhv.splat with the same
+    arrays); lights: [V, 13] records (light_vectors). Returns float32
+    [V, H, W, 4]."""
+    V, H, W = images.zbuf.shape
+    lights = np.asarray(lights, np.float32).reshape(V, 13)
+    arr = (Light_ * V)()
+    for i in range(V):
+        arr[i].l[:] = [float(x) for x in lights[i, 0:3]]
+        arr[i].v[:] = [float(x) for x in lights[i, 3:6]]
+        arr[i].h[:] = [float(x) for x in lights[i, 6:9]]
+        arr[i].ka, arr[i].kd, arr[i].ks = float(lights[i, 9]), float(lights[i, 10]), float(lights[i, 11])
+        arr[i].shine = int(lights[i, 12])
+    out = torch.empty((V, H, W, 4), dtype=torch.float32, device=images.zbuf.device)
+    ps = arrays.struct()
+    _check(lib().fhv_shade(ctx(), C.byref(ps), _ptr(images.zbuf), V, W, H, arr, _ptr(out), _stream()), "fhv_shade")
     return out
 
 

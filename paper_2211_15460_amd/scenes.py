@@ -320,6 +320,14 @@ def cube_view(theta_deg: float, levels: int, width: int, height: int,
 
 # ------------------------------------------------------------ named workloads
 
+def stereo_views(theta_deg: float, levels: int, width: int, height: int, eye_deg: float = 4.0,
+                 splat_px: int | None = None) -> list[View]:
+    """Left and right eye of a stereo pair (Sec. 5: several novel views from
+    one FHV): two orbit views eye_deg apart around theta_deg (toe-in)."""
+    return [cube_view(theta_deg - 0.5 * eye_deg, levels, width, height, splat_px=splat_px),
+            cube_view(theta_deg + 0.5 * eye_deg, levels, width, height, splat_px=splat_px)]
+
+
 def ppfl_plain(seed: int = 0) -> Mesh:
     """64 triangles, vertices uniform in [-1,1]^3 clip space (128x128 capture)."""
     return clip_soup(64, seed)
