@@ -984,6 +984,19 @@ def main():
     if not args.no_variants:
         out["capture_variants"] = capture_variants_report(torch, fhv, mesh)
         out["pofa_two_pass"] = arrays_report(torch, fhv, mesh)
+        # Blinn-Phong shading of the step's three splats (Sec. 5)
+        import numpy as np
+        lights = np.stack([fhv.light_vectors(v, (0.3, 1.0, -0.5)) for v in views])
+        fhv.shade(pofa, imgs, lights)
+        torch.cuda.synchronize()
+        fhv.profile_begin()
+        for _ in range(10):
+            fhv.shade(pofa, imgs, lights)
+        sh = fhv.profile_end()["shade"][1] / 10
+        out["shade"] = {"ms_per_call": sh, "views": len(views), "views_per_s": len(views) / (sh * 1e-3),
+                        "bytes": len(views) * W_OUT * H_OUT * (8 + 16),
+                        "gbs": len(views) * W_OUT * H_OUT * (8 + 16) / (sh * 1e-3) / 1e9,
+                        "what": "per pixel: z-buffer key read, float4 written (plus the winner's record)"}
     if not args.no_train:
         out["learned_fill"], _ = learned_fill_report(torch, fhv, scenes)
     if not args.no_cpu_baseline:
