@@ -568,6 +568,188 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
     }
 }
 
+// Deep 3x3 layers (Cin a multiple of 64, Cout a multiple of 64): a
+// workgroup of 8 waves computes 8 output rows x 62 pixels x 64 channels, one
+// row per wave with all 64 channels (4 x 4 MFMA tiles per tap). Per
+// 32-channel chunk, the input halo (10 rows x 64 pixels) and the weights of
+// all nine taps are staged in LDS by direct buffer-to-LDS loads (no
+// registers and no LDS write instructions in between), double-buffered: the
+// next chunk loads while the current one is computed, with one barrier per
+// chunk. LDS rows are 64 bytes (32 bf16); the 16-byte chunk q of row r sits
+// at position q ^ ((r >> 1) & 3), which keeps the operand reads of any 16
+// consecutive rows free of bank conflicts (measured on gfx950). Sums run in
+// the same order as in k_conv3 (chunks, then taps), so results are the same.
+namespace cva {
+// A tile is 62 pixels wide so that a halo row is 64 pixels: moving the
+// operand window by whole rows (the taps' dy) then leaves the swizzle of
+// every lane unchanged and its addresses differ by constants. The waves'
+// last two of 64 pixels are computed but not stored.
+constexpr int R = 8, TX = 62, HP = TX + 2, RP = R + 2, TN = 64, NW = 4;
+constexpr int HSLOTS = (RP * HP * 4 + 63) / 64 * 64;   // halo slots, whole wave-loads
+constexpr int WSLOTS = 9 * TN * 4;                      // weight slots (a multiple of 64)
+constexpr int SLOTS = HSLOTS + WSLOTS;
+constexpr int INSTR = SLOTS / 64;                       // wave-loads per stage
+constexpr int HINSTR = HSLOTS / 64;                     // the first HINSTR load halo rows
+constexpr int WAVES = 8;
+constexpr int JPW = (INSTR + WAVES - 1) / WAVES;        // wave-loads per wave
+constexpr int EP = 16 * NW + 8;                          // epilogue pitch (bf16 per pixel)
+static_assert(WSLOTS % 64 == 0, "weight region starts on a wave-load boundary");
+static_assert(WAVES * 64 * EP <= SLOTS * 8, "epilogue fits one stage");
+}  // namespace cva
+
+__device__ __forceinline__ uint32_t swz_slot(uint32_t row, uint32_t q)
+{
+    return row * 4 + (q ^ ((row >> 1) & 3u));
+}
+
+__global__ void __launch_bounds__(cva::WAVES * kWave) k_conv3a(ConvArgs a)
+{
+    using namespace cva;
+    __shared__ __attribute__((aligned(16))) uint16_t st0[SLOTS * 8];
+    __shared__ __attribute__((aligned(16))) uint16_t st1[SLOTS * 8];
+    const int lane = __lane_id(), wv = threadIdx.x / kWave;
+    const int g = lane >> 4, l16 = lane & 15;
+    const uint32_t xtiles = (a.W + TX - 1) / TX, ytiles = (a.H + R - 1) / R;
+    const uint32_t t = blockIdx.x;
+    const uint32_t co0 = blockIdx.y * TN;
+    const uint32_t n = t / (xtiles * ytiles), rem = t % (xtiles * ytiles);
+    const uint32_t y0 = (rem / xtiles) * R, x0 = (rem % xtiles) * TX;
+    const uint32_t Cin = a.Cin, K = 9 * Cin, nc = Cin >> 5;
+    const uint32_t r_first = y0 >= 1 ? y0 - 1 : 0;
+    const uint32_t r_last = y0 + R < a.H ? y0 + R : a.H - 1;
+    const uint32_t row_b = a.W * a.in_cs * 2;
+    const __amdgpu_buffer_rsrc_t ir = rsrc(a.in + ((size_t)n * a.H + r_first) * a.W * a.in_cs,
+                                           (r_last - r_first + 1) * row_b);
+    const __amdgpu_buffer_rsrc_t wrs = rsrc(a.wt, a.Cout * K * 2);
+    // this lane's source byte offset for each of its wave's loads (chunk 0;
+    // chunk cc adds 64 cc): wave wv issues loads j = wv, wv + 8, ...; load j
+    // fills slots 64 j .. 64 j + 63, lane i slot 64 j + i
+    uint32_t src[JPW];
+#pragma unroll
+    for (int k = 0; k < JPW; ++k) {
+        const uint32_t j = (uint32_t)(wv + WAVES * k), s = j * 64 + (uint32_t)lane;
+        uint32_t off = kOob;
+        if (j < (uint32_t)HINSTR) {
+            const uint32_t rl = s >> 2;
+            if (rl < (uint32_t)(RP * HP)) {
+                const uint32_t q = (s & 3u) ^ ((rl >> 1) & 3u);
+                const int ys = (int)y0 + (int)(rl / HP) - 1, xs = (int)x0 + (int)(rl % HP) - 1;
+                if (ys >= 0 && ys < (int)a.H && xs >= 0 && xs < (int)a.W)
+                    off = ((uint32_t)ys - r_first) * row_b + (uint32_t)xs * a.in_cs * 2 + q * 16;
+            }
+        } else if (j < (uint32_t)INSTR) {
+            const uint32_t s2 = s - HSLOTS, wrow = s2 >> 2, q = (s2 & 3u) ^ ((wrow >> 1) & 3u);
+            const uint32_t tap = wrow / TN, co = wrow % TN;
+            if (co0 + co < a.Cout) off = ((co0 + co) * K + tap * Cin) * 2 + q * 16;
+        }
+        src[k] = off;
+    }
+    auto issue = [&](uint16_t* stg, uint32_t cc) {
+#pragma unroll
+        for (int k = 0; k < JPW; ++k) {
+            const uint32_t j = (uint32_t)(wv + WAVES * k);
+            if (j >= (uint32_t)INSTR) break;   // wave-uniform
+            const uint32_t off = src[k] == kOob ? kOob : src[k] + cc * 64;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(j < (uint32_t)HINSTR ? ir : wrs,
+                                                     (__attribute__((address_space(3))) void*)(stg + j * 512), 16,
+                                                     off, 0, 0, 0);
+        }
+    };
+    floatx4 acc[4][NW];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < NW; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    auto compute = [&](const uint16_t* stg) {
+        const uint16_t* wts = stg + HSLOTS * 8;
+        u32x4 av[2][4], bv[2][NW];
+        auto rd = [&](int tap, u32x4 (&A)[4], u32x4 (&B)[NW]) {
+            const int dy = tap / 3, dx = tap % 3;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                A[i] = *(const u32x4*)&stg[swz_slot((uint32_t)((wv + dy) * HP + 16 * i + l16 + dx), (uint32_t)g) * 8];
+#pragma unroll
+            for (int j = 0; j < NW; ++j)
+                B[j] = *(const u32x4*)&wts[swz_slot((uint32_t)(tap * TN + 16 * j + l16), (uint32_t)g) * 8];
+        };
+        rd(0, av[0], bv[0]);
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int cur = tap & 1;
+            if (tap + 1 < 9) rd(tap + 1, av[cur ^ 1], bv[cur ^ 1]);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < NW; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(bf16x8, av[cur][i]), __builtin_bit_cast(bf16x8, bv[cur][j]), acc[i][j], 0, 0,
+                        0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    // chunk cc is in st0 when even, st1 when odd; a stage is refilled only
+    // after the barrier that follows every wave's reads of it
+    issue(st0, 0);
+    for (uint32_t cc = 0; cc < nc; cc += 2) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (cc + 1 < nc) issue(st1, cc + 1);
+        compute(st0);
+        if (cc + 1 >= nc) break;
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (cc + 2 < nc) issue(st0, cc + 2);
+        compute(st1);
+    }
+    __syncthreads();   // the epilogue reuses st0
+    const uint32_t y = y0 + (uint32_t)wv;
+    uint16_t* ep = st0 + wv * 64 * EP;
+    store_tile<4, NW>(ep, acc, a.bias, co0, a.Cout, a.relu != 0, [&](int px) -> uint16_t* {
+        const uint32_t x = x0 + (uint32_t)px;
+        if (px >= TX || y >= a.H || x >= a.W) return nullptr;
+        return a.out + (((size_t)n * a.H + y) * a.W + x) * a.out_cs + co0;
+    });
+    if (!a.pool) return;
+    // 2x2 max pool (even H and W) from the waves' epilogue tiles: one thread
+    // per pooled pixel and 8 channels; the first largest of the window in
+    // (0,0), (0,1), (1,0), (1,1) order
+    __syncthreads();
+    constexpr int PCH = TN / 8, RUNS = (TX / 2) * (R / 2) * PCH;
+    for (uint32_t run = threadIdx.x; run < (uint32_t)RUNS; run += WAVES * kWave) {
+        const uint32_t c8 = run % PCH, p2 = (run / PCH) % (TX / 2), pr = run / (PCH * (TX / 2));
+        const uint32_t xs = x0 + 2 * p2, ys = y0 + 2 * pr;
+        if (xs >= a.W || ys >= a.H || co0 + 8 * c8 >= a.Cout) continue;
+        u32x4 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t r = 2 * pr + (k >> 1), px = 2 * p2 + (k & 1);
+            v[k] = *(const u32x4*)&st0[r * 64 * EP + px * EP + 8 * c8];
+        }
+        u32x4 o;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            uint32_t word = 0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                float m = -INFINITY;
+                uint32_t best = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t bb = (v[k][c] >> (16 * h)) & 0xFFFFu;
+                    if (bf2f((uint16_t)bb) > m) {
+                        m = bf2f((uint16_t)bb);
+                        best = bb;
+                    }
+                }
+                word |= best << (16 * h);
+            }
+            o[c] = word;
+        }
+        *(u32x4*)(a.pool + (((size_t)n * (a.H / 2) + ys / 2) * (a.W / 2) + xs / 2) * a.pool_cs + co0 + 8 * c8) = o;
+    }
+}
+
 struct WgradArgs {
     const uint16_t* gr;   // gradient w.r.t. the layer output (first channel)
     const uint16_t* x;    // layer input (first channel)
@@ -1074,6 +1256,9 @@ hipError_t conv(const uint16_t* in, uint32_t in_cs, const uint16_t* wt, const fl
             k_conv3<2, 64, false, 4, true><<<pgrid(N * ((H + 3) / 4) * ((W + 63) / 64), (Cout + 31) / 32), blk, 0, s>>>(a);
         else if (narrow)
             k_conv3<2, 64, false, 4><<<pgrid(N * ((H + 3) / 4) * ((W + 63) / 64), (Cout + 31) / 32), blk, 0, s>>>(a);
+        else if (Cin % 64 == 0 && Cout % 64 == 0)
+            k_conv3a<<<dim3(N * ((H + cva::R - 1) / cva::R) * ((W + cva::TX - 1) / cva::TX), Cout / 64),
+                       dim3(cva::WAVES * kWave), 0, s>>>(a);
         else
             k_conv3<4, 64, false><<<pgrid(rows2 * ((W + 63) / 64), (Cout + 63) / 64), blk, 0, s>>>(a);
         break;
