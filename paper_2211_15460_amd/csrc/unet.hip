@@ -96,27 +96,49 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* p, uint32_t b
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, 0x00020000);
 }
 
+// rsrc from values that may sit in vector registers, read back as scalars
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t srsrc(const void* p, uint32_t bytes)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return rsrc((const void*)(lo | (hi << 32)), __builtin_amdgcn_readfirstlane(bytes));
+}
+
 __device__ __forceinline__ u32x4 bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
 {
     return __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
 }
 
-// Epilogue of a wave's (16 MI)-pixel x (16 NJ)-channel result tile: bias,
-// ReLU and bf16 rounding, then a pass through the wave's own LDS region
-// (pixel-major, pitch 16 NJ + 8) so that each lane stores whole 16-byte
-// runs of 8 channels of one pixel. dst(p) is the first output channel of
-// the tile's pixel p, or null when that pixel is outside the output.
+// The bias of this lane's output channel in each of a wave tile's NJ
+// 16-channel columns (zero without bias or past Cout).
+template <int NJ>
+__device__ __forceinline__ void tile_bias(float (&bv)[NJ], const float* __restrict__ bias, uint32_t co0,
+                                          uint32_t Cout)
+{
+    const int l16 = __lane_id() & 15;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const uint32_t co = co0 + 16 * j + l16;
+        bv[j] = (bias && co < Cout) ? bias[co] : 0.0f;
+    }
+}
+
+// Epilogue of a wave's (16 MI)-pixel x (16 NJ)-channel result tile: bias
+// (per column, from tile_bias), ReLU and bf16 rounding, then a pass through
+// the wave's own LDS region (pixel-major, pitch 16 NJ + 8) so that each lane
+// stores whole 16-byte runs of 8 channels of one pixel. dst(p) is the first
+// output channel of the tile's pixel p, or null when that pixel is outside
+// the output.
 template <int MI, int NJ, class Dst>
 __device__ __forceinline__ void store_tile(uint16_t* __restrict__ lds, const floatx4 (&acc)[MI][NJ],
-                                           const float* __restrict__ bias, uint32_t co0, uint32_t Cout,
-                                           bool relu, Dst dst)
+                                           const float (&bv)[NJ], uint32_t co0, uint32_t Cout, bool relu, Dst dst)
 {
     constexpr int P = 16 * NJ + 8, CH = 2 * NJ;
     const int lane = __lane_id(), g = lane >> 4, l16 = lane & 15;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-        const uint32_t co = co0 + 16 * j + l16;
-        const float b = (bias && co < Cout) ? bias[co] : 0.0f;
+        const float b = bv[j];
 #pragma unroll
         for (int i = 0; i < MI; ++i)
 #pragma unroll
@@ -136,6 +158,72 @@ __device__ __forceinline__ void store_tile(uint16_t* __restrict__ lds, const flo
         uint16_t* d = dst(px);
         if (d && co0 + 8 * q < Cout) *(u32x4*)(d + 8 * q) = v;
     }
+}
+
+template <int MI, int NJ, class Dst>
+__device__ __forceinline__ void store_tile(uint16_t* __restrict__ lds, const floatx4 (&acc)[MI][NJ],
+                                           const float* __restrict__ bias, uint32_t co0, uint32_t Cout,
+                                           bool relu, Dst dst)
+{
+    float bv[NJ];
+    tile_bias<NJ>(bv, bias, co0, Cout);
+    store_tile<MI, NJ>(lds, acc, bv, co0, Cout, relu, dst);
+}
+
+// 2x2 max pool of four 8-channel bf16 vectors, the window's pixels in
+// (0,0), (0,1), (1,0), (1,1) order: per channel the first largest value.
+__device__ __forceinline__ u32x4 max4_bf16(const u32x4 (&v)[4])
+{
+    u32x4 o;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        uint32_t word = 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            float m = -INFINITY;
+            uint32_t best = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t bb = (v[k][c] >> (16 * h)) & 0xFFFFu;
+                if (bf2f((uint16_t)bb) > m) {
+                    m = bf2f((uint16_t)bb);
+                    best = bb;
+                }
+            }
+            word |= best << (16 * h);
+        }
+        o[c] = word;
+    }
+    return o;
+}
+
+// The 1x1 head on pixel p from its 32 bf16 channels hp (in LDS): residual
+// W h + b (hw: W [3][32], then b [3]), added to the splat colour sp,
+// clamped, rounded half up; alpha 255.
+__device__ __forceinline__ void head_pixel(const ConvArgs& a, const float* hw, const uint16_t* hp, size_t p,
+                                           uint32_t sp)
+{
+    float r[3] = {hw[96], hw[97], hw[98]};
+#pragma unroll 1
+    for (int c4 = 0; c4 < 4; ++c4) {
+        const u32x4 hv = *(const u32x4*)(hp + 8 * c4);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int c = 8 * c4 + e;
+            const float v = bf2f((uint16_t)(hv[e >> 1] >> (16 * (e & 1))));
+#pragma unroll
+            for (int k = 0; k < 3; ++k) r[k] += hw[k * 32 + c] * v;
+        }
+    }
+    uint32_t o = 0xFF000000u;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float v = (float)((sp >> (8 * k)) & 0xFFu) / 255.0f + r[k];
+        v = v < 0.0f ? 0.0f : (v > 1.0f ? 1.0f : v);
+        o |= (uint32_t)floorf(v * 255.0f + 0.5f) << (8 * k);
+        if (a.head_res) a.head_res[p * 3 + k] = r[k];
+    }
+    a.head_out[p] = o;
 }
 
 // Wave tile (16 MI) pixels of one row x (16 NJ) output channels, MI x NJ
@@ -305,7 +393,7 @@ __global__ void __launch_bounds__(kBlock) k_conv(ConvArgs a)
 // tile per wave; the halo of 6 rows for 4 output rows re-reads less of the
 // input than 4 rows for 2, which matters for the memory-bound full-size
 // layers.
-template <int NJ, int TX, bool kUp, int R = 2, bool kHead = false>
+template <int NJ, int TX, bool kUp, int R = 2>
 __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
 {
     constexpr int T = kUp ? 1 : 9, PAD = kUp ? 0 : 1;
@@ -446,46 +534,12 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
                               });
             return;
         }
-        constexpr bool fuse_head = kHead;   // wave = 64 pixels x all 32 channels
-        static_assert(!kHead || (NW == 2 && R == 4), "head fusion needs whole 32-channel pixel rows per wave");
         store_tile<4, NW>(lds + wv * 64 * EP, acc, a.bias, co0 + wco, a.Cout, a.relu != 0,
                           [&](int px) -> uint16_t* {
                               const uint32_t x = q.x0 + wx + px;
-                              if (fuse_head || y >= a.H || x >= a.W) return nullptr;
+                              if (y >= a.H || x >= a.W) return nullptr;
                               return a.out + (((size_t)q.n * a.H + y) * a.W + x) * a.out_cs + co0 + wco;
                           });
-        if (fuse_head) {
-            // one lane per pixel of the wave's row: residual = W h + b over
-            // the 32 bf16 channels, added to the splat colour, clamped,
-            // rounded half up; alpha 255
-            const uint32_t x = q.x0 + wx + (uint32_t)lane;
-            if (y < a.H && x < a.W) {
-                const uint16_t* hp = lds + wv * 64 * EP + lane * EP;
-                float r[3] = {a.head_b[0], a.head_b[1], a.head_b[2]};
-#pragma unroll 1
-                for (int c4 = 0; c4 < 4; ++c4) {
-                    const u32x4 hv = *(const u32x4*)(hp + 8 * c4);
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const int c = 8 * c4 + e;
-                        const float v = bf2f((uint16_t)(hv[e >> 1] >> (16 * (e & 1))));
-#pragma unroll
-                        for (int k = 0; k < 3; ++k) r[k] += a.head_w[k * 32 + c] * v;
-                    }
-                }
-                const size_t p = ((size_t)q.n * a.H + y) * a.W + x;
-                const uint32_t sp = a.head_rgba[p];
-                uint32_t o = 0xFF000000u;
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    float v = (float)((sp >> (8 * k)) & 0xFFu) / 255.0f + r[k];
-                    v = v < 0.0f ? 0.0f : (v > 1.0f ? 1.0f : v);
-                    o |= (uint32_t)floorf(v * 255.0f + 0.5f) << (8 * k);
-                    if (a.head_res) a.head_res[p * 3 + k] = r[k];
-                }
-                a.head_out[p] = o;
-            }
-        }
         if (!a.pool) return;
         // 2x2 max pool of the output rows (even H and W, y0 even), from the
         // waves' epilogue tiles; one thread per pooled pixel and 8 channels,
@@ -508,26 +562,7 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
                 const uint32_t col = (R == 2 && TX == 64) ? (8 * c8) % (16 * NW) : 8 * c8;
                 v[k] = *(const u32x4*)&lds[w * 64 * EP + (px % 64) * EP + col];
             }
-            u32x4 o;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                uint32_t word = 0;
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    float m = -INFINITY;
-                    uint32_t best = 0;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const uint32_t bb = (v[k][c] >> (16 * h)) & 0xFFFFu;
-                        if (bf2f((uint16_t)bb) > m) {
-                            m = bf2f((uint16_t)bb);
-                            best = bb;
-                        }
-                    }
-                    word |= best << (16 * h);
-                }
-                o[c] = word;
-            }
+            const u32x4 o = max4_bf16(v);
             *(u32x4*)(a.pool + (((size_t)q.n * (a.H / 2) + ys / 2) * (a.W / 2) + xs / 2) * a.pool_cs + co0 + 8 * c8) = o;
         }
     };
@@ -726,27 +761,227 @@ __global__ void __launch_bounds__(cva::WAVES * kWave) k_conv3a(ConvArgs a)
             const uint32_t r = 2 * pr + (k >> 1), px = 2 * p2 + (k & 1);
             v[k] = *(const u32x4*)&st0[r * 64 * EP + px * EP + 8 * c8];
         }
-        u32x4 o;
+        const u32x4 o = max4_bf16(v);
+        *(u32x4*)(a.pool + (((size_t)n * (a.H / 2) + ys / 2) * (a.W / 2) + xs / 2) * a.pool_cs + co0 + 8 * c8) = o;
+    }
+}
+
+// Full-size 3x3 layers with 32 output channels and 32 or 64 input channels
+// (the first and last levels of the network, where the input dominates the
+// traffic): persistent workgroups of 8 computing waves and 1 loading wave.
+// A tile is 8 rows x 62 pixels x 32 channels (one row per computing wave,
+// 4 x 2 MFMA tiles per tap), read as 10 halo rows of 64 pixels. The weights
+// of every chunk stay in LDS for the whole launch; the halo of each (tile,
+// 32-channel chunk) unit goes into one of three LDS stages by direct
+// buffer-to-LDS loads, issued two units ahead by the loading wave alone, so
+// that its load counter orders nothing but those loads. Rows are 64 bytes
+// with the swizzle of k_conv3a; sums run over chunks, then taps, as in
+// k_conv3, so results are the same. The epilogue of a tile (and its pool or
+// head) uses the tile's own stage once every wave has left it.
+namespace cvr {
+constexpr int R = 8, TX = 62, HP = TX + 2, RP = R + 2, TN = 32, NW = 2, S = 3, MAXC = 2;
+constexpr int HSLOTS = RP * HP * 4;   // 16-byte slots of one unit's halo
+constexpr int HINSTR = HSLOTS / 64;   // wave-loads per unit
+constexpr int WSLOTS = 9 * TN * 4;    // slots of one chunk's weights
+constexpr int WINSTR = WSLOTS / 64;
+constexpr int CWAVES = 8, WAVES = CWAVES + 1;
+constexpr int EP = 16 * NW + 8;
+constexpr int LDS_ELEMS = (S * HSLOTS + MAXC * WSLOTS) * 8;
+static_assert(HSLOTS % 64 == 0 && WSLOTS % 64 == 0, "whole wave-loads");
+static_assert(CWAVES * 64 * EP <= HSLOTS * 8, "epilogue fits one stage");
+static_assert(HINSTR == 40, "the loading wave's wait below allows one unit's loads in flight");
+}  // namespace cvr
+
+template <bool kHead>
+__global__ void __launch_bounds__(cvr::WAVES * kWave) k_conv3r(ConvArgs a)
+{
+    using namespace cvr;
+    __shared__ __attribute__((aligned(16))) uint16_t lds[LDS_ELEMS];
+    __shared__ float hws[kHead ? 99 : 1];   // the head's weights, then its bias
+    uint16_t* const wts = lds + S * HSLOTS * 8;
+    // the wave index as a scalar, so that the loading wave's branches and
+    // its buffer resources stay scalar
+    const int lane = __lane_id(), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int g = lane >> 4, l16 = lane & 15;
+    const bool loader = wv == CWAVES;
+    const uint32_t xtiles = (a.W + TX - 1) / TX, ytiles = (a.H + R - 1) / R;
+    const uint32_t n_tiles = a.N * ytiles * xtiles, G = gridDim.x, b = blockIdx.x;
+    if (b >= n_tiles) return;   // whole workgroup
+    const uint32_t Cin = a.Cin, K = 9 * Cin, nc = kHead ? 1 : Cin >> 5;   // the head follows 32 channels
+    const uint32_t U = ((n_tiles - 1 - b) / G + 1) * nc;   // units of this workgroup
+    const uint32_t row_b = a.W * a.in_cs * 2;
+    struct Geo {
+        uint32_t n, y0, x0;
+    };
+    auto geo = [&](uint32_t u) {
+        const uint32_t t = b + __builtin_amdgcn_readfirstlane(u / nc) * G;
+        Geo q;
+        // divisions run on the vector unit: bring the results back to
+        // scalars, or every buffer load would be wrapped in a uniformity loop
+        q.n = __builtin_amdgcn_readfirstlane(t / (xtiles * ytiles));
+        const uint32_t rem = t - q.n * (xtiles * ytiles);
+        const uint32_t ty = __builtin_amdgcn_readfirstlane(rem / xtiles);
+        q.y0 = ty * R;
+        q.x0 = (rem - ty * xtiles) * TX;
+        return q;
+    };
+    // loading wave: the halo of unit u into stage u % S; lane i of wave-load
+    // j fills slot 64 j + i, halo row j / 4, pixel 16 (j % 4) + i / 4
+    auto issue = [&](uint32_t u) {
+        const Geo q = geo(u);
+        const uint32_t c = __builtin_amdgcn_readfirstlane(u % nc);
+        const uint32_t r_first = q.y0 >= 1 ? q.y0 - 1 : 0;
+        const uint32_t r_last = q.y0 + R < a.H ? q.y0 + R : a.H - 1;
+        const __amdgpu_buffer_rsrc_t ir =
+            srsrc(a.in + ((size_t)q.n * a.H + r_first) * a.W * a.in_cs, (r_last - r_first + 1) * row_b);
+        uint32_t col[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            uint32_t word = 0;
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t px = 16 * k + (lane >> 2), qq = (uint32_t)(lane & 3) ^ ((px >> 1) & 3u);
+            const int xs = (int)(q.x0 + px) - 1;
+            col[k] = (xs >= 0 && xs < (int)a.W) ? (uint32_t)xs * a.in_cs * 2 + qq * 16 + c * 64 : kOob;
+        }
+        uint16_t* stg = lds + (u % S) * HSLOTS * 8;
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                float m = -INFINITY;
-                uint32_t best = 0;
+        for (int j = 0; j < HINSTR; ++j) {
+            const int ys = (int)q.y0 + (j >> 2) - 1;
+            const bool rok = ys >= 0 && ys < (int)a.H;
+            const uint32_t off = (rok && col[j & 3] != kOob) ? ((uint32_t)ys - r_first) * row_b + col[j & 3] : kOob;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(ir, (__attribute__((address_space(3))) void*)(stg + j * 512),
+                                                     16, off, 0, 0, 0);
+        }
+    };
+    // Barriers are plain s_barrier: __syncthreads would make the loading
+    // wave wait for all its loads (they write LDS) at every barrier. Each
+    // side waits for what the other needs: the loading wave for its loads,
+    // the computing waves for their LDS accesses. Both sides pass the same
+    // sequence of barriers: one per unit, plus one (two with the pool) at
+    // the end of each tile.
+    const bool pool = !kHead && a.pool != nullptr;
+    if (loader) {
+        // the weights of every chunk, [chunk][tap][channel] rows, then the
+        // first two units
+        const __amdgpu_buffer_rsrc_t wrs = rsrc(a.wt, a.Cout * K * 2);
+        for (uint32_t jj = 0; jj < nc * WINSTR; ++jj) {
+            const uint32_t c = jj / WINSTR, j = jj % WINSTR, s3 = j * 64 + (uint32_t)lane;
+            const uint32_t wrow = s3 >> 2, qq = (s3 & 3u) ^ ((wrow >> 1) & 3u);
+            const uint32_t tap = wrow / TN, co = wrow % TN;
+            const uint32_t off = co < a.Cout ? (co * K + tap * Cin + c * 32) * 2 + qq * 16 : kOob;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                wrs, (__attribute__((address_space(3))) void*)(wts + (c * WSLOTS + j * 64) * 8), 16, off, 0, 0, 0);
+        }
+        issue(0);
+        if (U > 1) issue(1);
+        for (uint32_t u = 0; u < U; ++u) {
+            // unit u has landed once at most the next unit's loads are in flight
+            if (u + 1 < U)
+                asm volatile("s_waitcnt vmcnt(40)\n\ts_barrier" ::: "memory");
+            else
+                asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+            if (u + 2 < U) issue(u + 2);   // into the stage that unit u - 1 left
+            if ((u + 1) % nc != 0) continue;
+            asm volatile("s_barrier" ::: "memory");
+            if (pool) asm volatile("s_barrier" ::: "memory");
+        }
+        return;
+    }
+    floatx4 acc[4][NW];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < NW; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    auto compute = [&](const uint16_t* stg, const uint16_t* wc) {
+        u32x4 av[2][4], bv[2][NW];
+        auto rd = [&](int tap, u32x4 (&A)[4], u32x4 (&B)[NW]) {
+            const int dy = tap / 3, dx = tap % 3;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                A[i] = *(const u32x4*)&stg[swz_slot((uint32_t)((wv + dy) * HP + 16 * i + l16 + dx), (uint32_t)g) * 8];
+#pragma unroll
+            for (int j = 0; j < NW; ++j)
+                B[j] = *(const u32x4*)&wc[swz_slot((uint32_t)(tap * TN + 16 * j + l16), (uint32_t)g) * 8];
+        };
+        rd(0, av[0], bv[0]);
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int cur = tap & 1;
+            if (tap + 1 < 9) rd(tap + 1, av[cur ^ 1], bv[cur ^ 1]);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < NW; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(bf16x8, av[cur][i]), __builtin_bit_cast(bf16x8, bv[cur][j]), acc[i][j], 0, 0,
+                        0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    if (kHead && wv == 0) {   // visible to all after the first barrier
+        hws[lane] = a.head_w[lane];
+        if (lane < 32) hws[64 + lane] = a.head_w[64 + lane];
+        if (lane < 3) hws[96 + lane] = a.head_b[lane];
+    }
+    const uint32_t y_w = (uint32_t)wv;
+    float bv[NW];
+    tile_bias<NW>(bv, a.bias, 0, a.Cout);
+    for (uint32_t u = 0; u < U; ++u) {
+        // unit u staged (the loading wave waited); this wave's reads of the
+        // stage the next loads go to are done
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        uint16_t* stg = lds + (u % S) * HSLOTS * 8;
+        const uint32_t c = __builtin_amdgcn_readfirstlane(u % nc);
+        // the head's splat colour of this lane's pixel, loaded before the
+        // tile's last products so that they hide its latency
+        // (every lane loads: pixels outside the image read pixel 0)
+        uint32_t sp;
+        if (kHead && c + 1 == nc) {
+            const Geo q = geo(u);
+            const uint32_t y = q.y0 + y_w, x = q.x0 + (uint32_t)lane;
+            const bool in = lane < TX && y < a.H && x < a.W;
+            sp = a.head_rgba[in ? ((size_t)q.n * a.H + y) * a.W + x : 0];
+        }
+        compute(stg, wts + c * WSLOTS * 8);
+        if (c + 1 < nc) continue;
+        if (kHead) asm volatile("" : "+v"(sp));   // the load has landed on every path here
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");   // every wave done with the halo
+        const Geo q = geo(u);
+        const uint32_t y = q.y0 + y_w;
+        uint16_t* ep = stg + wv * 64 * EP;
+        store_tile<4, NW>(ep, acc, bv, 0, a.Cout, a.relu != 0, [&](int px) -> uint16_t* {
+            const uint32_t x = q.x0 + (uint32_t)px;
+            if (kHead || px >= TX || y >= a.H || x >= a.W) return nullptr;
+            return a.out + (((size_t)q.n * a.H + y) * a.W + x) * a.out_cs;
+        });
+        if (kHead) {
+            const uint32_t x = q.x0 + (uint32_t)lane;
+            if (lane < TX && y < a.H && x < a.W)
+                head_pixel(a, hws, ep + lane * EP, ((size_t)q.n * a.H + y) * a.W + x, sp);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < NW; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        if (!pool) continue;
+        // 2x2 max pool (even H and W) from the waves' epilogue rows
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        constexpr int PCH = TN / 8, RUNS = (TX / 2) * (R / 2) * PCH;
+        static_assert(RUNS <= CWAVES * kWave, "one pass over the pooled runs");
+        const uint32_t run = threadIdx.x;
+        if (run < (uint32_t)RUNS) {
+            const uint32_t c8 = run % PCH, p2 = (run / PCH) % (TX / 2), pr = run / (PCH * (TX / 2));
+            const uint32_t xs = q.x0 + 2 * p2, ys = q.y0 + 2 * pr;
+            if (xs < a.W && ys < a.H) {
+                u32x4 v[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    const uint32_t bb = (v[k][c] >> (16 * h)) & 0xFFFFu;
-                    if (bf2f((uint16_t)bb) > m) {
-                        m = bf2f((uint16_t)bb);
-                        best = bb;
-                    }
+                    const uint32_t r = 2 * pr + (k >> 1), px = 2 * p2 + (k & 1);
+                    v[k] = *(const u32x4*)&stg[r * 64 * EP + px * EP + 8 * c8];
                 }
-                word |= best << (16 * h);
+                *(u32x4*)(a.pool + (((size_t)q.n * (a.H / 2) + ys / 2) * (a.W / 2) + xs / 2) * a.pool_cs + 8 * c8) =
+                    max4_bf16(v);
             }
-            o[c] = word;
         }
-        *(u32x4*)(a.pool + (((size_t)n * (a.H / 2) + ys / 2) * (a.W / 2) + xs / 2) * a.pool_cs + co0 + 8 * c8) = o;
     }
 }
 
@@ -1252,9 +1487,14 @@ hipError_t conv(const uint16_t* in, uint32_t in_cs, const uint16_t* wt, const fl
     const uint32_t rows2 = N * ((H + 1) / 2);
     switch (mode) {
     case MODE_SAME3:
-        if (narrow && hf)
-            k_conv3<2, 64, false, 4, true><<<pgrid(N * ((H + 3) / 4) * ((W + 63) / 64), (Cout + 31) / 32), blk, 0, s>>>(a);
-        else if (narrow)
+        if (Cout == 32 && (Cin == 32 || Cin == 64)) {
+            const dim3 gr(std::min<uint32_t>(N * ((H + cvr::R - 1) / cvr::R) * ((W + cvr::TX - 1) / cvr::TX),
+                                             (uint32_t)cur_dev().cus));
+            if (hf)
+                k_conv3r<true><<<gr, dim3(cvr::WAVES * kWave), 0, s>>>(a);
+            else
+                k_conv3r<false><<<gr, dim3(cvr::WAVES * kWave), 0, s>>>(a);
+        } else if (narrow)
             k_conv3<2, 64, false, 4><<<pgrid(N * ((H + 3) / 4) * ((W + 63) / 64), (Cout + 31) / 32), blk, 0, s>>>(a);
         else if (Cin % 64 == 0 && Cout % 64 == 0)
             k_conv3a<<<dim3(N * ((H + cva::R - 1) / cva::R) * ((W + cva::TX - 1) / cva::TX), Cout / 64),
