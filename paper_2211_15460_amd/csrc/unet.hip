@@ -640,51 +640,70 @@ __device__ __forceinline__ uint32_t swz_slot(uint32_t row, uint32_t q)
 __global__ void __launch_bounds__(cva::WAVES * kWave) k_conv3a(ConvArgs a)
 {
     using namespace cva;
-    __shared__ __attribute__((aligned(16))) uint16_t st0[SLOTS * 8];
-    __shared__ __attribute__((aligned(16))) uint16_t st1[SLOTS * 8];
-    const int lane = __lane_id(), wv = threadIdx.x / kWave;
+    __shared__ __attribute__((aligned(16))) uint16_t st[2][SLOTS * 8];
+    const int lane = __lane_id(), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int g = lane >> 4, l16 = lane & 15;
     const uint32_t xtiles = (a.W + TX - 1) / TX, ytiles = (a.H + R - 1) / R;
-    const uint32_t t = blockIdx.x;
+    const uint32_t n_tiles = a.N * ytiles * xtiles, G = gridDim.x, b = blockIdx.x;
+    if (b >= n_tiles) return;   // whole workgroup
     const uint32_t co0 = blockIdx.y * TN;
-    const uint32_t n = t / (xtiles * ytiles), rem = t % (xtiles * ytiles);
-    const uint32_t y0 = (rem / xtiles) * R, x0 = (rem % xtiles) * TX;
     const uint32_t Cin = a.Cin, K = 9 * Cin, nc = Cin >> 5;
-    const uint32_t r_first = y0 >= 1 ? y0 - 1 : 0;
-    const uint32_t r_last = y0 + R < a.H ? y0 + R : a.H - 1;
+    const uint32_t U = ((n_tiles - 1 - b) / G + 1) * nc;   // (tile, chunk) units of this workgroup
     const uint32_t row_b = a.W * a.in_cs * 2;
-    const __amdgpu_buffer_rsrc_t ir = rsrc(a.in + ((size_t)n * a.H + r_first) * a.W * a.in_cs,
-                                           (r_last - r_first + 1) * row_b);
     const __amdgpu_buffer_rsrc_t wrs = rsrc(a.wt, a.Cout * K * 2);
-    // this lane's source byte offset for each of its wave's loads (chunk 0;
-    // chunk cc adds 64 cc): wave wv issues loads j = wv, wv + 8, ...; load j
-    // fills slots 64 j .. 64 j + 63, lane i slot 64 j + i
-    uint32_t src[JPW];
+    struct Geo {
+        uint32_t n, y0, x0;
+    };
+    auto geo = [&](uint32_t u) {
+        // divisions run on the vector unit: the results go back to scalars
+        const uint32_t t = b + __builtin_amdgcn_readfirstlane(u / nc) * G;
+        Geo q;
+        q.n = __builtin_amdgcn_readfirstlane(t / (xtiles * ytiles));
+        const uint32_t rem = t - q.n * (xtiles * ytiles);
+        const uint32_t ty = __builtin_amdgcn_readfirstlane(rem / xtiles);
+        q.y0 = ty * R;
+        q.x0 = (rem - ty * xtiles) * TX;
+        return q;
+    };
+    // this lane's weight byte offsets (chunk 0; chunk c adds 64 c): wave wv
+    // issues loads j = wv, wv + 8, ...; load j fills slots 64 j .. 64 j + 63,
+    // lane i slot 64 j + i; the first HINSTR loads are halo rows
+    uint32_t wsrc[JPW];
 #pragma unroll
     for (int k = 0; k < JPW; ++k) {
         const uint32_t j = (uint32_t)(wv + WAVES * k), s = j * 64 + (uint32_t)lane;
         uint32_t off = kOob;
-        if (j < (uint32_t)HINSTR) {
-            const uint32_t rl = s >> 2;
-            if (rl < (uint32_t)(RP * HP)) {
-                const uint32_t q = (s & 3u) ^ ((rl >> 1) & 3u);
-                const int ys = (int)y0 + (int)(rl / HP) - 1, xs = (int)x0 + (int)(rl % HP) - 1;
-                if (ys >= 0 && ys < (int)a.H && xs >= 0 && xs < (int)a.W)
-                    off = ((uint32_t)ys - r_first) * row_b + (uint32_t)xs * a.in_cs * 2 + q * 16;
-            }
-        } else if (j < (uint32_t)INSTR) {
+        if (j >= (uint32_t)HINSTR && j < (uint32_t)INSTR) {
             const uint32_t s2 = s - HSLOTS, wrow = s2 >> 2, q = (s2 & 3u) ^ ((wrow >> 1) & 3u);
             const uint32_t tap = wrow / TN, co = wrow % TN;
             if (co0 + co < a.Cout) off = ((co0 + co) * K + tap * Cin) * 2 + q * 16;
         }
-        src[k] = off;
+        wsrc[k] = off;
     }
-    auto issue = [&](uint16_t* stg, uint32_t cc) {
+    // unit u (tile u / nc, chunk u % nc) into stage u % 2
+    auto issue = [&](uint32_t u) {
+        const Geo q = geo(u);
+        const uint32_t c = __builtin_amdgcn_readfirstlane(u % nc);
+        const uint32_t r_first = q.y0 >= 1 ? q.y0 - 1 : 0;
+        const uint32_t r_last = q.y0 + R < a.H ? q.y0 + R : a.H - 1;
+        const __amdgpu_buffer_rsrc_t ir =
+            srsrc(a.in + ((size_t)q.n * a.H + r_first) * a.W * a.in_cs, (r_last - r_first + 1) * row_b);
+        uint16_t* stg = st[u & 1];
 #pragma unroll
         for (int k = 0; k < JPW; ++k) {
             const uint32_t j = (uint32_t)(wv + WAVES * k);
             if (j >= (uint32_t)INSTR) break;   // wave-uniform
-            const uint32_t off = src[k] == kOob ? kOob : src[k] + cc * 64;
+            uint32_t off;
+            if (j < (uint32_t)HINSTR) {
+                const uint32_t s = j * 64 + (uint32_t)lane, rl = s >> 2;
+                const uint32_t qq = (s & 3u) ^ ((rl >> 1) & 3u);
+                const int ys = (int)q.y0 + (int)(rl / HP) - 1, xs = (int)q.x0 + (int)(rl % HP) - 1;
+                off = (rl < (uint32_t)(RP * HP) && ys >= 0 && ys < (int)a.H && xs >= 0 && xs < (int)a.W)
+                          ? ((uint32_t)ys - r_first) * row_b + (uint32_t)xs * a.in_cs * 2 + qq * 16 + c * 64
+                          : kOob;
+            } else {
+                off = wsrc[k] == kOob ? kOob : wsrc[k] + c * 64;
+            }
             __builtin_amdgcn_raw_ptr_buffer_load_lds(j < (uint32_t)HINSTR ? ir : wrs,
                                                      (__attribute__((address_space(3))) void*)(stg + j * 512), 16,
                                                      off, 0, 0, 0);
@@ -723,46 +742,48 @@ __global__ void __launch_bounds__(cva::WAVES * kWave) k_conv3a(ConvArgs a)
             __builtin_amdgcn_sched_barrier(0);
         }
     };
-    // chunk cc is in st0 when even, st1 when odd; a stage is refilled only
-    // after the barrier that follows every wave's reads of it
-    issue(st0, 0);
-    for (uint32_t cc = 0; cc < nc; cc += 2) {
+    // The next unit loads while the current one is computed, across tiles
+    // too; a stage is refilled only after the barrier that follows every
+    // wave's reads of it (products and epilogue).
+    issue(0);
+    for (uint32_t u = 0; u < U; ++u) {
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
-        if (cc + 1 < nc) issue(st1, cc + 1);
-        compute(st0);
-        if (cc + 1 >= nc) break;
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
-        if (cc + 2 < nc) issue(st0, cc + 2);
-        compute(st1);
-    }
-    __syncthreads();   // the epilogue reuses st0
-    const uint32_t y = y0 + (uint32_t)wv;
-    uint16_t* ep = st0 + wv * 64 * EP;
-    store_tile<4, NW>(ep, acc, a.bias, co0, a.Cout, a.relu != 0, [&](int px) -> uint16_t* {
-        const uint32_t x = x0 + (uint32_t)px;
-        if (px >= TX || y >= a.H || x >= a.W) return nullptr;
-        return a.out + (((size_t)n * a.H + y) * a.W + x) * a.out_cs + co0;
-    });
-    if (!a.pool) return;
-    // 2x2 max pool (even H and W) from the waves' epilogue tiles: one thread
-    // per pooled pixel and 8 channels; the first largest of the window in
-    // (0,0), (0,1), (1,0), (1,1) order
-    __syncthreads();
-    constexpr int PCH = TN / 8, RUNS = (TX / 2) * (R / 2) * PCH;
-    for (uint32_t run = threadIdx.x; run < (uint32_t)RUNS; run += WAVES * kWave) {
-        const uint32_t c8 = run % PCH, p2 = (run / PCH) % (TX / 2), pr = run / (PCH * (TX / 2));
-        const uint32_t xs = x0 + 2 * p2, ys = y0 + 2 * pr;
-        if (xs >= a.W || ys >= a.H || co0 + 8 * c8 >= a.Cout) continue;
-        u32x4 v[4];
+        if (u + 1 < U) issue(u + 1);
+        uint16_t* stg = st[u & 1];
+        compute(stg);
+        if ((u + 1) % nc != 0) continue;
+        __syncthreads();   // the epilogue reuses this unit's stage
+        const Geo q = geo(u);
+        const uint32_t y = q.y0 + (uint32_t)wv;
+        uint16_t* ep = stg + wv * 64 * EP;
+        store_tile<4, NW>(ep, acc, a.bias, co0, a.Cout, a.relu != 0, [&](int px) -> uint16_t* {
+            const uint32_t x = q.x0 + (uint32_t)px;
+            if (px >= TX || y >= a.H || x >= a.W) return nullptr;
+            return a.out + (((size_t)q.n * a.H + y) * a.W + x) * a.out_cs + co0;
+        });
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t r = 2 * pr + (k >> 1), px = 2 * p2 + (k & 1);
-            v[k] = *(const u32x4*)&st0[r * 64 * EP + px * EP + 8 * c8];
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < NW; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        if (!a.pool) continue;
+        // 2x2 max pool (even H and W) from the waves' epilogue tiles: one
+        // thread per pooled pixel and 8 channels
+        __syncthreads();
+        constexpr int PCH = TN / 8, RUNS = (TX / 2) * (R / 2) * PCH;
+        for (uint32_t run = threadIdx.x; run < (uint32_t)RUNS; run += WAVES * kWave) {
+            const uint32_t c8 = run % PCH, p2 = (run / PCH) % (TX / 2), pr = run / (PCH * (TX / 2));
+            const uint32_t xs = q.x0 + 2 * p2, ys = q.y0 + 2 * pr;
+            if (xs >= a.W || ys >= a.H || co0 + 8 * c8 >= a.Cout) continue;
+            u32x4 v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t r = 2 * pr + (k >> 1), px = 2 * p2 + (k & 1);
+                v[k] = *(const u32x4*)&stg[r * 64 * EP + px * EP + 8 * c8];
+            }
+            *(u32x4*)(a.pool + (((size_t)q.n * (a.H / 2) + ys / 2) * (a.W / 2) + xs / 2) * a.pool_cs + co0 +
+                      8 * c8) = max4_bf16(v);
         }
-        const u32x4 o = max4_bf16(v);
-        *(u32x4*)(a.pool + (((size_t)n * (a.H / 2) + ys / 2) * (a.W / 2) + xs / 2) * a.pool_cs + co0 + 8 * c8) = o;
     }
 }
 
@@ -1497,8 +1518,12 @@ hipError_t conv(const uint16_t* in, uint32_t in_cs, const uint16_t* wt, const fl
         } else if (narrow)
             k_conv3<2, 64, false, 4><<<pgrid(N * ((H + 3) / 4) * ((W + 63) / 64), (Cout + 31) / 32), blk, 0, s>>>(a);
         else if (Cin % 64 == 0 && Cout % 64 == 0)
-            k_conv3a<<<dim3(N * ((H + cva::R - 1) / cva::R) * ((W + cva::TX - 1) / cva::TX), Cout / 64),
-                       dim3(cva::WAVES * kWave), 0, s>>>(a);
+        {
+            // persistent: one workgroup per compute unit over all channel blocks
+            const uint32_t tiles = N * ((H + cva::R - 1) / cva::R) * ((W + cva::TX - 1) / cva::TX);
+            const uint32_t per = std::max(1u, (uint32_t)cur_dev().cus / (Cout / 64));
+            k_conv3a<<<dim3(std::min(tiles, per), Cout / 64), dim3(cva::WAVES * kWave), 0, s>>>(a);
+        }
         else
             k_conv3<4, 64, false><<<pgrid(rows2 * ((W + 63) / 64), (Cout + 63) / 64), blk, 0, s>>>(a);
         break;
