@@ -485,9 +485,19 @@ def ceilings(torch, fhv, reps: int = 5) -> dict:
         else:
             res.setdefault("atomics_g_per_s", {})[name] = buf.numel() // line * passes / (ms * 1e-3) / 1e9
     del big, small
+    # the matrix cores' practical rate: the vendor library's bf16 GEMM
+    # (torch.matmul, fp32 accumulation) on 8192^3, the best case for it
+    n = 8192
+    ga = torch.randn(n, n, dtype=torch.bfloat16, device="cuda")
+    gb = torch.randn(n, n, dtype=torch.bfloat16, device="cuda")
+    for _ in range(3):
+        torch.matmul(ga, gb)
+    ms = timed(torch, lambda: torch.matmul(ga, gb), 10)
+    res["gemm_bf16_tflops"] = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
+    del ga, gb
     res["note"] = ("copy: GB/s read+written over 2 GiB; atomics: G ops/s; hbm = 2 GiB buffer, one pass; "
                    "llc = 64 MiB buffer, 32 passes; one atomic per 128-B line, or per 8-B word (dense); "
-                   "exch returns its value")
+                   "exch returns its value; gemm: the vendor library's bf16 matmul, 8192^3, TFLOP/s")
     return res
 
 
@@ -505,6 +515,8 @@ def add_ceilings(args, out: dict, torch, fhv, kernels: dict, n_exch: int | None,
     out["copy_frac"] = {k: kernels[k]["gbs"] / ceil["copy_gbs"] for k in kernels
                         if k in ("compact.scatter", "splat.zclear", "splat.resolve", "capture.reset")
                         and kernels[k].get("gbs")}
+    if kernels.get("fill.conv", {}).get("tflops"):
+        out["gemm_frac"] = {"fill.conv": kernels["fill.conv"]["tflops"] / ceil["gemm_bf16_tflops"]}
     r_ms = kernels.get("capture.raster", {}).get("avg_ms")
     if n_exch and r_ms:
         # one exchange per fragment; samples next to each other in a tile

@@ -73,7 +73,12 @@ def params_for(seed, levels):
                                           (4, 1, 8, 8),
                                           # ragged tiles: rows not a multiple of 4, several
                                           # 64-pixel column tiles with a partial last one
-                                          (1, 1, 13, 70), (2, 1, 18, 130), (3, 2, 20, 132)])
+                                          (1, 1, 13, 70), (2, 1, 18, 130), (3, 2, 20, 132),
+                                          # more 8-row x 62-pixel tiles than the persistent
+                                          # kernels have workgroups (256), so that workgroups
+                                          # go on to further tiles: full-size layers, then
+                                          # also the 64-channel layers of the second level
+                                          (1, 4, 64, 600), (2, 4, 144, 1000)])
 def test_forward_parity(F, levels, N, H, W):
     th = params_for(levels, levels)
     rgba, depth, cov, _ = splat_batch(levels, N, H, W)
