@@ -523,15 +523,25 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
     auto epilogue = [&](const Geo& q) {
         const uint32_t y = q.y0 + wr;
         if (kUp) {
-            // a wave's 32 columns are one sub-position (Cout is a multiple of 32)
-            const uint32_t cw = co0 + wco, tz = cw / a.Cout, cb = cw % a.Cout;
-            store_tile<4, NW>(lds + wv * 64 * EP, acc, a.bias, cb, cw < Cg ? a.Cout : 0u, a.relu != 0,
-                              [&](int px) -> uint16_t* {
-                                  const uint32_t x = q.x0 + wx + px;
-                                  if (y >= a.H || x >= a.W) return nullptr;
-                                  return a.out + (((size_t)q.n * 2 * a.H + 2 * y + (tz >> 1)) * (2 * (size_t)a.W) +
-                                                  2 * x + (tz & 1)) * a.out_cs + cb;
-                              });
+            // 32 columns at a time, each within one sub-position (Cout is a
+            // multiple of 32); the wave's LDS region is reused in order
+#pragma unroll
+            for (int h = 0; h < NW / 2; ++h) {
+                const uint32_t cw = co0 + wco + 32 * h, tz = cw / a.Cout, cb = cw % a.Cout;
+                floatx4 part[4][2];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    part[i][0] = acc[i][2 * h];
+                    part[i][1] = acc[i][2 * h + 1];
+                }
+                store_tile<4, 2>(lds + wv * 64 * EP, part, a.bias, cb, cw < Cg ? a.Cout : 0u, a.relu != 0,
+                                 [&](int px) -> uint16_t* {
+                                     const uint32_t x = q.x0 + wx + px;
+                                     if (y >= a.H || x >= a.W) return nullptr;
+                                     return a.out + (((size_t)q.n * 2 * a.H + 2 * y + (tz >> 1)) * (2 * (size_t)a.W) +
+                                                     2 * x + (tz & 1)) * a.out_cs + cb;
+                                 });
+            }
             return;
         }
         store_tile<4, NW>(lds + wv * 64 * EP, acc, a.bias, co0 + wco, a.Cout, a.relu != 0,
@@ -1529,7 +1539,9 @@ hipError_t conv(const uint16_t* in, uint32_t in_cs, const uint16_t* wt, const fl
         break;
     case MODE_UP2:
         if (Cout % 32 == 0) {
-            k_conv3<4, 64, true><<<pgrid(rows2 * ((W + 63) / 64), (4 * Cout + 63) / 64), blk, 0, s>>>(a);
+            // 128 columns per workgroup: the input tile is read once for
+            // every 128 of the 4 Cout columns
+            k_conv3<8, 64, true><<<pgrid(rows2 * ((W + 63) / 64), (4 * Cout + 127) / 128), blk, 0, s>>>(a);
             break;
         }
         if (narrow) k_conv<MODE_UP2, 4, 2, false><<<g32, blk, 0, s>>>(a);
