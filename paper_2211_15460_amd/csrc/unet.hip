@@ -1026,119 +1026,167 @@ struct WgradArgs {
     uint32_t chunks, per_split;   // 32-pixel chunks in total / per split
 };
 
-// One wave per (32 output channels, 32 input channels, tap, split).
+// One wave per (32 output channels, 32 input channels, split), all kT taps
+// (9: 3x3, 4: transposed 2x2). Per 32-pixel chunk the operand that does not
+// move with the tap (the output gradient for 3x3, the input for the
+// transposed convolution) is staged and read once; the other one is staged
+// per tap. Staging goes through LDS transposed (pixels contiguous): lane
+// (pixel, channel half) loads 2 x 8 channels of its pixel.
+template <int kT>
 __global__ void __launch_bounds__(kWave) k_wgrad(WgradArgs a)
 {
+    constexpr bool kUpm = kT == 4;   // the transposed convolution
     __shared__ __attribute__((aligned(16))) uint16_t sg[32][40];   // [co][px]
     __shared__ __attribute__((aligned(16))) uint16_t sx[32][40];   // [ci][px]
     const int lane = __lane_id();
     const int g = lane >> 4, l16 = lane & 15;
     const uint32_t ntc = (a.Cin + 31) / 32;
     const uint32_t co0 = (blockIdx.x / ntc) * 32, ci0 = (blockIdx.x % ntc) * 32;
-    const uint32_t tap = blockIdx.y, split = blockIdx.z;
+    const uint32_t split = blockIdx.y;
     const uint32_t P = a.N * a.H * a.W;
     const uint32_t c_begin = split * a.per_split;
     const uint32_t c_end = c_begin + a.per_split < a.chunks ? c_begin + a.per_split : a.chunks;
-    floatx4 acc[2][2];
+    floatx4 acc[kT][2][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int t = 0; t < kT; ++t)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[t][i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
     const int pl = lane & 31, hh = lane >> 5;   // staging: pixel, channel half
-    for (uint32_t c = c_begin; c < c_end; ++c) {
-        const uint32_t p = c * 32 + pl;
-        const bool pok = p < P;
-        const uint32_t n = p / (a.H * a.W), rem = p % (a.H * a.W), y = rem / a.W, xq = rem % a.W;
-        size_t gp, xp;
-        bool xok = pok;
-        if (a.mode == MODE_SAME3) {
-            gp = p;
-            const int ys = (int)y + (int)(tap / 3) - 1, xs = (int)xq + (int)(tap % 3) - 1;
-            xok = xok && ys >= 0 && ys < (int)a.H && xs >= 0 && xs < (int)a.W;
-            xp = ((size_t)n * a.H + (uint32_t)ys) * a.W + (uint32_t)xs;
-        } else {   // UP2: gradient lives on the doubled grid
-            gp = ((size_t)n * 2 * a.H + 2 * y + (tap >> 1)) * (2 * (size_t)a.W) + 2 * xq + (tap & 1);
-            xp = p;
-        }
-        u32x4 gv[2], xv[2];
+    auto stage = [&](const uint16_t* base, uint32_t cs, uint32_t c0, uint32_t climit, size_t pix, bool ok,
+                     uint16_t (*dst)[40]) {
+        u32x4 v[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            const uint32_t co = co0 + 16 * hh + 8 * q;
-            gv[q] = (pok && co < a.Cout) ? *(const u32x4*)(a.gr + gp * a.g_cs + co) : u32x4{0u, 0u, 0u, 0u};
-            const uint32_t ci = ci0 + 16 * hh + 8 * q;
-            xv[q] = (xok && ci < a.Cin) ? *(const u32x4*)(a.x + xp * a.x_cs + ci) : u32x4{0u, 0u, 0u, 0u};
+            const uint32_t ch = c0 + 16 * hh + 8 * q;
+            v[q] = (ok && ch < climit) ? *(const u32x4*)(base + pix * cs + ch) : u32x4{0u, 0u, 0u, 0u};
         }
 #pragma unroll
         for (int q = 0; q < 2; ++q)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int ch = 16 * hh + 8 * q + 2 * e;
-                sg[ch][pl] = (uint16_t)(gv[q][e] & 0xFFFFu);
-                sg[ch + 1][pl] = (uint16_t)(gv[q][e] >> 16);
-                sx[ch][pl] = (uint16_t)(xv[q][e] & 0xFFFFu);
-                sx[ch + 1][pl] = (uint16_t)(xv[q][e] >> 16);
+                dst[ch][pl] = (uint16_t)(v[q][e] & 0xFFFFu);
+                dst[ch + 1][pl] = (uint16_t)(v[q][e] >> 16);
             }
+    };
+    auto sync = [] {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         __builtin_amdgcn_wave_barrier();
-        u32x4 av[2], bv[2];
+    };
+    for (uint32_t c = c_begin; c < c_end; ++c) {
+        const uint32_t p = c * 32 + pl;
+        const bool pok = p < P;
+        const uint32_t n = p / (a.H * a.W), rem = p % (a.H * a.W), y = rem / a.W, xq = rem % a.W;
+        sync();   // the previous chunk's reads are done
+        if (kUpm)
+            stage(a.x, a.x_cs, ci0, a.Cin, p, pok, sx);
+        else
+            stage(a.gr, a.g_cs, co0, a.Cout, p, pok, sg);
+        sync();
+        u32x4 fix[2];   // fragments of the staged operand, the same for every tap
 #pragma unroll
-        for (int i = 0; i < 2; ++i) av[i] = *(const u32x4*)&sg[16 * i + l16][8 * g];
+        for (int i = 0; i < 2; ++i)
+            fix[i] = kUpm ? *(const u32x4*)&sx[16 * i + l16][8 * g] : *(const u32x4*)&sg[16 * i + l16][8 * g];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) bv[j] = *(const u32x4*)&sx[16 * j + l16][8 * g];
+        for (int tap = 0; tap < kT; ++tap) {
+            sync();   // the previous tap's reads are done
+            if (kUpm) {
+                // the gradient lives on the doubled grid
+                const size_t gp =
+                    ((size_t)n * 2 * a.H + 2 * y + (tap >> 1)) * (2 * (size_t)a.W) + 2 * xq + (tap & 1);
+                stage(a.gr, a.g_cs, co0, a.Cout, gp, pok, sg);
+            } else {
+                const int ys = (int)y + tap / 3 - 1, xs = (int)xq + tap % 3 - 1;
+                const bool ok = pok && ys >= 0 && ys < (int)a.H && xs >= 0 && xs < (int)a.W;
+                const size_t xp = ok ? ((size_t)n * a.H + (uint32_t)ys) * a.W + (uint32_t)xs : 0;
+                stage(a.x, a.x_cs, ci0, a.Cin, xp, ok, sx);
+            }
+            sync();
+            u32x4 av[2], bv[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                av[i] = kUpm ? *(const u32x4*)&sg[16 * i + l16][8 * g] : fix[i];
+                bv[i] = kUpm ? fix[i] : *(const u32x4*)&sx[16 * i + l16][8 * g];
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[tap][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(bf16x8, av[i]), __builtin_bit_cast(bf16x8, bv[j]), acc[tap][i][j], 0, 0,
+                        0);
+        }
+    }
+#pragma unroll
+    for (int tap = 0; tap < kT; ++tap)
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    __builtin_bit_cast(bf16x8, av[i]), __builtin_bit_cast(bf16x8, bv[j]), acc[i][j], 0, 0, 0);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-    }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const uint32_t co = co0 + 16 * i + 4 * g + r, ci = ci0 + 16 * j + l16;
-                if (co < a.Cout && ci < a.Cin)
-                    a.part[(((size_t)split * a.Cout + co) * a.T + tap) * a.Cin + ci] = acc[i][j][r];
-            }
+                for (int r = 0; r < 4; ++r) {
+                    const uint32_t co = co0 + 16 * i + 4 * g + r, ci = ci0 + 16 * j + l16;
+                    if (co < a.Cout && ci < a.Cin)
+                        a.part[(((size_t)split * a.Cout + co) * kT + tap) * a.Cin + ci] = acc[tap][i][j][r];
+                }
 }
 
-// dst[layout(co, tap, ci)] = sum over splits (in order) of part; ci < Creal.
+// dst[layout(co, tap, ci)] = sum over splits of part; ci < Creal. The splits
+// fall into 16 contiguous groups, each summed in order by one thread, and
+// the group sums are added in group order (a fixed order, so results do not
+// depend on timing): a workgroup takes 16 elements x 16 groups.
 // kind 0: 3x3 conv layout [co][tap][ci]; kind 1: transposed [tap][co][ci].
 __global__ void __launch_bounds__(kBlock)
 k_wgrad_reduce(const float* __restrict__ part, uint32_t splits, uint32_t Cout, uint32_t T,
                uint32_t Cin, uint32_t Creal, uint32_t kind, float* __restrict__ dst)
 {
-    const size_t n = (size_t)Cout * T * Cin, i = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
+    constexpr uint32_t E = 16, GR = kBlock / E;
+    __shared__ float red[GR][E];
+    const size_t n = (size_t)Cout * T * Cin;
+    const uint32_t e = threadIdx.x % E, grp = threadIdx.x / E;
+    const size_t i = (size_t)blockIdx.x * E + e;
+    const uint32_t per = (splits + GR - 1) / GR;
+    const uint32_t k0 = grp * per, k1 = k0 + per < splits ? k0 + per : splits;
+    float s = 0.0f;
+    if (i < n)
+        for (uint32_t k = k0; k < k1; ++k) s += part[(size_t)k * n + i];
+    red[grp][e] = s;
+    __syncthreads();
+    if (grp != 0 || i >= n) return;
+    float tot = 0.0f;
+    for (uint32_t g2 = 0; g2 < GR; ++g2) tot += red[g2][e];
     const uint32_t ci = (uint32_t)(i % Cin), tap = (uint32_t)((i / Cin) % T), co = (uint32_t)(i / ((size_t)Cin * T));
     if (ci >= Creal) return;
-    float s = 0.0f;
-    for (uint32_t k = 0; k < splits; ++k) s += part[(size_t)k * n + i];
     const size_t o = kind == 0 ? ((size_t)co * T + tap) * Creal + ci : ((size_t)tap * Cout + co) * Creal + ci;
-    dst[o] = s;
+    dst[o] = tot;
 }
 
-// Column sums of a [P][C] bf16 matrix (row stride cs) into fp32 partials
-// [splits][C]: thread t adds channel t % C of rows t / C, t / C + 256 / C...
+// Column sums of a [P][C] bf16 matrix (row stride cs, both multiples of 8)
+// into fp32 partials [splits][C]: thread t adds the 8 channels of group
+// t % (C / 8) of rows t / (C / 8), t / (C / 8) + 256 / (C / 8), ... with
+// 16-byte loads; the row phases are then added in order.
 __global__ void __launch_bounds__(kBlock)
 k_colsum(const uint16_t* __restrict__ m, uint32_t cs, uint32_t P, uint32_t C, uint32_t per_split,
          float* __restrict__ part)
 {
-    __shared__ float red[kBlock];
+    __shared__ float red[kBlock * 8];
     const uint32_t t = threadIdx.x;
-    const uint32_t lanes = kBlock / C;   // C divides 256 (C <= 256, power of two)
-    const uint32_t c = t % C, ph = t / C;
+    const uint32_t G = C / 8, lanes = kBlock / G;   // C / 8 divides 256 (C <= 2048, power of two)
+    const uint32_t cg = t % G, ph = t / G;
     const uint32_t r0 = blockIdx.x * per_split, r1 = r0 + per_split < P ? r0 + per_split : P;
-    float s = 0.0f;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (ph < lanes)
-        for (uint32_t r = r0 + ph; r < r1; r += lanes) s += bf2f(m[(size_t)r * cs + c]);
-    red[t] = s;
+        for (uint32_t r = r0 + ph; r < r1; r += lanes) {
+            const u32x4 v = *(const u32x4*)(m + (size_t)r * cs + 8 * cg);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) s[e] += bf2f((uint16_t)(v[e >> 1] >> (16 * (e & 1))));
+        }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) red[ph * C + 8 * cg + e] = s[e];
     __syncthreads();
-    if (ph == 0) {
+    for (uint32_t c = t; c < C; c += kBlock) {
         float tot = 0.0f;
         for (uint32_t k = 0; k < lanes; ++k) tot += red[k * C + c];
         part[(size_t)blockIdx.x * C + c] = tot;
@@ -1394,11 +1442,12 @@ struct Bufs {
     size_t part_elems, hpart_elems;
 };
 
-constexpr uint32_t kWgradTarget = 1024;   // wave tiles per weight-gradient launch
+constexpr uint32_t kWgradTarget = 1024;   // waves per weight-gradient launch
 
 void wgrad_dims(uint32_t P, uint32_t Cin, uint32_t Cout, uint32_t T, uint32_t* splits, uint32_t* per)
 {
-    const uint32_t tiles = (Cout / 32) * ((Cin + 31) / 32) * T;
+    (void)T;   // a wave takes every tap
+    const uint32_t tiles = (Cout / 32) * ((Cin + 31) / 32);
     const uint32_t chunks = (P + 31) / 32;
     uint32_t s = (kWgradTarget + tiles - 1) / tiles;
     s = s < 1 ? 1 : (s > chunks ? chunks : s);
@@ -1578,10 +1627,14 @@ hipError_t wgrad(const uint16_t* gr, uint32_t g_cs, const uint16_t* x, uint32_t 
     a.chunks = (P + 31) / 32;
     if ((size_t)splits * Cout * a.T * Cin > part_elems) return hipErrorInvalidValue;
     ProfScope ps(cur_dev(), "fill.wgrad", s);
-    k_wgrad<<<dim3((Cout / 32) * ((Cin + 31) / 32), a.T, splits), dim3(kWave), 0, s>>>(a);
+    const dim3 gr_((Cout / 32) * ((Cin + 31) / 32), splits);
+    if (a.T == 9)
+        k_wgrad<9><<<gr_, dim3(kWave), 0, s>>>(a);
+    else
+        k_wgrad<4><<<gr_, dim3(kWave), 0, s>>>(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_wgrad_reduce<<<blocks((size_t)Cout * a.T * Cin), dim3(kBlock), 0, s>>>(
+    k_wgrad_reduce<<<dim3((unsigned)(((size_t)Cout * a.T * Cin + 15) / 16)), dim3(kBlock), 0, s>>>(
         part, splits, Cout, a.T, Cin, Creal, mode == MODE_SAME3 ? 0u : 1u, dst);
     return hipGetLastError();
 }
