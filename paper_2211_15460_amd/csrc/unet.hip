@@ -1054,36 +1054,67 @@ __global__ void __launch_bounds__(kWave) k_wgrad(WgradArgs a)
 #pragma unroll
             for (int j = 0; j < 2; ++j) acc[t][i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
     const int pl = lane & 31, hh = lane >> 5;   // staging: pixel, channel half
-    auto stage = [&](const uint16_t* base, uint32_t cs, uint32_t c0, uint32_t climit, size_t pix, bool ok,
-                     uint16_t (*dst)[40]) {
+    // 16-byte loads of this lane's pixel (2 x 8 channels), then their
+    // transposed LDS writes: split so that the loads of the next tap are in
+    // flight while the current one is written and multiplied
+    // (every lane loads, outside the image from element 0, and the zero
+    // padding is applied when the values are written: no branch waits for
+    // a load)
+    struct Ld {
         u32x4 v[2];
+        bool ok[2];
+    };
+    auto load = [&](const uint16_t* base, uint32_t cs, uint32_t c0, uint32_t climit, size_t pix, bool ok, Ld& l) {
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const uint32_t ch = c0 + 16 * hh + 8 * q;
-            v[q] = (ok && ch < climit) ? *(const u32x4*)(base + pix * cs + ch) : u32x4{0u, 0u, 0u, 0u};
+            l.ok[q] = ok && ch < climit;
+            l.v[q] = *(const u32x4*)(base + (l.ok[q] ? pix * cs + ch : 0));
         }
+    };
+    auto put = [&](const Ld& l, uint16_t (*dst)[40]) {
 #pragma unroll
         for (int q = 0; q < 2; ++q)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int ch = 16 * hh + 8 * q + 2 * e;
-                dst[ch][pl] = (uint16_t)(v[q][e] & 0xFFFFu);
-                dst[ch + 1][pl] = (uint16_t)(v[q][e] >> 16);
+                const uint32_t w = l.ok[q] ? l.v[q][e] : 0u;
+                dst[ch][pl] = (uint16_t)(w & 0xFFFFu);
+                dst[ch + 1][pl] = (uint16_t)(w >> 16);
             }
     };
+    // the workgroup is one wave: ordering its own LDS accesses is enough,
+    // and a wider fence would also wait for the loads in flight
     auto sync = [] {
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
     };
     for (uint32_t c = c_begin; c < c_end; ++c) {
         const uint32_t p = c * 32 + pl;
         const bool pok = p < P;
         const uint32_t n = p / (a.H * a.W), rem = p % (a.H * a.W), y = rem / a.W, xq = rem % a.W;
-        sync();   // the previous chunk's reads are done
+        // the tap-moving operand of tap t: its loads
+        auto load_tap = [&](int tap, Ld& v) {
+            if (kUpm) {
+                // the gradient lives on the doubled grid
+                const size_t gp =
+                    ((size_t)n * 2 * a.H + 2 * y + (tap >> 1)) * (2 * (size_t)a.W) + 2 * xq + (tap & 1);
+                load(a.gr, a.g_cs, co0, a.Cout, gp, pok, v);
+            } else {
+                const int ys = (int)y + tap / 3 - 1, xs = (int)xq + tap % 3 - 1;
+                const bool ok = pok && ys >= 0 && ys < (int)a.H && xs >= 0 && xs < (int)a.W;
+                const size_t xp = ok ? ((size_t)n * a.H + (uint32_t)ys) * a.W + (uint32_t)xs : 0;
+                load(a.x, a.x_cs, ci0, a.Cin, xp, ok, v);
+            }
+        };
+        Ld fv, tv[2];
         if (kUpm)
-            stage(a.x, a.x_cs, ci0, a.Cin, p, pok, sx);
+            load(a.x, a.x_cs, ci0, a.Cin, p, pok, fv);
         else
-            stage(a.gr, a.g_cs, co0, a.Cout, p, pok, sg);
+            load(a.gr, a.g_cs, co0, a.Cout, p, pok, fv);
+        load_tap(0, tv[0]);
+        sync();   // the previous chunk's reads are done
+        put(fv, kUpm ? sx : sg);
         sync();
         u32x4 fix[2];   // fragments of the staged operand, the same for every tap
 #pragma unroll
@@ -1091,18 +1122,9 @@ __global__ void __launch_bounds__(kWave) k_wgrad(WgradArgs a)
             fix[i] = kUpm ? *(const u32x4*)&sx[16 * i + l16][8 * g] : *(const u32x4*)&sg[16 * i + l16][8 * g];
 #pragma unroll
         for (int tap = 0; tap < kT; ++tap) {
+            if (tap + 1 < kT) load_tap(tap + 1, tv[(tap + 1) & 1]);
             sync();   // the previous tap's reads are done
-            if (kUpm) {
-                // the gradient lives on the doubled grid
-                const size_t gp =
-                    ((size_t)n * 2 * a.H + 2 * y + (tap >> 1)) * (2 * (size_t)a.W) + 2 * xq + (tap & 1);
-                stage(a.gr, a.g_cs, co0, a.Cout, gp, pok, sg);
-            } else {
-                const int ys = (int)y + tap / 3 - 1, xs = (int)xq + tap % 3 - 1;
-                const bool ok = pok && ys >= 0 && ys < (int)a.H && xs >= 0 && xs < (int)a.W;
-                const size_t xp = ok ? ((size_t)n * a.H + (uint32_t)ys) * a.W + (uint32_t)xs : 0;
-                stage(a.x, a.x_cs, ci0, a.Cin, xp, ok, sx);
-            }
+            put(tv[tap & 1], kUpm ? sg : sx);
             sync();
             u32x4 av[2], bv[2];
 #pragma unroll
