@@ -282,12 +282,15 @@ __global__ void __launch_bounds__(kBlock) k_conv(ConvArgs a)
             const uint32_t dy = (tap * 11) >> 5, dx = tap - 3 * dy;   // tap / 3, tap % 3 for tap < 9
             const int ys = (int)y + (int)dy - 1;
             const bool rok = kok && ys >= 0 && ys < (int)a.H;
-            const uint16_t* rp = a.in + ((size_t)n * a.H + (uint32_t)(rok ? ys : 0)) * a.W * a.in_cs;
+            // image n as one buffer resource (the lane groups read different
+            // rows): taps outside the image read zeros through the range
+            // check, with no branch that would wait for the load
+            const __amdgpu_buffer_rsrc_t ir = rsrc(a.in + (size_t)n * a.H * a.W * a.in_cs, a.H * a.W * pix_b);
 #pragma unroll
             for (int i = 0; i < MI; ++i) {
                 const int xs = (int)(x0 + 16 * i + l16) + (int)dx - 1;
                 const bool ok = rok && xs >= 0 && xs < (int)a.W;
-                av[i] = ok ? *(const u32x4*)(rp + (uint32_t)xs * a.in_cs) : u32x4{0u, 0u, 0u, 0u};
+                av[i] = bload(ir, ok ? ((uint32_t)ys * a.W + (uint32_t)xs) * pix_b : kOob, 0);
             }
 #pragma unroll
             for (int j = 0; j < NJ; ++j) bv[j] = bload(wr, kok ? wo[j] - g * 16 + k * 2 : kOob, 0);
