@@ -1263,26 +1263,47 @@ k_maxpool_bwd(const uint16_t* __restrict__ src, uint32_t src_cs, const uint16_t*
               const uint16_t* __restrict__ dskip, uint32_t dskip_cs, uint32_t N, uint32_t H,
               uint32_t W, uint32_t C, uint16_t* __restrict__ out)
 {
-    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x, tot = (size_t)N * 4 * H * W * C;
-    if (i >= tot) return;
-    const uint32_t c = (uint32_t)(i % C);
-    const size_t p = i / C;
+    // one thread per source pixel and 8 channels (16-byte accesses; C, the
+    // strides and the channel offsets of the pointers are multiples of 8)
+    const uint32_t G = C / 8;
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x, tot = (size_t)N * 4 * H * W * G;
+    if (t >= tot) return;
+    const size_t p = t / G;
+    const uint32_t c = (uint32_t)(t - p * G) * 8;
     const uint32_t X = (uint32_t)(p % (2 * W)), Y = (uint32_t)((p / (2 * W)) % (2 * H)),
                    n = (uint32_t)(p / (4 * (size_t)W * H));
     const uint32_t y = Y >> 1, x = X >> 1, me = ((Y & 1) << 1) | (X & 1);
-    float m = -INFINITY;
-    uint32_t arg = 0;
+    u32x4 win[4];
+#pragma unroll
     for (uint32_t k = 0; k < 4; ++k) {
         const size_t s = ((size_t)n * 2 * H + 2 * y + (k >> 1)) * (2 * (size_t)W) + 2 * x + (k & 1);
-        const float v = bf2f(src[s * src_cs + c]);
-        if (v > m) {
-            m = v;
-            arg = k;
-        }
+        win[k] = *(const u32x4*)(src + s * src_cs + c);
     }
-    float g = bf2f(dskip[p * dskip_cs + c]);
-    if (arg == me) g += bf2f(dpool[(((size_t)n * H + y) * W + x) * C + c]);
-    out[p * C + c] = f2bf(g);
+    const u32x4 sk = *(const u32x4*)(dskip + p * dskip_cs + c);
+    const u32x4 dp = *(const u32x4*)(dpool + (((size_t)n * H + y) * W + x) * C + c);
+    u32x4 o;
+#pragma unroll
+    for (int e2 = 0; e2 < 4; ++e2) {
+        uint32_t word = 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            float m = -INFINITY;
+            uint32_t arg = 0;
+#pragma unroll
+            for (uint32_t k = 0; k < 4; ++k) {
+                const float v = bf2f((uint16_t)(win[k][e2] >> (16 * h)));
+                if (v > m) {
+                    m = v;
+                    arg = k;
+                }
+            }
+            float g = bf2f((uint16_t)(sk[e2] >> (16 * h)));
+            if (arg == me) g += bf2f((uint16_t)(dp[e2] >> (16 * h)));
+            word |= (uint32_t)f2bf(g) << (16 * h);
+        }
+        o[e2] = word;
+    }
+    *(u32x4*)(out + p * C + c) = o;
 }
 
 // dz = dy where y > 0, else 0 (both bf16 [P][C], y with row stride y_cs,
@@ -1291,11 +1312,22 @@ __global__ void __launch_bounds__(kBlock)
 k_relu_bwd(const uint16_t* __restrict__ dy, uint32_t dy_cs, const uint16_t* __restrict__ y,
            uint32_t y_cs, size_t P, uint32_t C, uint16_t* __restrict__ dz)
 {
-    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= P * C) return;
-    const size_t p = i / C;
-    const uint32_t c = (uint32_t)(i % C);
-    dz[i] = bf2f(y[p * y_cs + c]) > 0.0f ? dy[p * dy_cs + c] : (uint16_t)0;
+    // one thread per pixel and 8 channels (16-byte accesses; C, the strides
+    // and the channel offsets of the pointers are multiples of 8)
+    const uint32_t G = C / 8;
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= P * G) return;
+    const size_t p = t / G;
+    const uint32_t c = (uint32_t)(t - p * G) * 8;
+    const u32x4 yv = *(const u32x4*)(y + p * y_cs + c), gv = *(const u32x4*)(dy + p * dy_cs + c);
+    u32x4 o;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t lo = bf2f((uint16_t)(yv[k] & 0xFFFFu)) > 0.0f ? gv[k] & 0xFFFFu : 0u;
+        const uint32_t hi = bf2f((uint16_t)(yv[k] >> 16)) > 0.0f ? gv[k] & 0xFFFF0000u : 0u;
+        o[k] = lo | hi;
+    }
+    *(u32x4*)(dz + p * C + c) = o;
 }
 
 // Head in training: loss = mean over 3P of (rgb / 255 + residual - t / 255)^2.
@@ -1750,7 +1782,7 @@ hipError_t conv_bwd(const Net& net, size_t i, const Bufs& b, const uint16_t* x, 
 {
     const Layer& ly = net.layers[i];
     const size_t P = (size_t)N * Hl * Wl;
-    k_relu_bwd<<<blocks(P * ly.cout), dim3(kBlock), 0, s>>>(g, g_cs, y, y_cs, P, ly.cout, b.dz);
+    k_relu_bwd<<<blocks(P * (ly.cout / 8)), dim3(kBlock), 0, s>>>(g, g_cs, y, y_cs, P, ly.cout, b.dz);
     FHV_TRY(hipGetLastError());
     FHV_TRY(wgrad(b.dz, ly.cout, x, x_cs, N, Hl, Wl, ly.cpad, ly.cin, ly.cout, MODE_SAME3, b.part,
                   b.part_elems, b.grad + ly.off_w, s));
@@ -1796,7 +1828,7 @@ hipError_t backward(const Net& net, const float* th, const Bufs& b, uint32_t N, 
         if (l + 1 < (int)L) {
             uint16_t* nxt = cur == b.ga ? b.gb : b.ga;
             // pooled gradient (cur, on level l + 1) plus the skip gradient
-            k_maxpool_bwd<<<blocks((size_t)N * Hl * Wl * Cl), dim3(kBlock), 0, s>>>(
+            k_maxpool_bwd<<<blocks((size_t)N * Hl * Wl * (Cl / 8)), dim3(kBlock), 0, s>>>(
                 y1, y1_cs, cur, b.dcat[l] + Cl, 2 * Cl, N, Hl / 2, Wl / 2, Cl, nxt);
             FHV_TRY(hipGetLastError());
             cur = nxt;
