@@ -1339,16 +1339,21 @@ k_head_train(const uint16_t* __restrict__ x, const float* __restrict__ w, const 
              const uint32_t* __restrict__ rgba, const uint32_t* __restrict__ tgt, uint32_t P,
              uint16_t* __restrict__ dx, float* __restrict__ part)
 {
-    __shared__ float red[kBlock];
+    __shared__ float red[kBlock / kWave][kHeadPart];
     const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
+    const int lane = __lane_id(), wv = threadIdx.x / kWave;
     const float inv_n = 1.0f / (3.0f * (float)P);
     float xv[kBase], d[3] = {0.f, 0.f, 0.f}, l = 0.0f;
     if (p < P) {
         float r[3] = {b[0], b[1], b[2]};
-        for (int c = 0; c < kBase; ++c) {
-            xv[c] = bf2f(x[(size_t)p * kBase + c]);
-            for (int k = 0; k < 3; ++k) r[k] += w[k * kBase + c] * xv[c];
+#pragma unroll
+        for (int c4 = 0; c4 < kBase / 8; ++c4) {
+            const u32x4 v = *(const u32x4*)(x + (size_t)p * kBase + 8 * c4);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) xv[8 * c4 + e] = bf2f((uint16_t)(v[e >> 1] >> (16 * (e & 1))));
         }
+        for (int c = 0; c < kBase; ++c)
+            for (int k = 0; k < 3; ++k) r[k] += w[k * kBase + c] * xv[c];
         const uint32_t s = rgba[p], t = tgt[p];
         for (int k = 0; k < 3; ++k) {
             const float diff = ((float)((s >> (8 * k)) & 0xFFu) / 255.0f + r[k]) -
@@ -1356,25 +1361,38 @@ k_head_train(const uint16_t* __restrict__ x, const float* __restrict__ w, const 
             l += diff * diff;
             d[k] = 2.0f * diff * inv_n;
         }
-        for (int c = 0; c < kBase; ++c)
-            dx[(size_t)p * kBase + c] = f2bf(w[c] * d[0] + w[kBase + c] * d[1] + w[2 * kBase + c] * d[2]);
+#pragma unroll
+        for (int c4 = 0; c4 < kBase / 8; ++c4) {
+            u32x4 o;
+#pragma unroll
+            for (int e2 = 0; e2 < 4; ++e2) {
+                const int c = 8 * c4 + 2 * e2;
+                const uint32_t lo = f2bf(w[c] * d[0] + w[kBase + c] * d[1] + w[2 * kBase + c] * d[2]);
+                const uint32_t hi =
+                    f2bf(w[c + 1] * d[0] + w[kBase + c + 1] * d[1] + w[2 * kBase + c + 1] * d[2]);
+                o[e2] = lo | (hi << 16);
+            }
+            *(u32x4*)(dx + (size_t)p * kBase + 8 * c4) = o;
+        }
     } else {
         for (int c = 0; c < kBase; ++c) xv[c] = 0.0f;
     }
-    // block sums of dW[k][c] = d[k] x[c], db[k] = d[k], loss
+    // block sums of dW[k][c] = d[k] x[c], db[k] = d[k], loss: a butterfly
+    // within each wave, then the waves' sums in wave order
     for (int q = 0; q < kHeadPart; ++q) {
         float v;
         if (q < 3 * kBase) v = d[q / kBase] * xv[q % kBase];
         else if (q < 3 * kBase + 3) v = d[q - 3 * kBase];
         else v = l * inv_n;
-        red[threadIdx.x] = v;
-        __syncthreads();
-        for (int s = kBlock / 2; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) part[(size_t)blockIdx.x * kHeadPart + q] = red[0];
-        __syncthreads();
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) red[wv][q] = v;
+    }
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < (uint32_t)kHeadPart; q += kBlock) {
+        float tot = 0.0f;
+        for (int k = 0; k < kBlock / kWave; ++k) tot += red[k][q];
+        part[(size_t)blockIdx.x * kHeadPart + q] = tot;
     }
 }
 
