@@ -1410,32 +1410,43 @@ k_adam(float* __restrict__ th, float* __restrict__ m, float* __restrict__ v, con
     th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
 }
 
-// 3x3 conv weights: forward [co][tap][ci_pad] and input-gradient
-// [ci][tap'][co] with tap' = 8 - tap (spatial flip).
-__global__ void __launch_bounds__(kBlock)
-k_prep_c3(const float* __restrict__ w, uint32_t Cout, uint32_t Cin, uint32_t Cpad,
-          uint16_t* __restrict__ wf, uint16_t* __restrict__ wb)
-{
-    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= Cout * 9 * Cpad) return;
-    const uint32_t ci = i % Cpad, tap = (i / Cpad) % 9, co = i / (Cpad * 9);
-    const uint16_t v = ci < Cin ? f2bf(w[((size_t)co * 9 + tap) * Cin + ci]) : (uint16_t)0;
-    wf[i] = v;
-    if (wb && ci < Cin) wb[((size_t)ci * 9 + (8 - tap)) * Cout + co] = v;
-}
+// Weight conversion to bf16 layouts, all layers in one launch (per-layer
+// launches took a few microseconds each for little work): a table of
+// layers, each a range of the concatenated element space.
+//   3x3 conv: forward [co][tap][ci_pad] and input-gradient [ci][tap'][co]
+//             with tap' = 8 - tap (spatial flip; only when wb is given)
+//   transposed 2x2: forward [tap][co][ci] (= parameter layout) and
+//             input-gradient [ci][tap][co]
+constexpr int kMaxPrep = 32;
+struct PrepTable {
+    uint32_t n;
+    struct Entry {
+        uint32_t kind, cout, cin, cpad, start;   // kind 0: 3x3, 1: transposed 2x2
+        const float* w;
+        uint16_t* wf;
+        uint16_t* wb;   // or null
+    } e[kMaxPrep];
+};
 
-// Transposed conv weights: forward [tap][co][ci] (= parameter layout, bf16)
-// and input-gradient [ci][tap][co].
-__global__ void __launch_bounds__(kBlock)
-k_prep_t2(const float* __restrict__ w, uint32_t Cout, uint32_t Cin, uint16_t* __restrict__ wf,
-          uint16_t* __restrict__ wb)
+__global__ void __launch_bounds__(kBlock) k_prep_all(PrepTable t, uint32_t total)
 {
-    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= 4 * Cout * Cin) return;
-    const uint32_t ci = i % Cin, co = (i / Cin) % Cout, tap = i / (Cin * Cout);
-    const uint16_t v = f2bf(w[i]);
-    wf[i] = v;
-    wb[((size_t)ci * 4 + tap) * Cout + co] = v;
+    const uint32_t g = blockIdx.x * kBlock + threadIdx.x;
+    if (g >= total) return;
+    uint32_t l = 0;
+    while (l + 1 < t.n && g >= t.e[l + 1].start) ++l;
+    const PrepTable::Entry& y = t.e[l];
+    const uint32_t i = g - y.start;
+    if (y.kind == 0) {
+        const uint32_t ci = i % y.cpad, tap = (i / y.cpad) % 9, co = i / (y.cpad * 9);
+        const uint16_t v = ci < y.cin ? f2bf(y.w[((size_t)co * 9 + tap) * y.cin + ci]) : (uint16_t)0;
+        y.wf[i] = v;
+        if (y.wb && ci < y.cin) y.wb[((size_t)ci * 9 + (8 - tap)) * y.cout + co] = v;
+    } else {
+        const uint32_t ci = i % y.cin, co = (i / y.cin) % y.cout, tap = i / (y.cin * y.cout);
+        const uint16_t v = f2bf(y.w[i]);
+        y.wf[i] = v;
+        y.wb[((size_t)ci * 4 + tap) * y.cout + co] = v;
+    }
 }
 
 }  // namespace nn
@@ -1734,16 +1745,24 @@ hipError_t bgrad(const uint16_t* m, uint32_t cs, uint32_t P, uint32_t C, float* 
 
 hipError_t prep_weights(const Net& net, const float* th, bool training, const Bufs& b, hipStream_t s)
 {
+    PrepTable t{};
+    uint32_t total = 0;
     for (size_t i = 0; i < net.layers.size(); ++i) {
         const Layer& y = net.layers[i];
-        if (y.kind == 0)
-            k_prep_c3<<<blocks((size_t)y.cout * 9 * y.cpad), dim3(kBlock), 0, s>>>(
-                th + y.off_w, y.cout, y.cin, y.cpad, b.wt + y.wf_off,
-                (training && i > 0) ? b.wt + y.wb_off : nullptr);
-        else if (y.kind == 1)
-            k_prep_t2<<<blocks((size_t)4 * y.cout * y.cin), dim3(kBlock), 0, s>>>(
-                th + y.off_w, y.cout, y.cin, b.wt + y.wf_off, b.wt + y.wb_off);
+        if (y.kind != 0 && y.kind != 1) continue;
+        if (t.n == (uint32_t)kMaxPrep) return hipErrorInvalidValue;
+        PrepTable::Entry& e = t.e[t.n++];
+        e.kind = (uint32_t)y.kind;
+        e.cout = y.cout;
+        e.cin = y.cin;
+        e.cpad = y.cpad;
+        e.start = total;
+        e.w = th + y.off_w;
+        e.wf = b.wt + y.wf_off;
+        e.wb = y.kind == 1 || (training && i > 0) ? b.wt + y.wb_off : nullptr;
+        total += y.kind == 0 ? y.cout * 9 * y.cpad : 4 * y.cout * y.cin;
     }
+    if (total) k_prep_all<<<blocks(total), dim3(kBlock), 0, s>>>(t, total);
     return hipGetLastError();
 }
 
