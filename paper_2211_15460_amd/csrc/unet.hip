@@ -1029,6 +1029,8 @@ struct WgradArgs {
     uint32_t chunks, per_split;   // 32-pixel chunks in total / per split
 };
 
+constexpr int kWgradWaves = 4;   // waves (pixel splits) per workgroup, summed in the workgroup
+
 // One wave per (32 output channels, 32 input channels, split), all kT taps
 // (9: 3x3, 4: transposed 2x2). Per 32-pixel chunk the operand that does not
 // move with the tap (the output gradient for 3x3, the input for the
@@ -1036,16 +1038,19 @@ struct WgradArgs {
 // per tap. Staging goes through LDS transposed (pixels contiguous): lane
 // (pixel, channel half) loads 2 x 8 channels of its pixel.
 template <int kT>
-__global__ void __launch_bounds__(kWave) k_wgrad(WgradArgs a)
+__global__ void __launch_bounds__(kWgradWaves * kWave) k_wgrad(WgradArgs a)
 {
     constexpr bool kUpm = kT == 4;   // the transposed convolution
-    __shared__ __attribute__((aligned(16))) uint16_t sg[32][40];   // [co][px]
-    __shared__ __attribute__((aligned(16))) uint16_t sx[32][40];   // [ci][px]
-    const int lane = __lane_id();
+    __shared__ __attribute__((aligned(16))) uint16_t sgw[kWgradWaves][32][40];   // [co][px] per wave
+    __shared__ __attribute__((aligned(16))) uint16_t sxw[kWgradWaves][32][40];   // [ci][px] per wave
+    __shared__ float red[kT][2][2][4][kWave];   // one wave's accumulators
+    const int lane = __lane_id(), wv = threadIdx.x / kWave;
+    uint16_t (*sg)[40] = sgw[wv];
+    uint16_t (*sx)[40] = sxw[wv];
     const int g = lane >> 4, l16 = lane & 15;
     const uint32_t ntc = (a.Cin + 31) / 32;
     const uint32_t co0 = (blockIdx.x / ntc) * 32, ci0 = (blockIdx.x % ntc) * 32;
-    const uint32_t split = blockIdx.y;
+    const uint32_t split = blockIdx.y * kWgradWaves + (uint32_t)wv;   // this wave's pixel range
     const uint32_t P = a.N * a.H * a.W;
     const uint32_t c_begin = split * a.per_split;
     const uint32_t c_end = c_begin + a.per_split < a.chunks ? c_begin + a.per_split : a.chunks;
@@ -1144,6 +1149,31 @@ __global__ void __launch_bounds__(kWave) k_wgrad(WgradArgs a)
                         0);
         }
     }
+    // the waves' sums added in wave order through LDS, then one partial row
+    // per workgroup
+    for (int w2 = 1; w2 < kWgradWaves; ++w2) {
+        if (wv == w2)
+#pragma unroll
+            for (int tap = 0; tap < kT; ++tap)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) red[tap][i][j][r][lane] = acc[tap][i][j][r];
+        __syncthreads();
+        if (wv == 0)
+#pragma unroll
+            for (int tap = 0; tap < kT; ++tap)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[tap][i][j][r] += red[tap][i][j][r][lane];
+        __syncthreads();
+    }
+    if (wv != 0) return;
 #pragma unroll
     for (int tap = 0; tap < kT; ++tap)
 #pragma unroll
@@ -1154,7 +1184,7 @@ __global__ void __launch_bounds__(kWave) k_wgrad(WgradArgs a)
                 for (int r = 0; r < 4; ++r) {
                     const uint32_t co = co0 + 16 * i + 4 * g + r, ci = ci0 + 16 * j + l16;
                     if (co < a.Cout && ci < a.Cin)
-                        a.part[(((size_t)split * a.Cout + co) * kT + tap) * a.Cin + ci] = acc[tap][i][j][r];
+                        a.part[(((size_t)blockIdx.y * a.Cout + co) * kT + tap) * a.Cin + ci] = acc[tap][i][j][r];
                 }
 }
 
@@ -1713,15 +1743,16 @@ hipError_t wgrad(const uint16_t* gr, uint32_t g_cs, const uint16_t* x, uint32_t 
     a.chunks = (P + 31) / 32;
     if ((size_t)splits * Cout * a.T * Cin > part_elems) return hipErrorInvalidValue;
     ProfScope ps(cur_dev(), "fill.wgrad", s);
-    const dim3 gr_((Cout / 32) * ((Cin + 31) / 32), splits);
+    const uint32_t groups = (splits + kWgradWaves - 1) / kWgradWaves;   // partial rows
+    const dim3 gr_((Cout / 32) * ((Cin + 31) / 32), groups);
     if (a.T == 9)
-        k_wgrad<9><<<gr_, dim3(kWave), 0, s>>>(a);
+        k_wgrad<9><<<gr_, dim3(kWgradWaves * kWave), 0, s>>>(a);
     else
-        k_wgrad<4><<<gr_, dim3(kWave), 0, s>>>(a);
+        k_wgrad<4><<<gr_, dim3(kWgradWaves * kWave), 0, s>>>(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_wgrad_reduce<<<dim3((unsigned)(((size_t)Cout * a.T * Cin + 15) / 16)), dim3(kBlock), 0, s>>>(
-        part, splits, Cout, a.T, Cin, Creal, mode == MODE_SAME3 ? 0u : 1u, dst);
+        part, groups, Cout, a.T, Cin, Creal, mode == MODE_SAME3 ? 0u : 1u, dst);
     return hipGetLastError();
 }
 
