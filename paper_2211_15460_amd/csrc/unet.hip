@@ -1681,9 +1681,13 @@ hipError_t conv(const uint16_t* in, uint32_t in_cs, const uint16_t* wt, const fl
         return dim3(std::max(1u, std::min(tiles, want)), cols);
     };
     const uint32_t rows2 = N * ((H + 1) / 2);
+    const bool fits62 = (size_t)((W + 61) / 62) * 62 * 10 <= (size_t)W * 11;
     switch (mode) {
     case MODE_SAME3:
-        if (Cout == 32 && (Cin == 32 || Cin == 64)) {
+        // the 62-pixel tiles of k_conv3r and k_conv3a suit rows whose width
+        // they cover with little waste (at most a tenth); narrow rows such
+        // as 32, 64 or 128 pixels take the 64-pixel tiles of k_conv3
+        if (Cout == 32 && (Cin == 32 || Cin == 64) && (hf || fits62)) {
             const dim3 gr(std::min<uint32_t>(N * ((H + cvr::R - 1) / cvr::R) * ((W + cvr::TX - 1) / cvr::TX),
                                              (uint32_t)cur_dev().cus));
             if (hf)
@@ -1692,7 +1696,7 @@ hipError_t conv(const uint16_t* in, uint32_t in_cs, const uint16_t* wt, const fl
                 k_conv3r<false><<<gr, dim3(cvr::WAVES * kWave), 0, s>>>(a);
         } else if (narrow)
             k_conv3<2, 64, false, 4><<<pgrid(N * ((H + 3) / 4) * ((W + 63) / 64), (Cout + 31) / 32), blk, 0, s>>>(a);
-        else if (Cin % 64 == 0 && Cout % 64 == 0)
+        else if (Cin % 64 == 0 && Cout % 64 == 0 && fits62)
         {
             // persistent: one workgroup per compute unit over all channel blocks
             const uint32_t tiles = N * ((H + cva::R - 1) / cva::R) * ((W + cva::TX - 1) / cva::TX);

@@ -78,7 +78,10 @@ def params_for(seed, levels):
                                           # kernels have workgroups (256), so that workgroups
                                           # go on to further tiles: full-size layers, then
                                           # also the 64-channel layers of the second level
-                                          (1, 4, 64, 600), (2, 4, 144, 1000)])
+                                          # (widths that 62-pixel tiles cover with little
+                                          # waste, as those kernels are used only there;
+                                          # the last tile of a row partial)
+                                          (1, 4, 64, 600), (2, 4, 144, 960)])
 def test_forward_parity(F, levels, N, H, W):
     th = params_for(levels, levels)
     rgba, depth, cov, _ = splat_batch(levels, N, H, W)
