@@ -18,22 +18,28 @@
 // buffer, the decoder's transposed convolution into the other half, so the
 // concatenation costs nothing.
 //
-// Kernels
-//   k_conv3       implicit GEMM on MFMA 16x16x32 bf16 with the input halo and
-//                 the weights staged in LDS per 32-channel chunk: 3x3 same-size
-//                 convolutions (forward, and input gradients with flipped
+// Kernels (implicit GEMM on MFMA 16x16x32 bf16, fused bias, ReLU and bf16
+// rounding; sums over 32-channel chunks, then taps, in all of them)
+//   k_conv3r      full-size 3x3 layers with 32 output channels: persistent,
+//                 one loading wave feeding a three-stage LDS ring by direct
+//                 buffer-to-LDS loads, weights resident; optionally the
+//                 encoder's 2x2 max pool or, for the last layer in inference,
+//                 the 1x1 head with the filled image
+//   k_conv3a      3x3 layers with 64-multiple channels: persistent, halo and
+//                 weights double-buffered by direct buffer-to-LDS loads;
+//                 optionally the 2x2 max pool
+//   k_conv3       the other 3x3 layers (also input gradients with flipped
 //                 transposed weights) and the 2x2 stride-2 transposed
 //                 convolution as a 1x1 product onto (sub-position, channel)
-//                 columns. Fused bias, ReLU, bf16 rounding; optionally the
-//                 encoder's 2x2 max pool and, for the last layer in inference,
-//                 the 1x1 head with the filled image.
+//                 columns, input halo and weights staged in LDS per chunk
 //   k_conv        the remaining shapes (8 input channels; gathered input
 //                 gradient of the transposed convolution), operands through
 //                 buffer resources
-//   k_wgrad       weight gradients: GEMM over pixels, both operands staged
-//                 through LDS transposed (pixels contiguous), split over
-//                 pixel ranges with fp32 partials and a fixed-order reduction
-//   k_colsum      bias gradients, same split / reduce scheme
+//   k_wgrad       weight gradients: GEMM over pixels, every tap per wave, the
+//                 operands staged through LDS transposed (pixels contiguous),
+//                 four pixel splits per workgroup summed in LDS, fp32 partial
+//                 rows and a fixed-order reduction
+//   k_colsum      bias gradients, split over pixel ranges the same way
 //   elementwise   input packing, max-pool gradient (plus the skip gradient),
 //                 ReLU gradient, head with loss in training, Adam, weight
 //                 conversion to bf16 layouts
