@@ -96,10 +96,18 @@ def test_sphere_counts_follow_projected_area(orc):
     assert counts[2] == counts[3]
 
 
-def test_three_pass_and_one_pass_capture_the_same_fragments(orc):
+def test_three_axis_capture_contains_the_view_capture(orc):
+    """The three-axis variants rasterize every triangle in the y-z, z-x and
+    x-y planes; their fragments include, as a multiset, every fragment of the
+    x-y plane alone (1-Pass/View), and the rest come from the other two
+    planes (a triangle parallel to z is edge-on in x-y)."""
     mesh = S.cube_scene(1500, 21, scale_range=(0.05, 0.3), ground=4)
+    n1, c1 = _canon(orc, mesh, 6, 1)
     n2, c2 = _canon(orc, mesh, 6, 2)
-    n3, c3 = _canon(orc, mesh, 6, 3)
-    n0, _ = _canon(orc, mesh, 6, 0)
-    assert n2 == n3 and np.array_equal(c2, c3)
-    assert n2 > n0
+    assert n2 > n1 > 0
+    a = {}
+    for row in map(tuple, c2.tolist()):
+        a[row] = a.get(row, 0) + 1
+    for row in map(tuple, c1.tolist()):
+        assert a.get(row, 0) > 0, row
+        a[row] -= 1
