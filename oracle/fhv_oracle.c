@@ -557,7 +557,7 @@ static void frag_pos(int mode, uint32_t width, uint32_t levels, uint64_t key, ui
  * the fragment with the smallest (depth bits, index) wins; fragments with
  * depth <= 0 or NaN are skipped. Uncovered pixels keep colour 0, depth 0,
  * coverage 0. zbuf: u64 [V][H][W] scratch; outputs [V][H][W]. */
-void orc_splat(int mode, uint32_t width_cap, uint32_t levels, const uint64_t* oct_key,
+void orc_splat(int mode, uint32_t width_cap, uint32_t levels, const uint64_t* oct_key, uint64_t n_keys,
                const uint32_t* frag, uint64_t n_frag, const float* m, const uint32_t* wh_k,
                uint32_t n_views, uint64_t* zbuf, uint32_t* out_rgba, float* out_depth,
                uint8_t* out_cov)
@@ -572,6 +572,7 @@ void orc_splat(int mode, uint32_t width_cap, uint32_t levels, const uint64_t* oc
         for (uint64_t i = 0; i < n_frag; ++i) {
             const uint32_t* r = frag + 4 * i;
             float p[3], s[3];
+            if (r[3] >= n_keys) continue; /* octant row not stored: not drawn */
             frag_pos(mode, width_cap, levels, oct_key[r[3]], r[0], p);
             for (int row = 0; row < 3; ++row) {
                 float a = M[4 * row + 0] * p[0];

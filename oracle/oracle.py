@@ -59,7 +59,7 @@ def lib():
         L.orc_compact.argtypes = [u32p, C.c_uint64, u32p, C.c_uint64, C.c_uint64, u64p, u32p,
                                   u32p, C.c_uint64, u32p]
         L.orc_compact.restype = C.c_uint64
-        L.orc_splat.argtypes = [C.c_int, C.c_uint32, C.c_uint32, u64p, u32p, C.c_uint64, f32p,
+        L.orc_splat.argtypes = [C.c_int, C.c_uint32, C.c_uint32, u64p, C.c_uint64, u32p, C.c_uint64, f32p,
                                 u32p, C.c_uint32, u64p, u32p, f32p, u8p]
         L.orc_direct_raster.argtypes = [C.c_int, C.c_uint32, C.c_uint32, C.c_uint32, f32p, u32p,
                                         u32p, C.c_uint32, f32p, C.c_uint32, C.c_uint32, u64p, u32p,
@@ -191,7 +191,8 @@ def _views_arrays(views):
 
 def splat(mode: int, keys: np.ndarray, frag: np.ndarray, views, width_cap: int = 0,
           levels: int = 0, return_zbuf: bool = False):
-    """Point splat with nearest-fragment resolve (Sec. 3.3).
+    """Point splat with nearest-fragment resolve (Sec. 3.3). Fragments whose
+    octant rank has no row in `keys` (a truncated table) are not drawn.
 
     Returns (rgba uint32[V,H,W], depth float32[V,H,W], cov uint8[V,H,W]),
     and the z-buffer of winners (uint64 [V,H,W]) when return_zbuf; all
@@ -205,12 +206,13 @@ def splat(mode: int, keys: np.ndarray, frag: np.ndarray, views, width_cap: int =
     depth = np.zeros(V * H * W, np.float32)
     cov = np.zeros(V * H * W, np.uint8)
     keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    n_keys = keys.size
     if keys.size == 0:
         keys = np.zeros(1, np.uint64)
     fr = np.ascontiguousarray(frag, dtype=np.uint32).reshape(-1)
     if fr.size == 0:
         fr = np.zeros(4, np.uint32)
-    lib().orc_splat(mode, width_cap, levels, keys, fr, frag.shape[0], m, whk, V, z, rgba, depth, cov)
+    lib().orc_splat(mode, width_cap, levels, keys, n_keys, fr, frag.shape[0], m, whk, V, z, rgba, depth, cov)
     if return_zbuf:
         return rgba.reshape(V, H, W), depth.reshape(V, H, W), cov.reshape(V, H, W), z.reshape(V, H, W)
     return rgba.reshape(V, H, W), depth.reshape(V, H, W), cov.reshape(V, H, W)
