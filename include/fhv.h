@@ -238,21 +238,25 @@ typedef struct {
 
 /* Point splat (Sec. 3.3): every array fragment i covers the k x k pixels
  * whose lower-left pixel is floor(s + 1/2 - k/2) per axis in every view;
- * per pixel the smallest (fp32 depth bits << 32 | i) wins (64-bit atomic
- * minimum); fragments with depth <= 0 or NaN are skipped. Then each pixel
- * resolves to the winner's w1 colour, its depth and coverage 1, or to 0, 0.0
- * and 0 when nothing covers it.
+ * per pixel the smallest (fp32 depth bits << 32 | i) wins (a 64-bit minimum
+ * in an on-chip tile of the view); fragments with depth <= 0 or NaN are
+ * skipped. Then each pixel resolves to the winner's w1 colour, its depth and
+ * coverage 1, or to 0, 0.0 and 0 when nothing covers it.
  * Fragments whose rank has no stored table row (rank >= cap_occ) are not
- * drawn.
+ * drawn. The arrays must be in key order, as fhv_compact and
+ * fhv_capture_arrays leave them.
  * views: host array of n_views in [1, 32] entries sharing width, height in
- * [1, 16384]. zbuf: uint64 [n_views][height][width] scratch, 16-byte
- * aligned; rgba: uint32,
- * depth: float, cov: uint8, each [n_views][height][width].
+ * [1, 16384]. zbuf: uint64 [n_views][height][width] winning keys (the
+ * input of fhv_shade), 16-byte aligned; rgba: uint32, depth: float, cov:
+ * uint8, each [n_views][height][width]. ws: fhv_splat_workspace(
+ * arrays->cap_frag, n_views, width, height) bytes, device, caller-owned;
+ * 0 from the query means the sizes are out of range.
  * Errors: EINVAL (null pointers, views of different sizes, splat_px 0 or
- * above 64), ERANGE. */
+ * above 64), ERANGE, EWORKSPACE. */
+FHV_API size_t fhv_splat_workspace(uint64_t cap_frag, uint32_t n_views, uint32_t width, uint32_t height);
 FHV_API fhv_status fhv_splat(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_capture_desc* desc,
                      const fhv_view* views, uint32_t n_views, uint64_t* zbuf, uint32_t* rgba,
-                     float* depth, uint8_t* cov, fhv_stream stream);
+                     float* depth, uint8_t* cov, void* ws, size_t ws_bytes, fhv_stream stream);
 
 /* Ray casting (Sec. 3.3, evaluation by ray casting) of POFL per-octant
  * arrays into orthographic views. The ray of pixel (x, y) meets array
@@ -455,6 +459,11 @@ FHV_API fhv_status fhv_profile_end(fhv_ctx* ctx, fhv_kernel_stat* out, uint32_t 
  * HBM copies). Not an operation of the method.
  *   FHV_PROBE_COPY      second half of buf <- first half, 16-byte vector
  *                       loads and stores (bytes a multiple of 32)
+ *   FHV_PROBE_READ      every 16 bytes of buf loaded once (bytes a multiple
+ *                       of 16; buf is left as it was when filled with 0xFF
+ *                       bytes)
+ *   FHV_PROBE_WRITE     every byte of buf set to 0xFF with 16-byte stores
+ *                       (bytes a multiple of 16)
  *   FHV_PROBE_ADD_U32   per line of `line` bytes and per pass: atomic add of
  *                       1 to the line's first u32, result unused
  *   FHV_PROBE_EXCH_U32  atomic exchange of the line's first u32 with
@@ -466,11 +475,14 @@ FHV_API fhv_status fhv_profile_end(fhv_ctx* ctx, fhv_kernel_stat* out, uint32_t 
  * pointer owned by the caller, 16-byte aligned; `line` is a power of two in
  * [8, 4096] (atomic probes), `passes` in [1, 1024]; FHV_EINVAL otherwise.
  * Launches on `stream`; timed by fhv_profile_begin/end as "probe.copy",
- * "probe.add_u32", "probe.exch_u32", "probe.min_u64". */
+ * "probe.read", "probe.write", "probe.add_u32", "probe.exch_u32",
+ * "probe.min_u64". */
 #define FHV_PROBE_COPY 0u
 #define FHV_PROBE_ADD_U32 1u
 #define FHV_PROBE_EXCH_U32 2u
 #define FHV_PROBE_MIN_U64 3u
+#define FHV_PROBE_READ 4u
+#define FHV_PROBE_WRITE 5u
 
 FHV_API fhv_status fhv_probe(fhv_ctx* ctx, uint32_t kind, void* buf, uint64_t bytes, uint32_t line,
                              uint32_t passes, fhv_stream stream);

@@ -121,15 +121,20 @@ fhv_capture_desc batch_desc(const fhv_batch_mesh* m)
     return d;
 }
 
-// Workspace: the capture's, then the compaction's (256-byte aligned).
-size_t batch_ws(const fhv_batch_mesh* m, uint64_t capacity, void* ws, void** cap_ws, void** cmp_ws)
+// Workspace: the capture's, the compaction's, then the splat's (each
+// 256-byte aligned).
+size_t batch_ws(const fhv_batch_mesh* m, const fhv_batch_views* v, uint64_t capacity, void* ws, void** cap_ws,
+                void** cmp_ws, void** spl_ws)
 {
     const fhv_capture_desc d = batch_desc(m);
     const size_t a = (fhv::capture_ws_bytes(&d, m->n_tri) + 255) & ~(size_t)255;
-    const size_t b = fhv::compact_ws_bytes(&d, (uint64_t)m->n_scenes << (3 * m->levels), capacity);
+    const size_t b = (fhv::compact_ws_bytes(&d, (uint64_t)m->n_scenes << (3 * m->levels), capacity) + 255) &
+                     ~(size_t)255;
+    const size_t c = fhv::splat_ws_bytes(capacity, m->n_scenes, v->n_views, v->width, v->height);
     if (cap_ws) *cap_ws = ws;
     if (cmp_ws) *cmp_ws = ws ? (void*)((char*)ws + a) : nullptr;
-    return a + b;
+    if (spl_ws) *spl_ws = ws ? (void*)((char*)ws + a + b) : nullptr;
+    return a + b + c;
 }
 
 struct BatchCall {
@@ -150,7 +155,7 @@ hipError_t batch_capture(const fhv::Device& dev, const BatchCall& c, hipStream_t
     const fhv_mesh m{c.mesh->pos, c.mesh->rgba, c.mesh->tri, c.mesh->obj, c.mesh->n_vert, c.mesh->n_tri};
     const fhv::Scenes sc{c.mesh->scene_tri, c.mesh->n_scenes};
     void* cw = nullptr;
-    batch_ws(c.mesh, c.lists->capacity, c.ws, &cw, nullptr);
+    batch_ws(c.mesh, c.views, c.lists->capacity, c.ws, &cw, nullptr, nullptr);
     return fhv::capture_launch(dev, &m, &d, c.lists, cw, s, &sc);
 }
 
@@ -158,7 +163,7 @@ hipError_t batch_compact(const fhv::Device& dev, const BatchCall& c, hipStream_t
 {
     const fhv_capture_desc d = batch_desc(c.mesh);
     void* mw = nullptr;
-    batch_ws(c.mesh, c.lists->capacity, c.ws, nullptr, &mw);
+    batch_ws(c.mesh, c.views, c.lists->capacity, c.ws, nullptr, &mw, nullptr);
     return fhv::compact_launch(dev, c.lists, &d, c.out, mw, s);
 }
 
@@ -166,8 +171,12 @@ hipError_t batch_splat(const fhv::Device& dev, const BatchCall& c, hipStream_t s
 {
     const fhv::BatchViews bv{c.views->m, c.mesh->n_scenes, c.views->n_views, c.views->width,
                              c.views->height, c.views->splat_px};
-    return fhv::splat_batch_launch(dev, c.out, c.mesh->levels, bv, c.zbuf, c.rgba, c.depth, c.cov,
-                                   c.out->cap_frag, s);
+    void* sw = nullptr;
+    batch_ws(c.mesh, c.views, c.lists->capacity, c.ws, nullptr, nullptr, &sw);
+    // the arrays hold at most `capacity` records (the splat workspace's size)
+    fhv_pofa a = *c.out;
+    a.cap_frag = a.cap_frag < c.lists->capacity ? a.cap_frag : c.lists->capacity;
+    return fhv::splat_batch_launch(dev, &a, c.mesh->levels, bv, c.zbuf, c.rgba, c.depth, c.cov, sw, s);
 }
 
 hipError_t batch_enqueue(const fhv::Device& dev, const BatchCall& c, hipStream_t s)
@@ -380,9 +389,17 @@ fhv_status fhv_compact(fhv_ctx* ctx, const fhv_lists* lists, const fhv_capture_d
     return hip_status(fhv::compact_launch(ctx->dev, lists, desc, out, ws, (hipStream_t)stream));
 }
 
+size_t fhv_splat_workspace(uint64_t cap_frag, uint32_t n_views, uint32_t width, uint32_t height)
+{
+    if (n_views == 0 || n_views > fhv::kMaxViews || width < 1 || width > 16384 || height < 1 || height > 16384 ||
+        cap_frag >= 0xFFFFFFFFull || !fhv::splat_fits(cap_frag, 1, n_views, width, height))
+        return 0;
+    return fhv::splat_ws_bytes(cap_frag, 1, n_views, width, height);
+}
+
 fhv_status fhv_splat(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_capture_desc* desc,
                      const fhv_view* views, uint32_t n_views, uint64_t* zbuf, uint32_t* rgba,
-                     float* depth, uint8_t* cov, fhv_stream stream)
+                     float* depth, uint8_t* cov, void* ws, size_t ws_bytes, fhv_stream stream)
 {
     if (!ctx || !arrays || !desc_ok(desc) || !views) return FHV_EINVAL;
     if (n_views == 0 || n_views > fhv::kMaxViews) return FHV_ERANGE;
@@ -405,18 +422,23 @@ fhv_status fhv_splat(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_capture_des
         if (views[v].splat_px != 1) va.all_k1 = 0;
         va.c[v] = 0.5f - 0.5f * (float)views[v].splat_px;
     }
+    if (!fhv::splat_fits(arrays->cap_frag, 1, n_views, va.width, va.height)) return FHV_ERANGE;
+    if (ws_bytes < fhv::splat_ws_bytes(arrays->cap_frag, 1, n_views, va.width, va.height)) return FHV_EWORKSPACE;
+    if (!ws) return FHV_EINVAL;
     fhv_status st = set_device(ctx);
     if (st != FHV_OK) return st;
-    return hip_status(fhv::splat_launch(ctx->dev, arrays, desc, va, zbuf, rgba, depth, cov,
-                                        arrays->cap_frag, (hipStream_t)stream));
+    return hip_status(fhv::splat_launch(ctx->dev, arrays, desc, va, zbuf, rgba, depth, cov, ws,
+                                        (hipStream_t)stream));
 }
 
 fhv_status fhv_probe(fhv_ctx* ctx, uint32_t kind, void* buf, uint64_t bytes, uint32_t line,
                      uint32_t passes, fhv_stream stream)
 {
-    if (!ctx || !buf || ((uintptr_t)buf & 15) || kind > FHV_PROBE_MIN_U64) return FHV_EINVAL;
+    if (!ctx || !buf || ((uintptr_t)buf & 15) || kind > FHV_PROBE_WRITE) return FHV_EINVAL;
     if (kind == FHV_PROBE_COPY) {
         if (bytes < 32 || bytes % 32 != 0) return FHV_EINVAL;
+    } else if (kind == FHV_PROBE_READ || kind == FHV_PROBE_WRITE) {
+        if (bytes < 16 || bytes % 16 != 0) return FHV_EINVAL;
     } else {
         if (line < 8 || line > 4096 || (line & (line - 1)) || bytes < line) return FHV_EINVAL;
         if (passes < 1 || passes > 1024) return FHV_EINVAL;
@@ -589,8 +611,9 @@ fhv_status fhv_set_tuning(fhv_ctx* ctx, const fhv_tuning* t)
 
 size_t fhv_batch_workspace(const fhv_batch_mesh* mesh, const fhv_batch_views* views, uint64_t capacity)
 {
-    if (!batch_shape_ok(mesh, views)) return 0;
-    return batch_ws(mesh, capacity, nullptr, nullptr, nullptr);
+    if (!batch_shape_ok(mesh, views) || capacity >= 0xFFFFFFFFull) return 0;
+    if (!fhv::splat_fits(capacity, mesh->n_scenes, views->n_views, views->width, views->height)) return 0;
+    return batch_ws(mesh, views, capacity, nullptr, nullptr, nullptr, nullptr);
 }
 
 fhv_status fhv_batch_run(fhv_ctx* ctx, const fhv_batch_mesh* mesh, const fhv_batch_views* views,
@@ -614,7 +637,9 @@ fhv_status fhv_batch_run(fhv_ctx* ctx, const fhv_batch_mesh* mesh, const fhv_bat
     if ((uintptr_t)out->frag & 15) return FHV_EINVAL;
     if (out->cap_occ > 0 && (!out->oct_key || !out->oct_off || !out->oct_cnt)) return FHV_EINVAL;
     if (!zbuf || !rgba || !depth || !cov || ((uintptr_t)zbuf & 15)) return FHV_EINVAL;
-    if (ws_bytes < batch_ws(mesh, lists->capacity, nullptr, nullptr, nullptr)) return FHV_EWORKSPACE;
+    if (!fhv::splat_fits(lists->capacity, mesh->n_scenes, views->n_views, views->width, views->height))
+        return FHV_ERANGE;
+    if (ws_bytes < batch_ws(mesh, views, lists->capacity, nullptr, nullptr, nullptr, nullptr)) return FHV_EWORKSPACE;
     if (!ws) return FHV_EINVAL;
     fhv_status st = set_device(ctx);
     if (st != FHV_OK) return st;

@@ -453,7 +453,7 @@ k_raster(const TriRec* __restrict__ recs, const uint64_t* __restrict__ incl, uin
         if (kAct == kActCount) {
 #pragma unroll
             for (int g = 0; g < kBatch; ++g)
-                if (w + g < w1) wave_hist(key[g], has[g], bs.cnt, bs.occ, bs.bitmap);   // wave-uniform
+                if (w + g < w1) wave_hist(key[g], has[g], bs.cnt, bs.bitmap);   // wave-uniform
             continue;
         }
         if (kAct == kActInsert) {

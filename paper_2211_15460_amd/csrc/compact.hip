@@ -7,12 +7,16 @@
 // second time. Here the pool is read linearly instead, through the key
 // sidecar the capture wrote, and keys are grouped in buckets ("bricks") of
 // 512 consecutive keys so that every bucket fits a workgroup's LDS:
-//   k_hist     per brick: fragment count (atomic add) and number of
-//              distinct keys (atomic or into a key bitmap; the first setter
-//              of a bit counts the key); lanes of a wave that hit the same
-//              brick or bitmap word combine into one atomic
-//   scan       exclusive sums of both per-brick counts: brick fragment
-//              offsets and brick rank bases; totals = n_frag, n_occ
+//   k_hist     per brick: fragment count (atomic add) and the key's bit
+//              in a key bitmap (atomic or); lanes of a wave that hit the
+//              same brick or bitmap word combine into one atomic, and no
+//              atomic's result is waited for
+//   scan       exclusive sums of the brick counts: brick fragment offsets
+//              and the list of occupied bricks; total = n_frag
+//   k_brick_occ  per occupied brick: distinct keys = popcount of its 16
+//              bitmap words
+//   scan       exclusive sums of the distinct-key counts: brick rank bases;
+//              total = n_occ
 //   k_scatter  every pool record to its brick's range of a staging array
 //              (slot within the brick from an atomic cursor), its key's low
 //              9 bits (the key inside the brick) in w3
@@ -40,8 +44,7 @@ __device__ __forceinline__ uint64_t frag_count(const uint64_t* counter, uint64_t
 template <class KeyT>
 __global__ void __launch_bounds__(kBlock)
 k_hist(const KeyT* __restrict__ keys, const uint64_t* __restrict__ counter, uint64_t cap,
-       uint32_t* __restrict__ brick_cnt, uint32_t* __restrict__ brick_occ,
-       uint32_t* __restrict__ bitmap)
+       uint32_t* __restrict__ brick_cnt, uint32_t* __restrict__ bitmap)
 {
     const uint64_t F = frag_count(counter, cap);
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
@@ -51,7 +54,29 @@ k_hist(const KeyT* __restrict__ keys, const uint64_t* __restrict__ counter, uint
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < Fw; i += stride) {
         const bool act = i < F;
         const uint64_t key = act ? (uint64_t)keys[i] : 0u;
-        wave_hist(key, act, brick_cnt, brick_occ, bitmap);
+        wave_hist(key, act, brick_cnt, bitmap);
+    }
+}
+
+// Distinct keys of every occupied brick (the list from the count scan):
+// the popcount of its kBrickKeys / 32 bitmap words, one lane per word.
+__global__ void __launch_bounds__(kBlock)
+k_brick_occ(const uint32_t* __restrict__ list, const uint64_t* __restrict__ list_total,
+            const uint32_t* __restrict__ bitmap, uint32_t* __restrict__ brick_occ)
+{
+    constexpr uint32_t kWords = kBrickKeys / 32;   // 16: four bricks per wave
+    const uint32_t nl = (uint32_t)(*list_total >> 32);
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    const uint64_t nw = (uint64_t)nl * kWords;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < (nw + kWave - 1) / kWave * kWave;
+         i += stride) {
+        const bool act = i < nw;
+        const uint32_t b = act ? list[i / kWords] : 0u;
+        uint32_t c = act ? (uint32_t)__popc(bitmap[(uint64_t)b * kWords + i % kWords]) : 0u;
+        // sum over the 16 lanes of the brick (aligned groups of 16 lanes)
+#pragma unroll
+        for (int d = 1; d < (int)kWords; d <<= 1) c += (uint32_t)__shfl_xor((int)c, d, kWave);
+        if (act && i % kWords == 0) brick_occ[b] = c;
     }
 }
 
@@ -186,11 +211,11 @@ constexpr int kKeysPerLane = kBrickKeys / kWave;  // 8
 // One wave per brick of kLo < n <= kRecs records, with no workgroup
 // barriers (one-wave workgroups; the variant for small bricks needs less
 // LDS and fewer registers, so more of them share a compute unit): records
-// held in registers (kRecs / 64 per lane) are counted per key in
-// LDS, the 512 counts scanned across the wave (8 consecutive keys per lane),
-// the records grouped by key in LDS through cursors, and every record
-// written straight to its final slot: its key's offset plus its rank inside
-// the key's run in canonical order, with w3 = the key's table rank.
+// loaded into registers (kRecs / 64 per lane) are counted per key in LDS,
+// the 512 counts scanned across the wave (8 consecutive keys per lane), the
+// records grouped by key in LDS through cursors, and every record written
+// straight to its final slot: its key's offset plus its rank inside the
+// key's run in canonical order, with w3 = the key's table rank.
 template <int kRecs, int kLo>
 __global__ void __launch_bounds__(kWave)
 k_brick_wave(const uint4* __restrict__ stage, const uint32_t* __restrict__ brick_cnt,
@@ -249,15 +274,9 @@ k_brick_wave(const uint4* __restrict__ stage, const uint32_t* __restrict__ brick
             pz += c[k] ? 1u : 0u;
         }
         wave_lds_sync();
-        uint32_t pos[kPerLane];
 #pragma unroll
-        for (int k = 0; k < kPerLane; ++k) {
-            pos[k] = 0;
-            if ((uint32_t)(k * kWave + lane) < n) {
-                pos[k] = atomicAdd(cur + (r[k].w & (kBrickKeys - 1)), 1u);
-                buf[pos[k]] = r[k];
-            }
-        }
+        for (int k = 0; k < kPerLane; ++k)
+            if ((uint32_t)(k * kWave + lane) < n) buf[atomicAdd(cur + (r[k].w & (kBrickKeys - 1)), 1u)] = r[k];
         wave_lds_sync();
         // table rows, 8 consecutive keys per lane
 #pragma unroll
@@ -273,50 +292,42 @@ k_brick_wave(const uint4* __restrict__ stage, const uint32_t* __restrict__ brick
             }
         }
         // every record's place inside its key's run: the number of records
-        // of the run that precede it in (w0, w1, w2) order, equal records
-        // ordered by their LDS position. The loop runs over positions in the
-        // run (up to the brick's longest run) with the 16 records of a lane
-        // unrolled inside, so their LDS reads overlap.
-        uint32_t mrun = 0;
+        // of the run that precede it in (w0, w1, w2) order (bitwise equal
+        // records are interchangeable; they are ordered by LDS position).
+        // Records are taken in their key-grouped LDS order, 64 positions at
+        // a time, so a window's loop runs to the longest run it meets, with
+        // four reads of each lane in flight per step.
+        for (uint32_t w0 = 0; w0 < n; w0 += kWave) {
+            const uint32_t q = w0 + (uint32_t)lane;
+            const bool valid = q < n;
+            const uint4 x = buf[valid ? q : 0];
+            const uint32_t leaf = x.w & (kBrickKeys - 1);
+            const uint32_t lo = valid ? off[leaf] : 0u;
+            const uint32_t len = valid ? cur[leaf] - lo : 0u;   // cur = end of run
+            uint32_t mrun = len;
 #pragma unroll
-        for (int k = 0; k < kKeysPerLane; ++k) mrun = c[k] > mrun ? c[k] : mrun;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const uint32_t o2 = (uint32_t)__shfl_xor((int)mrun, d, kWave);
-            mrun = o2 > mrun ? o2 : mrun;
-        }
-        uint32_t lo[kPerLane], len[kPerLane], before[kPerLane];
-#pragma unroll
-        for (int k = 0; k < kPerLane; ++k) {
-            const uint32_t leaf = r[k].w & (kBrickKeys - 1);
-            const bool valid = (uint32_t)(k * kWave + lane) < n;
-            lo[k] = valid ? off[leaf] : 0u;
-            len[k] = valid ? cur[leaf] - lo[k] : 0u;   // cur = end of run
-            before[k] = 0;
-        }
-        for (uint32_t dd = 0; dd < mrun; ++dd) {
-            // branch-free: every lane reads (a clamped slot), so the 16 reads
-            // of an iteration are in flight together
-            uint4 y[kPerLane];
-#pragma unroll
-            for (int k = 0; k < kPerLane; ++k) {
-                const uint32_t q = lo[k] + (dd < len[k] ? dd : 0u);
-                y[k] = buf[q];
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint32_t o2 = (uint32_t)__shfl_xor((int)mrun, d, kWave);
+                mrun = o2 > mrun ? o2 : mrun;
             }
+            uint32_t before = 0;
+            for (uint32_t dd = 0; dd < mrun; dd += 4) {
+                uint4 y[4];
 #pragma unroll
-            for (int k = 0; k < kPerLane; ++k) {
-                const uint4 x = r[k];
-                const uint32_t q = lo[k] + dd;
-                const bool lt = rec_less(y[k], x) ||
-                                (q < pos[k] && y[k].x == x.x && y[k].y == x.y && y[k].z == x.z);
-                before[k] += (dd < len[k] && lt) ? 1u : 0u;
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t e = dd + (uint32_t)u;
+                    y[u] = buf[lo + (e < len ? e : 0u)];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t e = dd + (uint32_t)u;
+                    const bool lt = rec_less(y[u], x) ||
+                                    (lo + e < q && y[u].x == x.x && y[u].y == x.y && y[u].z == x.z);
+                    before += (e < len && lt) ? 1u : 0u;
+                }
             }
+            if (valid) frag[o + lo + before] = make_uint4(x.x, x.y, x.z, base_rank + rank[leaf]);
         }
-#pragma unroll
-        for (int k = 0; k < kPerLane; ++k)
-            if ((uint32_t)(k * kWave + lane) < n)
-                frag[o + lo[k] + before[k]] =
-                    make_uint4(r[k].x, r[k].y, r[k].z, base_rank + rank[r[k].w & (kBrickKeys - 1)]);
         wave_lds_sync();
     }
 }
@@ -401,8 +412,9 @@ static CompactWs carve_compact(void* ws, uint64_t n_head, uint64_t capacity, siz
     const uint64_t n_brick = (n_head + kBrickKeys - 1) / kBrickKeys;
     Carver c{(char*)ws, 0};
     CompactWs w;
-    // the three zero-initialised arrays are adjacent so one fill clears them
-    const uint64_t zlen = 3 * n_brick + (n_head + 31) / 32;
+    // the zero-initialised arrays are adjacent so one fill clears them; the
+    // bitmap has kBrickKeys / 32 words for every brick, the last one too
+    const uint64_t zlen = 3 * n_brick + n_brick * (kBrickKeys / 32);
     uint32_t* z = c.take<uint32_t>(zlen);
     w.brick_cnt = z;
     w.brick_occ = z ? z + n_brick : nullptr;
@@ -429,6 +441,17 @@ size_t compact_ws_bytes(const fhv_capture_desc* d, uint64_t n_head, uint64_t cap
 static hipError_t brick_sorts(const Device& dev, const CompactWs& w, const fhv_pofa* out, uint64_t n_brick,
                               const char* name, hipStream_t s);
 
+// Distinct keys per occupied brick, from the bitmap (after the count scan
+// has listed the occupied bricks).
+static hipError_t brick_occ_launch(const Device& dev, const CompactWs& w, uint64_t n_brick, hipStream_t s)
+{
+    uint64_t g = (n_brick * (kBrickKeys / 32) + kBlock - 1) / kBlock;
+    const uint64_t gmax = (uint64_t)dev.cus * 16;
+    g = g < 1 ? 1 : (g > gmax ? gmax : g);
+    k_brick_occ<<<dim3((unsigned)g), dim3(kBlock), 0, s>>>(w.list, w.list_total, w.bitmap, w.brick_occ);
+    return hipGetLastError();
+}
+
 hipError_t compact_launch(const Device& dev, const fhv_lists* L, const fhv_capture_desc* d,
                           const fhv_pofa* out, void* ws, hipStream_t s)
 {
@@ -441,16 +464,16 @@ hipError_t compact_launch(const Device& dev, const fhv_lists* L, const fhv_captu
     const unsigned grid = (unsigned)(gb < 1 ? 1 : (gb > gmax ? gmax : gb));
     {
         ProfScope ps(dev, "compact.hist", s);
-        e = fill_u32(w.brick_cnt, 3 * n_brick + (L->n_head + 31) / 32, 0u, s);
+        e = fill_u32(w.brick_cnt, 3 * n_brick + n_brick * (kBrickKeys / 32), 0u, s);
         if (e == hipSuccess) e = fill_u64(w.list_total, 1, 0, s);
         if (e != hipSuccess) return e;
         k_totals<<<dim3(1), dim3(64), 0, s>>>(L->counter, L->capacity, out->n_frag);
         if (L->n_head > (1ull << 32))
             k_hist<uint64_t><<<dim3(grid), dim3(kBlock), 0, s>>>((const uint64_t*)L->keys, L->counter,
-                                                             L->capacity, w.brick_cnt, w.brick_occ, w.bitmap);
+                                                             L->capacity, w.brick_cnt, w.bitmap);
         else
             k_hist<uint32_t><<<dim3(grid), dim3(kBlock), 0, s>>>((const uint32_t*)L->keys, L->counter,
-                                                             L->capacity, w.brick_cnt, w.brick_occ, w.bitmap);
+                                                             L->capacity, w.brick_cnt, w.bitmap);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
@@ -458,6 +481,7 @@ hipError_t compact_launch(const Device& dev, const fhv_lists* L, const fhv_captu
         ProfScope ps(dev, "compact.scan", s);
         e = scan<uint64_t>(LoadBrick{w.brick_cnt}, StoreBrick{w.brick_off, w.list}, n_brick, w.part,
                            w.list_total, s);
+        if (e == hipSuccess) e = brick_occ_launch(dev, w, n_brick, s);
         if (e == hipSuccess)
             e = scan<uint64_t>(LoadOcc{w.brick_occ}, StoreRank{w.brick_rank}, n_brick, w.part,
                                (uint64_t*)out->n_occ, s);
@@ -539,18 +563,19 @@ hipError_t capture_arrays_launch(const Device& dev, const fhv_mesh* m, const fhv
     hipError_t e;
     {
         ProfScope ps(dev, "arrays.reset", s);
-        e = fill_u32(w.brick_cnt, 3 * n_brick + (n_head + 31) / 32, 0u, s);
+        e = fill_u32(w.brick_cnt, 3 * n_brick + n_brick * (kBrickKeys / 32), 0u, s);
         if (e == hipSuccess) e = fill_u64(w.list_total, 1, 0, s);
         if (e == hipSuccess) e = fill_u32(skip, 1, 0u, s);
     }
     if (e != hipSuccess) return e;
-    BrickSink bs{w.brick_cnt, w.brick_occ, w.bitmap, w.brick_off, w.brick_cur, w.stage, skip};
+    BrickSink bs{w.brick_cnt, w.bitmap, w.brick_off, w.brick_cur, w.stage, skip};
     e = capture_bricks_launch(dev, m, d, ws, kActCount, bs, s);
     if (e != hipSuccess) return e;
     {
         ProfScope ps(dev, "arrays.scan", s);
         e = scan<uint64_t>(LoadBrick{w.brick_cnt}, StoreBrick{w.brick_off, w.list}, n_brick, w.part,
                            w.list_total, s);
+        if (e == hipSuccess) e = brick_occ_launch(dev, w, n_brick, s);
         if (e == hipSuccess)
             e = scan<uint64_t>(LoadOcc{w.brick_occ}, StoreRank{w.brick_rank}, n_brick, w.part,
                                (uint64_t*)out->n_occ, s);

@@ -96,11 +96,11 @@ __device__ __forceinline__ uint32_t wave_count_add(uint32_t* ctr, uint32_t b, bo
 
 // Per-brick histogram of keys (compaction buckets of kBrickKeys keys):
 // every active lane adds 1 to brick_cnt[key >> kBrickShift] and sets the
-// key's bit in `bitmap`; a bit set for the first time counts the key in
-// brick_occ. Lanes with the same brick or bitmap word share one atomic.
+// key's bit in `bitmap`. Lanes with the same brick or bitmap word share one
+// atomic; no atomic's result is waited for (the number of distinct keys of a
+// brick is the popcount of its bitmap words, taken afterwards).
 // Must be called by all lanes of the wave.
-__device__ __forceinline__ void wave_hist(uint64_t key, bool act, uint32_t* brick_cnt, uint32_t* brick_occ,
-                                          uint32_t* bitmap)
+__device__ __forceinline__ void wave_hist(uint64_t key, bool act, uint32_t* brick_cnt, uint32_t* bitmap)
 {
     const int lane = __lane_id();
     wave_count_add<false>(brick_cnt, (uint32_t)(key >> kBrickShift), act);
@@ -112,11 +112,7 @@ __device__ __forceinline__ void wave_hist(uint64_t key, bool act, uint32_t* bric
                             (uint32_t)__shfl((int)(uint32_t)word, leader, kWave);
         const uint64_t m = __ballot(act && word == lw) & todo;
         const uint32_t bits = wave_or(((m >> lane) & 1ull) ? (1u << (key & 31)) : 0u);
-        if (lane == leader) {
-            const uint32_t old = atomicOr(bitmap + lw, bits);
-            const uint32_t fresh = (uint32_t)__popc(bits & ~old);
-            if (fresh) atomicAdd(brick_occ + (lw >> (kBrickShift - 5)), fresh);
-        }
+        if (lane == leader) atomicOr(bitmap + lw, bits);
         todo &= ~m;
     }
 }
@@ -211,9 +207,14 @@ size_t compact_ws_bytes(const fhv_capture_desc* d, uint64_t n_head, uint64_t cap
 hipError_t compact_launch(const Device& dev, const fhv_lists* L, const fhv_capture_desc* d,
                           const fhv_pofa* out, void* ws, hipStream_t s);
 
+// Splat workspace for arrays of cap_frag records into n_scenes x n_views
+// views of width x height.
+size_t splat_ws_bytes(uint64_t cap_frag, uint32_t n_scenes, uint32_t n_views, uint32_t width, uint32_t height);
+// Whether the splat's bins of such a call fit its 32-bit offsets.
+bool splat_fits(uint64_t cap_frag, uint32_t n_scenes, uint32_t n_views, uint32_t width, uint32_t height);
 hipError_t splat_launch(const Device& dev, const fhv_pofa* a, const fhv_capture_desc* d,
                         const ViewArgs& va, uint64_t* zbuf, uint32_t* rgba, float* depth,
-                        uint8_t* cov, uint64_t max_frag, hipStream_t s);
+                        uint8_t* cov, void* ws, hipStream_t s);
 
 // Views of a batch: matrices [n_scenes][n_views][12] in device memory.
 struct BatchViews {
@@ -222,15 +223,15 @@ struct BatchViews {
 };
 
 hipError_t splat_batch_launch(const Device& dev, const fhv_pofa* a, uint32_t levels, const BatchViews& bv,
-                              uint64_t* zbuf, uint32_t* rgba, float* depth, uint8_t* cov,
-                              uint64_t max_frag, hipStream_t s);
+                              uint64_t* zbuf, uint32_t* rgba, float* depth, uint8_t* cov, void* ws,
+                              hipStream_t s);
 
 // Two-pass capture straight into per-octant arrays (fhv_capture_arrays):
 // the rasterizer counts fragments per brick (kActCount) or stores each at its
 // brick's next free staging slot (kActInsert) instead of appending to lists.
 enum RasterAct { kActList = 0, kActCount = 1, kActInsert = 2 };
 struct BrickSink {
-    uint32_t *cnt, *occ, *bitmap;   // kActCount: per-brick counts, distinct keys, key bitmap
+    uint32_t *cnt, *bitmap;         // kActCount: per-brick counts, key bitmap
     const uint32_t* off;            // kActInsert: brick offsets in the staging array
     uint32_t* cur;                  //             per-brick slot cursors (zeroed)
     uint4* stage;                   //             staging records, w3 = key within the brick

@@ -2,30 +2,51 @@
 // fragment is projected, covers a k x k pixel square (at least one pixel),
 // and per pixel the nearest fragment wins, as in deferred shading.
 //
-//   k_zclear   z-buffers <- ~0 (empty)
-//   k_splat    one fragment per thread, all views per fragment read: fp32
-//              3x4 transform without fused multiply-adds, footprint, 64-bit
-//              atomic minimum of (depth bits << 32 | fragment index), with a
-//              plain read first so covered pixels skip the atomic
-//   k_resolve  per pixel: winner's colour (w1), depth and coverage
+// Screen-tile ownership: every view is cut into tiles of 64 x 64 pixels and
+// one workgroup owns a tile, holding its depth test in LDS, so no z-buffer
+// entry is touched by more than one workgroup and no global atomic decides a
+// pixel. The arrays are cut into chunks of 64 consecutive fragments (one per
+// lane); in Morton order a chunk is a compact piece of surface, and its
+// positions' bounding box, projected into a view, names the few tiles the
+// chunk can reach there.
+//
+//   k_tile_count  one wave per chunk: the bounding box of its fragment
+//                 positions (and the range of scenes its keys belong to);
+//                 per (scene, view) of the chunk, the pixel rectangle its
+//                 footprints can reach (with a margin that covers the fp32
+//                 rounding of every fragment inside the box); a rectangle
+//                 over at most 4 tiles counts the chunk once in each tile's
+//                 bin, a larger one once in the view's own bin
+//   scan          bin offsets (bins: every tile, then every view)
+//   k_tile_write  the same rectangles again; the chunk's index goes into
+//                 each tile bin, or the chunk with its rectangle into the
+//                 view bin
+//   k_tile_splat  one workgroup per tile: z-tile of 64-bit keys (fp32 depth
+//                 bits << 32 | fragment index) in LDS, cleared; every chunk of
+//                 the tile's bin, and every chunk of the view's bin whose
+//                 rectangle meets the tile, projected fragment by fragment
+//                 (fp32 3x4 transform without fused multiply-adds) with an
+//                 LDS 64-bit minimum for each footprint pixel inside the tile;
+//                 then each pixel of the tile written once: key, winner's
+//                 colour (w1), depth and coverage
+//
+// A batch (many scenes in one key space, key = scene << 3L | Morton code)
+// runs the same kernels over (scene, view) slots; a fragment only draws into
+// the views of its own scene, and the matrices are read from device memory.
 #include <math.h>
+#include <string.h>
 
 #include "fhv_common.h"
+#include "scan.h"
 
 namespace fhv {
 
 namespace {
 
-__global__ void __launch_bounds__(kBlock) k_zclear(uint64_t* __restrict__ z, uint64_t n)
-{
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    uint4* q = (uint4*)z;
-    const uint4 e = make_uint4(~0u, ~0u, ~0u, ~0u);
-    const uint64_t nq = n / 2;
-    const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    for (uint64_t i = t; i < nq; i += stride) q[i] = e;
-    if (t == 0 && (n & 1)) z[n - 1] = ~0ull;
-}
+constexpr int kChunk = kWave;       // fragments per chunk, one per lane
+constexpr int kTile = 64;           // tile side in pixels
+constexpr int kTilePix = kTile * kTile;
+constexpr uint32_t kTileBinMax = 4; // larger rectangles go to the view's bin
 
 // Position of array fragment r in the view's input space: PPFL
 // (px + 1/2, py + 1/2, depth24), POFL grid position + 1/2.
@@ -46,318 +67,490 @@ __device__ __forceinline__ void frag_pos(const uint4& r, uint64_t key, uint32_t 
     }
 }
 
-// One-pixel footprints: target z-buffer entry of fragment i in view v, or
-// none (returns false).
-__device__ __forceinline__ bool pixel_of(const ViewArgs& va, uint32_t v, float x, float y, float z,
-                                         uint64_t i, uint64_t plane, uint64_t* off,
-                                         unsigned long long* zk)
+// What every kernel needs to know about the call.
+struct TileArgs {
+    uint32_t n_scenes;     // 1 for fhv_splat
+    uint32_t n_views;      // views per scene
+    uint32_t width, height;
+    uint32_t nx, ny;       // tiles per row and per column of a view
+    uint32_t per_view;     // nx * ny
+    uint32_t n_tiles;      // n_scenes * n_views * per_view
+    uint32_t shift;        // batches: scene = key >> shift; else 64 (no scene bits)
+    uint32_t cap_w;        // PPFL capture width (pixel keys)
+    uint64_t cap_frag, cap_occ;
+    // capacities of the two lists; arrays in key order never reach them (a
+    // write beyond is dropped, a read beyond is not made)
+    uint32_t cap_t, cap_b;
+};
+
+// Matrix, footprint side and offset 1/2 - k/2 of view slot g (scene g / V,
+// view g % V): from the kernel arguments (one scene) or, for a batch, from
+// device memory [scene][view][12] with one footprint for all views.
+template <bool kBatch>
+struct ViewSrc {
+    const ViewArgs& va;
+    const float* vm;
+    __device__ __forceinline__ const float* m(uint32_t g) const
+    {
+        return kBatch ? vm + 12ull * g : va.m[g];
+    }
+    __device__ __forceinline__ uint32_t k(uint32_t g) const { return kBatch ? va.k[0] : va.k[g]; }
+    __device__ __forceinline__ float c(uint32_t g) const { return kBatch ? va.c[0] : va.c[g]; }
+};
+
+// Inclusive pixel rectangle; empty when x0 > x1.
+struct PixRect {
+    int32_t x0, y0, x1, y1;
+};
+
+// Pixels that the footprint of any fragment in the box [lo, hi] can reach
+// in a view. The box's corners are projected in fp64 (every product of two
+// fp32 values is exact there); a fragment's fp32 projection differs from the
+// exact value at its position by less than 2^-21 of the sum of the absolute
+// terms, which is largest at a corner, so the margin 2^-20 (B + |c| + 1)
+// covers it and the rounding of sx + c. A matrix or box that is not finite
+// reaches the whole view; a box whose depth is <= 0 everywhere reaches
+// nothing (such fragments are not drawn).
+__device__ PixRect chunk_rect(const float* M, float c, uint32_t k, uint32_t W, uint32_t H, float4 lo, float4 hi)
 {
-    const float* M = va.m[v];
+    PixRect r{1, 1, 0, 0};
+    if (!(lo.x <= hi.x)) return r;   // no drawable fragment
+    double smin[3] = {INFINITY, INFINITY, INFINITY}, smax[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double B[3] = {0.0, 0.0, 0.0};
+    for (int q = 0; q < 8; ++q) {
+        const double x = (q & 1) ? hi.x : lo.x, y = (q & 2) ? hi.y : lo.y, z = (q & 4) ? hi.z : lo.z;
+        for (int row = 0; row < 3; ++row) {
+            const double a0 = (double)M[4 * row] * x, a1 = (double)M[4 * row + 1] * y,
+                         a2 = (double)M[4 * row + 2] * z, a3 = (double)M[4 * row + 3];
+            const double sv = ((a0 + a1) + a2) + a3;
+            const double b = ((fabs(a0) + fabs(a1)) + fabs(a2)) + fabs(a3);
+            smin[row] = fmin(smin[row], sv);
+            smax[row] = fmax(smax[row], sv);
+            B[row] = fmax(B[row], b);
+        }
+    }
+    const double eps = 0x1p-20;
+    bool finite = true;
+    for (int row = 0; row < 3; ++row) finite = finite && isfinite(smin[row]) && isfinite(smax[row]) && isfinite(B[row]);
+    if (!finite) return PixRect{0, 0, (int32_t)W - 1, (int32_t)H - 1};
+    if (smax[2] + eps * (B[2] + 1.0) <= 0.0) return r;
+    const double cc = (double)c;
+    const double mx = eps * (B[0] + fabs(cc) + 1.0), my = eps * (B[1] + fabs(cc) + 1.0);
+    const double fx0 = floor(smin[0] - mx + cc), fx1 = floor(smax[0] + mx + cc) + (double)(k - 1);
+    const double fy0 = floor(smin[1] - my + cc), fy1 = floor(smax[1] + my + cc) + (double)(k - 1);
+    if (fx1 < 0.0 || fy1 < 0.0 || fx0 > (double)W - 1.0 || fy0 > (double)H - 1.0) return r;
+    r.x0 = fx0 < 0.0 ? 0 : (int32_t)fx0;
+    r.y0 = fy0 < 0.0 ? 0 : (int32_t)fy0;
+    r.x1 = fx1 > (double)W - 1.0 ? (int32_t)W - 1 : (int32_t)fx1;
+    r.y1 = fy1 > (double)H - 1.0 ? (int32_t)H - 1 : (int32_t)fy1;
+    return r;
+}
+
+__device__ __forceinline__ float wave_fmin(float v)
+{
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) v = fminf(v, __shfl_xor(v, d, kWave));
+    return v;
+}
+
+__device__ __forceinline__ float wave_fmax(float v)
+{
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) v = fmaxf(v, __shfl_xor(v, d, kWave));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_umin(uint32_t v)
+{
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)v, d, kWave);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_umax(uint32_t v)
+{
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)v, d, kWave);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t frag_total(const uint64_t* n_frag, uint64_t cap)
+{
+    const uint64_t nf = *n_frag;
+    return nf < cap ? nf : cap;
+}
+
+// Binning of one chunk: `pass` 0 counts into cnt, pass 1 writes into the
+// lists at the cursors. Lanes take the chunk's (scene, view) slots.
+template <bool kBatch>
+__device__ void bin_chunk(int pass, uint32_t ch, float4 lo, float4 hi, const TileArgs& ta, const ViewSrc<kBatch>& vs,
+                          uint32_t* __restrict__ cnt, uint32_t* __restrict__ cur, uint32_t* __restrict__ list_t,
+                          uint4* __restrict__ list_b, const uint32_t* __restrict__ off)
+{
+    if (!(lo.x <= hi.x)) return;
+    const uint32_t s_lo = __float_as_uint(lo.w), s_hi = __float_as_uint(hi.w);
+    const uint32_t n_pairs = (s_hi - s_lo + 1) * ta.n_views;
+    for (uint32_t p = __lane_id(); p < n_pairs; p += kWave) {
+        const uint32_t g = (s_lo + p / ta.n_views) * ta.n_views + p % ta.n_views;
+        const PixRect r = chunk_rect(vs.m(g), vs.c(g), vs.k(g), ta.width, ta.height, lo, hi);
+        if (r.x0 > r.x1 || r.y0 > r.y1) continue;
+        const uint32_t tx0 = (uint32_t)r.x0 / kTile, tx1 = (uint32_t)r.x1 / kTile;
+        const uint32_t ty0 = (uint32_t)r.y0 / kTile, ty1 = (uint32_t)r.y1 / kTile;
+        const uint32_t n = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+        if (n <= kTileBinMax) {
+            for (uint32_t ty = ty0; ty <= ty1; ++ty)
+                for (uint32_t tx = tx0; tx <= tx1; ++tx) {
+                    const uint32_t b = g * ta.per_view + ty * ta.nx + tx;
+                    if (pass == 0) {
+                        atomicAdd(cnt + b, 1u);
+                    } else {
+                        const uint32_t at = atomicAdd(cur + b, 1u);
+                        if (at < ta.cap_t) list_t[at] = ch;
+                    }
+                }
+        } else {
+            const uint32_t b = ta.n_tiles + g;
+            if (pass == 0) {
+                atomicAdd(cnt + b, 1u);
+            } else {
+                const uint32_t at = atomicAdd(cur + b, 1u) - off[ta.n_tiles];
+                if (at < ta.cap_b)
+                    list_b[at] = make_uint4(ch, (uint32_t)r.x0 | ((uint32_t)r.y0 << 16),
+                                            (uint32_t)r.x1 | ((uint32_t)r.y1 << 16), 0u);
+            }
+        }
+    }
+}
+
+template <int kMode, bool kBatch>
+__global__ void __launch_bounds__(kBlock)
+k_tile_count(const uint4* __restrict__ frag, const uint64_t* __restrict__ oct_key, const uint64_t* __restrict__ n_frag,
+             TileArgs ta, ViewArgs va, const float* __restrict__ vm, float4* __restrict__ box,
+             uint32_t* __restrict__ cnt)
+{
+    if (ta.cap_occ == 0) return;   // no table rows: nothing to draw
+    const uint64_t F = frag_total(n_frag, ta.cap_frag);
+    const uint64_t nch = (F + kChunk - 1) / kChunk;
+    const int lane = __lane_id();
+    const uint64_t n_waves = (uint64_t)gridDim.x * (kBlock / kWave);
+    const ViewSrc<kBatch> vs{va, vm};
+    const uint64_t kmask = ta.shift >= 64 ? ~0ull : (1ull << ta.shift) - 1ull;
+    for (uint64_t ch = uniform64((uint64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave); ch < nch;
+         ch += n_waves) {
+        const uint64_t f = ch * kChunk + lane;
+        bool ok = f < F;
+        const uint4 r = ok ? frag[f] : make_uint4(0, 0, 0, 0);
+        ok = ok && r.w < ta.cap_occ;
+        const uint64_t key = oct_key[ok ? r.w : 0];
+        const uint32_t scene = ta.shift >= 64 ? 0u : (uint32_t)(key >> ta.shift);
+        ok = ok && scene < ta.n_scenes;
+        float x, y, z;
+        frag_pos<kMode>(r, key & kmask, ta.cap_w, &x, &y, &z);
+        float4 lo, hi;
+        lo.x = wave_fmin(ok ? x : INFINITY);
+        lo.y = wave_fmin(ok ? y : INFINITY);
+        lo.z = wave_fmin(ok ? z : INFINITY);
+        hi.x = wave_fmax(ok ? x : -INFINITY);
+        hi.y = wave_fmax(ok ? y : -INFINITY);
+        hi.z = wave_fmax(ok ? z : -INFINITY);
+        lo.w = __uint_as_float(wave_umin(ok ? scene : 0xFFFFFFFFu));
+        hi.w = __uint_as_float(wave_umax(ok ? scene : 0u));
+        if (lane == 0) {
+            box[2 * ch] = lo;
+            box[2 * ch + 1] = hi;
+        }
+        bin_chunk<kBatch>(0, (uint32_t)ch, lo, hi, ta, vs, cnt, nullptr, nullptr, nullptr, nullptr);
+    }
+}
+
+template <bool kBatch>
+__global__ void __launch_bounds__(kBlock)
+k_tile_write(const uint64_t* __restrict__ n_frag, TileArgs ta, ViewArgs va, const float* __restrict__ vm,
+             const float4* __restrict__ box, uint32_t* __restrict__ cur, const uint32_t* __restrict__ off,
+             uint32_t* __restrict__ list_t, uint4* __restrict__ list_b)
+{
+    if (ta.cap_occ == 0) return;
+    const uint64_t F = frag_total(n_frag, ta.cap_frag);
+    const uint64_t nch = (F + kChunk - 1) / kChunk;
+    const uint64_t n_waves = (uint64_t)gridDim.x * (kBlock / kWave);
+    const ViewSrc<kBatch> vs{va, vm};
+    for (uint64_t ch = uniform64((uint64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave); ch < nch;
+         ch += n_waves)
+        bin_chunk<kBatch>(1, (uint32_t)ch, box[2 * ch], box[2 * ch + 1], ta, vs, nullptr, cur, list_t, list_b, off);
+}
+
+// Bin offsets: off[b] = sum of the counts of bins before b; the write pass's
+// cursors start there.
+struct StoreBinOff {
+    uint32_t* off;
+    uint32_t* cur;
+    __device__ void operator()(uint64_t i, uint32_t, uint32_t ex) const
+    {
+        off[i] = ex;
+        cur[i] = ex;
+    }
+};
+
+// Workgroup order: consecutive workgroups go to the 8 accelerator dies in
+// turn, so that the tiles of one die form one contiguous run of tile indices
+// (neighbouring tiles share chunks, which then meet in that die's cache).
+__device__ __forceinline__ uint32_t die_major(uint32_t b, uint32_t n)
+{
+    const uint32_t q = n / 8, r = n % 8, x = b % 8, j = b / 8;
+    return x < r ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
+}
+
+// The lanes' fragments of chunk ch, drawn into the z-tile at (X0, Y0) of
+// view slot g of scene `scene`.
+template <int kMode, bool kBatch>
+__device__ __forceinline__ void tile_chunk(uint32_t ch, uint64_t F, const uint4* __restrict__ frag,
+                                           const uint64_t* __restrict__ oct_key, const TileArgs& ta, const float* M,
+                                           float c, int32_t k, uint32_t scene, int32_t X0, int32_t Y0,
+                                           unsigned long long* zt)
+{
+    const uint64_t kmask = ta.shift >= 64 ? ~0ull : (1ull << ta.shift) - 1ull;
+    const uint64_t f = (uint64_t)ch * kChunk + __lane_id();
+    bool ok = f < F;
+    const uint4 r = ok ? frag[f] : make_uint4(0, 0, 0, 0);
+    ok = ok && r.w < ta.cap_occ;
+    const uint64_t key = oct_key[ok ? r.w : 0];
+    if (kBatch) ok = ok && (uint32_t)(key >> ta.shift) == scene;
+    float x, y, z;
+    frag_pos<kMode>(r, key & kmask, ta.cap_w, &x, &y, &z);
     const float sx = ((M[0] * x + M[1] * y) + M[2] * z) + M[3];
     const float sy = ((M[4] * x + M[5] * y) + M[6] * z) + M[7];
     const float d = ((M[8] * x + M[9] * y) + M[10] * z) + M[11];
-    const float fx = floorf(sx + va.c[v]), fy = floorf(sy + va.c[v]);
-    const bool ok = d > 0.0f && fx >= 0.0f && fx < (float)va.width && fy >= 0.0f &&
-                    fy < (float)va.height;
-    *off = ok ? (uint64_t)v * plane + (uint64_t)(uint32_t)fy * va.width + (uint32_t)fx : 0;
-    *zk = ((unsigned long long)__float_as_uint(d) << 32) | (unsigned long long)(uint32_t)i;
-    return ok;
-}
-
-template <int kMode>
-__global__ void __launch_bounds__(kBlock)
-k_splat(const uint4* __restrict__ frag, const uint64_t* __restrict__ oct_key,
-        const uint64_t* __restrict__ n_frag, uint64_t cap_frag, uint64_t cap_occ, uint32_t cap_w,
-        ViewArgs va, unsigned long long* __restrict__ zbuf)
-{
-    const uint64_t nf = *n_frag;
-    const uint64_t F = nf < cap_frag ? nf : cap_frag;
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    const uint64_t plane = (uint64_t)va.width * va.height;
-    if (cap_occ == 0) return;   // no table rows: nothing to draw
-    if (va.all_k1) {
-        // one pixel per view; two fragments per iteration, and the z-buffer
-        // reads of all their views issued before any atomic, so that the
-        // memory latencies overlap
-        for (uint64_t i0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i0 < F; i0 += 2 * stride) {
-            const uint64_t i1 = i0 + stride;
-            const bool h1 = i1 < F;
-            const uint4 r0 = frag[i0];
-            const uint4 r1 = h1 ? frag[i1] : make_uint4(0, 0, 0, 0);
-            const bool v0ok = r0.w < cap_occ, v1ok = h1 && r1.w < cap_occ;
-            const uint64_t k0 = oct_key[v0ok ? r0.w : 0];
-            const uint64_t k1 = oct_key[v1ok ? r1.w : 0];
-            float x0, y0, z0, x1, y1, z1;
-            frag_pos<kMode>(r0, k0, cap_w, &x0, &y0, &z0);
-            frag_pos<kMode>(r1, k1, cap_w, &x1, &y1, &z1);
-            for (uint32_t vb = 0; vb < va.n_views; vb += 2) {
-                uint64_t off[4];
-                unsigned long long zk[4], cur[4];
-                bool ok[4];
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const uint32_t v = vb + j;
-                    const bool vv = v < va.n_views;
-                    const uint32_t vc = vv ? v : 0;
-                    ok[2 * j] = pixel_of(va, vc, x0, y0, z0, i0, plane, &off[2 * j], &zk[2 * j]) && vv && v0ok;
-                    ok[2 * j + 1] = pixel_of(va, vc, x1, y1, z1, i1, plane, &off[2 * j + 1], &zk[2 * j + 1]) && vv && v1ok;
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) cur[q] = zbuf[ok[q] ? off[q] : 0];
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (ok[q] && zk[q] < cur[q]) atomicMin(zbuf + off[q], zk[q]);
-            }
+    if (!ok || !(d > 0.0f)) return;
+    const float fx = floorf(sx + c), fy = floorf(sy + c);
+    const unsigned long long zk = ((unsigned long long)__float_as_uint(d) << 32) | (unsigned long long)(uint32_t)f;
+    if (k == 1) {
+        if (fx >= 0.0f && fx < (float)ta.width && fy >= 0.0f && fy < (float)ta.height) {
+            const int32_t px = (int32_t)fx - X0, py = (int32_t)fy - Y0;
+            if ((uint32_t)px < (uint32_t)kTile && (uint32_t)py < (uint32_t)kTile)
+                atomicMin(zt + py * kTile + px, zk);
         }
         return;
     }
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < F; i += stride) {
-        const uint4 r = frag[i];
-        if (r.w >= cap_occ) continue;   // table row not stored
-        float x, y, z;
-        frag_pos<kMode>(r, oct_key[r.w], cap_w, &x, &y, &z);
-        for (uint32_t v = 0; v < va.n_views; ++v) {
-            const float* M = va.m[v];
-            const float sx = ((M[0] * x + M[1] * y) + M[2] * z) + M[3];
-            const float sy = ((M[4] * x + M[5] * y) + M[6] * z) + M[7];
-            const float d = ((M[8] * x + M[9] * y) + M[10] * z) + M[11];
-            if (!(d > 0.0f)) continue;
-            const float fx = floorf(sx + va.c[v]), fy = floorf(sy + va.c[v]);
-            if (!(fx > -1073741824.0f && fx < 1073741824.0f)) continue;
-            if (!(fy > -1073741824.0f && fy < 1073741824.0f)) continue;
-            const int32_t k = (int32_t)va.k[v];
-            int32_t xa = (int32_t)fx, ya = (int32_t)fy;
-            int32_t xb = xa + k, yb = ya + k;   // exclusive
-            xa = xa < 0 ? 0 : xa;
-            ya = ya < 0 ? 0 : ya;
-            xb = xb > (int32_t)va.width ? (int32_t)va.width : xb;
-            yb = yb > (int32_t)va.height ? (int32_t)va.height : yb;
-            const unsigned long long zk =
-                ((unsigned long long)__float_as_uint(d) << 32) | (unsigned long long)(uint32_t)i;
-            unsigned long long* zb = zbuf + (uint64_t)v * plane;
-            for (int32_t yy = ya; yy < yb; ++yy)
-                for (int32_t xx = xa; xx < xb; ++xx) {
-                    unsigned long long* p = zb + (uint64_t)yy * va.width + xx;
-                    if (zk < *p) atomicMin(p, zk);
-                }
+    if (!(fx > -1073741824.0f && fx < 1073741824.0f)) return;
+    if (!(fy > -1073741824.0f && fy < 1073741824.0f)) return;
+    int32_t xa = (int32_t)fx, ya = (int32_t)fy;
+    int32_t xb = xa + k, yb = ya + k;   // exclusive
+    xa = xa < X0 ? X0 : xa;
+    ya = ya < Y0 ? Y0 : ya;
+    const int32_t xe = X0 + kTile < (int32_t)ta.width ? X0 + kTile : (int32_t)ta.width;
+    const int32_t ye = Y0 + kTile < (int32_t)ta.height ? Y0 + kTile : (int32_t)ta.height;
+    xb = xb > xe ? xe : xb;
+    yb = yb > ye ? ye : yb;
+    for (int32_t yy = ya; yy < yb; ++yy)
+        for (int32_t xx = xa; xx < xb; ++xx) atomicMin(zt + (yy - Y0) * kTile + (xx - X0), zk);
+}
+
+template <int kMode, bool kBatch>
+__global__ void __launch_bounds__(kBlock)
+k_tile_splat(const uint4* __restrict__ frag, const uint64_t* __restrict__ oct_key, const uint64_t* __restrict__ n_frag,
+             TileArgs ta, ViewArgs va, const float* __restrict__ vm, const uint32_t* __restrict__ off,
+             const uint32_t* __restrict__ list_t, const uint4* __restrict__ list_b,
+             unsigned long long* __restrict__ zbuf, uint32_t* __restrict__ rgba, float* __restrict__ depth,
+             uint8_t* __restrict__ cov)
+{
+    __shared__ unsigned long long zt[kTilePix];
+    const uint32_t tile = uniform32(die_major(blockIdx.x, gridDim.x));
+    const uint32_t g = tile / ta.per_view, t = tile % ta.per_view;
+    const int32_t X0 = (int32_t)((t % ta.nx) * kTile), Y0 = (int32_t)((t / ta.nx) * kTile);
+    const uint32_t scene = g / ta.n_views;
+    for (int p = threadIdx.x; p < kTilePix; p += kBlock) zt[p] = ~0ull;
+    __syncthreads();
+    if (ta.cap_occ > 0) {
+        const uint64_t F = frag_total(n_frag, ta.cap_frag);
+        const ViewSrc<kBatch> vs{va, vm};
+        float M[12];
+#pragma unroll
+        for (int q = 0; q < 12; ++q) M[q] = vs.m(g)[q];
+        const float c = vs.c(g);
+        const int32_t k = (int32_t)vs.k(g);
+        const uint32_t wave = threadIdx.x / kWave;
+        const uint32_t e0 = off[tile], e1 = off[tile + 1] < ta.cap_t ? off[tile + 1] : ta.cap_t;
+        for (uint32_t e = e0 + wave; e < e1; e += kBlock / kWave)
+            tile_chunk<kMode, kBatch>(uniform32(list_t[e]), F, frag, oct_key, ta, M, c, k, scene, X0, Y0, zt);
+        const uint32_t base = off[ta.n_tiles];
+        const uint32_t b0 = off[ta.n_tiles + g] - base;
+        const uint32_t b1 = off[ta.n_tiles + g + 1] - base < ta.cap_b ? off[ta.n_tiles + g + 1] - base : ta.cap_b;
+        for (uint32_t e = b0 + wave; e < b1; e += kBlock / kWave) {
+            const uint4 be = list_b[e];
+            const int32_t rx0 = (int32_t)(be.y & 0xFFFFu), ry0 = (int32_t)(be.y >> 16);
+            const int32_t rx1 = (int32_t)(be.z & 0xFFFFu), ry1 = (int32_t)(be.z >> 16);
+            if (rx1 < X0 || rx0 >= X0 + kTile || ry1 < Y0 || ry0 >= Y0 + kTile) continue;   // wave-uniform
+            tile_chunk<kMode, kBatch>(uniform32(be.x), F, frag, oct_key, ta, M, c, k, scene, X0, Y0, zt);
+        }
+    }
+    __syncthreads();
+    const uint64_t plane = (uint64_t)ta.width * ta.height;
+    const uint32_t* f32 = (const uint32_t*)frag;
+    for (int p = threadIdx.x; p < kTilePix; p += kBlock) {
+        const int32_t X = X0 + (p % kTile), Y = Y0 + (p / kTile);
+        if (X >= (int32_t)ta.width || Y >= (int32_t)ta.height) continue;
+        const uint64_t o = (uint64_t)g * plane + (uint64_t)Y * ta.width + (uint32_t)X;
+        const unsigned long long zk = zt[p];
+        zbuf[o] = zk;
+        if (zk == ~0ull) {
+            rgba[o] = 0u;
+            depth[o] = 0.0f;
+            cov[o] = 0;
+        } else {
+            rgba[o] = f32[4ull * (uint32_t)zk + 1];
+            depth[o] = __uint_as_float((uint32_t)(zk >> 32));
+            cov[o] = 1;
         }
     }
 }
 
-// Batches: the fragment's scene is the high part of its key (key >> 3L);
-// it draws only into its scene's views, whose matrices are read from device
-// memory [scene][view][12]. When every fragment of a wave belongs to one
-// scene (the usual case: arrays are in key order) the scene index is made
-// wave-uniform so that the matrix reads become scalar loads.
-struct BatchArgs {
-    uint32_t n_scenes, n_views, width, height, k, shift;
-    float c;   // 1/2 - k/2
+// Workspace of the tiled splat.
+struct TileWs {
+    float4* box;       // [2 * chunks]: low and high corner, scene range in w
+    uint32_t* cnt;     // [bins + 1] counts
+    uint32_t* cur;     // [bins + 1] write cursors
+    uint32_t* off;     // [bins + 1] exclusive offsets
+    uint32_t* list_t;  // tile bins: chunk indices
+    uint4* list_b;     // view bins: chunk, rectangle
+    uint32_t* part;    // scan scratch
 };
 
-__device__ __forceinline__ void splat_batch_one(const float* __restrict__ vm, uint32_t scene,
-                                                const BatchArgs& a, float x, float y, float z, uint32_t i,
-                                                unsigned long long* __restrict__ zbuf)
+TileArgs tile_args(uint32_t n_scenes, uint32_t n_views, uint32_t W, uint32_t H)
 {
-    const uint64_t plane = (uint64_t)a.width * a.height;
-    const unsigned long long idx = (unsigned long long)i;
-    if (a.k == 1) {
-        for (uint32_t vb = 0; vb < a.n_views; vb += 4) {
-            uint64_t off[4];
-            unsigned long long zk[4], cur[4];
-            bool ok[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uint32_t v = vb + j;
-                ok[j] = false;
-                off[j] = 0;
-                zk[j] = 0;
-                if (v < a.n_views) {
-                    const uint64_t pl = (uint64_t)scene * a.n_views + v;
-                    const float* M = vm + pl * 12;
-                    const float sx = ((M[0] * x + M[1] * y) + M[2] * z) + M[3];
-                    const float sy = ((M[4] * x + M[5] * y) + M[6] * z) + M[7];
-                    const float d = ((M[8] * x + M[9] * y) + M[10] * z) + M[11];
-                    const float fx = floorf(sx + a.c), fy = floorf(sy + a.c);
-                    ok[j] = d > 0.0f && fx >= 0.0f && fx < (float)a.width && fy >= 0.0f && fy < (float)a.height;
-                    if (ok[j]) off[j] = pl * plane + (uint64_t)(uint32_t)fy * a.width + (uint32_t)fx;
-                    zk[j] = ((unsigned long long)__float_as_uint(d) << 32) | idx;
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) cur[j] = ok[j] ? zbuf[off[j]] : 0ull;
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (ok[j] && zk[j] < cur[j]) atomicMin(zbuf + off[j], zk[j]);
-        }
-        return;
-    }
-    for (uint32_t v = 0; v < a.n_views; ++v) {
-        const uint64_t pl = (uint64_t)scene * a.n_views + v;
-        const float* M = vm + pl * 12;
-        const float sx = ((M[0] * x + M[1] * y) + M[2] * z) + M[3];
-        const float sy = ((M[4] * x + M[5] * y) + M[6] * z) + M[7];
-        const float d = ((M[8] * x + M[9] * y) + M[10] * z) + M[11];
-        if (!(d > 0.0f)) continue;
-        const float fx = floorf(sx + a.c), fy = floorf(sy + a.c);
-        if (!(fx > -1073741824.0f && fx < 1073741824.0f)) continue;
-        if (!(fy > -1073741824.0f && fy < 1073741824.0f)) continue;
-        const int32_t k = (int32_t)a.k;
-        int32_t xa = (int32_t)fx, ya = (int32_t)fy;
-        int32_t xb = xa + k, yb = ya + k;   // exclusive
-        xa = xa < 0 ? 0 : xa;
-        ya = ya < 0 ? 0 : ya;
-        xb = xb > (int32_t)a.width ? (int32_t)a.width : xb;
-        yb = yb > (int32_t)a.height ? (int32_t)a.height : yb;
-        const unsigned long long zk = ((unsigned long long)__float_as_uint(d) << 32) | idx;
-        unsigned long long* zb = zbuf + pl * plane;
-        for (int32_t yy = ya; yy < yb; ++yy)
-            for (int32_t xx = xa; xx < xb; ++xx) {
-                unsigned long long* p = zb + (uint64_t)yy * a.width + xx;
-                if (zk < *p) atomicMin(p, zk);
-            }
-    }
+    TileArgs ta{};
+    ta.n_scenes = n_scenes;
+    ta.n_views = n_views;
+    ta.width = W;
+    ta.height = H;
+    ta.nx = (W + kTile - 1) / kTile;
+    ta.ny = (H + kTile - 1) / kTile;
+    ta.per_view = ta.nx * ta.ny;
+    ta.n_tiles = n_scenes * n_views * ta.per_view;
+    ta.shift = 64;
+    return ta;
 }
 
-__global__ void __launch_bounds__(kBlock)
-k_splat_batch(const uint4* __restrict__ frag, const uint64_t* __restrict__ oct_key,
-              const uint64_t* __restrict__ n_frag, uint64_t cap_frag, uint64_t cap_occ,
-              const float* __restrict__ vm, BatchArgs a, unsigned long long* __restrict__ zbuf)
+// Bound on the (chunk, view slot) pairs: a chunk's slots are the views of
+// the scenes its fragments belong to, and each scene boundary adds at most
+// one scene to one chunk.
+uint64_t pair_bound(uint64_t cap_frag, uint32_t n_scenes, uint32_t n_views)
 {
-    const uint64_t nf = *n_frag;
-    const uint64_t F = nf < cap_frag ? nf : cap_frag;
-    if (cap_occ == 0) return;
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    const uint64_t kmask = (1ull << a.shift) - 1ull;
-    // whole waves iterate together (stride and wave bases are multiples of
-    // 64), so the ballots below see every lane
-    const uint64_t Fw = (F + kWave - 1) & ~(uint64_t)(kWave - 1);
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < Fw; i += stride) {
-        bool act = i < F;
-        const uint4 r = act ? frag[i] : make_uint4(0, 0, 0, 0);
-        act = act && r.w < cap_occ;
-        const uint64_t key = act ? oct_key[r.w] : 0ull;
-        const uint32_t scene = (uint32_t)(key >> a.shift);
-        act = act && scene < a.n_scenes;
-        const uint64_t live = __ballot(act);
-        if (live == 0) continue;
-        float x, y, z;
-        frag_pos<FHV_POFL>(r, key & kmask, 0, &x, &y, &z);
-        const int leader = __ffsll((unsigned long long)live) - 1;
-        const uint32_t s0 = uniform32((uint32_t)__shfl((int)scene, leader, kWave));
-        const bool one_scene = __ballot(act && scene != s0) == 0;
-        if (!act) continue;
-        if (one_scene)
-            splat_batch_one(vm, s0, a, x, y, z, (uint32_t)i, zbuf);
+    const uint64_t chunks = (cap_frag + kChunk - 1) / kChunk;
+    return (chunks + n_scenes) * n_views;
+}
+
+TileWs carve_tiles(void* ws, uint64_t cap_frag, const TileArgs& ta, size_t* bytes)
+{
+    const uint64_t chunks = (cap_frag + kChunk - 1) / kChunk;
+    const uint64_t bins = (uint64_t)ta.n_tiles + (uint64_t)ta.n_scenes * ta.n_views;
+    const uint64_t pairs = pair_bound(cap_frag, ta.n_scenes, ta.n_views);
+    Carver c{(char*)ws, 0};
+    TileWs w;
+    w.box = c.take<float4>(2 * chunks + 2);
+    w.cnt = c.take<uint32_t>(bins + 1);
+    w.cur = c.take<uint32_t>(bins + 1);
+    w.off = c.take<uint32_t>(bins + 1);
+    w.list_t = c.take<uint32_t>(kTileBinMax * pairs + 1);
+    w.list_b = c.take<uint4>(pairs + 1);
+    w.part = c.take<uint32_t>(scan_scratch(bins + 1));
+    if (bytes) *bytes = c.off + 256;
+    return w;
+}
+
+template <bool kBatch>
+hipError_t tiles_launch(const Device& dev, const fhv_pofa* a, int mode, TileArgs ta, const ViewArgs& va,
+                        const float* vm, void* ws, uint64_t* zbuf, uint32_t* rgba, float* depth, uint8_t* cov,
+                        hipStream_t s)
+{
+    const TileWs w = carve_tiles(ws, a->cap_frag, ta, nullptr);
+    const uint64_t pairs = pair_bound(a->cap_frag, ta.n_scenes, ta.n_views);
+    ta.cap_t = (uint32_t)(kTileBinMax * pairs);
+    ta.cap_b = (uint32_t)pairs;
+    const uint64_t bins = (uint64_t)ta.n_tiles + (uint64_t)ta.n_scenes * ta.n_views;
+    const uint64_t chunks = (a->cap_frag + kChunk - 1) / kChunk;
+    uint64_t gb = (chunks + (kBlock / kWave) - 1) / (kBlock / kWave);
+    const uint64_t gmax = (uint64_t)dev.cus * 16;
+    gb = gb < 1 ? 1 : (gb > gmax ? gmax : gb);
+    hipError_t e;
+    {
+        ProfScope ps(dev, "splat.bin", s);
+        e = fill_u32(w.cnt, bins + 1, 0u, s);
+        if (e != hipSuccess) return e;
+        if (mode == FHV_PPFL)
+            k_tile_count<FHV_PPFL, kBatch><<<dim3((unsigned)gb), dim3(kBlock), 0, s>>>(
+                (const uint4*)a->frag, a->oct_key, a->n_frag, ta, va, vm, w.box, w.cnt);
         else
-            splat_batch_one(vm, scene, a, x, y, z, (uint32_t)i, zbuf);
+            k_tile_count<FHV_POFL, kBatch><<<dim3((unsigned)gb), dim3(kBlock), 0, s>>>(
+                (const uint4*)a->frag, a->oct_key, a->n_frag, ta, va, vm, w.box, w.cnt);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        e = scan<uint32_t>(LoadArray<uint32_t>{w.cnt}, StoreBinOff{w.off, w.cur}, bins + 1, w.part,
+                           (uint32_t*)nullptr, s);
+        if (e != hipSuccess) return e;
+        k_tile_write<kBatch><<<dim3((unsigned)gb), dim3(kBlock), 0, s>>>(a->n_frag, ta, va, vm, w.box, w.cur, w.off,
+                                                                       w.list_t, w.list_b);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-}
-
-__global__ void __launch_bounds__(kBlock)
-k_resolve(const unsigned long long* __restrict__ zbuf, const uint4* __restrict__ frag, uint64_t n,
-          uint32_t* __restrict__ rgba, float* __restrict__ depth, uint8_t* __restrict__ cov)
-{
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x; p < n; p += stride) {
-        const unsigned long long zk = zbuf[p];
-        if (zk == ~0ull) {
-            rgba[p] = 0u;
-            depth[p] = 0.0f;
-            cov[p] = 0;
-        } else {
-            const uint32_t id = (uint32_t)zk;
-            rgba[p] = frag[id].y;
-            depth[p] = __uint_as_float((uint32_t)(zk >> 32));
-            cov[p] = 1;
-        }
-    }
+    ProfScope ps(dev, "splat.splat", s);
+    if (mode == FHV_PPFL)
+        k_tile_splat<FHV_PPFL, kBatch><<<dim3(ta.n_tiles), dim3(kBlock), 0, s>>>(
+            (const uint4*)a->frag, a->oct_key, a->n_frag, ta, va, vm, w.off, w.list_t, w.list_b,
+            (unsigned long long*)zbuf, rgba, depth, cov);
+    else
+        k_tile_splat<FHV_POFL, kBatch><<<dim3(ta.n_tiles), dim3(kBlock), 0, s>>>(
+            (const uint4*)a->frag, a->oct_key, a->n_frag, ta, va, vm, w.off, w.list_t, w.list_b,
+            (unsigned long long*)zbuf, rgba, depth, cov);
+    return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t splat_launch(const Device& dev, const fhv_pofa* a, const fhv_capture_desc* d,
-                        const ViewArgs& va, uint64_t* zbuf, uint32_t* rgba, float* depth,
-                        uint8_t* cov, uint64_t max_frag, hipStream_t s)
+bool splat_fits(uint64_t cap_frag, uint32_t n_scenes, uint32_t n_views, uint32_t width, uint32_t height)
 {
-    const uint64_t n = (uint64_t)va.n_views * va.width * va.height;
-    const uint64_t gmax = (uint64_t)dev.cus * 16;
-    uint64_t gz = (n / 2 + kBlock - 1) / kBlock;
-    gz = gz < 1 ? 1 : (gz > gmax ? gmax : gz);
-    hipError_t e;
-    {
-        ProfScope ps(dev, "splat.zclear", s);
-        k_zclear<<<dim3((unsigned)gz), dim3(kBlock), 0, s>>>(zbuf, n);
-        e = hipGetLastError();
-    }
-    if (e != hipSuccess) return e;
-    const uint64_t smax = (uint64_t)dev.cus * dev.tune.splat_wg;
-    uint64_t gs = (max_frag + kBlock - 1) / kBlock;
-    gs = gs < 1 ? 1 : (gs > smax ? smax : gs);
-    {
-    ProfScope ps(dev, "splat.splat", s);
-    if (d->mode == FHV_PPFL)
-        k_splat<FHV_PPFL><<<dim3((unsigned)gs), dim3(kBlock), 0, s>>>(
-            (const uint4*)a->frag, a->oct_key, a->n_frag, a->cap_frag, a->cap_occ, d->width, va,
-            (unsigned long long*)zbuf);
-    else
-        k_splat<FHV_POFL><<<dim3((unsigned)gs), dim3(kBlock), 0, s>>>(
-            (const uint4*)a->frag, a->oct_key, a->n_frag, a->cap_frag, a->cap_occ, d->width, va,
-            (unsigned long long*)zbuf);
-    e = hipGetLastError();
-    }
-    if (e != hipSuccess) return e;
-    uint64_t gr = (n + kBlock - 1) / kBlock;
-    gr = gr < 1 ? 1 : (gr > gmax ? gmax : gr);
-    ProfScope ps(dev, "splat.resolve", s);
-    k_resolve<<<dim3((unsigned)gr), dim3(kBlock), 0, s>>>((const unsigned long long*)zbuf,
-                                                          (const uint4*)a->frag, n, rgba, depth, cov);
-    return hipGetLastError();
+    const uint64_t tiles = (uint64_t)n_scenes * n_views * ((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile);
+    const uint64_t bins = tiles + (uint64_t)n_scenes * n_views + 1;
+    const uint64_t entries = (kTileBinMax + 1) * pair_bound(cap_frag, n_scenes, n_views);
+    return tiles < (1ull << 31) && bins < (1ull << 31) && entries < (1ull << 32) &&
+           (cap_frag + kChunk - 1) / kChunk < (1ull << 32);
 }
 
-}  // namespace fhv
+size_t splat_ws_bytes(uint64_t cap_frag, uint32_t n_scenes, uint32_t n_views, uint32_t width, uint32_t height)
+{
+    size_t b = 0;
+    carve_tiles(nullptr, cap_frag, tile_args(n_scenes, n_views, width, height), &b);
+    return b;
+}
 
-namespace fhv {
+hipError_t splat_launch(const Device& dev, const fhv_pofa* a, const fhv_capture_desc* d, const ViewArgs& va,
+                        uint64_t* zbuf, uint32_t* rgba, float* depth, uint8_t* cov, void* ws, hipStream_t s)
+{
+    TileArgs ta = tile_args(1, va.n_views, va.width, va.height);
+    ta.cap_w = d->width;
+    ta.cap_frag = a->cap_frag;
+    ta.cap_occ = a->cap_occ;
+    return tiles_launch<false>(dev, a, (int)d->mode, ta, va, nullptr, ws, zbuf, rgba, depth, cov, s);
+}
 
 hipError_t splat_batch_launch(const Device& dev, const fhv_pofa* a, uint32_t levels, const BatchViews& bv,
-                              uint64_t* zbuf, uint32_t* rgba, float* depth, uint8_t* cov,
-                              uint64_t max_frag, hipStream_t s)
+                              uint64_t* zbuf, uint32_t* rgba, float* depth, uint8_t* cov, void* ws, hipStream_t s)
 {
-    const uint64_t n = (uint64_t)bv.n_scenes * bv.n_views * bv.width * bv.height;
-    const uint64_t gmax = (uint64_t)dev.cus * 16;
-    uint64_t gz = (n / 2 + kBlock - 1) / kBlock;
-    gz = gz < 1 ? 1 : (gz > gmax ? gmax : gz);
-    hipError_t e;
-    {
-        ProfScope ps(dev, "splat.zclear", s);
-        k_zclear<<<dim3((unsigned)gz), dim3(kBlock), 0, s>>>(zbuf, n);
-        e = hipGetLastError();
-    }
-    if (e != hipSuccess) return e;
-    BatchArgs ba;
-    ba.n_scenes = bv.n_scenes;
-    ba.n_views = bv.n_views;
-    ba.width = bv.width;
-    ba.height = bv.height;
-    ba.k = bv.k;
-    ba.shift = 3 * levels;
-    ba.c = 0.5f - 0.5f * (float)bv.k;
-    const uint64_t smax = (uint64_t)dev.cus * dev.tune.splat_wg;
-    uint64_t gs = (max_frag + kBlock - 1) / kBlock;
-    gs = gs < 1 ? 1 : (gs > smax ? smax : gs);
-    {
-        ProfScope ps(dev, "splat.splat", s);
-        k_splat_batch<<<dim3((unsigned)gs), dim3(kBlock), 0, s>>>(
-            (const uint4*)a->frag, a->oct_key, a->n_frag, a->cap_frag, a->cap_occ, bv.m, ba,
-            (unsigned long long*)zbuf);
-        e = hipGetLastError();
-    }
-    if (e != hipSuccess) return e;
-    uint64_t gr = (n + kBlock - 1) / kBlock;
-    gr = gr < 1 ? 1 : (gr > gmax ? gmax : gr);
-    ProfScope ps(dev, "splat.resolve", s);
-    k_resolve<<<dim3((unsigned)gr), dim3(kBlock), 0, s>>>((const unsigned long long*)zbuf,
-                                                          (const uint4*)a->frag, n, rgba, depth, cov);
-    return hipGetLastError();
+    TileArgs ta = tile_args(bv.n_scenes, bv.n_views, bv.width, bv.height);
+    ta.shift = 3 * levels;
+    ta.cap_frag = a->cap_frag;
+    ta.cap_occ = a->cap_occ;
+    ViewArgs va;
+    memset(&va, 0, sizeof(va));
+    va.n_views = bv.n_views;
+    va.width = bv.width;
+    va.height = bv.height;
+    va.k[0] = bv.k;
+    va.c[0] = 0.5f - 0.5f * (float)bv.k;
+    return tiles_launch<true>(dev, a, FHV_POFL, ta, va, bv.m, ws, zbuf, rgba, depth, cov, s);
 }
 
 }  // namespace fhv

@@ -79,7 +79,7 @@ class KernelStat_(C.Structure):
 
 
 EXPORTS = ["fhv_create", "fhv_destroy", "fhv_status_str", "fhv_capture_workspace", "fhv_capture",
-           "fhv_compact_workspace", "fhv_compact", "fhv_splat", "fhv_profile_begin",
+           "fhv_compact_workspace", "fhv_compact", "fhv_splat_workspace", "fhv_splat", "fhv_profile_begin",
            "fhv_profile_end", "fhv_unet_param_count", "fhv_fill_workspace", "fhv_fill",
            "fhv_fill_train_step", "fhv_get_tuning", "fhv_set_tuning", "fhv_batch_workspace",
            "fhv_batch_run", "fhv_probe", "fhv_raycast_workspace", "fhv_raycast", "fhv_capture_arrays_workspace",
@@ -109,8 +109,10 @@ def lib():
         L.fhv_compact_workspace.restype = C.c_size_t
         L.fhv_compact.argtypes = [P, C.POINTER(Lists_), C.POINTER(Desc_), C.POINTER(Pofa_), P,
                                   C.c_size_t, P]
+        L.fhv_splat_workspace.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32]
+        L.fhv_splat_workspace.restype = C.c_size_t
         L.fhv_splat.argtypes = [P, C.POINTER(Pofa_), C.POINTER(Desc_), C.POINTER(View_), C.c_uint32,
-                                P, P, P, P, P]
+                                P, P, P, P, P, C.c_size_t, P]
         L.fhv_unet_param_count.argtypes = [C.c_uint32]
         L.fhv_unet_param_count.restype = C.c_uint64
         L.fhv_fill_workspace.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int]
@@ -339,18 +341,28 @@ def views_struct(views) -> C.Array:
     return arr
 
 
-def splat(arrays: Pofa, d: Desc_, views, out: Images | None = None, vstruct=None) -> Images:
+def splat_workspace(cap_frag: int, n_views: int, width: int, height: int) -> int:
+    return int(lib().fhv_splat_workspace(cap_frag, n_views, width, height))
+
+
+def splat(arrays: Pofa, d: Desc_, views, out: Images | None = None, vstruct=None,
+          ws: torch.Tensor | None = None) -> Images:
     """fhv_splat of all views (at most 32 per call; more are split)."""
     W, H = views[0].width, views[0].height
     if out is None:
         out = alloc_images(len(views), W, H, device=arrays.frag.device)
+    need = splat_workspace(arrays.cap_frag, min(len(views), 32), W, H)
+    if need == 0:
+        raise FhvError("fhv_splat_workspace: sizes out of range")
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=arrays.frag.device)
     ps = arrays.struct()
     for v0 in range(0, len(views), 32):
         vs = views[v0:v0 + 32]
         arr = vstruct if (vstruct is not None and len(views) <= 32) else views_struct(vs)
         _check(lib().fhv_splat(ctx(), C.byref(ps), C.byref(d), arr, len(vs),
                                _ptr(out.zbuf[v0:]), _ptr(out.rgba[v0:]), _ptr(out.depth[v0:]),
-                               _ptr(out.cov[v0:]), _stream()), "fhv_splat")
+                               _ptr(out.cov[v0:]), _ptr(ws), ws.numel(), _stream()), "fhv_splat")
     return out
 
 
@@ -431,12 +443,13 @@ def profile_end() -> dict[str, tuple[int, float]]:
 
 
 FHV_PROBE_COPY, FHV_PROBE_ADD_U32, FHV_PROBE_EXCH_U32, FHV_PROBE_MIN_U64 = 0, 1, 2, 3
+FHV_PROBE_READ, FHV_PROBE_WRITE = 4, 5
 
 
 def probe(kind: int, buf: torch.Tensor, line: int = 128, passes: int = 1):
     """One ceiling probe over `buf` (device tensor, any dtype) on torch's
-    current stream: a copy of its first half onto its second, or one
-    atomic per `line`-byte line and pass."""
+    current stream: a copy of its first half onto its second, a read or a
+    write of every byte, or one atomic per `line`-byte line and pass."""
     nbytes = buf.numel() * buf.element_size()
     _check(lib().fhv_probe(ctx(), kind, _ptr(buf), nbytes, line, passes, _stream()), "fhv_probe")
 

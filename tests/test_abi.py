@@ -82,7 +82,7 @@ def test_bad_arguments_rejected_before_launch(F):
     ls = F.Lists_(None, 64, None, 0, None, None)
     assert L.fhv_capture(None, C.byref(m), C.byref(d), C.byref(ls), None, 0, None) == -1
     assert L.fhv_compact(None, C.byref(ls), C.byref(d), None, None, 0, None) == -1
-    assert L.fhv_splat(None, None, C.byref(d), None, 0, None, None, None, None, None) == -1
+    assert L.fhv_splat(None, None, C.byref(d), None, 0, None, None, None, None, None, 0, None) == -1
     assert L.fhv_create(None, 0) == -1
 
 

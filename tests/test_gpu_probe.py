@@ -34,6 +34,21 @@ def test_probe_copy(F):
     assert np.array_equal(out[n // 2:], h[: n // 2])
 
 
+def test_probe_read_and_write(F):
+    """The read probe leaves a 0xFF buffer as it was; the write probe sets
+    every byte to 0xFF and nothing beyond."""
+    import torch
+    n = (5 << 20) + 48            # bytes, a multiple of 16 that is not a power of two
+    buf = torch.full((n + 64,), 0x11, dtype=torch.uint8, device="cuda")
+    F.probe(F.FHV_PROBE_WRITE, buf[:n])
+    torch.cuda.synchronize()
+    out = buf.cpu().numpy()
+    assert np.all(out[:n] == 0xFF) and np.all(out[n:] == 0x11)
+    F.probe(F.FHV_PROBE_READ, buf[:n])
+    torch.cuda.synchronize()
+    assert np.array_equal(buf.cpu().numpy(), out)
+
+
 @pytest.mark.parametrize("line,n_lines,passes", [(128, 1000, 3), (8, 5000, 2), (4096, 17, 5),
                                                  (128, 600_000, 2)])
 def test_probe_atomics(F, line, n_lines, passes):
