@@ -214,14 +214,21 @@ def forward(theta, x, levels: int = 4, base: int = 32, round_acts: bool = False)
     return out, acts
 
 
-def backward(theta, acts, dout, levels: int = 4, base: int = 32, round_grads: bool = False):
+def backward(theta, acts, dout, levels: int = 4, base: int = 32, round_grads: bool = False,
+             abs_terms: bool = False):
     """Gradient of sum(dout * output) w.r.t. the flat parameter vector, by
     the chain rule through the layers in reverse order. round_grads=True
-    rounds every stored activation gradient to bfloat16 as the GPU does."""
+    rounds every stored activation gradient to bfloat16 as the GPU does.
+
+    abs_terms=True also returns, per parameter, the sum of the absolute
+    values of the terms its gradient adds up (|dz|^T |x| for a weight,
+    sum |dz| for a bias, with the same dz and x): the scale of the rounding
+    error any order of summation can make in it."""
     rnd = bf16_round if round_grads else (lambda a: a)
     P = unpack(theta, levels, base)
     nl = len(P)
     grads = [None] * nl
+    absg = [None] * nl
     # layer indices
     enc = [(2 * l, 2 * l + 1) for l in range(levels)]
     dec = {}
@@ -232,6 +239,9 @@ def backward(theta, acts, dout, levels: int = 4, base: int = 32, round_grads: bo
     hidx = i
     hlast = acts["d0_1"] if levels > 1 else acts[f"e{levels - 1}_1"]
     grads[hidx] = (dout.reshape(-1, 3).T @ hlast.reshape(-1, hlast.shape[-1]), dout.sum((0, 1, 2)))
+    if abs_terms:
+        absg[hidx] = (np.abs(dout.reshape(-1, 3)).T @ np.abs(hlast.reshape(-1, hlast.shape[-1])),
+                      np.abs(dout).sum((0, 1, 2)))
     g = rnd(dout @ P[hidx][0])
     skip_g = {}
     for l in range(levels - 1):             # decoder, top level first
@@ -241,12 +251,17 @@ def backward(theta, acts, dout, levels: int = 4, base: int = 32, round_grads: bo
             xin = acts[f"cat{l}"] if s == 0 else acts[f"d{l}_0"]
             gx, dw, db = conv3_bwd(xin, P[li][0], g * (y > 0))
             grads[li] = (dw, db)
+            if abs_terms:
+                absg[li] = conv3_abs_terms(xin, np.abs(g * (y > 0)), P[li][0].shape)
             g = rnd(gx)
         cu = P[it][0].shape[2]
         g_up, skip_g[l] = g[..., :cu], g[..., cu:]
         hin = acts[f"e{levels - 1}_1"] if l == levels - 2 else acts[f"d{l + 1}_1"]
         gx, dw, db = convT2_bwd(hin, P[it][0], g_up)
         grads[it] = (dw, db)
+        if abs_terms:
+            _, aw, ab = convT2_bwd(np.abs(hin), np.abs(P[it][0]), np.abs(g_up))
+            absg[it] = (aw, ab)
         g = rnd(gx)
     for l in reversed(range(levels)):       # encoder, deepest level first
         if l < levels - 1:
@@ -257,8 +272,21 @@ def backward(theta, acts, dout, levels: int = 4, base: int = 32, round_grads: bo
             xin = (acts["x"] if l == 0 else acts[f"p{l - 1}"][0]) if s == 0 else acts[f"e{l}_0"]
             gx, dw, db = conv3_bwd(xin, P[li][0], g * (y > 0))
             grads[li] = (dw, db)
+            if abs_terms:
+                absg[li] = conv3_abs_terms(xin, np.abs(g * (y > 0)), P[li][0].shape)
             g = rnd(gx)
-    return np.concatenate([np.concatenate([dw.reshape(-1), db.reshape(-1)]) for dw, db in grads])
+    flat = lambda gs: np.concatenate([np.concatenate([dw.reshape(-1), db.reshape(-1)]) for dw, db in gs])
+    return (flat(grads), flat(absg)) if abs_terms else flat(grads)
+
+
+def conv3_abs_terms(x, adz, wshape):
+    """|dz|^T |patches| and sum |dz|: the absolute term sums of a 3x3
+    convolution's weight and bias gradients."""
+    N, H, W, C = x.shape
+    co = wshape[0]
+    d = adz.reshape(-1, co)
+    P = np.abs(patches3(x)).reshape(N * H * W, 9 * C)
+    return (d.T @ P).reshape(wshape), d.sum(0)
 
 
 def loss_and_grad(theta, x, rgb_splat, rgb_target, levels: int = 4, base: int = 32,

@@ -159,3 +159,22 @@ def test_parameter_count_of_the_full_network():
     # + 590080; decoder 131200 + 295040 + 147584, 32832 + 73792 + 36928,
     # 8224 + 18464 + 9248; head 99
     assert U.n_params(4, 32) == 1_926_531
+
+
+def test_absolute_term_sums_bound_the_gradient():
+    """The absolute term sums bound every gradient element (triangle
+    inequality) and equal it when every factor is non-negative: then no
+    term cancels another."""
+    rng = np.random.default_rng(3)
+    levels = 2
+    th = U.init_params(2, levels) + 0.05 * rng.standard_normal(U.n_params(levels))
+    x = rng.random((1, 8, 8, U.IN_CH))
+    out, acts = U.forward(th, x, levels)
+    g, t = U.backward(th, acts, rng.standard_normal(out.shape), levels, abs_terms=True)
+    assert np.all(np.abs(g) <= t * (1 + 1e-12))
+    # one level, non-negative weights, inputs and output gradient
+    th1 = np.abs(U.init_params(4, 1)) + 0.01
+    x1 = rng.random((1, 6, 6, U.IN_CH))
+    out1, acts1 = U.forward(th1, x1, 1)
+    g1, t1 = U.backward(th1, acts1, rng.random(out1.shape), 1, abs_terms=True)
+    assert np.allclose(g1, t1, rtol=1e-12, atol=0)
