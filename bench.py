@@ -58,38 +58,68 @@ def host_info():
 
 
 def algorithmic_bytes(F: int, n_occ: int, n_tri: int, n_head: int, n_views: int, pix: int,
-                      key_bytes: int = 4, link: bool = True) -> dict:
-    """Bytes each kernel scope must move at minimum, per launch (one step).
+                      key_bytes: int = 4, link: bool = True, covered: int | None = None) -> dict:
+    """Bytes each kernel scope must read and write at minimum, per launch
+    (one step), as (read, written).
 
     capture.reset    4 per head entry written (8 for the counter alone when
                      no lists are linked)
-    capture.setup    3 x (12 + 4) vertex bytes + 12 index bytes + 128 record
-                     + 8 tile count per triangle
+    capture.setup    3 x (12 + 4) vertex bytes + 12 index bytes read, 128
+                     record + 8 tile count written per triangle
     capture.raster   per fragment: 16 record + key (4, or 8 beyond 2^32
-                     keys) written, 8 for the head exchange (read + write
-                     of 4) when linking; 128 per triangle record
+                     keys) written, 4 read and 4 written by the head exchange
+                     when linking; 128 per triangle record read
     compact.hist     one key read per fragment
     compact.scatter  per fragment: 16 record + key read, 16 staged record
                      written
     compact.brick    per fragment 16 read + 16 written; 16 per table row
-    splat.zclear     8 per z-buffer pixel
-    splat.splat      16 per fragment read + 8 per table key read
-    splat.resolve    8 z read + 4 colour + 4 depth + 1 coverage written per
-                     pixel, 4 per covered pixel gathered (counted for all)
+                     written
+    splat.bin        the chunk boxes: 16 per fragment and 8 per table key
+                     read (the arrays once)
+    splat.splat      the tiles: 16 per fragment and 8 per table key read
+                     once; per pixel and view 8 key + 4 colour + 4 depth + 1
+                     coverage written and the winner's 4-byte colour read
+                     (covered pixels; all pixels when `covered` is None)
     """
     n_brick = (n_head + 511) // 512
+    cov = n_views * pix if covered is None else covered
     return {
-        "capture.reset": 4 * n_head if link else 8,
-        "capture.setup": n_tri * (3 * 16 + 12 + 128 + 8),
-        "capture.raster": F * (16 + key_bytes + (8 if link else 0)) + 128 * n_tri,
-        "compact.hist": key_bytes * F,
-        "compact.scan": 2 * 2 * 4 * n_brick,
-        "compact.scatter": F * (16 + key_bytes + 16),
-        "compact.brick": F * 32 + 16 * n_occ,
-        "splat.zclear": 8 * n_views * pix,
-        "splat.splat": 16 * F + 8 * n_occ,
-        "splat.resolve": n_views * pix * (8 + 4 + 4 + 1 + 4),
+        "capture.reset": (0, 4 * n_head if link else 8),
+        "capture.setup": (n_tri * (3 * 16 + 12), n_tri * (128 + 8)),
+        "capture.raster": (128 * n_tri + (4 * F if link else 0), F * (16 + key_bytes + (4 if link else 0))),
+        "compact.hist": (key_bytes * F, 0),
+        "compact.scan": (2 * 4 * n_brick, 2 * 4 * n_brick),
+        "compact.scatter": (F * (16 + key_bytes), 16 * F),
+        "compact.brick": (16 * F, 16 * F + 16 * n_occ),
+        "splat.bin": (16 * F + 8 * n_occ, 0),
+        "splat.splat": (16 * F + 8 * n_occ + 4 * cov, n_views * pix * (8 + 4 + 4 + 1)),
     }
+
+
+def survey_bytes(F: int, n_occ: int, levels: int, n_views: int, pix: int) -> dict:
+    """The algorithmic bytes of compaction and splat as the method's
+    measurement defines them: B_c = 16F read + 16F written + 16 per table
+    row + 8 per brick of 512 keys (counts and offsets); per view B_s = 16F/V
+    (the fragment stream shared by the views) + 8 WH clear + 8 WH resolve
+    read + 4 WH colour written + 4 WH winner gathered."""
+    b_c = 32 * F + 16 * n_occ + 8 * 8 ** max(levels - 3, 0)
+    b_s = 16 * F + n_views * 24 * pix
+    return {"B_c": b_c, "B_s": b_s}
+
+
+def compact_splat_fracs(algo: dict, F: int, n_occ: int, levels: int, n_views: int, pix: int,
+                        compact_ms: float, splat_ms: float) -> dict:
+    """Compaction plus splat against the HBM peak: with the method's
+    algorithmic bytes B_c + sum of B_s (the headline figure), and with the
+    bytes these kernels must move as built (`impl`)."""
+    sb = survey_bytes(F, n_occ, levels, n_views, pix)
+    t = (compact_ms + splat_ms) * 1e-3
+    impl = sum(r + w for k, (r, w) in algo.items() if k.startswith(("compact.", "splat.")))
+    return {"compact_splat_hbm_frac": (sb["B_c"] + sb["B_s"]) / t / 1e9 / HBM_PEAK_GBS,
+            "compact_splat_bytes": {"B_c": sb["B_c"], "B_s": sb["B_s"], "impl": impl,
+                                    "impl_hbm_frac": impl / t / 1e9 / HBM_PEAK_GBS,
+                                    "splat_hbm_frac": sb["B_s"] / (splat_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                    "compact_hbm_frac": sb["B_c"] / (compact_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
 
 # kernel-name prefixes behind each timed scope (POFL mode)
@@ -97,8 +127,8 @@ SCOPE_KERNELS = {
     "fill.conv": ("k_conv",),
     "capture.setup": ("k_setup",), "capture.raster": ("k_raster",),
     "compact.hist": ("k_hist",), "compact.scatter": ("k_scatter",),
-    "compact.brick": ("k_brick_wave", "k_brick"), "splat.zclear": ("k_zclear",),
-    "splat.splat": ("k_splat",), "splat.resolve": ("k_resolve",),
+    "compact.brick": ("k_brick_wave", "k_brick"),
+    "splat.bin": ("k_tile_count", "k_tile_write"), "splat.splat": ("k_tile_splat",),
     "ray.occupancy": ("k_occ_build",), "ray.cast": ("k_raycast",),
 }
 
@@ -247,55 +277,46 @@ def unet_flops_per_pixel(levels: int = 4, training: bool = False) -> float:
     return 3 * fwd - first if training else fwd
 
 
-def learned_fill_report(torch, fhv, scenes, train_steps: int = 600, eval_seeds: int = 10):
-    """Train the fill on splats of separate scenes (octree depth 8, 1080p,
-    random orbit angles) against reference renders of the same views (the
-    library's per-pixel capture of the triangles, nearest fragment kept),
-    then compare PSNR of fill and plain splat on held-out scenes (seeds
-    0..eval_seeds-1, which no training scene uses) at 30 and 60 degrees.
+def learned_fill_report(torch, fhv, scenes, n_crops: int = 20000, eval_seeds: int = 10):
+    """Train the fill on splats of the benchmark's scene family (seeds
+    100-115, 1080p, two random orbit views per scene at octree depths 9 and
+    8) against reference renders of the same views (the library's per-pixel
+    capture of the triangles, nearest fragment kept; the tests check it
+    against the oracle's direct raster), on n_crops distinct random 256x256
+    crops in batches of 8; then compare PSNR of fill and plain splat on
+    held-out scenes (seeds 0..eval_seeds-1, which no training scene uses) at
+    30 and 60 degrees, at depth 9 (the timed step's configuration) and 8.
     Returns the report and the trained model."""
     import numpy as np
     from paper_2211_15460_amd import learned_fill as LF
-    L, W, H = 8, 1920, 1080
     rng = np.random.default_rng(0)
-    srcs, tgts = [], []
-    for s in range(4):
-        mesh = LF.training_scene(100 + s)
-        views = [scenes.cube_view(float(t), L, W, H) for t in rng.uniform(0, 90, 4)]
-        img, _ = LF.render_splats(mesh, L, views)
-        srcs.append(img)
-        tgts.append(torch.cat([LF.reference_render(mesh, L, v) for v in views]))
-    data = LF.SplatImages(*(torch.cat([getattr(i, f) for i in srcs]) for f in ("rgba", "depth", "cov")))
-    target = torch.cat(tgts)
+    t0 = time.perf_counter()
+    ts = LF.training_set(LF.gpu_reference, range(100, 116), (9, 8), 2, rng)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
     model = LF.FillModel(4, 0)
-    # crops are cut before the timed loop, which then runs without host syncs
-    batches = [LF.random_crops(data, target, 8, 256, rng) for _ in range(64)]
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
-    for st in range(1, train_steps + 1):
-        model.train_step(*batches[st % len(batches)], LF.lr_at(st, train_steps, 1e-3, 5e-5))
+    steps = LF.train(model, ts, n_crops, 8, 256, rng)
     e1.record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / train_steps
-    res = {"train_steps": train_steps, "batch": "8 x 256 x 256", "train_ms_per_step": ms,
+    ms = e0.elapsed_time(e1) / steps
+    res = {"crops": n_crops, "train_steps": steps, "batch": "8 x 256 x 256",
+           "train_views": len(ts.views), "train_scenes": "pofl_scene seeds 100-115, depths 9 and 8",
+           "data_s": t_data, "train_ms_per_step": ms,
            "train_tflops": unet_flops_per_pixel(4, True) * 8 * 256 * 256 / (ms * 1e-3) / 1e12,
-           "octree_levels": L, "eval": []}
-    for seed in range(eval_seeds):
-        mesh = LF.training_scene(seed)
-        for th in (30.0, 60.0):
-            v = scenes.cube_view(th, L, W, H)
-            img, _ = LF.render_splats(mesh, L, [v])
-            ref = LF.reference_render(mesh, L, v)
-            out = model.fill(img)
-            res["eval"].append({"seed": seed, "theta": th, "psnr_splat_db": LF.psnr_rgb(img.rgba, ref),
-                                "psnr_fill_db": LF.psnr_rgb(out, ref)})
-    gain = np.array([e["psnr_fill_db"] - e["psnr_splat_db"] for e in res["eval"]])
-    res["margin_db"] = float(gain.min())
-    res["gain_db"] = {"mean": float(gain.mean()), "std": float(gain.std()), "min": float(gain.min()),
-                      "max": float(gain.max()), "n": int(gain.size),
-                      "over": f"held-out scenes of seeds 0..{eval_seeds - 1} at 30 and 60 degrees"}
-    res["reference"] = "library per-pixel capture of the triangles in the view, nearest fragment"
+           "what": "train step time includes cutting the batch's crops on the device"}
+    del ts
+    for L, key in ((9, "eval"), (8, "eval_depth8")):
+        ev = LF.evaluate(model, LF.gpu_reference, range(eval_seeds), L)
+        gain = np.array([e["psnr_fill_db"] - e["psnr_splat_db"] for e in ev])
+        res[key] = {"levels": L, "views": ev, "margin_db": float(gain.min()),
+                    "gain_db": {"mean": float(gain.mean()), "std": float(gain.std()), "min": float(gain.min()),
+                                "max": float(gain.max()), "n": int(gain.size),
+                                "over": f"held-out scenes of seeds 0..{eval_seeds - 1} at 30 and 60 degrees"}}
+    res["reference"] = ("library per-pixel capture of the triangles in the view, nearest fragment kept "
+                        "(tests/test_learned_fill_psnr.py checks it against the oracle's direct raster)")
     return res, model
 
 
@@ -433,8 +454,10 @@ def kernel_table(prof: dict, algo: dict) -> dict:
     kernels = {}
     for name, (launches, tot) in prof.items():
         avg = tot / max(launches, 1)
-        b = algo.get(name, 0)
+        r, w = algo.get(name, (0, 0))
+        b = r + w
         kernels[name] = {"avg_ms": round(avg, 5), "launches": launches, "algo_bytes": b,
+                         "read_bytes": r, "write_bytes": w,
                          "gbs": round(b / (avg * 1e-3) / 1e9, 1) if avg > 0 and b else None}
     return kernels
 
@@ -459,7 +482,9 @@ def ceilings(torch, fhv, reps: int = 5) -> dict:
     stream; buffers are reset before every launch, outside the timing."""
     big = torch.empty(2 << 30, dtype=torch.uint8, device="cuda")
     small = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
-    cases = [("copy", fhv.FHV_PROBE_COPY, big, 128, 1, "probe.copy")]
+    cases = [("copy", fhv.FHV_PROBE_COPY, big, 128, 1, "probe.copy"),
+             ("read", fhv.FHV_PROBE_READ, big, 128, 1, "probe.read"),
+             ("write", fhv.FHV_PROBE_WRITE, big, 128, 1, "probe.write")]
     for op, kind, scope in (("add_u32", fhv.FHV_PROBE_ADD_U32, "probe.add_u32"),
                             ("exch_u32", fhv.FHV_PROBE_EXCH_U32, "probe.exch_u32"),
                             ("min_u64", fhv.FHV_PROBE_MIN_U64, "probe.min_u64")):
@@ -480,8 +505,8 @@ def ceilings(torch, fhv, reps: int = 5) -> dict:
             if r > 0:
                 tot += prof[scope][1]
         ms = tot / reps
-        if kind == fhv.FHV_PROBE_COPY:
-            res["copy_gbs"] = buf.numel() / (ms * 1e-3) / 1e9
+        if kind in (fhv.FHV_PROBE_COPY, fhv.FHV_PROBE_READ, fhv.FHV_PROBE_WRITE):
+            res[name + "_gbs"] = buf.numel() / (ms * 1e-3) / 1e9
         else:
             res.setdefault("atomics_g_per_s", {})[name] = buf.numel() // line * passes / (ms * 1e-3) / 1e9
     del big, small
@@ -495,7 +520,8 @@ def ceilings(torch, fhv, reps: int = 5) -> dict:
     ms = timed(torch, lambda: torch.matmul(ga, gb), 10)
     res["gemm_bf16_tflops"] = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
     del ga, gb
-    res["note"] = ("copy: GB/s read+written over 2 GiB; atomics: G ops/s; hbm = 2 GiB buffer, one pass; "
+    res["note"] = ("copy: GB/s read+written over 2 GiB; read, write: GB/s of a read-only and a write-only "
+                   "stream over 2 GiB; atomics: G ops/s; hbm = 2 GiB buffer, one pass; "
                    "llc = 64 MiB buffer, 32 passes; one atomic per 128-B line, or per 8-B word (dense); "
                    "exch returns its value; gemm: the vendor library's bf16 matmul, 8192^3, TFLOP/s")
     return res
@@ -512,9 +538,18 @@ def add_ceilings(args, out: dict, torch, fhv, kernels: dict, n_exch: int | None,
         return
     ceil = ceilings(torch, fhv)
     out["ceilings"] = ceil
-    out["copy_frac"] = {k: kernels[k]["gbs"] / ceil["copy_gbs"] for k in kernels
-                        if k in ("compact.scatter", "splat.zclear", "splat.resolve", "capture.reset")
-                        and kernels[k].get("gbs")}
+    # each streaming kernel against the stream ceiling of its own mix of
+    # reads and writes: the time the read-only and write-only probes would
+    # take for its bytes, added
+    sf = {}
+    for k in ("capture.reset", "compact.hist", "compact.scatter", "compact.brick", "splat.bin", "splat.splat"):
+        kk = kernels.get(k, {})
+        if not kk.get("avg_ms") or not (kk.get("read_bytes") or kk.get("write_bytes")):
+            continue
+        r, w = kk["read_bytes"], kk["write_bytes"]
+        t_ceil = r / (ceil["read_gbs"] * 1e9) + w / (ceil["write_gbs"] * 1e9)
+        sf[k] = t_ceil / (kk["avg_ms"] * 1e-3)
+    out["stream_frac"] = sf
     if kernels.get("fill.conv", {}).get("tflops"):
         out["gemm_frac"] = {"fill.conv": kernels["fill.conv"]["tflops"] / ceil["gemm_bf16_tflops"]}
     r_ms = kernels.get("capture.raster", {}).get("avg_ms")
@@ -541,19 +576,6 @@ def add_ceilings(args, out: dict, torch, fhv, kernels: dict, n_exch: int | None,
                                       "what": "requests not counted for this workload; exchanges per second "
                                               "exceed the one-request-per-exchange rate where samples share "
                                               "lines"}
-    # the splat's z-buffer minima are data dependent (a pixel already
-    # holding a nearer fragment is skipped): their memory-side requests come
-    # from the committed counter run, compared with the probes' request rates
-    sc, cal = measured_scope("splat.splat") if counters else (None, None)
-    s_ms = kernels.get("splat.splat", {}).get("avg_ms")
-    if sc and "atomic_requests" in sc and "TCC_ATOMIC" in (cal or {}) and s_ms:
-        c = cal["TCC_ATOMIC"]
-        a = ceil["atomics_g_per_s"]
-        rate = sc["atomic_requests"] / (s_ms * 1e-3) / 1e9
-        peaks = {"min_u64.llc": a["min_u64.llc"] * c["requests_per_op_sparse"],
-                 "min_u64.dense_llc": a["min_u64.dense_llc"] * c["requests_per_op_dense"]}
-        out["splat_atomics"] = {"requests_per_launch": sc["atomic_requests"], "achieved_g_per_s": rate,
-                                "probe_requests_g_per_s": peaks, "unit": "G memory-side atomic requests/s"}
 
 
 def timed(torch, fn, steps: int) -> float:
@@ -613,6 +635,8 @@ def bench_batch64(args, torch, fhv, scenes):
     kernels = kernel_table(prof, algo)
     for kk in kernels.values():
         kk["launches_per_step"] = kk["launches"] / args.steps
+    stage = lambda pre: sum(kernels[k]["avg_ms"] * kernels[k]["launches"] / args.steps
+                            for k in kernels if k.startswith(pre))
     out = {
         "metric": "fragments captured/s; 1080p novel views/s; learned-fill vs plain-splat PSNR",
         "value": F / (ms_graph * 1e-3), "unit": "fragments/s", "n_gpus": 1, "steps": args.steps,
@@ -626,6 +650,8 @@ def bench_batch64(args, torch, fhv, scenes):
         "views_per_s_720p": n_views / (ms_graph * 1e-3),
         "ms_per_step_eager": ms_eager,
         "graph_saves_ms": ms_eager - ms_graph,
+        "stage_ms": {"capture": stage("capture."), "compact": stage("compact."), "splat": stage("splat.")},
+        **compact_splat_fracs(algo, F, n_occ, L, n_views, W * H, stage("compact."), stage("splat.")),
         "tuning": tuning,
         "kernels": kernels,
         "roofline": hbm_roofline(kernels),
@@ -673,12 +699,13 @@ def bench_ppfl64(args, torch, fhv, scenes):
     imgs = fhv.alloc_images(1, Wc, Hc)
     ws_c = torch.empty(fhv.capture_workspace(d, mesh.n_tri), dtype=torch.uint8, device="cuda")
     ws_k = torch.empty(fhv.compact_workspace(d, cap), dtype=torch.uint8, device="cuda")
+    ws_s = torch.empty(fhv.splat_workspace(cap, 1, Wc, Hc), dtype=torch.uint8, device="cuda")
     vs = fhv.views_struct(views)
 
     def step():
         fhv.capture(dm, d, lists, ws_c)
         fhv.compact(lists, d, pofa, ws_k)
-        fhv.splat(pofa, d, views, imgs, vs)
+        fhv.splat(pofa, d, views, imgs, vs, ws_s)
 
     for _ in range(args.warmup):
         step()
@@ -754,12 +781,13 @@ def bench_large5m(args, torch, fhv, scenes):
     imgs = fhv.alloc_images(V, W, H)
     ws_c = torch.empty(fhv.capture_workspace(d, mesh.n_tri), dtype=torch.uint8, device="cuda")
     ws_k = torch.empty(fhv.compact_workspace(d, cap), dtype=torch.uint8, device="cuda")
+    ws_s = torch.empty(fhv.splat_workspace(cap, V, W, H), dtype=torch.uint8, device="cuda")
     vs = fhv.views_struct(views)
 
     def step():
         fhv.capture(dm, d, lists, ws_c)
         fhv.compact(lists, d, pofa, ws_k)
-        fhv.splat(pofa, d, views, imgs, vs)
+        fhv.splat(pofa, d, views, imgs, vs, ws_s)
 
     for _ in range(args.warmup):
         step()
@@ -774,7 +802,6 @@ def bench_large5m(args, torch, fhv, scenes):
     kernels = kernel_table(prof, algo)
     stage = lambda pre: sum(kernels[k]["avg_ms"] * kernels[k]["launches"] / args.steps
                             for k in kernels if k.startswith(pre))
-    cs_bytes = sum(algo[k] for k in algo if k.startswith(("compact.", "splat.")))
     out = {
         "metric": "fragments captured/s; 1080p novel views/s; learned-fill vs plain-splat PSNR",
         "value": F / (ms * 1e-3), "unit": "fragments/s", "n_gpus": 1, "steps": args.steps,
@@ -786,8 +813,7 @@ def bench_large5m(args, torch, fhv, scenes):
                    "views": V, "view_size": [W, H]},
         "views_per_s_4k": V / (ms * 1e-3),
         "stage_ms": {"capture": stage("capture."), "compact": stage("compact."), "splat": stage("splat.")},
-        "compact_gbs": sum(algo[k] for k in algo if k.startswith("compact.")) / (stage("compact.") * 1e-3) / 1e9,
-        "compact_splat_hbm_frac": cs_bytes / ((stage("compact.") + stage("splat.")) * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        **compact_splat_fracs(algo, F, n_occ, L, V, W * H, stage("compact."), stage("splat.")),
         "kernels": kernels,
         "roofline": hbm_roofline(kernels),
         "wall_s_timed": wall,
@@ -892,16 +918,24 @@ def main():
     imgs = fhv.alloc_images(len(views), W_OUT, H_OUT)
     ws_c = torch.empty(fhv.capture_workspace(d, mesh.n_tri), dtype=torch.uint8, device="cuda")
     ws_k = torch.empty(fhv.compact_workspace(d, cap), dtype=torch.uint8, device="cuda")
+    ws_s = torch.empty(fhv.splat_workspace(cap, len(views), W_OUT, H_OUT), dtype=torch.uint8, device="cuda")
     vs = fhv.views_struct(views)
     from paper_2211_15460_amd import learned_fill as LF
-    fill_params = torch.from_numpy(LF.init_params(0, 4)).cuda()
+    lf_report = None
+    if not args.no_train:
+        # the fill is trained first, so that the timed step runs the trained
+        # network
+        lf_report, lf_model = learned_fill_report(torch, fhv, scenes)
+        fill_params = lf_model.params
+    else:
+        fill_params = torch.from_numpy(LF.init_params(0, 4)).cuda()
     ws_f = torch.empty(fhv.fill_workspace(4, len(views), H_OUT, W_OUT, False), dtype=torch.uint8,
                        device="cuda")
 
     def step():
         fhv.capture(dm, d, lists, ws_c)
         fhv.compact(lists, d, pofa, ws_k)
-        fhv.splat(pofa, d, views, imgs, vs)
+        fhv.splat(pofa, d, views, imgs, vs, ws_s)
         fhv.fill(fill_params, imgs.rgba, imgs.depth, imgs.cov, 4, ws=ws_f)
 
     if args.copy_mib > 0:
@@ -943,15 +977,16 @@ def main():
             kernels[name] = {"avg_ms": round(avg, 5), "launches": launches, "algo_flops": fl,
                              "tflops": round(fl / (avg * 1e-3) / 1e12, 2) if avg > 0 else None}
             continue
-        b = algo.get(name, 0)
-        kernels[name] = {"avg_ms": round(avg, 5), "launches": launches,
-                         "algo_bytes": b, "gbs": round(b / (avg * 1e-3) / 1e9, 1) if avg > 0 else None}
+        r, w = algo.get(name, (0, 0))
+        b = r + w
+        kernels[name] = {"avg_ms": round(avg, 5), "launches": launches, "algo_bytes": b,
+                         "read_bytes": r, "write_bytes": w,
+                         "gbs": round(b / (avg * 1e-3) / 1e9, 1) if avg > 0 else None}
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
     dk = kernels[dom]
     stage = lambda pre: sum(kernels[k]["avg_ms"] * kernels[k]["launches"] / args.steps
                             for k in kernels if k.startswith(pre))
     splat_ms, capture_ms, compact_ms, fill_ms = stage("splat."), stage("capture."), stage("compact."), stage("fill.")
-    cs_bytes = sum(algo[k] for k in algo if k.startswith(("compact.", "splat.")))
     if dom == "fill.conv":
         roof = {"bound": "mfma", "kernel": "k_conv (fill.conv)", "achieved": dk["tflops"],
                 "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -976,14 +1011,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "n_tri": mesh.n_tri, "levels": LEVELS,
                    "fragments": F, "occupied_octants": n_occ, "views": len(views),
-                   "view_size": [W_OUT, H_OUT]},
+                   "view_size": [W_OUT, H_OUT],
+                   "fill_weights": "trained (learned_fill)" if lf_report is not None else "untrained (--no-train)"},
         "views_per_s_1080p": len(views) / (ms_step * 1e-3),
         "splat_views_per_s_1080p": len(views) / (splat_ms * 1e-3),
         "capture_fragments_per_s": F / (capture_ms * 1e-3),
         "fill_ms_per_1080p_view": fill_ms / len(views),
         "fill_tflops": fill_flops / (fill_ms * 1e-3) / 1e12 if fill_ms else None,
         "stage_ms": {"capture": capture_ms, "compact": compact_ms, "splat": splat_ms, "fill": fill_ms},
-        "compact_splat_hbm_frac": (cs_bytes / ((compact_ms + splat_ms) * 1e-3) / 1e9) / HBM_PEAK_GBS,
+        **compact_splat_fracs(algo, F, n_occ, LEVELS, len(views), pix, compact_ms, splat_ms),
         "kernels": kernels,
         "roofline": roof,
         "wall_s_timed": wall,
@@ -1009,10 +1045,23 @@ def main():
                         "bytes": len(views) * W_OUT * H_OUT * (8 + 16),
                         "gbs": len(views) * W_OUT * H_OUT * (8 + 16) / (sh * 1e-3) / 1e9,
                         "what": "per pixel: z-buffer key read, float4 written (plus the winner's record)"}
-    if not args.no_train:
-        out["learned_fill"], _ = learned_fill_report(torch, fhv, scenes)
+    if lf_report is not None:
+        # the timed step's own three views: plain splat and trained fill
+        # against the reference render
+        fimg, _ = fhv.fill(fill_params, imgs.rgba, imgs.depth, imgs.cov, 4, ws=ws_f)
+        torch.cuda.synchronize()
+        lf_report["step_views"] = [
+            {"theta": th, "psnr_splat_db": LF.psnr_rgb(imgs.rgba[i], ref),
+             "psnr_fill_db": LF.psnr_rgb(fimg[i], ref)}
+            for i, (th, ref) in enumerate((th, LF.gpu_reference(mesh, LEVELS, v)) for th, v in zip(THETAS, views))]
+        out["learned_fill"] = lf_report
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, views)
+        # the oracle's step has no fill: the GPU's time for the same work
+        gpu_ms = capture_ms + compact_ms + splat_ms
+        out["cpu_baseline"]["gpu_same_work"] = {
+            "value": F / (gpu_ms * 1e-3), "unit": "fragments/s", "ms": gpu_ms,
+            "what": "capture + compaction + three splats of the timed step (no fill), as the oracle's step"}
     print(json.dumps(out), flush=True)
 
 

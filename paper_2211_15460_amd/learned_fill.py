@@ -45,29 +45,103 @@ def render_splats(mesh, levels: int, views, capacity: int | None = None) -> tupl
     return SplatImages(img.rgba, img.depth, img.cov), F
 
 
-def random_crops(src: SplatImages, target: torch.Tensor, n: int, size: int, rng: np.random.Generator,
-                 min_cover: float = 0.3, tries: int = 20):
-    """n crops of size x size from random views; a crop is redrawn (up to
-    `tries` times) while less than min_cover of its pixels are covered in
-    the target (alpha > 0)."""
-    V, H, W = src.rgba.shape
-    idx_v, ys, xs = [], [], []
-    tgt_alpha = (target.view(torch.int32) >> 24) & 0xFF
-    for _ in range(n):
-        for _t in range(tries):
-            v = int(rng.integers(V))
-            y = int(rng.integers(0, H - size + 1))
-            x = int(rng.integers(0, W - size + 1))
-            frac = (tgt_alpha[v, y:y + size, x:x + size] > 0).float().mean().item()
-            if frac >= min_cover:
-                break
-        idx_v.append(v)
-        ys.append(y)
-        xs.append(x)
+def crop_origins(target: torch.Tensor, n: int, size: int, rng: np.random.Generator, min_cover: float = 0.3,
+                 oversample: int = 4) -> np.ndarray:
+    """n crop origins (view, y, x) of size x size drawn uniformly, keeping
+    only crops with at least min_cover of their pixels covered in the target
+    (alpha > 0); the coverage of every candidate comes from a summed-area
+    table of the targets (one pass on the host). Origins are distinct."""
+    V, H, W = target.shape
+    cov = (((target.view(torch.int32) >> 24) & 0xFF) > 0).cpu().numpy()
+    sat = np.zeros((V, H + 1, W + 1), np.int64)
+    sat[:, 1:, 1:] = cov.cumsum(1).cumsum(2)
+    chosen: list[tuple[int, int, int]] = []
+    seen = set()
+    for _round in range(64):
+        if len(chosen) == n:
+            break
+        m = oversample * (n - len(chosen))
+        v = rng.integers(0, V, m)
+        y = rng.integers(0, H - size + 1, m)
+        x = rng.integers(0, W - size + 1, m)
+        c = sat[v, y + size, x + size] - sat[v, y, x + size] - sat[v, y + size, x] + sat[v, y, x]
+        for vi, yi, xi, ci in zip(v.tolist(), y.tolist(), x.tolist(), c.tolist()):
+            if ci >= min_cover * size * size and (vi, yi, xi) not in seen:
+                seen.add((vi, yi, xi))
+                chosen.append((vi, yi, xi))
+                if len(chosen) == n:
+                    break
+    if len(chosen) < n:
+        raise ValueError(f"only {len(chosen)} of {n} crops reach the coverage {min_cover}")
+    return np.array(chosen, np.int64)
 
-    def cut(t):
-        return torch.stack([t[v, y:y + size, x:x + size] for v, y, x in zip(idx_v, ys, xs)]).contiguous()
-    return cut(src.rgba), cut(src.depth), cut(src.cov), cut(target)
+
+def cut_crops(src: SplatImages, target: torch.Tensor, origins: np.ndarray, size: int):
+    """The crops at `origins` (rows of view, y, x): device gathers only."""
+    dev = target.device
+    o = torch.from_numpy(np.ascontiguousarray(origins)).to(dev)
+    ar = torch.arange(size, device=dev)
+    vv = o[:, 0].view(-1, 1, 1)
+    yy = (o[:, 1].view(-1, 1) + ar).view(-1, size, 1)
+    xx = (o[:, 2].view(-1, 1) + ar).view(-1, 1, size)
+    g = lambda t: t[vv, yy, xx].contiguous()
+    return g(src.rgba), g(src.depth), g(src.cov), g(target)
+
+
+@dataclass
+class TrainingSet:
+    src: SplatImages          # splats of the training views
+    target: torch.Tensor      # reference images of the same views, int32 RGBA8
+    views: list               # (scene seed, octree depth, theta) per view
+
+
+def training_set(reference, seeds, levels_list, views_per_scene: int, rng: np.random.Generator,
+                 width: int = 1920, height: int = 1080) -> TrainingSet:
+    """Splats and reference images of random orbit views (theta uniform in
+    [0, 90) degrees) of the benchmark's scene family (scenes.pofl_scene) at
+    each octree depth of levels_list. reference(mesh, levels, view) returns
+    the reference RGBA8 image [H, W] of a view (int32 device tensor)."""
+    srcs, tgts, meta = [], [], []
+    for seed in seeds:
+        mesh = scenes.pofl_scene(seed)
+        for L in levels_list:
+            thetas = [float(t) for t in rng.uniform(0.0, 90.0, views_per_scene)]
+            views = [scenes.cube_view(t, L, width, height) for t in thetas]
+            img, _ = render_splats(mesh, L, views)
+            srcs.append(img)
+            tgts.append(torch.stack([reference(mesh, L, v) for v in views]))
+            meta += [(seed, L, t) for t in thetas]
+    cat = lambda f: torch.cat([getattr(i, f) for i in srcs])
+    return TrainingSet(SplatImages(cat("rgba"), cat("depth"), cat("cov")), torch.cat(tgts), meta)
+
+
+def train(model: "FillModel", ts: TrainingSet, n_crops: int, batch: int, size: int, rng: np.random.Generator,
+          lr0: float = 1e-3, lr1: float = 5e-5) -> int:
+    """Adam steps over n_crops distinct random crops (n_crops / batch steps,
+    cosine learning-rate decay); crops are cut on the device, so the loop
+    waits for nothing. Returns the number of steps."""
+    origins = crop_origins(ts.target, n_crops, size, rng)
+    steps = n_crops // batch
+    for st in range(steps):
+        rgba, depth, cov, tgt = cut_crops(ts.src, ts.target, origins[st * batch:(st + 1) * batch], size)
+        model.train_step(rgba, depth, cov, tgt, lr_at(st + 1, steps, lr0, lr1))
+    return steps
+
+
+def evaluate(model: "FillModel", reference, seeds, levels: int, thetas=(30.0, 60.0), width: int = 1920,
+             height: int = 1080) -> list[dict]:
+    """PSNR over RGB of the plain splat and of the filled splat against the
+    reference image, per (held-out scene, view)."""
+    out = []
+    for seed in seeds:
+        mesh = scenes.pofl_scene(seed)
+        for th in thetas:
+            v = scenes.cube_view(th, levels, width, height)
+            img, _ = render_splats(mesh, levels, [v])
+            ref = reference(mesh, levels, v)
+            out.append({"seed": seed, "levels": levels, "theta": th,
+                        "psnr_splat_db": psnr_rgb(img.rgba[0], ref), "psnr_fill_db": psnr_rgb(model.fill(img)[0], ref)})
+    return out
 
 
 class FillModel:
@@ -144,6 +218,11 @@ def psnr_rgb(a: torch.Tensor, b: torch.Tensor) -> float:
         se += float((d * d).sum())
     mse = se / (3.0 * ai.numel())
     return float("inf") if mse == 0 else 10.0 * math.log10(255.0 ** 2 / mse)
+
+
+def gpu_reference(mesh, levels: int, view) -> torch.Tensor:
+    """reference_render's image as [H, W]."""
+    return reference_render(mesh, levels, view)[0]
 
 
 def reference_render(mesh, levels: int, view) -> torch.Tensor:
