@@ -258,6 +258,7 @@ FHV_API fhv_status fhv_splat(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_cap
                      const fhv_view* views, uint32_t n_views, uint64_t* zbuf, uint32_t* rgba,
                      float* depth, uint8_t* cov, void* ws, size_t ws_bytes, fhv_stream stream);
 
+
 /* Ray casting (Sec. 3.3, evaluation by ray casting) of POFL per-octant
  * arrays into orthographic views. The ray of pixel (x, y) meets array
  * fragment i when i projects into that pixel, floor(s) = (x, y) per axis,
@@ -412,6 +413,12 @@ FHV_API fhv_status fhv_batch_run(fhv_ctx* ctx, const fhv_batch_mesh* mesh, const
  * Images: n_img x height x width, row-major, height and width multiples of
  *   2^(levels-1); n_img * height * width < 2^31. */
 FHV_API uint64_t fhv_unet_param_count(uint32_t levels);
+/* Workspace bytes of fhv_fill (training FHV_FILL_INFER), fhv_fill_train_step
+ * (FHV_FILL_TRAIN) or fhv_fill_train_step_traced (FHV_FILL_TRACE); 0 for
+ * sizes or a mode out of range. */
+#define FHV_FILL_INFER 0
+#define FHV_FILL_TRAIN 1
+#define FHV_FILL_TRACE 2
 FHV_API size_t fhv_fill_workspace(uint32_t levels, uint32_t n_img, uint32_t height, uint32_t width,
                                   int training);
 
@@ -436,6 +443,38 @@ FHV_API fhv_status fhv_fill_train_step(fhv_ctx* ctx, uint32_t levels, float* par
                                        const uint32_t* target_rgba, uint32_t n_img, uint32_t height,
                                        uint32_t width, float* loss_out, float* grad_out, void* ws,
                                        size_t ws_bytes, fhv_stream stream);
+
+/* Layer-by-layer tracing of the training step, for checking every kernel
+ * on the tensors it actually read: fhv_fill_train_step_traced does exactly
+ * what fhv_fill_train_step does (same kernels, same results) but keeps every
+ * activation gradient in a buffer of its own instead of reusing scratch
+ * buffers; ws: fhv_fill_workspace(..., FHV_FILL_TRACE) bytes.
+ * fhv_fill_trace_tensors describes where the tensors are afterwards: five
+ * entries per parameter layer, in parameter order: [0] the layer's input
+ * activation, [1] its output activation (after ReLU), [2] the gradient of
+ * the loss w.r.t. that output as the layer's backward pass received it,
+ * [3] that gradient after the ReLU mask (3x3 convolutions), [4] the
+ * gradient w.r.t. the layer's input. The head (last layer) has [0] and [4].
+ * A tensor is bfloat16 NHWC: element (i, y, x, c) at byte offset + 2 *
+ * (((i * height + y) * width + x) * stride + c) of ws; channels 0 marks an
+ * entry the layer does not have. out: host array of `cap` entries (NULL to
+ * query the count). Returns the number of entries, 0 for bad sizes. */
+typedef struct {
+    uint64_t offset;
+    uint32_t stride;
+    uint32_t channels;
+    uint32_t n;
+    uint32_t height;
+    uint32_t width;
+} fhv_fill_tensor;
+FHV_API uint32_t fhv_fill_trace_tensors(uint32_t levels, uint32_t n_img, uint32_t height, uint32_t width,
+                                        fhv_fill_tensor* out, uint32_t cap);
+FHV_API fhv_status fhv_fill_train_step_traced(fhv_ctx* ctx, uint32_t levels, float* params, float* adam_m,
+                                              float* adam_v, uint32_t step, float lr, const uint32_t* rgba,
+                                              const float* depth, const uint8_t* cov,
+                                              const uint32_t* target_rgba, uint32_t n_img, uint32_t height,
+                                              uint32_t width, float* loss_out, float* grad_out, void* ws,
+                                              size_t ws_bytes, fhv_stream stream);
 
 /* Kernel timing (tracing). Between fhv_profile_begin and fhv_profile_end
  * every kernel the library enqueues is bracketed by two HIP events on the

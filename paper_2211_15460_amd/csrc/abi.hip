@@ -397,9 +397,13 @@ size_t fhv_splat_workspace(uint64_t cap_frag, uint32_t n_views, uint32_t width, 
     return fhv::splat_ws_bytes(cap_frag, 1, n_views, width, height);
 }
 
-fhv_status fhv_splat(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_capture_desc* desc,
-                     const fhv_view* views, uint32_t n_views, uint64_t* zbuf, uint32_t* rgba,
-                     float* depth, uint8_t* cov, void* ws, size_t ws_bytes, fhv_stream stream)
+namespace {
+
+// Host-side checks of a splat call; fills the
+// kernels' view arguments and the workspace the call needs.
+fhv_status splat_check(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_capture_desc* desc, const fhv_view* views,
+                       uint32_t n_views, uint64_t* zbuf, uint32_t* rgba, float* depth, uint8_t* cov,
+                       fhv::ViewArgs* out, size_t* need)
 {
     if (!ctx || !arrays || !desc_ok(desc) || !views) return FHV_EINVAL;
     if (n_views == 0 || n_views > fhv::kMaxViews) return FHV_ERANGE;
@@ -423,10 +427,24 @@ fhv_status fhv_splat(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_capture_des
         va.c[v] = 0.5f - 0.5f * (float)views[v].splat_px;
     }
     if (!fhv::splat_fits(arrays->cap_frag, 1, n_views, va.width, va.height)) return FHV_ERANGE;
-    if (ws_bytes < fhv::splat_ws_bytes(arrays->cap_frag, 1, n_views, va.width, va.height)) return FHV_EWORKSPACE;
-    if (!ws) return FHV_EINVAL;
-    fhv_status st = set_device(ctx);
+    *need = fhv::splat_ws_bytes(arrays->cap_frag, 1, n_views, va.width, va.height);
+    *out = va;
+    return FHV_OK;
+}
+
+}  // namespace
+
+fhv_status fhv_splat(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_capture_desc* desc,
+                     const fhv_view* views, uint32_t n_views, uint64_t* zbuf, uint32_t* rgba,
+                     float* depth, uint8_t* cov, void* ws, size_t ws_bytes, fhv_stream stream)
+{
+    fhv::ViewArgs va;
+    size_t need = 0;
+    fhv_status st = splat_check(ctx, arrays, desc, views, n_views, zbuf, rgba, depth, cov, &va, &need);
     if (st != FHV_OK) return st;
+    if (ws_bytes < need) return FHV_EWORKSPACE;
+    if (!ws) return FHV_EINVAL;
+    if ((st = set_device(ctx)) != FHV_OK) return st;
     return hip_status(fhv::splat_launch(ctx->dev, arrays, desc, va, zbuf, rgba, depth, cov, ws,
                                         (hipStream_t)stream));
 }
@@ -553,7 +571,17 @@ size_t fhv_fill_workspace(uint32_t levels, uint32_t n_img, uint32_t height, uint
 {
     if (!fill_dims_ok(levels, n_img, height, width)) return 0;
     if ((uint64_t)n_img * height * width >= (1ull << 31)) return 0;
-    return fhv::nn::fill_ws_bytes(levels, n_img, height, width, training != 0);
+    if (training < FHV_FILL_INFER || training > FHV_FILL_TRACE) return 0;
+    return fhv::nn::fill_ws_bytes(levels, n_img, height, width, training != FHV_FILL_INFER,
+                                  training == FHV_FILL_TRACE);
+}
+
+uint32_t fhv_fill_trace_tensors(uint32_t levels, uint32_t n_img, uint32_t height, uint32_t width,
+                                fhv_fill_tensor* out, uint32_t cap)
+{
+    if (!fill_dims_ok(levels, n_img, height, width)) return 0;
+    if ((uint64_t)n_img * height * width >= (1ull << 31)) return 0;
+    return fhv::nn::trace_tensors(levels, n_img, height, width, out, cap);
 }
 
 fhv_status fhv_fill(fhv_ctx* ctx, uint32_t levels, const float* params, const uint32_t* rgba,
@@ -571,22 +599,45 @@ fhv_status fhv_fill(fhv_ctx* ctx, uint32_t levels, const float* params, const ui
                                     out_residual, ws, (hipStream_t)stream));
 }
 
+namespace {
+
+fhv_status train_call(fhv_ctx* ctx, uint32_t levels, float* params, float* adam_m, float* adam_v, uint32_t step,
+                      float lr, const uint32_t* rgba, const float* depth, const uint8_t* cov,
+                      const uint32_t* target_rgba, uint32_t n_img, uint32_t height, uint32_t width, float* loss_out,
+                      float* grad_out, void* ws, size_t ws_bytes, fhv_stream stream, bool trace)
+{
+    if (!ctx || !params || !rgba || !depth || !cov || !target_rgba || !ws) return FHV_EINVAL;
+    if (step > 0 && (!adam_m || !adam_v)) return FHV_EINVAL;
+    if (!fill_dims_ok(levels, n_img, height, width)) return FHV_EINVAL;
+    if ((uint64_t)n_img * height * width >= (1ull << 31)) return FHV_ERANGE;
+    if (ws_bytes < fhv::nn::fill_ws_bytes(levels, n_img, height, width, true, trace)) return FHV_EWORKSPACE;
+    fhv_status st = set_device(ctx);
+    if (st != FHV_OK) return st;
+    return hip_status(fhv::nn::train_step(ctx->dev, levels, params, adam_m, adam_v, step, lr, rgba, depth, cov,
+                                          target_rgba, n_img, height, width, loss_out, grad_out, ws,
+                                          (hipStream_t)stream, trace));
+}
+
+}  // namespace
+
 fhv_status fhv_fill_train_step(fhv_ctx* ctx, uint32_t levels, float* params, float* adam_m,
                                float* adam_v, uint32_t step, float lr, const uint32_t* rgba,
                                const float* depth, const uint8_t* cov, const uint32_t* target_rgba,
                                uint32_t n_img, uint32_t height, uint32_t width, float* loss_out,
                                float* grad_out, void* ws, size_t ws_bytes, fhv_stream stream)
 {
-    if (!ctx || !params || !rgba || !depth || !cov || !target_rgba || !ws) return FHV_EINVAL;
-    if (step > 0 && (!adam_m || !adam_v)) return FHV_EINVAL;
-    if (!fill_dims_ok(levels, n_img, height, width)) return FHV_EINVAL;
-    if ((uint64_t)n_img * height * width >= (1ull << 31)) return FHV_ERANGE;
-    if (ws_bytes < fhv::nn::fill_ws_bytes(levels, n_img, height, width, true)) return FHV_EWORKSPACE;
-    fhv_status st = set_device(ctx);
-    if (st != FHV_OK) return st;
-    return hip_status(fhv::nn::train_step(ctx->dev, levels, params, adam_m, adam_v, step, lr, rgba, depth, cov,
-                                          target_rgba, n_img, height, width, loss_out, grad_out, ws,
-                                          (hipStream_t)stream));
+    return train_call(ctx, levels, params, adam_m, adam_v, step, lr, rgba, depth, cov, target_rgba, n_img, height,
+                      width, loss_out, grad_out, ws, ws_bytes, stream, false);
+}
+
+fhv_status fhv_fill_train_step_traced(fhv_ctx* ctx, uint32_t levels, float* params, float* adam_m,
+                                      float* adam_v, uint32_t step, float lr, const uint32_t* rgba,
+                                      const float* depth, const uint8_t* cov, const uint32_t* target_rgba,
+                                      uint32_t n_img, uint32_t height, uint32_t width, float* loss_out,
+                                      float* grad_out, void* ws, size_t ws_bytes, fhv_stream stream)
+{
+    return train_call(ctx, levels, params, adam_m, adam_v, step, lr, rgba, depth, cov, target_rgba, n_img, height,
+                      width, loss_out, grad_out, ws, ws_bytes, stream, true);
 }
 
 fhv_status fhv_get_tuning(fhv_ctx* ctx, fhv_tuning* out)

@@ -271,14 +271,15 @@ hipError_t probe_launch(const Device& dev, uint32_t kind, void* buf, uint64_t by
 
 namespace nn {
 uint64_t param_count(uint32_t levels);
-size_t fill_ws_bytes(uint32_t levels, uint32_t N, uint32_t H, uint32_t W, bool training);
+size_t fill_ws_bytes(uint32_t levels, uint32_t N, uint32_t H, uint32_t W, bool training, bool trace = false);
+uint32_t trace_tensors(uint32_t levels, uint32_t N, uint32_t H, uint32_t W, fhv_fill_tensor* out, uint32_t cap);
 hipError_t fill(const Device& dev, uint32_t levels, const float* th, const uint32_t* rgba, const float* depth,
                 const uint8_t* cov, uint32_t N, uint32_t H, uint32_t W, uint32_t* out, float* residual,
                 void* ws, hipStream_t s);
 hipError_t train_step(const Device& dev, uint32_t levels, float* th, float* m, float* v, uint32_t step,
                       float lr, const uint32_t* rgba, const float* depth, const uint8_t* cov,
                       const uint32_t* tgt, uint32_t N, uint32_t H, uint32_t W, float* loss, float* grad_out,
-                      void* ws, hipStream_t s);
+                      void* ws, hipStream_t s, bool trace);
 }  // namespace nn
 
 // Workspace carving with 256-byte alignment.

@@ -1554,6 +1554,8 @@ struct Net {
     size_t head() const { return layers.size() - 1; }
 };
 
+constexpr size_t kMaxLayers = 32;
+
 struct Bufs {
     uint16_t* wt;          // bf16 weights (forward and input-gradient layouts)
     uint16_t* x0;
@@ -1562,6 +1564,11 @@ struct Bufs {
     uint16_t *gh, *dz, *ga, *gb, *dcat[4];
     float *part, *hpart, *grad;
     size_t part_elems, hpart_elems;
+    // traced training: every layer's masked output gradient (tz) and input
+    // gradient (tg), and every max pool's input gradient (tp), kept in
+    // buffers of their own instead of the shared dz, ga and gb
+    bool trace;
+    uint16_t *tz[kMaxLayers], *tg[kMaxLayers], *tp[4];
 };
 
 constexpr uint32_t kWgradTarget = 1024;   // waves per weight-gradient launch
@@ -1577,7 +1584,8 @@ void wgrad_dims(uint32_t P, uint32_t Cin, uint32_t Cout, uint32_t T, uint32_t* s
     *splits = (chunks + *per - 1) / *per;
 }
 
-size_t carve(const Net& net, uint32_t N, uint32_t H, uint32_t W, bool training, char* base, Bufs* b)
+size_t carve(const Net& net, uint32_t N, uint32_t H, uint32_t W, bool training, char* base, Bufs* b,
+             bool trace = false)
 {
     Carver c{base, 0};
     const uint32_t L = net.L;
@@ -1617,6 +1625,17 @@ size_t carve(const Net& net, uint32_t N, uint32_t H, uint32_t W, bool training, 
         b->hpart_elems = ((P(0) + kBlock - 1) / kBlock) * kHeadPart;
         b->hpart = c.take<float>(b->hpart_elems);
         b->grad = c.take<float>(net.n_params);
+    }
+    b->trace = training && trace;
+    for (size_t i = 0; i < kMaxLayers; ++i) b->tz[i] = b->tg[i] = nullptr;
+    for (uint32_t l = 0; l < 4; ++l) b->tp[l] = nullptr;
+    if (b->trace) {
+        for (size_t i = 0; i < net.layers.size(); ++i) {
+            const Layer& y = net.layers[i];
+            if (y.kind == 0) b->tz[i] = c.take<uint16_t>(P(y.lvl) * y.cout);
+            if ((y.kind == 0 && i > 0) || y.kind == 1) b->tg[i] = c.take<uint16_t>(P(y.lvl) * y.cin);
+        }
+        for (uint32_t l = 0; l + 1 < L; ++l) b->tp[l] = c.take<uint16_t>(P(l) * net.C[l]);
     }
     return c.off + 256;
 }
@@ -1860,13 +1879,14 @@ hipError_t conv_bwd(const Net& net, size_t i, const Bufs& b, const uint16_t* x, 
 {
     const Layer& ly = net.layers[i];
     const size_t P = (size_t)N * Hl * Wl;
-    k_relu_bwd<<<blocks(P * (ly.cout / 8)), dim3(kBlock), 0, s>>>(g, g_cs, y, y_cs, P, ly.cout, b.dz);
+    uint16_t* dz = b.trace ? b.tz[i] : b.dz;
+    k_relu_bwd<<<blocks(P * (ly.cout / 8)), dim3(kBlock), 0, s>>>(g, g_cs, y, y_cs, P, ly.cout, dz);
     FHV_TRY(hipGetLastError());
-    FHV_TRY(wgrad(b.dz, ly.cout, x, x_cs, N, Hl, Wl, ly.cpad, ly.cin, ly.cout, MODE_SAME3, b.part,
+    FHV_TRY(wgrad(dz, ly.cout, x, x_cs, N, Hl, Wl, ly.cpad, ly.cin, ly.cout, MODE_SAME3, b.part,
                   b.part_elems, b.grad + ly.off_w, s));
-    FHV_TRY(bgrad(b.dz, ly.cout, (uint32_t)P, ly.cout, b.part, b.grad + ly.off_b, s));
+    FHV_TRY(bgrad(dz, ly.cout, (uint32_t)P, ly.cout, b.part, b.grad + ly.off_b, s));
     if (gin)
-        FHV_TRY(conv(b.dz, ly.cout, b.wt + ly.wb_off, nullptr, gin, gin_cs, N, Hl, Wl, ly.cout, ly.cpad,
+        FHV_TRY(conv(dz, ly.cout, b.wt + ly.wb_off, nullptr, gin, gin_cs, N, Hl, Wl, ly.cout, ly.cpad,
                      MODE_SAME3, false, s));
     return hipSuccess;
 }
@@ -1880,8 +1900,9 @@ hipError_t backward(const Net& net, const float* th, const Bufs& b, uint32_t N, 
     for (uint32_t l = 0; l + 1 < L; ++l) {
         const uint32_t Hl = H >> l, Wl = W >> l, Cl = net.C[l];
         const size_t it = net.dec(l);
-        FHV_TRY(conv_bwd(net, it + 2, b, b.d0[l], Cl, b.d1[l], Cl, g, Cl, b.ga, Cl, N, Hl, Wl, s));
-        FHV_TRY(conv_bwd(net, it + 1, b, b.cat[l], 2 * Cl, b.d0[l], Cl, b.ga, Cl, b.dcat[l], 2 * Cl, N, Hl,
+        uint16_t* g2 = b.trace ? b.tg[it + 2] : b.ga;
+        FHV_TRY(conv_bwd(net, it + 2, b, b.d0[l], Cl, b.d1[l], Cl, g, Cl, g2, Cl, N, Hl, Wl, s));
+        FHV_TRY(conv_bwd(net, it + 1, b, b.cat[l], 2 * Cl, b.d0[l], Cl, g2, Cl, b.dcat[l], 2 * Cl, N, Hl,
                          Wl, s));
         // transposed conv: input hin on level l + 1, output gradient = first half of dcat
         const Layer& t = net.layers[it];
@@ -1890,9 +1911,10 @@ hipError_t backward(const Net& net, const float* th, const Bufs& b, uint32_t N, 
         FHV_TRY(wgrad(b.dcat[l], 2 * Cl, hin, Cu, N, Hl / 2, Wl / 2, Cu, Cu, Cl, MODE_UP2, b.part,
                       b.part_elems, b.grad + t.off_w, s));
         FHV_TRY(bgrad(b.dcat[l], 2 * Cl, N * Hl * Wl, Cl, b.part, b.grad + t.off_b, s));
-        FHV_TRY(conv(b.dcat[l], 2 * Cl, b.wt + t.wb_off, nullptr, b.gb, Cu, N, Hl / 2, Wl / 2, Cl, Cu,
+        uint16_t* gt = b.trace ? b.tg[it] : b.gb;
+        FHV_TRY(conv(b.dcat[l], 2 * Cl, b.wt + t.wb_off, nullptr, gt, Cu, N, Hl / 2, Wl / 2, Cl, Cu,
                      MODE_GATHER4, false, s));
-        g = b.gb;
+        g = gt;
     }
     // encoder, deepest level first. The gradient stays in one buffer (each
     // layer's ReLU-gradient kernel consumes it before the layer's input
@@ -1904,18 +1926,23 @@ hipError_t backward(const Net& net, const float* th, const Bufs& b, uint32_t N, 
         const uint16_t* y1 = l + 1 < (int)L ? b.cat[l] + Cl : b.elast;
         const uint32_t y1_cs = l + 1 < (int)L ? 2 * Cl : Cl;
         if (l + 1 < (int)L) {
-            uint16_t* nxt = cur == b.ga ? b.gb : b.ga;
+            uint16_t* nxt = b.trace ? b.tp[l] : (cur == b.ga ? b.gb : b.ga);
             // pooled gradient (cur, on level l + 1) plus the skip gradient
             k_maxpool_bwd<<<blocks((size_t)N * Hl * Wl * (Cl / 8)), dim3(kBlock), 0, s>>>(
                 y1, y1_cs, cur, b.dcat[l] + Cl, 2 * Cl, N, Hl / 2, Wl / 2, Cl, nxt);
             FHV_TRY(hipGetLastError());
             cur = nxt;
         }
-        FHV_TRY(conv_bwd(net, net.enc(l, 1), b, b.e0[l], Cl, y1, y1_cs, cur, Cl, cur, Cl, N, Hl, Wl, s));
+        // traced: every input gradient into a buffer of its own
+        uint16_t* g1 = b.trace ? b.tg[net.enc(l, 1)] : cur;
+        FHV_TRY(conv_bwd(net, net.enc(l, 1), b, b.e0[l], Cl, y1, y1_cs, cur, Cl, g1, Cl, N, Hl, Wl, s));
+        cur = g1;
         const uint16_t* x0 = l == 0 ? b.x0 : b.pool[l - 1];
         const uint32_t x0_cs = l == 0 ? kInPad : net.C[l - 1];
-        FHV_TRY(conv_bwd(net, net.enc(l, 0), b, x0, x0_cs, b.e0[l], Cl, cur, Cl, l > 0 ? cur : nullptr,
-                         l > 0 ? net.C[l - 1] : 0, N, Hl, Wl, s));
+        uint16_t* g0 = l > 0 ? (b.trace ? b.tg[net.enc(l, 0)] : cur) : nullptr;
+        FHV_TRY(conv_bwd(net, net.enc(l, 0), b, x0, x0_cs, b.e0[l], Cl, cur, Cl, g0, l > 0 ? net.C[l - 1] : 0, N,
+                         Hl, Wl, s));
+        if (g0) cur = g0;
     }
     return hipSuccess;
 }
@@ -1930,11 +1957,88 @@ struct DevScope {
     ~DevScope() { t_dev = nullptr; }
 };
 
-size_t fill_ws_bytes(uint32_t levels, uint32_t N, uint32_t H, uint32_t W, bool training)
+size_t fill_ws_bytes(uint32_t levels, uint32_t N, uint32_t H, uint32_t W, bool training, bool trace)
 {
     Net net(levels);
     Bufs b;
-    return carve(net, N, H, W, training, nullptr, &b);
+    return carve(net, N, H, W, training, nullptr, &b, trace);
+}
+
+// Where a traced training step leaves every tensor of every layer in its
+// workspace: five entries per parameter layer (input, output, gradient
+// received for the output, that gradient after the ReLU mask, gradient of
+// the input), channels 0 where a layer has no such tensor.
+uint32_t trace_tensors(uint32_t levels, uint32_t N, uint32_t H, uint32_t W, fhv_fill_tensor* out, uint32_t cap)
+{
+    Net net(levels);
+    Bufs b;
+    // offsets from a stand-in base address (nothing is dereferenced)
+    char* const base = (char*)(uintptr_t)4096;
+    carve(net, N, H, W, true, base, &b, true);
+    const uint32_t L = levels;
+    const uint32_t n = (uint32_t)net.layers.size() * 5;
+    if (!out) return n;
+    auto put = [&](uint32_t k, const uint16_t* p, uint32_t stride, uint32_t ch, uint32_t lvl) {
+        if (k >= cap) return;
+        fhv_fill_tensor t{};
+        if (p && ch) {
+            t.offset = (uint64_t)((const char*)p - base);
+            t.stride = stride;
+            t.channels = ch;
+            t.n = N;
+            t.height = H >> lvl;
+            t.width = W >> lvl;
+        }
+        out[k] = t;
+    };
+    for (uint32_t k = 0; k < n && k < cap; ++k) out[k] = fhv_fill_tensor{};
+    const auto& C = net.C;
+    for (uint32_t l = 0; l < L; ++l) {
+        const uint32_t Cl = C[l];
+        const uint32_t e1 = (uint32_t)net.enc(l, 0) * 5, e2 = (uint32_t)net.enc(l, 1) * 5;
+        // first convolution of encoder level l
+        if (l == 0) put(e1 + 0, b.x0, kInPad, kInPad, 0);
+        else put(e1 + 0, b.pool[l - 1], C[l - 1], C[l - 1], l);
+        put(e1 + 1, b.e0[l], Cl, Cl, l);
+        put(e1 + 2, b.tg[net.enc(l, 1)], Cl, Cl, l);
+        put(e1 + 3, b.tz[net.enc(l, 0)], Cl, Cl, l);
+        if (l > 0) put(e1 + 4, b.tg[net.enc(l, 0)], C[l - 1], C[l - 1], l);
+        // second convolution
+        put(e2 + 0, b.e0[l], Cl, Cl, l);
+        if (l + 1 < L) put(e2 + 1, b.cat[l] + Cl, 2 * Cl, Cl, l);
+        else put(e2 + 1, b.elast, Cl, Cl, l);
+        if (l + 1 < L) put(e2 + 2, b.tp[l], Cl, Cl, l);
+        else if (L > 1) put(e2 + 2, b.tg[net.dec(L - 2)], Cl, Cl, l);
+        else put(e2 + 2, b.gh, Cl, Cl, l);
+        put(e2 + 3, b.tz[net.enc(l, 1)], Cl, Cl, l);
+        put(e2 + 4, b.tg[net.enc(l, 1)], Cl, Cl, l);
+    }
+    for (int l = (int)L - 2; l >= 0; --l) {
+        const uint32_t Cl = C[l], Cu = C[l + 1];
+        const uint32_t it = (uint32_t)net.dec((uint32_t)l);
+        const uint32_t t5 = it * 5, c15 = (it + 1) * 5, c25 = (it + 2) * 5;
+        // transposed convolution from level l + 1
+        put(t5 + 0, l + 2 == (int)L ? b.elast : b.d1[l + 1], Cu, Cu, (uint32_t)l + 1);
+        put(t5 + 1, b.cat[l], 2 * Cl, Cl, (uint32_t)l);
+        put(t5 + 2, b.dcat[l], 2 * Cl, Cl, (uint32_t)l);
+        put(t5 + 4, b.tg[it], Cu, Cu, (uint32_t)l + 1);
+        // the level's two convolutions
+        put(c15 + 0, b.cat[l], 2 * Cl, 2 * Cl, (uint32_t)l);
+        put(c15 + 1, b.d0[l], Cl, Cl, (uint32_t)l);
+        put(c15 + 2, b.tg[it + 2], Cl, Cl, (uint32_t)l);
+        put(c15 + 3, b.tz[it + 1], Cl, Cl, (uint32_t)l);
+        put(c15 + 4, b.dcat[l], 2 * Cl, 2 * Cl, (uint32_t)l);
+        put(c25 + 0, b.d0[l], Cl, Cl, (uint32_t)l);
+        put(c25 + 1, b.d1[l], Cl, Cl, (uint32_t)l);
+        if (l == 0) put(c25 + 2, b.gh, Cl, Cl, 0);
+        else put(c25 + 2, b.tg[net.dec((uint32_t)l - 1)], Cl, Cl, (uint32_t)l);
+        put(c25 + 3, b.tz[it + 2], Cl, Cl, (uint32_t)l);
+        put(c25 + 4, b.tg[it + 2], Cl, Cl, (uint32_t)l);
+    }
+    const uint32_t h5 = (uint32_t)net.head() * 5;
+    put(h5 + 0, L > 1 ? b.d1[0] : b.elast, C[0], C[0], 0);
+    put(h5 + 4, b.gh, C[0], C[0], 0);
+    return n;
 }
 
 hipError_t fill(const Device& dev, uint32_t levels, const float* th, const uint32_t* rgba, const float* depth,
@@ -1962,12 +2066,12 @@ hipError_t fill(const Device& dev, uint32_t levels, const float* th, const uint3
 hipError_t train_step(const Device& dev, uint32_t levels, float* th, float* m, float* v, uint32_t step,
                       float lr, const uint32_t* rgba, const float* depth, const uint8_t* cov,
                       const uint32_t* tgt, uint32_t N, uint32_t H, uint32_t W, float* loss, float* grad_out,
-                      void* ws, hipStream_t s)
+                      void* ws, hipStream_t s, bool trace)
 {
     DevScope dscope(dev);
     Net net(levels);
     Bufs b;
-    carve(net, N, H, W, true, (char*)ws, &b);
+    carve(net, N, H, W, true, (char*)ws, &b, trace);
     if (grad_out) b.grad = grad_out;
     const uint32_t P = N * H * W;
     k_pack_input<<<blocks(P), dim3(kBlock), 0, s>>>(rgba, depth, cov, P, b.x0);

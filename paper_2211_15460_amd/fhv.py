@@ -67,6 +67,11 @@ class BatchViews_(C.Structure):
                 ("height", C.c_uint32), ("splat_px", C.c_uint32)]
 
 
+class FillTensor_(C.Structure):
+    _fields_ = [("offset", C.c_uint64), ("stride", C.c_uint32), ("channels", C.c_uint32), ("n", C.c_uint32),
+                ("height", C.c_uint32), ("width", C.c_uint32)]
+
+
 class Tuning_(C.Structure):
     _fields_ = [("tile_w", C.c_uint32), ("raster_wg", C.c_uint32), ("splat_wg", C.c_uint32)]
 
@@ -83,7 +88,8 @@ EXPORTS = ["fhv_create", "fhv_destroy", "fhv_status_str", "fhv_capture_workspace
            "fhv_profile_end", "fhv_unet_param_count", "fhv_fill_workspace", "fhv_fill",
            "fhv_fill_train_step", "fhv_get_tuning", "fhv_set_tuning", "fhv_batch_workspace",
            "fhv_batch_run", "fhv_probe", "fhv_raycast_workspace", "fhv_raycast", "fhv_capture_arrays_workspace",
-           "fhv_capture_arrays", "fhv_shade"]
+           "fhv_capture_arrays", "fhv_shade", "fhv_fill_trace_tensors",
+           "fhv_fill_train_step_traced"]
 
 _lib = None
 _ctx: dict[int, C.c_void_p] = {}
@@ -121,6 +127,10 @@ def lib():
                                C.c_size_t, P]
         L.fhv_fill_train_step.argtypes = [P, C.c_uint32, P, P, P, C.c_uint32, C.c_float, P, P, P, P,
                                           C.c_uint32, C.c_uint32, C.c_uint32, P, P, P, C.c_size_t, P]
+        L.fhv_fill_train_step_traced.argtypes = L.fhv_fill_train_step.argtypes
+        L.fhv_fill_trace_tensors.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
+                                             C.POINTER(FillTensor_), C.c_uint32]
+        L.fhv_fill_trace_tensors.restype = C.c_uint32
         L.fhv_get_tuning.argtypes = [P, C.POINTER(Tuning_)]
         L.fhv_set_tuning.argtypes = [P, C.POINTER(Tuning_)]
         L.fhv_batch_workspace.argtypes = [C.POINTER(BatchMesh_), C.POINTER(BatchViews_), C.c_uint64]
@@ -141,7 +151,8 @@ def lib():
         L.fhv_profile_end.argtypes = [P, C.POINTER(KernelStat_), C.c_uint32, C.POINTER(C.c_uint32)]
         for f in ("fhv_create", "fhv_destroy", "fhv_capture", "fhv_compact", "fhv_splat",
                   "fhv_profile_begin", "fhv_profile_end", "fhv_fill", "fhv_fill_train_step",
-                  "fhv_get_tuning", "fhv_set_tuning", "fhv_batch_run", "fhv_probe", "fhv_raycast", "fhv_capture_arrays", "fhv_shade"):
+                  "fhv_get_tuning", "fhv_set_tuning", "fhv_batch_run", "fhv_probe", "fhv_raycast", "fhv_capture_arrays",
+                  "fhv_shade", "fhv_fill_train_step_traced"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -460,8 +471,12 @@ def unet_param_count(levels: int = 4) -> int:
     return int(lib().fhv_unet_param_count(levels))
 
 
-def fill_workspace(levels: int, n_img: int, height: int, width: int, training: bool) -> int:
-    return int(lib().fhv_fill_workspace(levels, n_img, height, width, 1 if training else 0))
+FHV_FILL_INFER, FHV_FILL_TRAIN, FHV_FILL_TRACE = 0, 1, 2
+
+
+def fill_workspace(levels: int, n_img: int, height: int, width: int, training: bool | int) -> int:
+    mode = training if isinstance(training, int) and not isinstance(training, bool) else (1 if training else 0)
+    return int(lib().fhv_fill_workspace(levels, n_img, height, width, mode))
 
 
 def _ws(t: torch.Tensor | None, need: int, device) -> torch.Tensor:
@@ -494,6 +509,34 @@ def fill_train_step(params: torch.Tensor, m: torch.Tensor | None, v: torch.Tenso
                                      _ptr(rgba), _ptr(depth), _ptr(cov), _ptr(target), N, H, W,
                                      _ptr(loss), _ptr(grad), _ptr(ws), ws.numel(), _stream()),
            "fhv_fill_train_step")
+    return ws
+
+
+def fill_trace_tensors(levels: int, n_img: int, height: int, width: int) -> list[dict]:
+    """fhv_fill_trace_tensors: five entries per parameter layer (input,
+    output, gradient received, masked gradient, input gradient); None where
+    a layer has no such tensor."""
+    n = int(lib().fhv_fill_trace_tensors(levels, n_img, height, width, None, 0))
+    if n == 0:
+        raise FhvError("fhv_fill_trace_tensors: sizes out of range")
+    arr = (FillTensor_ * n)()
+    lib().fhv_fill_trace_tensors(levels, n_img, height, width, arr, n)
+    return [None if t.channels == 0 else {"offset": int(t.offset), "stride": int(t.stride),
+                                          "channels": int(t.channels), "shape": (t.n, t.height, t.width)}
+            for t in arr]
+
+
+def fill_train_step_traced(params: torch.Tensor, rgba: torch.Tensor, depth: torch.Tensor, cov: torch.Tensor,
+                           target: torch.Tensor, levels: int = 4, loss: torch.Tensor | None = None,
+                           grad: torch.Tensor | None = None) -> torch.Tensor:
+    """fhv_fill_train_step_traced with step 0 (gradients only); returns the
+    workspace, whose tensors fill_trace_tensors locates."""
+    N, H, W = rgba.shape
+    ws = _ws(None, fill_workspace(levels, N, H, W, FHV_FILL_TRACE), rgba.device)
+    _check(lib().fhv_fill_train_step_traced(ctx(), levels, _ptr(params), None, None, 0, 0.0,
+                                            _ptr(rgba), _ptr(depth), _ptr(cov), _ptr(target), N, H, W,
+                                            _ptr(loss), _ptr(grad), _ptr(ws), ws.numel(), _stream()),
+           "fhv_fill_train_step_traced")
     return ws
 
 

@@ -91,7 +91,7 @@ def test_probe_rejects_bad_arguments(F):
     buf = torch.zeros(4096, dtype=torch.uint8, device="cuda")
     L = F.lib()
     p = C.c_void_p(buf.data_ptr())
-    for kind, nbytes, line, passes in ((4, 4096, 128, 1), (1, 4096, 96, 1), (1, 4096, 4, 1),
+    for kind, nbytes, line, passes in ((6, 4096, 128, 1), (1, 4096, 96, 1), (1, 4096, 4, 1),
                                        (1, 4096, 8192, 1), (1, 64, 128, 1), (1, 4096, 128, 0),
                                        (1, 4096, 128, 1025), (0, 48, 0, 0), (0, 16, 0, 0)):
         assert L.fhv_probe(F.ctx(), kind, p, nbytes, line, passes, None) == -1
