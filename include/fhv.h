@@ -20,7 +20,8 @@
  * Conventions shared by every call:
  *   - Every buffer pointer in a struct or argument is a DEVICE pointer owned
  *     by the caller, unless the comment says "host". The library allocates
- *     nothing on the device; scratch memory comes in through `ws`.
+ *     nothing on the device; scratch memory comes in through `ws` (except
+ *     fhv_splat_static, whose scratch is a fixed array in the library).
  *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream)
  *     and the calls return without waiting for it. Results that are data
  *     dependent (fragment counts, occupied octants) stay on the device.
@@ -258,6 +259,26 @@ FHV_API fhv_status fhv_splat(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_cap
                      const fhv_view* views, uint32_t n_views, uint64_t* zbuf, uint32_t* rgba,
                      float* depth, uint8_t* cov, void* ws, size_t ws_bytes, fhv_stream stream);
 
+/* fhv_splat without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid allocation): same arguments (minus ws), same kernels, same
+ * results. The scratch is a FHV_SPLAT_STATIC_BYTES array in the library's
+ * device image, one per GPU, present from the library's load until the
+ * process ends; fhv_create looks up its address on the context's device.
+ * The call allocates nothing and calls no allocating routine.
+ * Limit: fhv_splat_workspace(arrays->cap_frag, n_views, width, height) must
+ * be at most FHV_SPLAT_STATIC_BYTES (e.g. cap_frag up to about 15 M records
+ * with 3 views); larger calls return EWORKSPACE before anything is
+ * enqueued. Every call on one GPU shares that GPU's array, which keeps the
+ * last call's contents (each call clears what it counts in): calls on one
+ * stream are ordered, but calls that can overlap on one GPU (different
+ * streams, or different contexts on the same device) race on it and must be
+ * ordered by the caller.
+ * Errors: as fhv_splat, and EWORKSPACE for calls beyond the limit. */
+#define FHV_SPLAT_STATIC_BYTES (32u << 20)
+FHV_API fhv_status fhv_splat_static(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_capture_desc* desc,
+                                    const fhv_view* views, uint32_t n_views, uint64_t* zbuf, uint32_t* rgba,
+                                    float* depth, uint8_t* cov, fhv_stream stream);
 
 /* Ray casting (Sec. 3.3, evaluation by ray casting) of POFL per-octant
  * arrays into orthographic views. The ray of pixel (x, y) meets array

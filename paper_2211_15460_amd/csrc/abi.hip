@@ -60,7 +60,15 @@ struct fhv_ctx {
     };
     std::vector<Graph> graphs;
     hipStream_t rec_stream = nullptr;   // stream the graphs are recorded on
+    // device address of the static splat scratch on this context's device
+    void* scratch = nullptr;
 };
+
+// Scratch of fhv_splat_static: one array per GPU in the library's device
+// image. Host code never uses this name as an address (on the host it is a
+// stand-in, not device memory): fhv_create looks up the array's address on
+// its device and keeps it in the context.
+static __device__ __align__(256) unsigned char scratch[FHV_SPLAT_STATIC_BYTES];
 
 namespace {
 
@@ -267,8 +275,22 @@ fhv_status fhv_create(fhv_ctx** out, int hip_device)
     int cus = 0;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device);
     if (e != hipSuccess) return hip_status(e);
+    // the static splat scratch's address on this device (each GPU holds its
+    // own copy of the array), looked up with the device current
+    int prev = 0;
+    e = hipGetDevice(&prev);
+    if (e != hipSuccess) return hip_status(e);
+    e = hipSetDevice(hip_device);
+    if (e != hipSuccess) return hip_status(e);
+    void* sp = nullptr;
+    e = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+    const hipError_t e2 = hipSetDevice(prev);
+    if (e != hipSuccess) return hip_status(e);
+    if (e2 != hipSuccess) return hip_status(e2);
+    if (!sp) return FHV_EHIP + (int)hipErrorInvalidSymbol;
     fhv_ctx* c = new (std::nothrow) fhv_ctx;
     if (!c) return FHV_EINVAL;
+    c->scratch = sp;
     c->dev.id = hip_device;
     c->dev.cus = cus > 0 ? cus : 256;
     c->dev.prof = nullptr;
@@ -399,7 +421,7 @@ size_t fhv_splat_workspace(uint64_t cap_frag, uint32_t n_views, uint32_t width, 
 
 namespace {
 
-// Host-side checks of a splat call; fills the
+// Host-side checks shared by fhv_splat and fhv_splat_static; fills the
 // kernels' view arguments and the workspace the call needs.
 fhv_status splat_check(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_capture_desc* desc, const fhv_view* views,
                        uint32_t n_views, uint64_t* zbuf, uint32_t* rgba, float* depth, uint8_t* cov,
@@ -446,6 +468,22 @@ fhv_status fhv_splat(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_capture_des
     if (!ws) return FHV_EINVAL;
     if ((st = set_device(ctx)) != FHV_OK) return st;
     return hip_status(fhv::splat_launch(ctx->dev, arrays, desc, va, zbuf, rgba, depth, cov, ws,
+                                        (hipStream_t)stream));
+}
+
+fhv_status fhv_splat_static(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_capture_desc* desc,
+                            const fhv_view* views, uint32_t n_views, uint64_t* zbuf, uint32_t* rgba,
+                            float* depth, uint8_t* cov, fhv_stream stream)
+{
+    fhv::ViewArgs va;
+    size_t need = 0;
+    fhv_status st = splat_check(ctx, arrays, desc, views, n_views, zbuf, rgba, depth, cov, &va, &need);
+    if (st != FHV_OK) return st;
+    if (need > (size_t)FHV_SPLAT_STATIC_BYTES) return FHV_EWORKSPACE;
+    if (!ctx->scratch) return FHV_EINVAL;
+    if ((st = set_device(ctx)) != FHV_OK) return st;
+    // the kernels get the array's device address, never its host-side name
+    return hip_status(fhv::splat_launch(ctx->dev, arrays, desc, va, zbuf, rgba, depth, cov, ctx->scratch,
                                         (hipStream_t)stream));
 }
 

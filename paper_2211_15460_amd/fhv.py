@@ -88,7 +88,7 @@ EXPORTS = ["fhv_create", "fhv_destroy", "fhv_status_str", "fhv_capture_workspace
            "fhv_profile_end", "fhv_unet_param_count", "fhv_fill_workspace", "fhv_fill",
            "fhv_fill_train_step", "fhv_get_tuning", "fhv_set_tuning", "fhv_batch_workspace",
            "fhv_batch_run", "fhv_probe", "fhv_raycast_workspace", "fhv_raycast", "fhv_capture_arrays_workspace",
-           "fhv_capture_arrays", "fhv_shade", "fhv_fill_trace_tensors",
+           "fhv_capture_arrays", "fhv_shade", "fhv_splat_static", "fhv_fill_trace_tensors",
            "fhv_fill_train_step_traced"]
 
 _lib = None
@@ -119,6 +119,8 @@ def lib():
         L.fhv_splat_workspace.restype = C.c_size_t
         L.fhv_splat.argtypes = [P, C.POINTER(Pofa_), C.POINTER(Desc_), C.POINTER(View_), C.c_uint32,
                                 P, P, P, P, P, C.c_size_t, P]
+        L.fhv_splat_static.argtypes = [P, C.POINTER(Pofa_), C.POINTER(Desc_), C.POINTER(View_), C.c_uint32,
+                                       P, P, P, P, P]
         L.fhv_unet_param_count.argtypes = [C.c_uint32]
         L.fhv_unet_param_count.restype = C.c_uint64
         L.fhv_fill_workspace.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int]
@@ -152,7 +154,7 @@ def lib():
         for f in ("fhv_create", "fhv_destroy", "fhv_capture", "fhv_compact", "fhv_splat",
                   "fhv_profile_begin", "fhv_profile_end", "fhv_fill", "fhv_fill_train_step",
                   "fhv_get_tuning", "fhv_set_tuning", "fhv_batch_run", "fhv_probe", "fhv_raycast", "fhv_capture_arrays",
-                  "fhv_shade", "fhv_fill_train_step_traced"):
+                  "fhv_shade", "fhv_splat_static", "fhv_fill_train_step_traced"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -374,6 +376,22 @@ def splat(arrays: Pofa, d: Desc_, views, out: Images | None = None, vstruct=None
         _check(lib().fhv_splat(ctx(), C.byref(ps), C.byref(d), arr, len(vs),
                                _ptr(out.zbuf[v0:]), _ptr(out.rgba[v0:]), _ptr(out.depth[v0:]),
                                _ptr(out.cov[v0:]), _ptr(ws), ws.numel(), _stream()), "fhv_splat")
+    return out
+
+
+SPLAT_STATIC_BYTES = 32 << 20   # FHV_SPLAT_STATIC_BYTES
+
+
+def splat_static(arrays: Pofa, d: Desc_, views, out: Images, vstruct=None) -> Images:
+    """fhv_splat_static of up to 32 views into the caller's images: the
+    library's static scratch instead of a workspace; nothing is allocated."""
+    if len(views) > 32:
+        raise FhvError("fhv_splat_static: at most 32 views per call")
+    arr = vstruct if vstruct is not None else views_struct(views)
+    ps = arrays.struct()
+    _check(lib().fhv_splat_static(ctx(), C.byref(ps), C.byref(d), arr, len(views), _ptr(out.zbuf),
+                                  _ptr(out.rgba), _ptr(out.depth), _ptr(out.cov), _stream()),
+           "fhv_splat_static")
     return out
 
 
