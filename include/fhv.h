@@ -267,15 +267,15 @@ FHV_API fhv_status fhv_splat(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_cap
  * process ends; fhv_create looks up its address on the context's device.
  * The call allocates nothing and calls no allocating routine.
  * Limit: fhv_splat_workspace(arrays->cap_frag, n_views, width, height) must
- * be at most FHV_SPLAT_STATIC_BYTES (e.g. cap_frag up to about 15 M records
- * with 3 views); larger calls return EWORKSPACE before anything is
+ * be at most FHV_SPLAT_STATIC_BYTES (cap_frag up to about 7.8 M records,
+ * whatever the views); larger calls return EWORKSPACE before anything is
  * enqueued. Every call on one GPU shares that GPU's array, which keeps the
  * last call's contents (each call clears what it counts in): calls on one
  * stream are ordered, but calls that can overlap on one GPU (different
  * streams, or different contexts on the same device) race on it and must be
  * ordered by the caller.
  * Errors: as fhv_splat, and EWORKSPACE for calls beyond the limit. */
-#define FHV_SPLAT_STATIC_BYTES (32u << 20)
+#define FHV_SPLAT_STATIC_BYTES (64u << 20)
 FHV_API fhv_status fhv_splat_static(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_capture_desc* desc,
                                     const fhv_view* views, uint32_t n_views, uint64_t* zbuf, uint32_t* rgba,
                                     float* depth, uint8_t* cov, fhv_stream stream);
@@ -347,7 +347,8 @@ FHV_API fhv_status fhv_shade(fhv_ctx* ctx, const fhv_pofa* arrays, const uint64_
  * the concatenated pos/rgba; scene_tri: DEVICE uint32 [n_scenes + 1],
  * non-decreasing, scene_tri[0] = 0, scene_tri[n_scenes] = n_tri: scene s
  * owns triangles [scene_tri[s], scene_tri[s+1]). Every scene uses the scene
- * cube [0,1)^3 and octree depth `levels` (1..11). */
+ * cube [0,1)^3 and octree depth `levels` (1..11); the key space
+ * n_scenes * 8^levels is at most 2^39. */
 typedef struct {
     const float* pos;
     const uint32_t* rgba;

@@ -109,9 +109,10 @@ bool batch_shape_ok(const fhv_batch_mesh* m, const fhv_batch_views* v)
 {
     if (!m || !v) return false;
     if (m->n_scenes < 1 || m->levels < 1 || m->levels > 11) return false;
-    // key space n_scenes * 8^L up to 2^40 (bricks and bitmap of the
-    // compaction grow with it)
-    if (((uint64_t)m->n_scenes << (3 * m->levels)) > (1ull << 40)) return false;
+    // key space n_scenes * 8^L up to 2^39 (bricks and bitmap of the
+    // compaction grow with it; the splat packs a fragment's scene and grid
+    // position into 63 bits)
+    if (((uint64_t)m->n_scenes << (3 * m->levels)) > (1ull << 39)) return false;
     if (v->n_views < 1 || v->n_views > fhv::kMaxViews) return false;
     if (v->width < 1 || v->width > 16384 || v->height < 1 || v->height > 16384) return false;
     if (v->splat_px < 1 || v->splat_px > 64) return false;

@@ -6,29 +6,27 @@
 // one workgroup owns a tile, holding its depth test in LDS, so no z-buffer
 // entry is touched by more than one workgroup and no global atomic decides a
 // pixel. The arrays are cut into chunks of 64 consecutive fragments (one per
-// lane); in Morton order a chunk is a compact piece of surface, and its
-// positions' bounding box, projected into a view, names the few tiles the
-// chunk can reach there.
+// lane); in Morton order a chunk is a compact piece of surface, and so is a
+// run of 64 consecutive chunks, and of 64 such runs, and so on: the bounding
+// boxes of those runs form a tree over the arrays that a tile's workgroup
+// walks to find the few chunks that can reach it, with no binning pass and
+// no atomic on global memory.
 //
-//   k_tile_count  one wave per chunk: the bounding box of its fragment
-//                 positions (and the range of scenes its keys belong to);
-//                 per (scene, view) of the chunk, the pixel rectangle its
-//                 footprints can reach (with a margin that covers the fp32
-//                 rounding of every fragment inside the box); a rectangle
-//                 over at most 4 tiles counts the chunk once in each tile's
-//                 bin, a larger one once in the view's own bin
-//   scan          bin offsets (bins: every tile, then every view)
-//   k_tile_write  the same rectangles again; the chunk's index goes into
-//                 each tile bin, or the chunk with its rectangle into the
-//                 view bin
-//   k_tile_splat  one workgroup per tile: z-tile of 64-bit keys (fp32 depth
-//                 bits << 32 | fragment index) in LDS, cleared; every chunk of
-//                 the tile's bin, and every chunk of the view's bin whose
-//                 rectangle meets the tile, projected fragment by fragment
-//                 (fp32 3x4 transform without fused multiply-adds) with an
-//                 LDS 64-bit minimum for each footprint pixel inside the tile;
-//                 then each pixel of the tile written once: key, winner's
-//                 colour (w1), depth and coverage
+//   k_chunk_box   one wave per chunk: the bounding box of its fragment
+//                 positions (and the range of scenes its keys belong to)
+//   k_node_box    one wave per node of the next level up: the union of its
+//                 64 children's boxes, up to a single root
+//   k_tile_splat  one workgroup of 16 waves per tile: z-tile of 64-bit keys
+//                 (fp32 depth bits << 32 | fragment index) in LDS, cleared;
+//                 the tree walked from the root, each node's 64 children
+//                 tested at once (one per lane) by projecting the child's box
+//                 into the view with a margin that covers the fp32 rounding
+//                 of every fragment inside it; every chunk that can reach the
+//                 tile projected fragment by fragment (fp32 3x4 transform
+//                 without fused multiply-adds) with an LDS 64-bit minimum for
+//                 each footprint pixel inside the tile; then each pixel of the
+//                 tile written once: key, winner's colour (w1), depth and
+//                 coverage
 //
 // A batch (many scenes in one key space, key = scene << 3L | Morton code)
 // runs the same kernels over (scene, view) slots; a fragment only draws into
@@ -37,7 +35,6 @@
 #include <string.h>
 
 #include "fhv_common.h"
-#include "scan.h"
 
 namespace fhv {
 
@@ -46,7 +43,6 @@ namespace {
 constexpr int kChunk = kWave;       // fragments per chunk, one per lane
 constexpr int kTile = 64;           // tile side in pixels
 constexpr int kTilePix = kTile * kTile;
-constexpr uint32_t kTileBinMax = 4; // larger rectangles go to the view's bin
 
 // Position of array fragment r in the view's input space: PPFL
 // (px + 1/2, py + 1/2, depth24), POFL grid position + 1/2.
@@ -78,9 +74,12 @@ struct TileArgs {
     uint32_t shift;        // batches: scene = key >> shift; else 64 (no scene bits)
     uint32_t cap_w;        // PPFL capture width (pixel keys)
     uint64_t cap_frag, cap_occ;
-    // capacities of the two lists; arrays in key order never reach them (a
-    // write beyond is dropped, a read beyond is not made)
-    uint32_t cap_t, cap_b;
+    // chunk tree: levels (level 0 = chunks, the last = the root), where each
+    // level's boxes start (in nodes), nodes of all levels for cap_frag
+    uint32_t levels;
+    uint64_t lv_off[8];
+    uint64_t n_nodes;
+    uint32_t gbits;        // POFL: bits per grid coordinate (octree depth + 8)
 };
 
 // Matrix, footprint side and offset 1/2 - k/2 of view slot g (scene g / V,
@@ -104,45 +103,53 @@ struct PixRect {
 };
 
 // Pixels that the footprint of any fragment in the box [lo, hi] can reach
-// in a view. The box's corners are projected in fp64 (every product of two
-// fp32 values is exact there); a fragment's fp32 projection differs from the
-// exact value at its position by less than 2^-21 of the sum of the absolute
-// terms, which is largest at a corner, so the margin 2^-20 (B + |c| + 1)
-// covers it and the rounding of sx + c. A matrix or box that is not finite
+// in a view, in fp32. Each row of the matrix taken over the box has its
+// smallest and largest values at m3 plus, per axis, the smaller and the
+// larger of the products with the box's two bounds; B (per axis the larger
+// absolute product, plus |m3|) bounds the sum of the absolute terms at any
+// point of the box. A fragment's fp32 projection differs from the exact
+// value at its position by less than 2^-21 B, the fp32 evaluation here
+// (four products and sums) by less than 2^-22 B, and the rounding of the
+// shifted bounds below by less than 2^-24 (B + |c| + 1): the margin
+// 2^-20 (B + |c| + 1) covers all three. A matrix or box that is not finite
 // reaches the whole view; a box whose depth is <= 0 everywhere reaches
 // nothing (such fragments are not drawn).
 __device__ PixRect chunk_rect(const float* M, float c, uint32_t k, uint32_t W, uint32_t H, float4 lo, float4 hi)
 {
     PixRect r{1, 1, 0, 0};
     if (!(lo.x <= hi.x)) return r;   // no drawable fragment
-    double smin[3] = {INFINITY, INFINITY, INFINITY}, smax[3] = {-INFINITY, -INFINITY, -INFINITY};
-    double B[3] = {0.0, 0.0, 0.0};
-    for (int q = 0; q < 8; ++q) {
-        const double x = (q & 1) ? hi.x : lo.x, y = (q & 2) ? hi.y : lo.y, z = (q & 4) ? hi.z : lo.z;
-        for (int row = 0; row < 3; ++row) {
-            const double a0 = (double)M[4 * row] * x, a1 = (double)M[4 * row + 1] * y,
-                         a2 = (double)M[4 * row + 2] * z, a3 = (double)M[4 * row + 3];
-            const double sv = ((a0 + a1) + a2) + a3;
-            const double b = ((fabs(a0) + fabs(a1)) + fabs(a2)) + fabs(a3);
-            smin[row] = fmin(smin[row], sv);
-            smax[row] = fmax(smax[row], sv);
-            B[row] = fmax(B[row], b);
+    const float l3[3] = {lo.x, lo.y, lo.z}, h3[3] = {hi.x, hi.y, hi.z};
+    float smin[3], smax[3], B[3];
+#pragma unroll
+    for (int row = 0; row < 3; ++row) {
+        const float m3 = M[4 * row + 3];
+        float mn = m3, mx = m3, b = fabsf(m3);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float m = M[4 * row + a];
+            const float p = m * l3[a], q = m * h3[a];
+            mn += fminf(p, q);
+            mx += fmaxf(p, q);
+            b += fmaxf(fabsf(p), fabsf(q));
         }
+        smin[row] = mn;
+        smax[row] = mx;
+        B[row] = b;
     }
-    const double eps = 0x1p-20;
+    const float eps = 0x1p-20f;
     bool finite = true;
+#pragma unroll
     for (int row = 0; row < 3; ++row) finite = finite && isfinite(smin[row]) && isfinite(smax[row]) && isfinite(B[row]);
     if (!finite) return PixRect{0, 0, (int32_t)W - 1, (int32_t)H - 1};
-    if (smax[2] + eps * (B[2] + 1.0) <= 0.0) return r;
-    const double cc = (double)c;
-    const double mx = eps * (B[0] + fabs(cc) + 1.0), my = eps * (B[1] + fabs(cc) + 1.0);
-    const double fx0 = floor(smin[0] - mx + cc), fx1 = floor(smax[0] + mx + cc) + (double)(k - 1);
-    const double fy0 = floor(smin[1] - my + cc), fy1 = floor(smax[1] + my + cc) + (double)(k - 1);
-    if (fx1 < 0.0 || fy1 < 0.0 || fx0 > (double)W - 1.0 || fy0 > (double)H - 1.0) return r;
-    r.x0 = fx0 < 0.0 ? 0 : (int32_t)fx0;
-    r.y0 = fy0 < 0.0 ? 0 : (int32_t)fy0;
-    r.x1 = fx1 > (double)W - 1.0 ? (int32_t)W - 1 : (int32_t)fx1;
-    r.y1 = fy1 > (double)H - 1.0 ? (int32_t)H - 1 : (int32_t)fy1;
+    if (smax[2] + eps * (B[2] + 1.0f) <= 0.0f) return r;
+    const float mx = eps * (B[0] + fabsf(c) + 1.0f), my = eps * (B[1] + fabsf(c) + 1.0f);
+    const float fx0 = floorf(smin[0] - mx + c), fx1 = floorf(smax[0] + mx + c) + (float)(k - 1);
+    const float fy0 = floorf(smin[1] - my + c), fy1 = floorf(smax[1] + my + c) + (float)(k - 1);
+    if (!(fx1 >= 0.0f && fy1 >= 0.0f && fx0 <= (float)W - 1.0f && fy0 <= (float)H - 1.0f)) return r;
+    r.x0 = fx0 < 0.0f ? 0 : (int32_t)fx0;
+    r.y0 = fy0 < 0.0f ? 0 : (int32_t)fy0;
+    r.x1 = fx1 > (float)W - 1.0f ? (int32_t)W - 1 : (int32_t)fx1;
+    r.y1 = fy1 > (float)H - 1.0f ? (int32_t)H - 1 : (int32_t)fy1;
     return r;
 }
 
@@ -186,60 +193,52 @@ __device__ __forceinline__ uint64_t frag_total(const uint64_t* n_frag, uint64_t 
     return nf < cap ? nf : cap;
 }
 
-// Binning of one chunk: `pass` 0 counts into cnt, pass 1 writes into the
-// lists at the cursors. Lanes take the chunk's (scene, view) slots.
-template <bool kBatch>
-__device__ void bin_chunk(int pass, uint32_t ch, float4 lo, float4 hi, const TileArgs& ta, const ViewSrc<kBatch>& vs,
-                          uint32_t* __restrict__ cnt, uint32_t* __restrict__ cur, uint32_t* __restrict__ list_t,
-                          uint4* __restrict__ list_b, const uint32_t* __restrict__ off)
+// The chunk tree: level 0 holds the chunks' boxes, every node of level
+// l + 1 the union of the boxes of its kFan children (nodes kFan n .. kFan n
+// + kFan - 1 of level l), up to a single root. Boxes are pairs (low, high)
+// of float4 with the scene range in w (as uint bits: lowest scene in the
+// low corner, highest in the high one); an empty box has low > high.
+constexpr int kFan = kWave;
+constexpr int kMaxLevels = 8;
+
+// Nodes of each level for F fragments, into n[0 .. levels).
+__device__ __forceinline__ void level_counts(uint64_t F, uint32_t levels, uint32_t* n)
 {
-    if (!(lo.x <= hi.x)) return;
-    const uint32_t s_lo = __float_as_uint(lo.w), s_hi = __float_as_uint(hi.w);
-    const uint32_t n_pairs = (s_hi - s_lo + 1) * ta.n_views;
-    for (uint32_t p = __lane_id(); p < n_pairs; p += kWave) {
-        const uint32_t g = (s_lo + p / ta.n_views) * ta.n_views + p % ta.n_views;
-        const PixRect r = chunk_rect(vs.m(g), vs.c(g), vs.k(g), ta.width, ta.height, lo, hi);
-        if (r.x0 > r.x1 || r.y0 > r.y1) continue;
-        const uint32_t tx0 = (uint32_t)r.x0 / kTile, tx1 = (uint32_t)r.x1 / kTile;
-        const uint32_t ty0 = (uint32_t)r.y0 / kTile, ty1 = (uint32_t)r.y1 / kTile;
-        const uint32_t n = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
-        if (n <= kTileBinMax) {
-            for (uint32_t ty = ty0; ty <= ty1; ++ty)
-                for (uint32_t tx = tx0; tx <= tx1; ++tx) {
-                    const uint32_t b = g * ta.per_view + ty * ta.nx + tx;
-                    if (pass == 0) {
-                        atomicAdd(cnt + b, 1u);
-                    } else {
-                        const uint32_t at = atomicAdd(cur + b, 1u);
-                        if (at < ta.cap_t) list_t[at] = ch;
-                    }
-                }
-        } else {
-            const uint32_t b = ta.n_tiles + g;
-            if (pass == 0) {
-                atomicAdd(cnt + b, 1u);
-            } else {
-                const uint32_t at = atomicAdd(cur + b, 1u) - off[ta.n_tiles];
-                if (at < ta.cap_b)
-                    list_b[at] = make_uint4(ch, (uint32_t)r.x0 | ((uint32_t)r.y0 << 16),
-                                            (uint32_t)r.x1 | ((uint32_t)r.y1 << 16), 0u);
-            }
-        }
+    uint64_t c = (F + kChunk - 1) / kChunk;
+    for (uint32_t l = 0; l < levels; ++l) {
+        n[l] = (uint32_t)c;
+        c = (c + kFan - 1) / kFan;
     }
+}
+
+// Packed position of a fragment for the tile kernel: bit 63 set when the
+// fragment is drawn at all; POFL: grid x, y, z (gbits each) and the scene
+// above them; PPFL: pixel x, y (14 bits each) and depth24.
+template <int kMode>
+__device__ __forceinline__ uint64_t pack_pos(const uint4& r, uint64_t key, uint32_t scene, bool ok, const TileArgs& ta)
+{
+    if (!ok) return 0;
+    if (kMode == FHV_PPFL) {
+        const uint64_t px = key % ta.cap_w, py = key / ta.cap_w;
+        return (1ull << 63) | px | (py << 14) | ((uint64_t)(r.x & 0xFFFFFFu) << 28);
+    }
+    const uint32_t S = ta.gbits;
+    const uint64_t kx = compact3(key >> 2), ky = compact3(key >> 1), kz = compact3(key);
+    const uint64_t gx = (kx << 8) | (r.x & 0xFFu), gy = (ky << 8) | ((r.x >> 8) & 0xFFu),
+                   gz = (kz << 8) | ((r.x >> 16) & 0xFFu);
+    return (1ull << 63) | gx | (gy << S) | (gz << (2 * S)) | ((uint64_t)scene << (3 * S));
 }
 
 template <int kMode, bool kBatch>
 __global__ void __launch_bounds__(kBlock)
-k_tile_count(const uint4* __restrict__ frag, const uint64_t* __restrict__ oct_key, const uint64_t* __restrict__ n_frag,
-             TileArgs ta, ViewArgs va, const float* __restrict__ vm, float4* __restrict__ box,
-             uint32_t* __restrict__ cnt)
+k_chunk_box(const uint4* __restrict__ frag, const uint64_t* __restrict__ oct_key, const uint64_t* __restrict__ n_frag,
+            TileArgs ta, float4* __restrict__ box, uint64_t* __restrict__ pos)
 {
     if (ta.cap_occ == 0) return;   // no table rows: nothing to draw
     const uint64_t F = frag_total(n_frag, ta.cap_frag);
     const uint64_t nch = (F + kChunk - 1) / kChunk;
     const int lane = __lane_id();
     const uint64_t n_waves = (uint64_t)gridDim.x * (kBlock / kWave);
-    const ViewSrc<kBatch> vs{va, vm};
     const uint64_t kmask = ta.shift >= 64 ? ~0ull : (1ull << ta.shift) - 1ull;
     for (uint64_t ch = uniform64((uint64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave); ch < nch;
          ch += n_waves) {
@@ -252,6 +251,7 @@ k_tile_count(const uint4* __restrict__ frag, const uint64_t* __restrict__ oct_ke
         ok = ok && scene < ta.n_scenes;
         float x, y, z;
         frag_pos<kMode>(r, key & kmask, ta.cap_w, &x, &y, &z);
+        pos[f] = pack_pos<kMode>(r, key & kmask, scene, ok, ta);
         float4 lo, hi;
         lo.x = wave_fmin(ok ? x : INFINITY);
         lo.y = wave_fmin(ok ? y : INFINITY);
@@ -265,37 +265,42 @@ k_tile_count(const uint4* __restrict__ frag, const uint64_t* __restrict__ oct_ke
             box[2 * ch] = lo;
             box[2 * ch + 1] = hi;
         }
-        bin_chunk<kBatch>(0, (uint32_t)ch, lo, hi, ta, vs, cnt, nullptr, nullptr, nullptr, nullptr);
     }
 }
 
-template <bool kBatch>
+// Boxes of level l (its nodes' children are on level l - 1): one wave per
+// node, one lane per child.
 __global__ void __launch_bounds__(kBlock)
-k_tile_write(const uint64_t* __restrict__ n_frag, TileArgs ta, ViewArgs va, const float* __restrict__ vm,
-             const float4* __restrict__ box, uint32_t* __restrict__ cur, const uint32_t* __restrict__ off,
-             uint32_t* __restrict__ list_t, uint4* __restrict__ list_b)
+k_node_box(const uint64_t* __restrict__ n_frag, TileArgs ta, uint32_t l, float4* __restrict__ box)
 {
     if (ta.cap_occ == 0) return;
-    const uint64_t F = frag_total(n_frag, ta.cap_frag);
-    const uint64_t nch = (F + kChunk - 1) / kChunk;
+    uint32_t n[kMaxLevels];
+    level_counts(frag_total(n_frag, ta.cap_frag), ta.levels, n);
+    const int lane = __lane_id();
     const uint64_t n_waves = (uint64_t)gridDim.x * (kBlock / kWave);
-    const ViewSrc<kBatch> vs{va, vm};
-    for (uint64_t ch = uniform64((uint64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave); ch < nch;
-         ch += n_waves)
-        bin_chunk<kBatch>(1, (uint32_t)ch, box[2 * ch], box[2 * ch + 1], ta, vs, nullptr, cur, list_t, list_b, off);
-}
-
-// Bin offsets: off[b] = sum of the counts of bins before b; the write pass's
-// cursors start there.
-struct StoreBinOff {
-    uint32_t* off;
-    uint32_t* cur;
-    __device__ void operator()(uint64_t i, uint32_t, uint32_t ex) const
-    {
-        off[i] = ex;
-        cur[i] = ex;
+    const float4* src = box + 2 * ta.lv_off[l - 1];
+    float4* dst = box + 2 * ta.lv_off[l];
+    for (uint64_t node = uniform64((uint64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave); node < n[l];
+         node += n_waves) {
+        const uint64_t c = node * kFan + lane;
+        const bool ok = c < n[l - 1];
+        const float4 a = ok ? src[2 * c] : make_float4(INFINITY, INFINITY, INFINITY, __uint_as_float(0xFFFFFFFFu));
+        const float4 b = ok ? src[2 * c + 1] : make_float4(-INFINITY, -INFINITY, -INFINITY, __uint_as_float(0u));
+        float4 lo, hi;
+        lo.x = wave_fmin(a.x);
+        lo.y = wave_fmin(a.y);
+        lo.z = wave_fmin(a.z);
+        hi.x = wave_fmax(b.x);
+        hi.y = wave_fmax(b.y);
+        hi.z = wave_fmax(b.z);
+        lo.w = __uint_as_float(wave_umin(__float_as_uint(a.w)));
+        hi.w = __uint_as_float(wave_umax(__float_as_uint(b.w)));
+        if (lane == 0) {
+            dst[2 * node] = lo;
+            dst[2 * node + 1] = hi;
+        }
     }
-};
+}
 
 // Workgroup order: consecutive workgroups go to the 8 accelerator dies in
 // turn, so that the tiles of one die form one contiguous run of tile indices
@@ -306,29 +311,70 @@ __device__ __forceinline__ uint32_t die_major(uint32_t b, uint32_t n)
     return x < r ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
 }
 
-// The lanes' fragments of chunk ch, drawn into the z-tile at (X0, Y0) of
-// view slot g of scene `scene`.
-template <int kMode, bool kBatch>
-__device__ __forceinline__ void tile_chunk(uint32_t ch, uint64_t F, const uint4* __restrict__ frag,
-                                           const uint64_t* __restrict__ oct_key, const TileArgs& ta, const float* M,
-                                           float c, int32_t k, uint32_t scene, int32_t X0, int32_t Y0,
-                                           unsigned long long* zt)
+constexpr int kTileWaves = 16;                 // waves per tile workgroup
+constexpr int kTileThreads = kTileWaves * kWave;
+constexpr uint32_t kFront = 2048;              // breadth-first frontier capacity (node ids)
+
+// What one tile's workgroup knows about its view.
+struct TileView {
+    float M[12];
+    float c;
+    int32_t k;
+    uint32_t scene;
+    int32_t X0, Y0;
+};
+
+// Which of the kFan children of node `node` (on level l, children on level
+// l - 1) can reach the tile: a bit per lane.
+template <bool kBatch>
+__device__ __forceinline__ uint64_t test_children(const float4* __restrict__ box, const TileArgs& ta,
+                                                  const uint32_t* nl, uint32_t l, uint32_t node, const TileView& tv)
 {
-    const uint64_t kmask = ta.shift >= 64 ? ~0ull : (1ull << ta.shift) - 1ull;
-    const uint64_t f = (uint64_t)ch * kChunk + __lane_id();
-    bool ok = f < F;
-    const uint4 r = ok ? frag[f] : make_uint4(0, 0, 0, 0);
-    ok = ok && r.w < ta.cap_occ;
-    const uint64_t key = oct_key[ok ? r.w : 0];
-    if (kBatch) ok = ok && (uint32_t)(key >> ta.shift) == scene;
+    const uint64_t c = (uint64_t)node * kFan + __lane_id();
+    bool ok = c < nl[l - 1];
+    float4 lo = make_float4(1.f, 0.f, 0.f, 0.f), hi = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (ok) {
+        const float4* b = box + 2 * (ta.lv_off[l - 1] + c);
+        lo = b[0];
+        hi = b[1];
+    }
+    if (kBatch) ok = ok && __float_as_uint(lo.w) <= tv.scene && tv.scene <= __float_as_uint(hi.w);
+    if (ok) {
+        const PixRect r = chunk_rect(tv.M, tv.c, (uint32_t)tv.k, ta.width, ta.height, lo, hi);
+        ok = r.x0 <= r.x1 && r.y0 <= r.y1 && r.x1 >= tv.X0 && r.x0 < tv.X0 + kTile && r.y1 >= tv.Y0 &&
+             r.y0 < tv.Y0 + kTile;
+    }
+    return __ballot(ok);
+}
+
+// The lanes' fragments (packed position p, array index f) drawn into the
+// z-tile.
+template <int kMode, bool kBatch>
+__device__ __forceinline__ void draw_pos(uint64_t p, uint64_t f, const TileArgs& ta, const TileView& tv,
+                                         unsigned long long* zt)
+{
+    bool ok = (p >> 63) != 0;
     float x, y, z;
-    frag_pos<kMode>(r, key & kmask, ta.cap_w, &x, &y, &z);
+    if (kMode == FHV_PPFL) {
+        x = (float)(uint32_t)(p & 0x3FFFu) + 0.5f;
+        y = (float)(uint32_t)((p >> 14) & 0x3FFFu) + 0.5f;
+        z = (float)(uint32_t)((p >> 28) & 0xFFFFFFu);
+    } else {
+        const uint32_t S = ta.gbits;
+        const uint64_t gm = (1ull << S) - 1ull;
+        x = (float)(uint32_t)(p & gm) + 0.5f;
+        y = (float)(uint32_t)((p >> S) & gm) + 0.5f;
+        z = (float)(uint32_t)((p >> (2 * S)) & gm) + 0.5f;
+        if (kBatch) ok = ok && (uint32_t)((p & ~(1ull << 63)) >> (3 * S)) == tv.scene;
+    }
+    const float* M = tv.M;
     const float sx = ((M[0] * x + M[1] * y) + M[2] * z) + M[3];
     const float sy = ((M[4] * x + M[5] * y) + M[6] * z) + M[7];
     const float d = ((M[8] * x + M[9] * y) + M[10] * z) + M[11];
     if (!ok || !(d > 0.0f)) return;
-    const float fx = floorf(sx + c), fy = floorf(sy + c);
+    const float fx = floorf(sx + tv.c), fy = floorf(sy + tv.c);
     const unsigned long long zk = ((unsigned long long)__float_as_uint(d) << 32) | (unsigned long long)(uint32_t)f;
+    const int32_t k = tv.k, X0 = tv.X0, Y0 = tv.Y0;
     if (k == 1) {
         if (fx >= 0.0f && fx < (float)ta.width && fy >= 0.0f && fy < (float)ta.height) {
             const int32_t px = (int32_t)fx - X0, py = (int32_t)fy - Y0;
@@ -351,49 +397,160 @@ __device__ __forceinline__ void tile_chunk(uint32_t ch, uint64_t F, const uint4*
         for (int32_t xx = xa; xx < xb; ++xx) atomicMin(zt + (yy - Y0) * kTile + (xx - X0), zk);
 }
 
+// The chunks q[i] (or base + i when q is null), i = i0, i0 + step, ... < n,
+// drawn in batches of kDrawBatch, the next batch's positions loading while
+// the current batch is drawn (so that up to 2 kDrawBatch loads of a wave
+// are in flight). Chunks beyond the arrays' end hold positions that are not
+// drawn.
+constexpr int kDrawBatch = 4;
+
 template <int kMode, bool kBatch>
-__global__ void __launch_bounds__(kBlock)
-k_tile_splat(const uint4* __restrict__ frag, const uint64_t* __restrict__ oct_key, const uint64_t* __restrict__ n_frag,
-             TileArgs ta, ViewArgs va, const float* __restrict__ vm, const uint32_t* __restrict__ off,
-             const uint32_t* __restrict__ list_t, const uint4* __restrict__ list_b,
+__device__ __forceinline__ void draw_queue(const uint32_t* q, uint64_t base, uint32_t i0, uint32_t step, uint32_t n,
+                                           const uint64_t* __restrict__ pos, const TileArgs& ta, const TileView& tv,
+                                           unsigned long long* zt)
+{
+    if (i0 >= n) return;
+    const int lane = __lane_id();
+    auto chunk = [&](uint32_t i) { return q ? (uint64_t)q[i] : base + i; };
+    uint64_t ca[kDrawBatch], pa[kDrawBatch];
+#pragma unroll
+    for (int j = 0; j < kDrawBatch; ++j) {
+        const uint32_t i = i0 + (uint32_t)j * step;
+        ca[j] = i < n ? chunk(i) : 0;
+        pa[j] = i < n ? pos[ca[j] * kChunk + lane] : 0;
+    }
+    for (uint32_t ib = i0; ib < n; ib += kDrawBatch * step) {
+        uint64_t cb[kDrawBatch], pb[kDrawBatch];
+#pragma unroll
+        for (int j = 0; j < kDrawBatch; ++j) {
+            const uint32_t i = ib + (uint32_t)(kDrawBatch + j) * step;
+            cb[j] = i < n ? chunk(i) : 0;
+            pb[j] = i < n ? pos[cb[j] * kChunk + lane] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < kDrawBatch; ++j)
+            if (ib + (uint32_t)j * step < n) draw_pos<kMode, kBatch>(pa[j], ca[j] * kChunk + lane, ta, tv, zt);
+#pragma unroll
+        for (int j = 0; j < kDrawBatch; ++j) {
+            ca[j] = cb[j];
+            pa[j] = pb[j];
+        }
+    }
+}
+
+// One workgroup per 64 x 64 tile of one view slot: the chunk tree is
+// walked from the root breadth first (children tested one per lane) down to
+// the groups of 64 chunks that can reach the tile; then, in rounds of one
+// group per wave, the chunks of those groups that can reach the tile are
+// queued in LDS and drawn by all waves in turn into the z-tile in LDS with
+// 64-bit minima. Should a level's frontier not fit in LDS, every chunk
+// below the last frontier that did is drawn. Then each pixel of the tile is
+// written once.
+template <int kMode, bool kBatch>
+__global__ void __launch_bounds__(kTileThreads)
+k_tile_splat(const uint4* __restrict__ frag, const uint64_t* __restrict__ pos, const uint64_t* __restrict__ n_frag,
+             TileArgs ta, ViewArgs va, const float* __restrict__ vm, const float4* __restrict__ box,
              unsigned long long* __restrict__ zbuf, uint32_t* __restrict__ rgba, float* __restrict__ depth,
              uint8_t* __restrict__ cov)
 {
     __shared__ unsigned long long zt[kTilePix];
+    __shared__ uint32_t front[2][kFront];
+    __shared__ uint32_t queue[kTileWaves * kFan];
+    __shared__ uint32_t nl[kMaxLevels];
+    __shared__ uint32_t sh_next, sh_over, sh_q;
     const uint32_t tile = uniform32(die_major(blockIdx.x, gridDim.x));
     const uint32_t g = tile / ta.per_view, t = tile % ta.per_view;
-    const int32_t X0 = (int32_t)((t % ta.nx) * kTile), Y0 = (int32_t)((t / ta.nx) * kTile);
-    const uint32_t scene = g / ta.n_views;
-    for (int p = threadIdx.x; p < kTilePix; p += kBlock) zt[p] = ~0ull;
+    TileView tv;
+    tv.X0 = (int32_t)((t % ta.nx) * kTile);
+    tv.Y0 = (int32_t)((t / ta.nx) * kTile);
+    tv.scene = g / ta.n_views;
+    for (int p = threadIdx.x; p < kTilePix; p += kTileThreads) zt[p] = ~0ull;
+    const uint64_t F = frag_total(n_frag, ta.cap_frag);
+    if (threadIdx.x == 0) {
+        uint32_t n[kMaxLevels];
+        level_counts(F, ta.levels, n);
+        for (uint32_t l = 0; l < ta.levels; ++l) nl[l] = n[l];
+        front[0][0] = 0;   // the root
+    }
     __syncthreads();
-    if (ta.cap_occ > 0) {
-        const uint64_t F = frag_total(n_frag, ta.cap_frag);
+    if (ta.cap_occ > 0 && F > 0) {
         const ViewSrc<kBatch> vs{va, vm};
-        float M[12];
 #pragma unroll
-        for (int q = 0; q < 12; ++q) M[q] = vs.m(g)[q];
-        const float c = vs.c(g);
-        const int32_t k = (int32_t)vs.k(g);
+        for (int q = 0; q < 12; ++q) tv.M[q] = vs.m(g)[q];
+        tv.c = vs.c(g);
+        tv.k = (int32_t)vs.k(g);
         const uint32_t wave = threadIdx.x / kWave;
-        const uint32_t e0 = off[tile], e1 = off[tile + 1] < ta.cap_t ? off[tile + 1] : ta.cap_t;
-        for (uint32_t e = e0 + wave; e < e1; e += kBlock / kWave)
-            tile_chunk<kMode, kBatch>(uniform32(list_t[e]), F, frag, oct_key, ta, M, c, k, scene, X0, Y0, zt);
-        const uint32_t base = off[ta.n_tiles];
-        const uint32_t b0 = off[ta.n_tiles + g] - base;
-        const uint32_t b1 = off[ta.n_tiles + g + 1] - base < ta.cap_b ? off[ta.n_tiles + g + 1] - base : ta.cap_b;
-        for (uint32_t e = b0 + wave; e < b1; e += kBlock / kWave) {
-            const uint4 be = list_b[e];
-            const int32_t rx0 = (int32_t)(be.y & 0xFFFFu), ry0 = (int32_t)(be.y >> 16);
-            const int32_t rx1 = (int32_t)(be.z & 0xFFFFu), ry1 = (int32_t)(be.z >> 16);
-            if (rx1 < X0 || rx0 >= X0 + kTile || ry1 < Y0 || ry0 >= Y0 + kTile) continue;   // wave-uniform
-            tile_chunk<kMode, kBatch>(uniform32(be.x), F, frag, oct_key, ta, M, c, k, scene, X0, Y0, zt);
+        const int lane = __lane_id();
+        // breadth first: the frontier holds nodes of level lv
+        uint32_t lv = ta.levels - 1, cur = 0, curn = 1;
+        while (lv >= 2) {
+            if (threadIdx.x == 0) {
+                sh_next = 0;
+                sh_over = 0;
+            }
+            __syncthreads();
+            for (uint32_t e = wave; e < curn; e += kTileWaves) {
+                const uint32_t node = front[cur][e];
+                const uint64_t m = test_children<kBatch>(box, ta, nl, lv, node, tv);
+                const uint32_t cnt = (uint32_t)__popcll(m);
+                uint32_t base = 0;
+                if (lane == 0 && cnt) base = atomicAdd(&sh_next, cnt);
+                base = uniform32((uint32_t)__shfl((int)base, 0, kWave));
+                if ((m >> lane) & 1ull) {
+                    const uint32_t pos = base + (uint32_t)__popcll(m & lanemask_lt());
+                    if (pos < kFront) front[cur ^ 1][pos] = node * kFan + (uint32_t)lane;
+                    else sh_over = 1;
+                }
+            }
+            __syncthreads();
+            const uint32_t nn = sh_next, over = sh_over;
+            __syncthreads();
+            if (over) break;   // keep the current frontier; depth first from here
+            cur ^= 1;
+            curn = nn;
+            --lv;
+        }
+        const uint32_t* fr = front[cur];
+        if (lv <= 1) {
+            // rounds: every wave tests one group's chunks and queues those
+            // that can reach the tile; all waves then draw the queue
+            for (uint32_t r0 = 0; r0 < curn; r0 += kTileWaves) {
+                if (threadIdx.x == 0) sh_q = 0;
+                __syncthreads();
+                const uint32_t e = r0 + wave;
+                if (e < curn) {
+                    const uint32_t node = fr[e];
+                    const uint64_t m = lv == 1 ? test_children<kBatch>(box, ta, nl, 1, node, tv) : 1ull;
+                    const uint32_t cnt = (uint32_t)__popcll(m);
+                    uint32_t base = 0;
+                    if (lane == 0 && cnt) base = atomicAdd(&sh_q, cnt);
+                    base = uniform32((uint32_t)__shfl((int)base, 0, kWave));
+                    if ((m >> lane) & 1ull)
+                        queue[base + (uint32_t)__popcll(m & lanemask_lt())] =
+                            lv == 1 ? node * kFan + (uint32_t)lane : node;
+                }
+                __syncthreads();
+                const uint32_t nq = sh_q;
+                draw_queue<kMode, kBatch>(queue, 0, wave, kTileWaves, nq, pos, ta, tv, zt);
+                __syncthreads();
+            }
+        } else {
+            // a frontier too large for LDS (a tile that the whole scene
+            // projects into): every chunk below each frontier node is drawn,
+            // the fragments outside the tile rejected one by one
+            for (uint32_t e = 0; e < curn; ++e) {
+                uint64_t lo = fr[e];
+                for (uint32_t l = 0; l < lv; ++l) lo *= kFan;
+                const uint64_t span = lo + ((uint64_t)1 << (6 * lv)) < nl[0] ? (uint64_t)1 << (6 * lv) : nl[0] - lo;
+                draw_queue<kMode, kBatch>(nullptr, lo, wave, kTileWaves, (uint32_t)span, pos, ta, tv, zt);
+            }
         }
     }
     __syncthreads();
     const uint64_t plane = (uint64_t)ta.width * ta.height;
     const uint32_t* f32 = (const uint32_t*)frag;
-    for (int p = threadIdx.x; p < kTilePix; p += kBlock) {
-        const int32_t X = X0 + (p % kTile), Y = Y0 + (p / kTile);
+    for (int p = threadIdx.x; p < kTilePix; p += kTileThreads) {
+        const int32_t X = tv.X0 + (p % kTile), Y = tv.Y0 + (p / kTile);
         if (X >= (int32_t)ta.width || Y >= (int32_t)ta.height) continue;
         const uint64_t o = (uint64_t)g * plane + (uint64_t)Y * ta.width + (uint32_t)X;
         const unsigned long long zk = zt[p];
@@ -410,18 +567,7 @@ k_tile_splat(const uint4* __restrict__ frag, const uint64_t* __restrict__ oct_ke
     }
 }
 
-// Workspace of the tiled splat.
-struct TileWs {
-    float4* box;       // [2 * chunks]: low and high corner, scene range in w
-    uint32_t* cnt;     // [bins + 1] counts
-    uint32_t* cur;     // [bins + 1] write cursors
-    uint32_t* off;     // [bins + 1] exclusive offsets
-    uint32_t* list_t;  // tile bins: chunk indices
-    uint4* list_b;     // view bins: chunk, rectangle
-    uint32_t* part;    // scan scratch
-};
-
-TileArgs tile_args(uint32_t n_scenes, uint32_t n_views, uint32_t W, uint32_t H)
+TileArgs tile_args(uint32_t n_scenes, uint32_t n_views, uint32_t W, uint32_t H, uint64_t cap_frag)
 {
     TileArgs ta{};
     ta.n_scenes = n_scenes;
@@ -433,34 +579,29 @@ TileArgs tile_args(uint32_t n_scenes, uint32_t n_views, uint32_t W, uint32_t H)
     ta.per_view = ta.nx * ta.ny;
     ta.n_tiles = n_scenes * n_views * ta.per_view;
     ta.shift = 64;
+    ta.cap_frag = cap_frag;
+    // levels of the chunk tree for the largest fragment count, and where
+    // each level's boxes start
+    uint64_t c = (cap_frag + kChunk - 1) / kChunk, off = 0;
+    if (c == 0) c = 1;
+    ta.levels = 0;
+    for (;;) {
+        ta.lv_off[ta.levels++] = off;
+        off += c;
+        if (c == 1) break;
+        c = (c + kFan - 1) / kFan;
+    }
+    ta.n_nodes = off;
     return ta;
 }
 
-// Bound on the (chunk, view slot) pairs: a chunk's slots are the views of
-// the scenes its fragments belong to, and each scene boundary adds at most
-// one scene to one chunk.
-uint64_t pair_bound(uint64_t cap_frag, uint32_t n_scenes, uint32_t n_views)
-{
-    const uint64_t chunks = (cap_frag + kChunk - 1) / kChunk;
-    return (chunks + n_scenes) * n_views;
-}
+// Workspace: the tree's boxes, then the packed positions (a whole number of
+// chunks).
+size_t tile_pos_off(const TileArgs& ta) { return ((size_t)ta.n_nodes * 2 * sizeof(float4) + 255) & ~(size_t)255; }
 
-TileWs carve_tiles(void* ws, uint64_t cap_frag, const TileArgs& ta, size_t* bytes)
+size_t tile_ws_bytes(const TileArgs& ta)
 {
-    const uint64_t chunks = (cap_frag + kChunk - 1) / kChunk;
-    const uint64_t bins = (uint64_t)ta.n_tiles + (uint64_t)ta.n_scenes * ta.n_views;
-    const uint64_t pairs = pair_bound(cap_frag, ta.n_scenes, ta.n_views);
-    Carver c{(char*)ws, 0};
-    TileWs w;
-    w.box = c.take<float4>(2 * chunks + 2);
-    w.cnt = c.take<uint32_t>(bins + 1);
-    w.cur = c.take<uint32_t>(bins + 1);
-    w.off = c.take<uint32_t>(bins + 1);
-    w.list_t = c.take<uint32_t>(kTileBinMax * pairs + 1);
-    w.list_b = c.take<uint4>(pairs + 1);
-    w.part = c.take<uint32_t>(scan_scratch(bins + 1));
-    if (bytes) *bytes = c.off + 256;
-    return w;
+    return tile_pos_off(ta) + (size_t)((ta.cap_frag + kChunk - 1) / kChunk) * kChunk * sizeof(uint64_t) + 256;
 }
 
 template <bool kBatch>
@@ -468,43 +609,38 @@ hipError_t tiles_launch(const Device& dev, const fhv_pofa* a, int mode, TileArgs
                         const float* vm, void* ws, uint64_t* zbuf, uint32_t* rgba, float* depth, uint8_t* cov,
                         hipStream_t s)
 {
-    const TileWs w = carve_tiles(ws, a->cap_frag, ta, nullptr);
-    const uint64_t pairs = pair_bound(a->cap_frag, ta.n_scenes, ta.n_views);
-    ta.cap_t = (uint32_t)(kTileBinMax * pairs);
-    ta.cap_b = (uint32_t)pairs;
-    const uint64_t bins = (uint64_t)ta.n_tiles + (uint64_t)ta.n_scenes * ta.n_views;
+    char* base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+    float4* box = (float4*)base;
+    uint64_t* pos = (uint64_t*)(base + tile_pos_off(ta));
     const uint64_t chunks = (a->cap_frag + kChunk - 1) / kChunk;
-    uint64_t gb = (chunks + (kBlock / kWave) - 1) / (kBlock / kWave);
     const uint64_t gmax = (uint64_t)dev.cus * 16;
-    gb = gb < 1 ? 1 : (gb > gmax ? gmax : gb);
+    auto grid_for = [&](uint64_t waves) {
+        uint64_t gb = (waves + (kBlock / kWave) - 1) / (kBlock / kWave);
+        return (unsigned)(gb < 1 ? 1 : (gb > gmax ? gmax : gb));
+    };
     hipError_t e;
     {
         ProfScope ps(dev, "splat.bin", s);
-        e = fill_u32(w.cnt, bins + 1, 0u, s);
-        if (e != hipSuccess) return e;
         if (mode == FHV_PPFL)
-            k_tile_count<FHV_PPFL, kBatch><<<dim3((unsigned)gb), dim3(kBlock), 0, s>>>(
-                (const uint4*)a->frag, a->oct_key, a->n_frag, ta, va, vm, w.box, w.cnt);
+            k_chunk_box<FHV_PPFL, kBatch><<<dim3(grid_for(chunks)), dim3(kBlock), 0, s>>>(
+                (const uint4*)a->frag, a->oct_key, a->n_frag, ta, box, pos);
         else
-            k_tile_count<FHV_POFL, kBatch><<<dim3((unsigned)gb), dim3(kBlock), 0, s>>>(
-                (const uint4*)a->frag, a->oct_key, a->n_frag, ta, va, vm, w.box, w.cnt);
+            k_chunk_box<FHV_POFL, kBatch><<<dim3(grid_for(chunks)), dim3(kBlock), 0, s>>>(
+                (const uint4*)a->frag, a->oct_key, a->n_frag, ta, box, pos);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        e = scan<uint32_t>(LoadArray<uint32_t>{w.cnt}, StoreBinOff{w.off, w.cur}, bins + 1, w.part,
-                           (uint32_t*)nullptr, s);
-        if (e != hipSuccess) return e;
-        k_tile_write<kBatch><<<dim3((unsigned)gb), dim3(kBlock), 0, s>>>(a->n_frag, ta, va, vm, w.box, w.cur, w.off,
-                                                                       w.list_t, w.list_b);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        for (uint32_t l = 1; l < ta.levels; ++l) {
+            const uint64_t nodes = (l + 1 < ta.levels ? ta.lv_off[l + 1] : ta.n_nodes) - ta.lv_off[l];
+            k_node_box<<<dim3(grid_for(nodes)), dim3(kBlock), 0, s>>>(a->n_frag, ta, l, box);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     }
     ProfScope ps(dev, "splat.splat", s);
     if (mode == FHV_PPFL)
-        k_tile_splat<FHV_PPFL, kBatch><<<dim3(ta.n_tiles), dim3(kBlock), 0, s>>>(
-            (const uint4*)a->frag, a->oct_key, a->n_frag, ta, va, vm, w.off, w.list_t, w.list_b,
-            (unsigned long long*)zbuf, rgba, depth, cov);
+        k_tile_splat<FHV_PPFL, kBatch><<<dim3(ta.n_tiles), dim3(kTileThreads), 0, s>>>(
+            (const uint4*)a->frag, pos, a->n_frag, ta, va, vm, box, (unsigned long long*)zbuf, rgba, depth, cov);
     else
-        k_tile_splat<FHV_POFL, kBatch><<<dim3(ta.n_tiles), dim3(kBlock), 0, s>>>(
-            (const uint4*)a->frag, a->oct_key, a->n_frag, ta, va, vm, w.off, w.list_t, w.list_b,
-            (unsigned long long*)zbuf, rgba, depth, cov);
+        k_tile_splat<FHV_POFL, kBatch><<<dim3(ta.n_tiles), dim3(kTileThreads), 0, s>>>(
+            (const uint4*)a->frag, pos, a->n_frag, ta, va, vm, box, (unsigned long long*)zbuf, rgba, depth, cov);
     return hipGetLastError();
 }
 
@@ -513,36 +649,31 @@ hipError_t tiles_launch(const Device& dev, const fhv_pofa* a, int mode, TileArgs
 bool splat_fits(uint64_t cap_frag, uint32_t n_scenes, uint32_t n_views, uint32_t width, uint32_t height)
 {
     const uint64_t tiles = (uint64_t)n_scenes * n_views * ((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile);
-    const uint64_t bins = tiles + (uint64_t)n_scenes * n_views + 1;
-    const uint64_t entries = (kTileBinMax + 1) * pair_bound(cap_frag, n_scenes, n_views);
-    return tiles < (1ull << 31) && bins < (1ull << 31) && entries < (1ull << 32) &&
-           (cap_frag + kChunk - 1) / kChunk < (1ull << 32);
+    return tiles < (1ull << 31) && (cap_frag + kChunk - 1) / kChunk < (1ull << 32);
 }
 
 size_t splat_ws_bytes(uint64_t cap_frag, uint32_t n_scenes, uint32_t n_views, uint32_t width, uint32_t height)
 {
-    size_t b = 0;
-    carve_tiles(nullptr, cap_frag, tile_args(n_scenes, n_views, width, height), &b);
-    return b;
+    return tile_ws_bytes(tile_args(n_scenes, n_views, width, height, cap_frag));
 }
 
 hipError_t splat_launch(const Device& dev, const fhv_pofa* a, const fhv_capture_desc* d, const ViewArgs& va,
                         uint64_t* zbuf, uint32_t* rgba, float* depth, uint8_t* cov, void* ws, hipStream_t s)
 {
-    TileArgs ta = tile_args(1, va.n_views, va.width, va.height);
+    TileArgs ta = tile_args(1, va.n_views, va.width, va.height, a->cap_frag);
     ta.cap_w = d->width;
-    ta.cap_frag = a->cap_frag;
     ta.cap_occ = a->cap_occ;
+    ta.gbits = d->levels + 8;
     return tiles_launch<false>(dev, a, (int)d->mode, ta, va, nullptr, ws, zbuf, rgba, depth, cov, s);
 }
 
 hipError_t splat_batch_launch(const Device& dev, const fhv_pofa* a, uint32_t levels, const BatchViews& bv,
                               uint64_t* zbuf, uint32_t* rgba, float* depth, uint8_t* cov, void* ws, hipStream_t s)
 {
-    TileArgs ta = tile_args(bv.n_scenes, bv.n_views, bv.width, bv.height);
+    TileArgs ta = tile_args(bv.n_scenes, bv.n_views, bv.width, bv.height, a->cap_frag);
     ta.shift = 3 * levels;
-    ta.cap_frag = a->cap_frag;
     ta.cap_occ = a->cap_occ;
+    ta.gbits = levels + 8;
     ViewArgs va;
     memset(&va, 0, sizeof(va));
     va.n_views = bv.n_views;

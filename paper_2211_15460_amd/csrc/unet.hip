@@ -25,7 +25,7 @@
 //                 buffer-to-LDS loads, weights resident; optionally the
 //                 encoder's 2x2 max pool or, for the last layer in inference,
 //                 the 1x1 head with the filled image
-//   k_conv3a      3x3 layers with 64-multiple channels: persistent, halo and
+//   k_conv3a      3x3 layers with 64-multiple output channels: persistent, halo and
 //                 weights double-buffered by direct buffer-to-LDS loads;
 //                 optionally the 2x2 max pool
 //   k_conv3       the other 3x3 layers (also input gradients with flipped
@@ -622,7 +622,7 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
     }
 }
 
-// Deep 3x3 layers (Cin a multiple of 64, Cout a multiple of 64): a
+// Deep 3x3 layers (Cin a multiple of 32, Cout a multiple of 64): a
 // workgroup of 8 waves computes 8 output rows x 62 pixels x 64 channels, one
 // row per wave with all 64 channels (4 x 4 MFMA tiles per tap). Per
 // 32-channel chunk, the input halo (10 rows x 64 pixels) and the weights of
@@ -1721,7 +1721,7 @@ hipError_t conv(const uint16_t* in, uint32_t in_cs, const uint16_t* wt, const fl
                 k_conv3r<false><<<gr, dim3(cvr::WAVES * kWave), 0, s>>>(a);
         } else if (narrow)
             k_conv3<2, 64, false, 4><<<pgrid(N * ((H + 3) / 4) * ((W + 63) / 64), (Cout + 31) / 32), blk, 0, s>>>(a);
-        else if (Cin % 64 == 0 && Cout % 64 == 0 && fits62)
+        else if (Cin % 32 == 0 && Cout % 64 == 0 && fits62)
         {
             // persistent: one workgroup per compute unit over all channel blocks
             const uint32_t tiles = N * ((H + cva::R - 1) / cva::R) * ((W + cva::TX - 1) / cva::TX);

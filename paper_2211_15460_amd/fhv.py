@@ -379,7 +379,7 @@ def splat(arrays: Pofa, d: Desc_, views, out: Images | None = None, vstruct=None
     return out
 
 
-SPLAT_STATIC_BYTES = 32 << 20   # FHV_SPLAT_STATIC_BYTES
+SPLAT_STATIC_BYTES = 64 << 20   # FHV_SPLAT_STATIC_BYTES
 
 
 def splat_static(arrays: Pofa, d: Desc_, views, out: Images, vstruct=None) -> Images:

@@ -1,9 +1,9 @@
 """The splat's screen tiles against the oracle, bit for bit, where the tile
-binning has cases of its own: footprints up to the largest side (chunks whose
-rectangle covers more than four tiles go to the view's own bin), one view per
-footprint side in one call, views of one pixel, ragged tile edges, views with
-part of the scene behind the viewer or entirely off screen, matrices that are
-not finite, a truncated octant table, and 32 views in one call."""
+walk has cases of its own: footprints up to the largest side (a chunk's box
+then reaches many tiles), one view per footprint side in one call, views of
+one pixel, ragged tile edges, views with part of the scene behind the viewer
+or entirely off screen, matrices that are not finite, a truncated octant
+table, and 32 views in one call."""
 from __future__ import annotations
 
 import numpy as np
@@ -48,11 +48,11 @@ def check(F, orc, scene, views, keys=None, pofa=None):
     return oc
 
 
-def test_large_footprints_use_the_view_bins(F, orc, scene):
+def test_large_footprints(F, orc, scene):
     _, L, _, _, _ = scene
     for k in (17, 64):
         cov = check(F, orc, scene, [S.cube_view(40.0, L, 300, 200, splat_px=k)])
-        assert cov.mean() > 0.2
+        assert cov.mean() > 0.1   # the footprints cover a good part of the view
 
 
 def test_per_view_footprints_in_one_call(F, orc, scene):

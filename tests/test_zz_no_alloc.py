@@ -63,7 +63,7 @@ def test_static_splat_matches_splat_on_two_calls(F):
 def test_static_splat_refuses_calls_beyond_its_scratch(F):
     L, W, H = 6, 64, 64
     d = F.desc(F.FHV_POFL, levels=L)
-    cap = 1 << 25        # the workspace of this call is above 32 MiB
+    cap = 1 << 23        # the workspace of this call is above 64 MiB
     assert F.splat_workspace(cap, 1, W, H) > F.SPLAT_STATIC_BYTES
     pofa = F.alloc_pofa(cap, 1)         # n_frag = n_occ = 0: nothing to draw
     img = patterned_images(F, 1, W, H)
