@@ -699,31 +699,40 @@ __global__ void __launch_bounds__(cva::WAVES * kWave) k_conv3a(ConvArgs a)
         }
         wsrc[k] = off;
     }
-    // unit u (tile u / nc, chunk u % nc) into stage u % 2
-    auto issue = [&](uint32_t u) {
+    // This lane's halo load offsets for the tile being loaded (chunk 0;
+    // chunk c adds 64 c), set once per tile: loads j < HINSTR (k < JH) are
+    // halo rows. Offsets outside the image are kOob, which stays out of
+    // range with the chunk added.
+    constexpr int JH = HINSTR / WAVES;
+    static_assert(HINSTR % WAVES == 0, "every wave issues the same number of halo loads");
+    uint32_t hv[JH];
+    __amdgpu_buffer_rsrc_t ir = wrs;
+    auto set_tile = [&](uint32_t u) {
         const Geo q = geo(u);
-        const uint32_t c = __builtin_amdgcn_readfirstlane(u % nc);
         const uint32_t r_first = q.y0 >= 1 ? q.y0 - 1 : 0;
         const uint32_t r_last = q.y0 + R < a.H ? q.y0 + R : a.H - 1;
-        const __amdgpu_buffer_rsrc_t ir =
-            srsrc(a.in + ((size_t)q.n * a.H + r_first) * a.W * a.in_cs, (r_last - r_first + 1) * row_b);
+        ir = srsrc(a.in + ((size_t)q.n * a.H + r_first) * a.W * a.in_cs, (r_last - r_first + 1) * row_b);
+#pragma unroll
+        for (int k = 0; k < JH; ++k) {
+            const uint32_t s = (uint32_t)(wv + WAVES * k) * 64 + (uint32_t)lane, rl = s >> 2;
+            const uint32_t qq = (s & 3u) ^ ((rl >> 1) & 3u);
+            const int ys = (int)q.y0 + (int)(rl / HP) - 1, xs = (int)q.x0 + (int)(rl % HP) - 1;
+            hv[k] = (rl < (uint32_t)(RP * HP) && ys >= 0 && ys < (int)a.H && xs >= 0 && xs < (int)a.W)
+                        ? ((uint32_t)ys - r_first) * row_b + (uint32_t)xs * a.in_cs * 2 + qq * 16
+                        : kOob;
+        }
+    };
+    // unit u (tile u / nc, chunk u % nc) into stage u % 2
+    auto issue = [&](uint32_t u) {
+        const uint32_t c = __builtin_amdgcn_readfirstlane(u % nc);
+        if (c == 0) set_tile(u);
         uint16_t* stg = st[u & 1];
 #pragma unroll
         for (int k = 0; k < JPW; ++k) {
             const uint32_t j = (uint32_t)(wv + WAVES * k);
             if (j >= (uint32_t)INSTR) break;   // wave-uniform
-            uint32_t off;
-            if (j < (uint32_t)HINSTR) {
-                const uint32_t s = j * 64 + (uint32_t)lane, rl = s >> 2;
-                const uint32_t qq = (s & 3u) ^ ((rl >> 1) & 3u);
-                const int ys = (int)q.y0 + (int)(rl / HP) - 1, xs = (int)q.x0 + (int)(rl % HP) - 1;
-                off = (rl < (uint32_t)(RP * HP) && ys >= 0 && ys < (int)a.H && xs >= 0 && xs < (int)a.W)
-                          ? ((uint32_t)ys - r_first) * row_b + (uint32_t)xs * a.in_cs * 2 + qq * 16 + c * 64
-                          : kOob;
-            } else {
-                off = wsrc[k] == kOob ? kOob : wsrc[k] + c * 64;
-            }
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(j < (uint32_t)HINSTR ? ir : wrs,
+            const uint32_t off = (k < JH ? hv[k] : wsrc[k]) + c * 64;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(k < JH ? ir : wrs,
                                                      (__attribute__((address_space(3))) void*)(stg + j * 512), 16,
                                                      off, 0, 0, 0);
         }
@@ -1017,6 +1026,262 @@ __global__ void __launch_bounds__(cvr::WAVES * kWave) k_conv3r(ConvArgs a)
                 for (int k = 0; k < 4; ++k) {
                     const uint32_t r = 2 * pr + (k >> 1), px = 2 * p2 + (k & 1);
                     v[k] = *(const u32x4*)&stg[r * 64 * EP + px * EP + 8 * c8];
+                }
+                *(u32x4*)(a.pool + (((size_t)q.n * (a.H / 2) + ys / 2) * (a.W / 2) + xs / 2) * a.pool_cs + 8 * c8) =
+                    max4_bf16(v);
+            }
+        }
+    }
+}
+
+// The first encoder level in inference: both of its 3x3 convolutions (the
+// 8-channel input to 32 channels, then 32 to 32 with the 2x2 max pool) in
+// one kernel, so that the first convolution's full-size output never goes
+// to memory. Persistent workgroups of 8 computing waves and 1 loading wave,
+// tiles of 8 rows x 62 pixels as in k_conv3r. The loading wave stages each
+// tile's input halo (12 rows x 66 pixels x 8 channels, zero outside the
+// image) by direct buffer-to-LDS loads, two tiles ahead into a three-stage
+// ring. The computing waves run the first convolution over the second one's
+// halo (10 rows x 64 pixels; zero where it falls outside the image, which
+// is the second convolution's padding) into LDS in k_conv3r's swizzled
+// layout, then the second convolution from there. The first convolution's
+// products are transposed (weights as the row operand, pixels as the column
+// operand), so that a lane ends with 4 consecutive channels of one pixel
+// and writes them as one 8-byte word; its K chunks are k_conv's (four taps
+// of 8 channels, lane group g taking tap 4 c + g, the chunks in order), so
+// both layers sum exactly as the unfused kernels do and the results are
+// the same.
+namespace cv2 {
+constexpr int R = 8, TX = 62, HP = TX + 2, RP = R + 2, IR = R + 4, IP = TX + 4, S = 3;
+constexpr int ISLOTS = (IR * IP + 63) / 64 * 64;   // 16-byte slots of one input halo
+constexpr int IINSTR = ISLOTS / 64;                // wave-loads per tile
+constexpr int HSLOTS = RP * HP * 4;                // the first convolution's output halo
+constexpr int WSLOTS = 9 * 32 * 4;                 // the second convolution's weights
+constexpr int WINSTR = WSLOTS / 64;
+constexpr int CWAVES = 8, WAVES = CWAVES + 1;
+constexpr int EP = 16 * 2 + 8;
+constexpr int BLOCKS = RP * (HP / 16);             // 16-pixel blocks of the output halo
+constexpr int BPW = BLOCKS / CWAVES;               // blocks per computing wave
+constexpr int W1SLOTS = 3 * 2 * 64;                // first convolution's weights, one slot per lane and operand
+// then the first convolution's bias: 64 floats, one per lane of its load
+constexpr int LDS_ELEMS = (HSLOTS + S * ISLOTS + WSLOTS + W1SLOTS) * 8 + 64 * 2;
+static_assert(IINSTR == 13, "the loading wave's wait below allows one tile's loads in flight");
+static_assert(BLOCKS % CWAVES == 0, "whole blocks per wave");
+static_assert(CWAVES * 64 * EP <= HSLOTS * 8, "epilogue rows fit the output halo");
+}  // namespace cv2
+
+struct Conv2Args {
+    const uint16_t* in;   // 8-channel input (first channel), in_cs elements per pixel
+    const uint16_t* w1;   // first convolution [32][9 * 8] bf16
+    const float* b1;      // [32]
+    const uint16_t* w2;   // second convolution [32][9 * 32] bf16
+    const float* b2;      // [32]
+    uint16_t* out;        // the second convolution's output (first channel)
+    uint16_t* pool;       // its 2x2 max pool (first channel)
+    uint32_t in_cs, out_cs, pool_cs, N, H, W;
+};
+
+__global__ void __launch_bounds__(cv2::WAVES * kWave) k_conv33(Conv2Args a)
+{
+    using namespace cv2;
+    __shared__ __attribute__((aligned(16))) uint16_t lds[LDS_ELEMS];
+    // the output halo comes first: the second convolution's reads past its
+    // end (the two unstored pixels of the last row) stay inside the array
+    uint16_t* const h1 = lds;
+    uint16_t* const ist = lds + HSLOTS * 8;
+    uint16_t* const wts = lds + (HSLOTS + S * ISLOTS) * 8;
+    uint16_t* const w1s = wts + WSLOTS * 8;
+    const float* const b1s = (const float*)(w1s + W1SLOTS * 8);
+    const int lane = __lane_id(), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int g = lane >> 4, l16 = lane & 15;
+    const bool loader = wv == CWAVES;
+    const uint32_t xtiles = (a.W + TX - 1) / TX, ytiles = (a.H + R - 1) / R;
+    const uint32_t n_tiles = a.N * ytiles * xtiles, G = gridDim.x, b = blockIdx.x;
+    if (b >= n_tiles) return;   // whole workgroup
+    const uint32_t U = (n_tiles - 1 - b) / G + 1;   // tiles of this workgroup
+    const uint32_t row_b = a.W * a.in_cs * 2;
+    struct Geo {
+        uint32_t n, y0, x0;
+    };
+    auto geo = [&](uint32_t u) {
+        const uint32_t t = b + u * G;
+        Geo q;
+        q.n = __builtin_amdgcn_readfirstlane(t / (xtiles * ytiles));
+        const uint32_t rem = t - q.n * (xtiles * ytiles);
+        const uint32_t ty = __builtin_amdgcn_readfirstlane(rem / xtiles);
+        q.y0 = ty * R;
+        q.x0 = (rem - ty * xtiles) * TX;
+        return q;
+    };
+    // loading wave: the input halo of tile u into stage u % S; lane i of
+    // wave-load j fills slot 64 j + i, halo pixel (s / IP, s % IP)
+    auto issue = [&](uint32_t u) {
+        const Geo q = geo(u);
+        const int r_first = q.y0 >= 2 ? (int)q.y0 - 2 : 0;
+        const int r_last = q.y0 + R + 1 < a.H ? (int)q.y0 + R + 1 : (int)a.H - 1;
+        const __amdgpu_buffer_rsrc_t ir = srsrc(a.in + ((size_t)q.n * a.H + (uint32_t)r_first) * a.W * a.in_cs,
+                                                (uint32_t)(r_last - r_first + 1) * row_b);
+        uint16_t* stg = ist + (u % S) * ISLOTS * 8;
+#pragma unroll
+        for (int j = 0; j < IINSTR; ++j) {
+            const uint32_t s = (uint32_t)(j * 64 + lane), hr = s / IP, hp = s % IP;
+            const int ys = (int)q.y0 - 2 + (int)hr, xs = (int)q.x0 - 2 + (int)hp;
+            const bool ok = s < (uint32_t)(IR * IP) && ys >= 0 && ys < (int)a.H && xs >= 0 && xs < (int)a.W;
+            const uint32_t off = ok ? (uint32_t)(ys - r_first) * row_b + (uint32_t)xs * a.in_cs * 2 : kOob;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(ir, (__attribute__((address_space(3))) void*)(stg + j * 512),
+                                                     16, off, 0, 0, 0);
+        }
+    };
+    // Barriers are plain s_barrier, four per tile on both sides: input
+    // staged, output halo written, output halo read, epilogue rows written.
+    if (loader) {
+        // the second convolution's weights, [tap][channel] rows
+        const __amdgpu_buffer_rsrc_t wrs = rsrc(a.w2, 32 * 9 * 32 * 2);
+        for (uint32_t j = 0; j < (uint32_t)WINSTR; ++j) {
+            const uint32_t s3 = j * 64 + (uint32_t)lane;
+            const uint32_t wrow = s3 >> 2, qq = (s3 & 3u) ^ ((wrow >> 1) & 3u);
+            const uint32_t tap = wrow / 32, co = wrow % 32;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(wrs, (__attribute__((address_space(3))) void*)(wts + j * 512), 16,
+                                                     (co * 9 * 32 + tap * 32) * 2 + qq * 16, 0, 0, 0);
+        }
+        // the first convolution's weights as the products' row operands:
+        // slot 64 (2 c + j) + lane holds, for lane (g, l16), output channel
+        // 16 j + l16, K entries 32 c + 8 g .. 32 c + 8 g + 7 (tap 4 c + g;
+        // zeros past the ninth tap); then its bias
+        const __amdgpu_buffer_rsrc_t w1rs = rsrc(a.w1, 32 * 9 * 8 * 2);
+#pragma unroll
+        for (int jj = 0; jj < 6; ++jj) {
+            const int c = jj >> 1, j = jj & 1, tap = 4 * c + (lane >> 4);
+            const uint32_t off = tap < 9 ? ((16 * j + (lane & 15)) * 72 + 8 * tap) * 2 : kOob;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(w1rs, (__attribute__((address_space(3))) void*)(w1s + jj * 512), 16,
+                                                     off, 0, 0, 0);
+        }
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc(a.b1, 32 * 4), (__attribute__((address_space(3))) void*)b1s, 4,
+                                                 lane < 32 ? (uint32_t)lane * 4 : kOob, 0, 0, 0);
+        issue(0);
+        if (U > 1) issue(1);
+        for (uint32_t u = 0; u < U; ++u) {
+            // tile u has landed once at most the next tile's loads are in flight
+            if (u + 1 < U)
+                asm volatile("s_waitcnt vmcnt(13)\n\ts_barrier" ::: "memory");
+            else
+                asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+            if (u + 2 < U) issue(u + 2);   // into the stage that tile u - 1 left
+            asm volatile("s_barrier\n\ts_barrier\n\ts_barrier" ::: "memory");
+        }
+        return;
+    }
+    float bv[2];
+    tile_bias<2>(bv, a.b2, 0, 32);
+    floatx4 acc[4][2];
+    auto compute2 = [&]() {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        u32x4 av[2][4], bw[2][2];
+        auto rd = [&](int tap, u32x4 (&A)[4], u32x4 (&B)[2]) {
+            const int dy = tap / 3, dx = tap % 3;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                A[i] = *(const u32x4*)&h1[swz_slot((uint32_t)((wv + dy) * HP + 16 * i + l16 + dx), (uint32_t)g) * 8];
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                B[j] = *(const u32x4*)&wts[swz_slot((uint32_t)(tap * 32 + 16 * j + l16), (uint32_t)g) * 8];
+        };
+        rd(0, av[0], bw[0]);
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int cur = tap & 1;
+            if (tap + 1 < 9) rd(tap + 1, av[cur ^ 1], bw[cur ^ 1]);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(bf16x8, av[cur][i]), __builtin_bit_cast(bf16x8, bw[cur][j]), acc[i][j], 0, 0,
+                        0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    for (uint32_t u = 0; u < U; ++u) {
+        // tile u staged (the loading wave waited); the previous tile's pool
+        // reads of the output halo are done
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        const Geo q = geo(u);
+        const uint16_t* in_s = ist + (u % S) * ISLOTS * 8;
+        // first convolution: blocks wv, wv + 8, ... of the output halo, each
+        // 16 pixels of one halo row x 32 channels; the next block's operands
+        // are read while the current block's products run
+        auto rd1 = [&](int k, u32x4 (&xb)[3]) {
+            const int blk = wv + CWAVES * k, hr = blk >> 2, hp = 16 * (blk & 3) + l16;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                // past the ninth tap: read tap 8 and clear it (no branch)
+                const int tap = 4 * c + g, t = tap < 9 ? tap : 8, dy = t / 3, dx = t - 3 * dy;
+                const uint32_t keep = tap < 9 ? ~0u : 0u;
+                xb[c] = *(const u32x4*)&in_s[((hr + dy) * IP + hp + dx) * 8] & keep;
+            }
+        };
+        u32x4 xb[3], xn[3];
+        rd1(0, xn);
+        // not unrolled: unrolled, the blocks' addresses stay live in registers
+#pragma unroll 1
+        for (int k = 0; k < BPW; ++k) {
+            const int blk = wv + CWAVES * k, hr = blk >> 2, hp = 16 * (blk & 3) + l16;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) xb[c] = xn[c];
+            if (k + 1 < BPW) rd1(k + 1, xn);
+            floatx4 d[2] = {floatx4{0.f, 0.f, 0.f, 0.f}, floatx4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    d[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(bf16x8, *(const u32x4*)&w1s[((2 * c + j) * 64 + lane) * 8]),
+                        __builtin_bit_cast(bf16x8, xb[c]), d[j], 0, 0, 0);
+            const int y = (int)q.y0 - 1 + hr, x = (int)q.x0 - 1 + hp;
+            const bool in = y >= 0 && y < (int)a.H && x >= 0 && x < (int)a.W;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                // bias of the 4 channels 16 j + 4 g + r this lane holds
+                const floatx4 bj = *(const floatx4*)&b1s[16 * j + 4 * g];
+                uint32_t w[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    float v0 = d[j][2 * h] + bj[2 * h], v1 = d[j][2 * h + 1] + bj[2 * h + 1];
+                    v0 = v0 > 0.0f ? v0 : 0.0f;
+                    v1 = v1 > 0.0f ? v1 : 0.0f;
+                    w[h] = in ? ((uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16)) : 0u;
+                }
+                const uint32_t slot = swz_slot((uint32_t)(hr * HP + hp), (uint32_t)(2 * j + (g >> 1)));
+                *(uint2*)&h1[slot * 8 + (g & 1) * 4] = make_uint2(w[0], w[1]);
+            }
+        }
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");   // output halo complete
+        compute2();
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");   // every wave done with it
+        const uint32_t y = q.y0 + (uint32_t)wv;
+        store_tile<4, 2>(h1 + wv * 64 * EP, acc, bv, 0, 32, true, [&](int px) -> uint16_t* {
+            const uint32_t x = q.x0 + (uint32_t)px;
+            if (px >= TX || y >= a.H || x >= a.W) return nullptr;
+            return a.out + (((size_t)q.n * a.H + y) * a.W + x) * a.out_cs;
+        });
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");   // epilogue rows complete
+        // 2x2 max pool (even H and W) from the waves' epilogue rows
+        constexpr int PCH = 4, RUNS = (TX / 2) * (R / 2) * PCH;
+        static_assert(RUNS <= CWAVES * kWave, "one pass over the pooled runs");
+        const uint32_t run = threadIdx.x;
+        if (run < (uint32_t)RUNS) {
+            const uint32_t c8 = run % PCH, p2 = (run / PCH) % (TX / 2), pr = run / (PCH * (TX / 2));
+            const uint32_t xs = q.x0 + 2 * p2, ys = q.y0 + 2 * pr;
+            if (xs < a.W && ys < a.H) {
+                u32x4 v[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t r = 2 * pr + (k >> 1), px = 2 * p2 + (k & 1);
+                    v[k] = *(const u32x4*)&h1[r * 64 * EP + px * EP + 8 * c8];
                 }
                 *(u32x4*)(a.pool + (((size_t)q.n * (a.H / 2) + ys / 2) * (a.W / 2) + xs / 2) * a.pool_cs + 8 * c8) =
                     max4_bf16(v);
@@ -1749,6 +2014,33 @@ hipError_t conv(const uint16_t* in, uint32_t in_cs, const uint16_t* wt, const fl
     return hipGetLastError();
 }
 
+// Both convolutions of the first encoder level and its pool, fused
+// (inference: the first convolution's output is not kept).
+hipError_t conv_first(const uint16_t* in, uint32_t in_cs, const uint16_t* w1, const float* b1, const uint16_t* w2,
+                      const float* b2, uint16_t* out, uint32_t out_cs, uint16_t* pool, uint32_t pool_cs, uint32_t N,
+                      uint32_t H, uint32_t W, hipStream_t s)
+{
+    if ((H & 1) || (W & 1) || in_cs != kInPad) return hipErrorInvalidValue;
+    Conv2Args a;
+    a.in = in;
+    a.w1 = w1;
+    a.b1 = b1;
+    a.w2 = w2;
+    a.b2 = b2;
+    a.out = out;
+    a.pool = pool;
+    a.in_cs = in_cs;
+    a.out_cs = out_cs;
+    a.pool_cs = pool_cs;
+    a.N = N;
+    a.H = H;
+    a.W = W;
+    ProfScope ps(cur_dev(), "fill.conv", s);
+    const uint32_t tiles = N * ((H + cv2::R - 1) / cv2::R) * ((W + cv2::TX - 1) / cv2::TX);
+    k_conv33<<<dim3(std::min<uint32_t>(tiles, (uint32_t)cur_dev().cus)), dim3(cv2::WAVES * kWave), 0, s>>>(a);
+    return hipGetLastError();
+}
+
 hipError_t wgrad(const uint16_t* gr, uint32_t g_cs, const uint16_t* x, uint32_t x_cs, uint32_t N,
                  uint32_t H, uint32_t W, uint32_t Cin, uint32_t Creal, uint32_t Cout, int mode,
                  float* part, size_t part_elems, float* dst, hipStream_t s)
@@ -1837,6 +2129,15 @@ hipError_t forward(const Net& net, const float* th, const Bufs& b, uint32_t N, u
         const uint32_t Hl = H >> l, Wl = W >> l, Cl = net.C[l];
         const Layer& a0 = net.layers[net.enc(l, 0)];
         const Layer& a1 = net.layers[net.enc(l, 1)];
+        if (l == 0 && hf && L > 1) {
+            // inference: the first level's two convolutions in one kernel
+            FHV_TRY(conv_first(h, h_cs, b.wt + a0.wf_off, th + a0.off_b, b.wt + a1.wf_off, th + a1.off_b,
+                               b.cat[0] + Cl, 2 * Cl, b.pool[0], Cl, N, Hl, Wl, s));
+            h = b.pool[0];
+            h_cs = Cl;
+            cin = Cl;
+            continue;
+        }
         FHV_TRY(conv(h, h_cs, b.wt + a0.wf_off, th + a0.off_b, b.e0[l], Cl, N, Hl, Wl, cin, Cl, MODE_SAME3, true, s));
         uint16_t* o1 = l + 1 < L ? b.cat[l] + Cl : b.elast;
         const uint32_t o1_cs = l + 1 < L ? 2 * Cl : Cl;
