@@ -138,10 +138,11 @@ __device__ __forceinline__ void tile_bias(float (&bv)[NJ], const float* __restri
 // the output.
 template <int MI, int NJ, class Dst>
 __device__ __forceinline__ void store_tile(uint16_t* __restrict__ lds, const floatx4 (&acc)[MI][NJ],
-                                           const float (&bv)[NJ], uint32_t co0, uint32_t Cout, bool relu, Dst dst)
+                                           const float (&bv)[NJ], uint32_t co0, uint32_t Cout, bool relu, Dst dst,
+                                           int lane = __lane_id())
 {
     constexpr int P = 16 * NJ + 8, CH = 2 * NJ;
-    const int lane = __lane_id(), g = lane >> 4, l16 = lane & 15;
+    const int g = lane >> 4, l16 = lane & 15;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
         const float b = bv[j];
@@ -623,32 +624,34 @@ __global__ void __launch_bounds__(kBlock) k_conv3(ConvArgs a)
 }
 
 // Deep 3x3 layers (Cin a multiple of 32, Cout a multiple of 64): a
-// workgroup of 8 waves computes 8 output rows x 62 pixels x 64 channels, one
-// row per wave with all 64 channels (4 x 4 MFMA tiles per tap). Per
-// 32-channel chunk, the input halo (10 rows x 64 pixels) and the weights of
-// all nine taps are staged in LDS by direct buffer-to-LDS loads (no
-// registers and no LDS write instructions in between), double-buffered: the
-// next chunk loads while the current one is computed, with one barrier per
-// chunk. LDS rows are 64 bytes (32 bf16); the 16-byte chunk q of row r sits
-// at position q ^ ((r >> 1) & 3), which keeps the operand reads of any 16
-// consecutive rows free of bank conflicts (measured on gfx950). Sums run in
-// the same order as in k_conv3 (chunks, then taps), so results are the same.
+// workgroup computes 8 output rows x 62 pixels x 64 channels with 8
+// computing waves, one row per wave with all 64 channels (4 x 4 MFMA tiles
+// per tap), and 1 loading wave. Per 32-channel chunk, the input halo (10
+// rows x 64 pixels) and the weights of all nine taps are staged in LDS by
+// direct buffer-to-LDS loads (no registers and no LDS write instructions in
+// between), double-buffered: the loading wave fills the next (tile, chunk)
+// unit while the current one is computed, and it alone waits for those
+// loads, so the computing waves never wait on the memory counter (which
+// also counts their own output stores). LDS rows are 64 bytes (32 bf16);
+// the 16-byte chunk q of row r sits at position q ^ ((r >> 1) & 3), which
+// keeps the operand reads of any 16 consecutive rows free of bank conflicts
+// (measured on gfx950). Sums run in the same order as in k_conv3 (chunks,
+// then taps), so results are the same.
 namespace cva {
 // A tile is 62 pixels wide so that a halo row is 64 pixels: moving the
 // operand window by whole rows (the taps' dy) then leaves the swizzle of
 // every lane unchanged and its addresses differ by constants. The waves'
 // last two of 64 pixels are computed but not stored.
 constexpr int R = 8, TX = 62, HP = TX + 2, RP = R + 2, TN = 64, NW = 4;
-constexpr int HSLOTS = (RP * HP * 4 + 63) / 64 * 64;   // halo slots, whole wave-loads
-constexpr int WSLOTS = 9 * TN * 4;                      // weight slots (a multiple of 64)
+constexpr int HSLOTS = RP * HP * 4;     // halo slots (16 bytes each)
+constexpr int WSLOTS = 9 * TN * 4;      // weight slots
 constexpr int SLOTS = HSLOTS + WSLOTS;
-constexpr int INSTR = SLOTS / 64;                       // wave-loads per stage
-constexpr int HINSTR = HSLOTS / 64;                     // the first HINSTR load halo rows
-constexpr int WAVES = 8;
-constexpr int JPW = (INSTR + WAVES - 1) / WAVES;        // wave-loads per wave
-constexpr int EP = 16 * NW + 8;                          // epilogue pitch (bf16 per pixel)
-static_assert(WSLOTS % 64 == 0, "weight region starts on a wave-load boundary");
-static_assert(WAVES * 64 * EP <= SLOTS * 8, "epilogue fits one stage");
+constexpr int HINSTR = HSLOTS / 64;     // halo wave-loads per unit
+constexpr int WINSTR = WSLOTS / 64;     // weight wave-loads per unit
+constexpr int CWAVES = 8, WAVES = CWAVES + 1;
+constexpr int EP = 16 * NW + 8;         // epilogue pitch (bf16 per pixel)
+static_assert(HSLOTS % 64 == 0 && WSLOTS % 64 == 0, "whole wave-loads");
+static_assert(CWAVES * 64 * EP <= SLOTS * 8, "epilogue fits one stage");
 }  // namespace cva
 
 __device__ __forceinline__ uint32_t swz_slot(uint32_t row, uint32_t q)
@@ -662,6 +665,7 @@ __global__ void __launch_bounds__(cva::WAVES * kWave) k_conv3a(ConvArgs a)
     __shared__ __attribute__((aligned(16))) uint16_t st[2][SLOTS * 8];
     const int lane = __lane_id(), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int g = lane >> 4, l16 = lane & 15;
+    const bool loader = wv == CWAVES;
     const uint32_t xtiles = (a.W + TX - 1) / TX, ytiles = (a.H + R - 1) / R;
     const uint32_t n_tiles = a.N * ytiles * xtiles, G = gridDim.x, b = blockIdx.x;
     if (b >= n_tiles) return;   // whole workgroup
@@ -669,7 +673,6 @@ __global__ void __launch_bounds__(cva::WAVES * kWave) k_conv3a(ConvArgs a)
     const uint32_t Cin = a.Cin, K = 9 * Cin, nc = Cin >> 5;
     const uint32_t U = ((n_tiles - 1 - b) / G + 1) * nc;   // (tile, chunk) units of this workgroup
     const uint32_t row_b = a.W * a.in_cs * 2;
-    const __amdgpu_buffer_rsrc_t wrs = rsrc(a.wt, a.Cout * K * 2);
     struct Geo {
         uint32_t n, y0, x0;
     };
@@ -684,122 +687,152 @@ __global__ void __launch_bounds__(cva::WAVES * kWave) k_conv3a(ConvArgs a)
         q.x0 = (rem - ty * xtiles) * TX;
         return q;
     };
-    // this lane's weight byte offsets (chunk 0; chunk c adds 64 c): wave wv
-    // issues loads j = wv, wv + 8, ...; load j fills slots 64 j .. 64 j + 63,
-    // lane i slot 64 j + i; the first HINSTR loads are halo rows
-    uint32_t wsrc[JPW];
+    const bool pool = a.pool != nullptr;
+    // Barriers are plain s_barrier, the same sequence on both sides: one per
+    // unit (its stage is loaded, and every wave is done with the previous
+    // unit), plus one at the end of each tile (every wave is done reading the
+    // stage the epilogue reuses) and one more with the pool (the epilogue
+    // rows are written).
+    if (loader) {
+        // Unit u (tile u / nc, chunk u % nc) into stage u % 2. Wave-load j < HINSTR fills
+        // slots 64 j + i with halo row j / 4, pixel 16 (j % 4) + i / 4, chunk
+        // position i % 4; wave-load HINSTR + m the weight rows of tap m / 4,
+        // channels 16 (m % 4) + i / 4, the same way.
+        const __amdgpu_buffer_rsrc_t wrs = rsrc(a.wt, a.Cout * K * 2);
+        uint32_t wcol[4];   // this lane's weight offsets per m % 4 (tap 0, chunk 0)
 #pragma unroll
-    for (int k = 0; k < JPW; ++k) {
-        const uint32_t j = (uint32_t)(wv + WAVES * k), s = j * 64 + (uint32_t)lane;
-        uint32_t off = kOob;
-        if (j >= (uint32_t)HINSTR && j < (uint32_t)INSTR) {
-            const uint32_t s2 = s - HSLOTS, wrow = s2 >> 2, q = (s2 & 3u) ^ ((wrow >> 1) & 3u);
-            const uint32_t tap = wrow / TN, co = wrow % TN;
-            if (co0 + co < a.Cout) off = ((co0 + co) * K + tap * Cin) * 2 + q * 16;
+        for (int m = 0; m < 4; ++m) {
+            const uint32_t co = (uint32_t)(16 * m) + ((uint32_t)lane >> 2);
+            const uint32_t qq = ((uint32_t)lane & 3u) ^ (((uint32_t)lane >> 3) & 3u);
+            wcol[m] = ((co0 + co) * K) * 2 + qq * 16;
         }
-        wsrc[k] = off;
+        uint32_t col[4];   // this lane's halo column offsets per j % 4 (chunk 0), kOob outside
+        __amdgpu_buffer_rsrc_t ir = wrs;
+        uint32_t r_first = 0;
+        Geo q{0, 0, 0};
+        auto issue = [&](uint32_t u) {
+            const uint32_t c = __builtin_amdgcn_readfirstlane(u % nc);
+            if (c == 0) {
+                q = geo(u);
+                r_first = q.y0 >= 1 ? q.y0 - 1 : 0;
+                const uint32_t r_last = q.y0 + R < a.H ? q.y0 + R : a.H - 1;
+                ir = srsrc(a.in + ((size_t)q.n * a.H + r_first) * a.W * a.in_cs, (r_last - r_first + 1) * row_b);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t px = 16 * k + ((uint32_t)lane >> 2);
+                    const uint32_t qq = ((uint32_t)lane & 3u) ^ ((px >> 1) & 3u);
+                    const int xs = (int)(q.x0 + px) - 1;
+                    col[k] = (xs >= 0 && xs < (int)a.W) ? (uint32_t)xs * a.in_cs * 2 + qq * 16 : kOob;
+                }
+            }
+            uint16_t* stg = st[u & 1];
+#pragma unroll
+            for (int j = 0; j < HINSTR; ++j) {
+                const int ys = (int)q.y0 + (j >> 2) - 1;
+                const bool rok = ys >= 0 && ys < (int)a.H;
+                const uint32_t off =
+                    (rok && col[j & 3] != kOob) ? ((uint32_t)ys - r_first) * row_b + col[j & 3] + c * 64 : kOob;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(ir, (__attribute__((address_space(3))) void*)(stg + j * 512),
+                                                         16, off, 0, 0, 0);
+            }
+#pragma unroll
+            for (int m = 0; m < WINSTR; ++m)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    wrs, (__attribute__((address_space(3))) void*)(stg + (HINSTR + m) * 512), 16,
+                    wcol[m & 3] + (uint32_t)(m >> 2) * Cin * 2 + c * 64, 0, 0, 0);
+        };
+        issue(0);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        for (uint32_t u = 0; u < U; ++u) {
+            asm volatile("s_barrier" ::: "memory");   // unit u staged; unit u - 1 done
+            if (u + 1 < U) issue(u + 1);              // into the stage unit u - 1 left
+            if ((u + 1) % nc == 0) {
+                asm volatile("s_barrier" ::: "memory");
+                if (pool) asm volatile("s_barrier" ::: "memory");
+            }
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        }
+        return;
     }
-    // This lane's halo load offsets for the tile being loaded (chunk 0;
-    // chunk c adds 64 c), set once per tile: loads j < HINSTR (k < JH) are
-    // halo rows. Offsets outside the image are kOob, which stays out of
-    // range with the chunk added.
-    constexpr int JH = HINSTR / WAVES;
-    static_assert(HINSTR % WAVES == 0, "every wave issues the same number of halo loads");
-    uint32_t hv[JH];
-    __amdgpu_buffer_rsrc_t ir = wrs;
-    auto set_tile = [&](uint32_t u) {
-        const Geo q = geo(u);
-        const uint32_t r_first = q.y0 >= 1 ? q.y0 - 1 : 0;
-        const uint32_t r_last = q.y0 + R < a.H ? q.y0 + R : a.H - 1;
-        ir = srsrc(a.in + ((size_t)q.n * a.H + r_first) * a.W * a.in_cs, (r_last - r_first + 1) * row_b);
-#pragma unroll
-        for (int k = 0; k < JH; ++k) {
-            const uint32_t s = (uint32_t)(wv + WAVES * k) * 64 + (uint32_t)lane, rl = s >> 2;
-            const uint32_t qq = (s & 3u) ^ ((rl >> 1) & 3u);
-            const int ys = (int)q.y0 + (int)(rl / HP) - 1, xs = (int)q.x0 + (int)(rl % HP) - 1;
-            hv[k] = (rl < (uint32_t)(RP * HP) && ys >= 0 && ys < (int)a.H && xs >= 0 && xs < (int)a.W)
-                        ? ((uint32_t)ys - r_first) * row_b + (uint32_t)xs * a.in_cs * 2 + qq * 16
-                        : kOob;
-        }
-    };
-    // unit u (tile u / nc, chunk u % nc) into stage u % 2
-    auto issue = [&](uint32_t u) {
-        const uint32_t c = __builtin_amdgcn_readfirstlane(u % nc);
-        if (c == 0) set_tile(u);
-        uint16_t* stg = st[u & 1];
-#pragma unroll
-        for (int k = 0; k < JPW; ++k) {
-            const uint32_t j = (uint32_t)(wv + WAVES * k);
-            if (j >= (uint32_t)INSTR) break;   // wave-uniform
-            const uint32_t off = (k < JH ? hv[k] : wsrc[k]) + c * 64;
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(k < JH ? ir : wrs,
-                                                     (__attribute__((address_space(3))) void*)(stg + j * 512), 16,
-                                                     off, 0, 0, 0);
-        }
-    };
+    float bv[NW];
+    tile_bias<NW>(bv, a.bias, co0, a.Cout);
     floatx4 acc[4][NW];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < NW; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // Byte offsets of the operands within a stage: pixel block i of tap
+    // (dy, dx) at abase[dx] + 4096 dy + 1024 i (halo row (wv + dy) HP + 16 i
+    // + l16 + dx, whose swizzle depends on l16 + dx alone), the weights of
+    // column block j of tap t at bbase + 4096 t + 1024 j; the constants go
+    // into the LDS instructions' offset field.
+    static_assert(HP == 64 && TN == 64, "row strides of 4096 bytes");
+    uint32_t abase[3];
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx)
+        abase[dx] = swz_slot((uint32_t)(wv * HP + l16 + dx), (uint32_t)g) * 16;
+    const uint32_t bbase = HSLOTS * 16 + swz_slot((uint32_t)l16, (uint32_t)g) * 16;
     auto compute = [&](const uint16_t* stg) {
-        const uint16_t* wts = stg + HSLOTS * 8;
-        u32x4 av[2][4], bv[2][NW];
+        const char* sb = (const char*)stg;
+        u32x4 av[2][4], bw[2][NW];
         auto rd = [&](int tap, u32x4 (&A)[4], u32x4 (&B)[NW]) {
             const int dy = tap / 3, dx = tap % 3;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                A[i] = *(const u32x4*)&stg[swz_slot((uint32_t)((wv + dy) * HP + 16 * i + l16 + dx), (uint32_t)g) * 8];
+            for (int i = 0; i < 4; ++i) A[i] = *(const u32x4*)(sb + abase[dx] + (dy * 4096 + i * 1024));
 #pragma unroll
-            for (int j = 0; j < NW; ++j)
-                B[j] = *(const u32x4*)&wts[swz_slot((uint32_t)(tap * TN + 16 * j + l16), (uint32_t)g) * 8];
+            for (int j = 0; j < NW; ++j) B[j] = *(const u32x4*)(sb + bbase + (tap * 4096 + j * 1024));
         };
-        rd(0, av[0], bv[0]);
+        rd(0, av[0], bw[0]);
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
             const int cur = tap & 1;
-            if (tap + 1 < 9) rd(tap + 1, av[cur ^ 1], bv[cur ^ 1]);
+            if (tap + 1 < 9) rd(tap + 1, av[cur ^ 1], bw[cur ^ 1]);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < NW; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        __builtin_bit_cast(bf16x8, av[cur][i]), __builtin_bit_cast(bf16x8, bv[cur][j]), acc[i][j], 0, 0,
+                        __builtin_bit_cast(bf16x8, av[cur][i]), __builtin_bit_cast(bf16x8, bw[cur][j]), acc[i][j], 0, 0,
                         0);
             __builtin_amdgcn_sched_barrier(0);
         }
     };
-    // The next unit loads while the current one is computed, across tiles
-    // too; a stage is refilled only after the barrier that follows every
-    // wave's reads of it (products and epilogue).
-    issue(0);
     for (uint32_t u = 0; u < U; ++u) {
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
-        if (u + 1 < U) issue(u + 1);
+        // unit u staged (the loading wave waited); this wave's reads of the
+        // stage the next unit goes to are done
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
         uint16_t* stg = st[u & 1];
         compute(stg);
         if ((u + 1) % nc != 0) continue;
-        __syncthreads();   // the epilogue reuses this unit's stage
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");   // the epilogue reuses this stage
         const Geo q = geo(u);
         const uint32_t y = q.y0 + (uint32_t)wv;
         uint16_t* ep = stg + wv * 64 * EP;
-        store_tile<4, NW>(ep, acc, a.bias, co0, a.Cout, a.relu != 0, [&](int px) -> uint16_t* {
-            const uint32_t x = q.x0 + (uint32_t)px;
-            if (px >= TX || y >= a.H || x >= a.W) return nullptr;
-            return a.out + (((size_t)q.n * a.H + y) * a.W + x) * a.out_cs + co0;
-        });
+        // the lane index made opaque here: otherwise the compiler keeps the
+        // epilogue's per-lane addresses live across the whole loop
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+        store_tile<4, NW>(
+            ep, acc, bv, co0, a.Cout, a.relu != 0,
+            [&](int px) -> uint16_t* {
+                const uint32_t x = q.x0 + (uint32_t)px;
+                if (px >= TX || y >= a.H || x >= a.W) return nullptr;
+                return a.out + (((size_t)q.n * a.H + y) * a.W + x) * a.out_cs + co0;
+            },
+            ln);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < NW; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-        if (!a.pool) continue;
-        // 2x2 max pool (even H and W) from the waves' epilogue tiles: one
+        if (!pool) continue;
+        // 2x2 max pool (even H and W) from the waves' epilogue rows: one
         // thread per pooled pixel and 8 channels
-        __syncthreads();
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
         constexpr int PCH = TN / 8, RUNS = (TX / 2) * (R / 2) * PCH;
-        for (uint32_t run = threadIdx.x; run < (uint32_t)RUNS; run += WAVES * kWave) {
+        uint32_t tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        for (uint32_t run = tid; run < (uint32_t)RUNS; run += CWAVES * kWave) {
             const uint32_t c8 = run % PCH, p2 = (run / PCH) % (TX / 2), pr = run / (PCH * (TX / 2));
             const uint32_t xs = q.x0 + 2 * p2, ys = q.y0 + 2 * pr;
             if (xs >= a.W || ys >= a.H || co0 + 8 * c8 >= a.Cout) continue;
