@@ -972,16 +972,24 @@ __global__ void __launch_bounds__(cvr::WAVES * kWave) k_conv3r(ConvArgs a)
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < NW; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // operand byte offsets as in k_conv3a: pixel block i of tap (dy, dx) at
+    // abase[dx] + 4096 dy + 1024 i into a stage, the weights of column block
+    // j, tap t at bbase + 2048 t + 1024 j into a chunk's weights
+    static_assert(HP == 64 && TN == 32, "row strides of 4096 and 2048 bytes");
+    uint32_t abase[3];
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) abase[dx] = swz_slot((uint32_t)(wv * HP + l16 + dx), (uint32_t)g) * 16;
+    const uint32_t bbase = swz_slot((uint32_t)l16, (uint32_t)g) * 16;
     auto compute = [&](const uint16_t* stg, const uint16_t* wc) {
+        const char* sb = (const char*)stg;
+        const char* wb = (const char*)wc;
         u32x4 av[2][4], bv[2][NW];
         auto rd = [&](int tap, u32x4 (&A)[4], u32x4 (&B)[NW]) {
             const int dy = tap / 3, dx = tap % 3;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                A[i] = *(const u32x4*)&stg[swz_slot((uint32_t)((wv + dy) * HP + 16 * i + l16 + dx), (uint32_t)g) * 8];
+            for (int i = 0; i < 4; ++i) A[i] = *(const u32x4*)(sb + abase[dx] + (dy * 4096 + i * 1024));
 #pragma unroll
-            for (int j = 0; j < NW; ++j)
-                B[j] = *(const u32x4*)&wc[swz_slot((uint32_t)(tap * TN + 16 * j + l16), (uint32_t)g) * 8];
+            for (int j = 0; j < NW; ++j) B[j] = *(const u32x4*)(wb + bbase + (tap * 2048 + j * 1024));
         };
         rd(0, av[0], bv[0]);
 #pragma unroll
@@ -1030,11 +1038,16 @@ __global__ void __launch_bounds__(cvr::WAVES * kWave) k_conv3r(ConvArgs a)
         const Geo q = geo(u);
         const uint32_t y = q.y0 + y_w;
         uint16_t* ep = stg + wv * 64 * EP;
-        store_tile<4, NW>(ep, acc, bv, 0, a.Cout, a.relu != 0, [&](int px) -> uint16_t* {
-            const uint32_t x = q.x0 + (uint32_t)px;
-            if (kHead || px >= TX || y >= a.H || x >= a.W) return nullptr;
-            return a.out + (((size_t)q.n * a.H + y) * a.W + x) * a.out_cs;
-        });
+        int ln = lane;
+        asm volatile("" : "+v"(ln));   // keeps the epilogue's per-lane addresses out of the loop
+        store_tile<4, NW>(
+            ep, acc, bv, 0, a.Cout, a.relu != 0,
+            [&](int px) -> uint16_t* {
+                const uint32_t x = q.x0 + (uint32_t)px;
+                if (kHead || px >= TX || y >= a.H || x >= a.W) return nullptr;
+                return a.out + (((size_t)q.n * a.H + y) * a.W + x) * a.out_cs;
+            },
+            ln);
         if (kHead) {
             const uint32_t x = q.x0 + (uint32_t)lane;
             if (lane < TX && y < a.H && x < a.W)
@@ -1320,6 +1333,297 @@ __global__ void __launch_bounds__(cv2::WAVES * kWave) k_conv33(Conv2Args a)
                     max4_bf16(v);
             }
         }
+    }
+}
+
+// The decoder's last level in inference: its 2x2 stride-2 transposed
+// convolution (64 to 32 channels) computed inside its first 3x3 convolution
+// (over the concatenation of that output with the encoder's 32 skip
+// channels, 64 to 32), so that the up-sampled half of the concatenation
+// never goes to memory. Persistent workgroups of 8 computing waves and 1
+// loading wave, tiles of 8 rows x 62 pixels as in k_conv3r. Per tile the
+// loading wave stages the low-resolution input under the tile (6 rows x 33
+// pixels x 64 channels) and the skip channels' halo (10 rows x 64 pixels);
+// the computing waves compute the up-sampled channels' halo into LDS (zero
+// outside the image, which is the 3x3 convolution's padding), then the 3x3
+// products over it (chunk 0) and over the skip halo (chunk 1), the order in
+// which the unfused kernels sum, so the results are the same. The
+// transposed convolution's products are transposed (weights of one
+// sub-position as the row operand, 16 low-resolution pixels as the column
+// operand, which land on every other pixel of one output row), so a lane
+// writes 4 channels of one pixel at once.
+namespace cvu {
+constexpr int R = 8, TX = 62, HP = TX + 2, RP = R + 2;
+constexpr int LR = R / 2 + 2, LP = TX / 2 + 2;           // low-resolution rows and pixels under a tile
+constexpr int LSLOTS = (LR * LP * 8 + 63) / 64 * 64;     // 16-byte slots, 8 per low-resolution pixel
+constexpr int LINSTR = LSLOTS / 64;
+constexpr int HSLOTS = RP * HP * 4;                      // one 32-channel halo
+constexpr int HINSTR = HSLOTS / 64;
+constexpr int WSLOTS = 2 * 9 * 32 * 4;                   // 3x3 weights, both chunks
+constexpr int WINSTR = WSLOTS / 64;
+constexpr int USLOTS = 16 * 64;                          // transposed-convolution weights, one slot per lane and operand
+constexpr int UINSTR = USLOTS / 64;
+constexpr int CWAVES = 8, WAVES = CWAVES + 1;
+constexpr int EP = 16 * 2 + 8;
+constexpr int ITEMS = RP * 2 * 2;                        // (halo row, column parity, 16-pixel block)
+constexpr int IPW = ITEMS / CWAVES;
+// LDS layout in 16-byte slots: up-sampled halo (later the epilogue rows),
+// skip halo, low-resolution stage, 3x3 weights, transposed-convolution
+// weights, its bias (64 floats: one per lane of its load)
+constexpr int O_UP = 0, O_SK = HSLOTS, O_LR = 2 * HSLOTS, O_W = O_LR + LSLOTS, O_U = O_W + WSLOTS, O_B = O_U + USLOTS;
+constexpr int LDS_ELEMS = (O_B + 16) * 8;
+static_assert(LINSTR == 25 && HINSTR == 40, "the loading wave's waits below");
+static_assert(ITEMS % CWAVES == 0 && IPW == 5 && CWAVES == 8, "two waves per sub-position, 5 items each");
+static_assert(CWAVES * 64 * EP <= HSLOTS * 8, "epilogue rows fit the up-sampled halo");
+static_assert(O_SK * 16 + 11264 < 65536 && 18432 + 8 * 2048 + 1024 < 65536, "constant LDS offsets fit");
+}  // namespace cvu
+
+struct ConvUpArgs {
+    const uint16_t* low;   // decoder input at half resolution (first channel), low_cs elements per pixel
+    const uint16_t* wu;    // transposed convolution [4][32][64] bf16 (sub-position 2 dy + dx)
+    const float* bu;       // [32]
+    const uint16_t* skip;  // the encoder's 32 skip channels (first channel), skip_cs per pixel
+    const uint16_t* wt;    // 3x3 convolution [32][9 * 64] bf16 (up-sampled channels first)
+    const float* bias;     // [32]
+    uint16_t* out;         // output (first channel), out_cs per pixel
+    uint32_t low_cs, skip_cs, out_cs, N, H, W;   // H, W: full resolution, even
+};
+
+__global__ void __launch_bounds__(cvu::WAVES * kWave) k_conv3u(ConvUpArgs a)
+{
+    using namespace cvu;
+    __shared__ __attribute__((aligned(16))) uint16_t lds[LDS_ELEMS];
+    const int lane = __lane_id(), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int g = lane >> 4, l16 = lane & 15;
+    const bool loader = wv == CWAVES;
+    const uint32_t xtiles = (a.W + TX - 1) / TX, ytiles = (a.H + R - 1) / R;
+    const uint32_t n_tiles = a.N * ytiles * xtiles, G = gridDim.x, b = blockIdx.x;
+    if (b >= n_tiles) return;   // whole workgroup
+    const uint32_t U = (n_tiles - 1 - b) / G + 1;   // tiles of this workgroup
+    const uint32_t Hl = a.H / 2, Wl = a.W / 2;
+    struct Geo {
+        uint32_t n, y0, x0;
+    };
+    auto geo = [&](uint32_t u) {
+        const uint32_t t = b + u * G;
+        Geo q;
+        q.n = __builtin_amdgcn_readfirstlane(t / (xtiles * ytiles));
+        const uint32_t rem = t - q.n * (xtiles * ytiles);
+        const uint32_t ty = __builtin_amdgcn_readfirstlane(rem / xtiles);
+        q.y0 = ty * R;
+        q.x0 = (rem - ty * xtiles) * TX;
+        return q;
+    };
+    auto lds_at = [&](int slot) { return (__attribute__((address_space(3))) void*)(lds + slot * 8); };
+    // Barriers are plain s_barrier, four per tile on both sides: low-resolution
+    // stage loaded, up-sampled halo written, skip halo loaded, products done.
+    if (loader) {
+        // resident: the 3x3 weights as [chunk][tap][channel] rows of 64
+        // bytes (swizzled as in k_conv3r), the transposed convolution's
+        // weights as row operands (slot 64 (4 sub + 2 j + c) + lane holds, for
+        // lane (g, l16), channel 16 j + l16, inputs 32 c + 8 g .. 32 c + 8 g + 7),
+        // then its bias
+        const __amdgpu_buffer_rsrc_t wrs = rsrc(a.wt, 32 * 9 * 64 * 2);
+        for (int jj = 0; jj < WINSTR; ++jj) {
+            const uint32_t c = (uint32_t)jj / (WINSTR / 2), j = (uint32_t)jj % (WINSTR / 2);
+            const uint32_t s3 = j * 64 + (uint32_t)lane, wrow = s3 >> 2, qq = (s3 & 3u) ^ ((wrow >> 1) & 3u);
+            const uint32_t tap = wrow / 32, co = wrow % 32;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(wrs, lds_at(O_W + jj * 64), 16,
+                                                     (co * 9 * 64 + tap * 64 + c * 32) * 2 + qq * 16, 0, 0, 0);
+        }
+        const __amdgpu_buffer_rsrc_t urs = rsrc(a.wu, 4 * 32 * 64 * 2);
+        for (int m = 0; m < UINSTR; ++m) {
+            const uint32_t sub = (uint32_t)m >> 2, j = ((uint32_t)m >> 1) & 1u, c = (uint32_t)m & 1u;
+            const uint32_t co = 16 * j + ((uint32_t)lane & 15u);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(urs, lds_at(O_U + m * 64), 16,
+                                                     ((sub * 32 + co) * 64 + 32 * c + 8 * ((uint32_t)lane >> 4)) * 2, 0,
+                                                     0, 0);
+        }
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc(a.bu, 32 * 4), lds_at(O_B), 4,
+                                                 lane < 32 ? (uint32_t)lane * 4 : kOob, 0, 0, 0);
+        // the low-resolution pixels under tile u: slot 64 j + i holds pixel
+        // (s / 8) / LP, (s / 8) % LP of the stage (from the low-resolution
+        // pixel one above and left of the tile's), channel chunk
+        // (s % 8) ^ (pixel % 8) (s = 64 j + i)
+        auto issue_lr = [&](uint32_t u) {
+            const Geo q = geo(u);
+            const int ly0 = (int)q.y0 / 2 - 1, lx0 = (int)q.x0 / 2 - 1;
+            const int r_first = ly0 >= 0 ? ly0 : 0;
+            const int r_last = ly0 + LR - 1 < (int)Hl ? ly0 + LR - 1 : (int)Hl - 1;
+            const uint32_t row_b = Wl * a.low_cs * 2;
+            const __amdgpu_buffer_rsrc_t ir = srsrc(a.low + ((size_t)q.n * Hl + (uint32_t)r_first) * Wl * a.low_cs,
+                                                    (uint32_t)(r_last - r_first + 1) * row_b);
+#pragma unroll
+            for (int j = 0; j < LINSTR; ++j) {
+                const uint32_t s = (uint32_t)(j * 64 + lane), pi = s >> 3, lr = pi / LP, lp = pi % LP;
+                const uint32_t qq = (s & 7u) ^ (lp & 7u);
+                const int ly = ly0 + (int)lr, lx = lx0 + (int)lp;
+                const bool ok = pi < (uint32_t)(LR * LP) && ly >= 0 && ly < (int)Hl && lx >= 0 && lx < (int)Wl;
+                const uint32_t off = ok ? (uint32_t)(ly - r_first) * row_b + (uint32_t)lx * a.low_cs * 2 + qq * 16 : kOob;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(ir, lds_at(O_LR + j * 64), 16, off, 0, 0, 0);
+            }
+        };
+        // the skip channels' halo of tile u, laid out as k_conv3r's halo
+        auto issue_sk = [&](uint32_t u) {
+            const Geo q = geo(u);
+            const uint32_t r_first = q.y0 >= 1 ? q.y0 - 1 : 0;
+            const uint32_t r_last = q.y0 + R < a.H ? q.y0 + R : a.H - 1;
+            const uint32_t row_b = a.W * a.skip_cs * 2;
+            const __amdgpu_buffer_rsrc_t ir =
+                srsrc(a.skip + ((size_t)q.n * a.H + r_first) * a.W * a.skip_cs, (r_last - r_first + 1) * row_b);
+            uint32_t col[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t px = 16 * k + ((uint32_t)lane >> 2), qq = ((uint32_t)lane & 3u) ^ ((px >> 1) & 3u);
+                const int xs = (int)(q.x0 + px) - 1;
+                col[k] = (xs >= 0 && xs < (int)a.W) ? (uint32_t)xs * a.skip_cs * 2 + qq * 16 : kOob;
+            }
+#pragma unroll
+            for (int j = 0; j < HINSTR; ++j) {
+                const int ys = (int)q.y0 + (j >> 2) - 1;
+                const bool rok = ys >= 0 && ys < (int)a.H;
+                const uint32_t off = (rok && col[j & 3] != kOob) ? ((uint32_t)ys - r_first) * row_b + col[j & 3] : kOob;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(ir, lds_at(O_SK + j * 64), 16, off, 0, 0, 0);
+            }
+        };
+        issue_lr(0);
+        issue_sk(0);
+        for (uint32_t u = 0; u < U; ++u) {
+            // the low-resolution stage of tile u has landed once at most the
+            // skip halo's loads are in flight
+            asm volatile("s_waitcnt vmcnt(40)\n\ts_barrier" ::: "memory");
+            asm volatile("s_barrier" ::: "memory");   // up-sampled halo written: the stage is free
+            if (u + 1 < U) {
+                issue_lr(u + 1);
+                asm volatile("s_waitcnt vmcnt(25)\n\ts_barrier" ::: "memory");   // skip halo landed
+            } else {
+                asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+            }
+            asm volatile("s_barrier" ::: "memory");   // products done: the skip halo is free
+            if (u + 1 < U) issue_sk(u + 1);
+        }
+        return;
+    }
+    float bv[2];
+    tile_bias<2>(bv, a.bias, 0, 32);
+    floatx4 acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // 3x3 operands as in k_conv3a: pixel block i of tap (dy, dx) at
+    // abase[dx] + 4096 dy + 1024 i bytes into a halo, the weights of column
+    // block j, tap t, chunk c at bbase + 18432 c + 2048 t + 1024 j
+    uint32_t abase[3];
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) abase[dx] = swz_slot((uint32_t)(wv * HP + l16 + dx), (uint32_t)g) * 16;
+    const uint32_t bbase = O_W * 16 + swz_slot((uint32_t)l16, (uint32_t)g) * 16;
+    const char* const lb = (const char*)lds;
+    auto compute = [&](int halo, int c) {
+        u32x4 av[2][4], bw[2][2];
+        auto rd = [&](int tap, u32x4 (&A)[4], u32x4 (&B)[2]) {
+            const int dy = tap / 3, dx = tap % 3;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) A[i] = *(const u32x4*)(lb + abase[dx] + (halo * 16 + dy * 4096 + i * 1024));
+#pragma unroll
+            for (int j = 0; j < 2; ++j) B[j] = *(const u32x4*)(lb + bbase + (c * 18432 + tap * 2048 + j * 1024));
+        };
+        rd(0, av[0], bw[0]);
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int cur = tap & 1;
+            if (tap + 1 < 9) rd(tap + 1, av[cur ^ 1], bw[cur ^ 1]);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(bf16x8, av[cur][i]), __builtin_bit_cast(bf16x8, bw[cur][j]), acc[i][j], 0, 0,
+                        0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    const float* const bus = (const float*)(lds + O_B * 8);
+    // this wave's sub-position of the transposed convolution and its
+    // weights as row operands (read from LDS once they have landed)
+    const int sub = wv >> 1, sy = sub >> 1, sx = sub & 1;
+    u32x4 wup[2][2];
+    for (uint32_t u = 0; u < U; ++u) {
+        // low-resolution stage of tile u loaded; the previous tile's
+        // epilogue reads of the up-sampled halo are done
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        const Geo q = geo(u);
+        // up-sampled halo: wave wv computes sub-position sub (rows of parity
+        // sy, pixels of column parity sx) for 5 of its 10 (row, 16-pixel
+        // block) items; halo pixel x0 - 1 + hp has column parity sx when hp
+        // has parity 1 - sx (x0 is even), halo row hr row parity sy when hr
+        // has parity 1 - sy
+        if (u == 0) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    wup[j][c] = *(const u32x4*)(lb + (O_U + (4 * sub + 2 * j + c) * 64 + lane) * 16);
+        }
+        auto rd1 = [&](int k, u32x4 (&xb)[2]) {
+            const int m = 5 * (wv & 1) + k, hr = 2 * (m >> 1) + 1 - sy, blk = m & 1;
+            const int lr = (hr + 1 - sy) >> 1, lp = 16 * blk + l16 + 1 - sx;
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                xb[c] = *(const u32x4*)(lb + (O_LR + (lr * LP + lp) * 8 + ((4 * c + g) ^ (lp & 7))) * 16);
+        };
+        u32x4 xb[2], xn[2];
+        rd1(0, xn);
+#pragma unroll 1
+        for (int k = 0; k < IPW; ++k) {
+            const int m = 5 * (wv & 1) + k, hr = 2 * (m >> 1) + 1 - sy, blk = m & 1;
+            const int hp = 2 * (16 * blk + l16) + 1 - sx;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) xb[c] = xn[c];
+            if (k + 1 < IPW) rd1(k + 1, xn);
+            floatx4 d[2] = {floatx4{0.f, 0.f, 0.f, 0.f}, floatx4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    d[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, wup[j][c]),
+                                                                   __builtin_bit_cast(bf16x8, xb[c]), d[j], 0, 0, 0);
+            const int y = (int)q.y0 - 1 + hr, x = (int)q.x0 - 1 + hp;
+            const bool in = y >= 0 && y < (int)a.H && x >= 0 && x < (int)a.W;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const floatx4 bj = *(const floatx4*)&bus[16 * j + 4 * g];
+                uint32_t w[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const float v0 = d[j][2 * h] + bj[2 * h], v1 = d[j][2 * h + 1] + bj[2 * h + 1];
+                    w[h] = in ? ((uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16)) : 0u;
+                }
+                const uint32_t slot = O_UP + swz_slot((uint32_t)(hr * HP + hp), (uint32_t)(2 * j + (g >> 1)));
+                *(uint2*)&lds[slot * 8 + (g & 1) * 4] = make_uint2(w[0], w[1]);
+            }
+        }
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");   // up-sampled halo complete
+        compute(O_UP, 0);
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");   // skip halo loaded
+        compute(O_SK, 1);
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");   // every wave done with both halos
+        const uint32_t y = q.y0 + (uint32_t)wv;
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+        store_tile<4, 2>(
+            lds + O_UP * 8 + wv * 64 * EP, acc, bv, 0, 32, true,
+            [&](int px) -> uint16_t* {
+                const uint32_t x = q.x0 + (uint32_t)px;
+                if (px >= TX || y >= a.H || x >= a.W) return nullptr;
+                return a.out + (((size_t)q.n * a.H + y) * a.W + x) * a.out_cs;
+            },
+            ln);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
 }
 
@@ -2074,6 +2378,33 @@ hipError_t conv_first(const uint16_t* in, uint32_t in_cs, const uint16_t* w1, co
     return hipGetLastError();
 }
 
+// The decoder's last transposed convolution and first 3x3 convolution,
+// fused (inference: the up-sampled channels are not kept).
+hipError_t conv_up_first(const uint16_t* low, uint32_t low_cs, const uint16_t* wu, const float* bu,
+                         const uint16_t* skip, uint32_t skip_cs, const uint16_t* wt, const float* bias, uint16_t* out,
+                         uint32_t out_cs, uint32_t N, uint32_t H, uint32_t W, hipStream_t s)
+{
+    if ((H & 1) || (W & 1)) return hipErrorInvalidValue;
+    ConvUpArgs a;
+    a.low = low;
+    a.wu = wu;
+    a.bu = bu;
+    a.skip = skip;
+    a.wt = wt;
+    a.bias = bias;
+    a.out = out;
+    a.low_cs = low_cs;
+    a.skip_cs = skip_cs;
+    a.out_cs = out_cs;
+    a.N = N;
+    a.H = H;
+    a.W = W;
+    ProfScope ps(cur_dev(), "fill.conv", s);
+    const uint32_t tiles = N * ((H + cvu::R - 1) / cvu::R) * ((W + cvu::TX - 1) / cvu::TX);
+    k_conv3u<<<dim3(std::min<uint32_t>(tiles, (uint32_t)cur_dev().cus)), dim3(cvu::WAVES * kWave), 0, s>>>(a);
+    return hipGetLastError();
+}
+
 hipError_t wgrad(const uint16_t* gr, uint32_t g_cs, const uint16_t* x, uint32_t x_cs, uint32_t N,
                  uint32_t H, uint32_t W, uint32_t Cin, uint32_t Creal, uint32_t Cout, int mode,
                  float* part, size_t part_elems, float* dst, hipStream_t s)
@@ -2191,10 +2522,16 @@ hipError_t forward(const Net& net, const float* th, const Bufs& b, uint32_t N, u
         const Layer& t = net.layers[net.dec(l)];
         const Layer& c0 = net.layers[net.dec(l) + 1];
         const Layer& c1 = net.layers[net.dec(l) + 2];
-        FHV_TRY(conv(h, h_cs, b.wt + t.wf_off, th + t.off_b, b.cat[l], 2 * Cl, N, Hl / 2, Wl / 2,
-                     net.C[l + 1], Cl, MODE_UP2, false, s));
-        FHV_TRY(conv(b.cat[l], 2 * Cl, b.wt + c0.wf_off, th + c0.off_b, b.d0[l], Cl, N, Hl, Wl, 2 * Cl, Cl,
-                     MODE_SAME3, true, s));
+        if (l == 0 && hf) {
+            // inference: the transposed convolution inside the first 3x3 one
+            FHV_TRY(conv_up_first(h, h_cs, b.wt + t.wf_off, th + t.off_b, b.cat[0] + Cl, 2 * Cl, b.wt + c0.wf_off,
+                                  th + c0.off_b, b.d0[0], Cl, N, Hl, Wl, s));
+        } else {
+            FHV_TRY(conv(h, h_cs, b.wt + t.wf_off, th + t.off_b, b.cat[l], 2 * Cl, N, Hl / 2, Wl / 2,
+                         net.C[l + 1], Cl, MODE_UP2, false, s));
+            FHV_TRY(conv(b.cat[l], 2 * Cl, b.wt + c0.wf_off, th + c0.off_b, b.d0[l], Cl, N, Hl, Wl, 2 * Cl, Cl,
+                         MODE_SAME3, true, s));
+        }
         FHV_TRY(conv(b.d0[l], Cl, b.wt + c1.wf_off, th + c1.off_b, b.d1[l], Cl, N, Hl, Wl, Cl, Cl,
                      MODE_SAME3, true, s, nullptr, 0, l == 0 ? hf : nullptr));
         h = b.d1[l];
