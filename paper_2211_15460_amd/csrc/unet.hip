@@ -61,11 +61,17 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kBase = 32;
 constexpr int kInPad = 8;   // 6 input channels padded to 8
 
-__device__ __forceinline__ uint16_t f2bf(float f)
+// fp32 to bf16, round to nearest even: the conversion instruction of
+// gfx950 (two values per instruction in f2bf2)
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+
+// lo in the low half, hi in the high half
+__device__ __forceinline__ uint32_t f2bf2(float lo, float hi)
 {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(floatx2{lo, hi}, bf16x2));
 }
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
@@ -205,8 +211,9 @@ __device__ __forceinline__ u32x4 max4_bf16(const u32x4 (&v)[4])
 }
 
 // The 1x1 head on pixel p from its 32 bf16 channels hp (in LDS): residual
-// W h + b (hw: W [3][32], then b [3]), added to the splat colour sp,
-// clamped, rounded half up; alpha 255.
+// W h + b (hw: W [3][32], then b [3], in LDS) as a chain of fused
+// multiply-adds, added to the splat colour sp (times the fp32 reciprocal of
+// 255), clamped, rounded half up; alpha 255.
 __device__ __forceinline__ void head_pixel(const ConvArgs& a, const float* hw, const uint16_t* hp, size_t p,
                                            uint32_t sp)
 {
@@ -219,13 +226,13 @@ __device__ __forceinline__ void head_pixel(const ConvArgs& a, const float* hw, c
             const int c = 8 * c4 + e;
             const float v = bf2f((uint16_t)(hv[e >> 1] >> (16 * (e & 1))));
 #pragma unroll
-            for (int k = 0; k < 3; ++k) r[k] += hw[k * 32 + c] * v;
+            for (int k = 0; k < 3; ++k) r[k] = __builtin_fmaf(hw[k * 32 + c], v, r[k]);   // one rounding per term
         }
     }
     uint32_t o = 0xFF000000u;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        float v = (float)((sp >> (8 * k)) & 0xFFu) / 255.0f + r[k];
+        float v = (float)((sp >> (8 * k)) & 0xFFu) * (1.0f / 255.0f) + r[k];
         v = v < 0.0f ? 0.0f : (v > 1.0f ? 1.0f : v);
         o |= (uint32_t)floorf(v * 255.0f + 0.5f) << (8 * k);
         if (a.head_res) a.head_res[p * 3 + k] = r[k];
@@ -1219,7 +1226,19 @@ __global__ void __launch_bounds__(cv2::WAVES * kWave) k_conv33(Conv2Args a)
     }
     float bv[2];
     tile_bias<2>(bv, a.b2, 0, 32);
+    // the first convolution's weights as row operands (slot 64 (2 c + j) +
+    // lane of w1s), held in registers once they have landed
+    u32x4 w1r[2][3];
     floatx4 acc[4][2];
+    // second-convolution operand byte offsets as in k_conv3a: pixel block i
+    // of tap (dy, dx) at abase[dx] + 4096 dy + 1024 i into the output halo,
+    // the weights of column block j, tap t at bbase + 2048 t + 1024 j
+    static_assert(HP == 64, "row stride of 4096 bytes");
+    uint32_t abase[3];
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) abase[dx] = swz_slot((uint32_t)(wv * HP + l16 + dx), (uint32_t)g) * 16;
+    const uint32_t bbase = (HSLOTS + S * ISLOTS) * 16 + swz_slot((uint32_t)l16, (uint32_t)g) * 16;
+    const char* const lb = (const char*)lds;
     auto compute2 = [&]() {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
@@ -1229,11 +1248,9 @@ __global__ void __launch_bounds__(cv2::WAVES * kWave) k_conv33(Conv2Args a)
         auto rd = [&](int tap, u32x4 (&A)[4], u32x4 (&B)[2]) {
             const int dy = tap / 3, dx = tap % 3;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                A[i] = *(const u32x4*)&h1[swz_slot((uint32_t)((wv + dy) * HP + 16 * i + l16 + dx), (uint32_t)g) * 8];
+            for (int i = 0; i < 4; ++i) A[i] = *(const u32x4*)(lb + abase[dx] + (dy * 4096 + i * 1024));
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
-                B[j] = *(const u32x4*)&wts[swz_slot((uint32_t)(tap * 32 + 16 * j + l16), (uint32_t)g) * 8];
+            for (int j = 0; j < 2; ++j) B[j] = *(const u32x4*)(lb + bbase + (tap * 2048 + j * 1024));
         };
         rd(0, av[0], bw[0]);
 #pragma unroll
@@ -1258,35 +1275,44 @@ __global__ void __launch_bounds__(cv2::WAVES * kWave) k_conv33(Conv2Args a)
         const Geo q = geo(u);
         const uint16_t* in_s = ist + (u % S) * ISLOTS * 8;
         // first convolution: blocks wv, wv + 8, ... of the output halo, each
-        // 16 pixels of one halo row x 32 channels; the next block's operands
-        // are read while the current block's products run
-        auto rd1 = [&](int k, u32x4 (&xb)[3]) {
+        // 16 pixels of one halo row x 32 channels. All operands of the
+        // wave's blocks are read first, then all products issued (ten
+        // independent accumulators), then the results written.
+        if (u == 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) w1r[j][c] = *(const u32x4*)&w1s[((2 * c + j) * 64 + lane) * 8];
+        }
+        u32x4 xb[BPW][3];
+#pragma unroll
+        for (int k = 0; k < BPW; ++k) {
             const int blk = wv + CWAVES * k, hr = blk >> 2, hp = 16 * (blk & 3) + l16;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 // past the ninth tap: read tap 8 and clear it (no branch)
                 const int tap = 4 * c + g, t = tap < 9 ? tap : 8, dy = t / 3, dx = t - 3 * dy;
                 const uint32_t keep = tap < 9 ? ~0u : 0u;
-                xb[c] = *(const u32x4*)&in_s[((hr + dy) * IP + hp + dx) * 8] & keep;
+                xb[k][c] = *(const u32x4*)&in_s[((hr + dy) * IP + hp + dx) * 8] & keep;
             }
-        };
-        u32x4 xb[3], xn[3];
-        rd1(0, xn);
-        // not unrolled: unrolled, the blocks' addresses stay live in registers
-#pragma unroll 1
-        for (int k = 0; k < BPW; ++k) {
-            const int blk = wv + CWAVES * k, hr = blk >> 2, hp = 16 * (blk & 3) + l16;
+        }
+        floatx4 d[BPW][2];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) xb[c] = xn[c];
-            if (k + 1 < BPW) rd1(k + 1, xn);
-            floatx4 d[2] = {floatx4{0.f, 0.f, 0.f, 0.f}, floatx4{0.f, 0.f, 0.f, 0.f}};
+        for (int k = 0; k < BPW; ++k)
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
+            for (int j = 0; j < 2; ++j) d[k][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int k = 0; k < BPW; ++k)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
-                    d[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        __builtin_bit_cast(bf16x8, *(const u32x4*)&w1s[((2 * c + j) * 64 + lane) * 8]),
-                        __builtin_bit_cast(bf16x8, xb[c]), d[j], 0, 0, 0);
+                    d[k][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, w1r[j][c]),
+                                                                      __builtin_bit_cast(bf16x8, xb[k][c]), d[k][j], 0,
+                                                                      0, 0);
+#pragma unroll
+        for (int k = 0; k < BPW; ++k) {
+            const int blk = wv + CWAVES * k, hr = blk >> 2, hp = 16 * (blk & 3) + l16;
             const int y = (int)q.y0 - 1 + hr, x = (int)q.x0 - 1 + hp;
             const bool in = y >= 0 && y < (int)a.H && x >= 0 && x < (int)a.W;
 #pragma unroll
@@ -1296,10 +1322,10 @@ __global__ void __launch_bounds__(cv2::WAVES * kWave) k_conv33(Conv2Args a)
                 uint32_t w[2];
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    float v0 = d[j][2 * h] + bj[2 * h], v1 = d[j][2 * h + 1] + bj[2 * h + 1];
+                    float v0 = d[k][j][2 * h] + bj[2 * h], v1 = d[k][j][2 * h + 1] + bj[2 * h + 1];
                     v0 = v0 > 0.0f ? v0 : 0.0f;
                     v1 = v1 > 0.0f ? v1 : 0.0f;
-                    w[h] = in ? ((uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16)) : 0u;
+                    w[h] = in ? f2bf2(v0, v1) : 0u;
                 }
                 const uint32_t slot = swz_slot((uint32_t)(hr * HP + hp), (uint32_t)(2 * j + (g >> 1)));
                 *(uint2*)&h1[slot * 8 + (g & 1) * 4] = make_uint2(w[0], w[1]);
@@ -1309,16 +1335,22 @@ __global__ void __launch_bounds__(cv2::WAVES * kWave) k_conv33(Conv2Args a)
         compute2();
         asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");   // every wave done with it
         const uint32_t y = q.y0 + (uint32_t)wv;
-        store_tile<4, 2>(h1 + wv * 64 * EP, acc, bv, 0, 32, true, [&](int px) -> uint16_t* {
-            const uint32_t x = q.x0 + (uint32_t)px;
-            if (px >= TX || y >= a.H || x >= a.W) return nullptr;
-            return a.out + (((size_t)q.n * a.H + y) * a.W + x) * a.out_cs;
-        });
+        int ln = lane;
+        asm volatile("" : "+v"(ln));   // keeps the epilogue's per-lane addresses out of the loop
+        store_tile<4, 2>(
+            h1 + wv * 64 * EP, acc, bv, 0, 32, true,
+            [&](int px) -> uint16_t* {
+                const uint32_t x = q.x0 + (uint32_t)px;
+                if (px >= TX || y >= a.H || x >= a.W) return nullptr;
+                return a.out + (((size_t)q.n * a.H + y) * a.W + x) * a.out_cs;
+            },
+            ln);
         asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");   // epilogue rows complete
         // 2x2 max pool (even H and W) from the waves' epilogue rows
         constexpr int PCH = 4, RUNS = (TX / 2) * (R / 2) * PCH;
         static_assert(RUNS <= CWAVES * kWave, "one pass over the pooled runs");
-        const uint32_t run = threadIdx.x;
+        uint32_t run = threadIdx.x;
+        asm volatile("" : "+v"(run));
         if (run < (uint32_t)RUNS) {
             const uint32_t c8 = run % PCH, p2 = (run / PCH) % (TX / 2), pr = run / (PCH * (TX / 2));
             const uint32_t xs = q.x0 + 2 * p2, ys = q.y0 + 2 * pr;
@@ -1598,7 +1630,7 @@ __global__ void __launch_bounds__(cvu::WAVES * kWave) k_conv3u(ConvUpArgs a)
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const float v0 = d[j][2 * h] + bj[2 * h], v1 = d[j][2 * h + 1] + bj[2 * h + 1];
-                    w[h] = in ? ((uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16)) : 0u;
+                    w[h] = in ? f2bf2(v0, v1) : 0u;
                 }
                 const uint32_t slot = O_UP + swz_slot((uint32_t)(hr * HP + hp), (uint32_t)(2 * j + (g >> 1)));
                 *(uint2*)&lds[slot * 8 + (g & 1) * 4] = make_uint2(w[0], w[1]);
