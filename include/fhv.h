@@ -445,8 +445,11 @@ FHV_API size_t fhv_fill_workspace(uint32_t levels, uint32_t n_img, uint32_t heig
                                   int training);
 
 /* Inference: out_rgba = clamp(splat RGB / 255 + residual, 0, 1) * 255
- * rounded half up, alpha 255; out_residual (nullable) receives the fp32
- * residual [n_img][height][width][3].
+ * rounded half up, alpha 255 (in fp32, splat RGB times the fp32
+ * reciprocal of 255, so a channel may differ by one step from the exact
+ * quotient's where the sum lands next to a rounding boundary);
+ * out_residual (nullable) receives the fp32 residual
+ * [n_img][height][width][3].
  * Errors: EINVAL (null pointers, levels, sizes), ERANGE, EWORKSPACE. */
 FHV_API fhv_status fhv_fill(fhv_ctx* ctx, uint32_t levels, const float* params, const uint32_t* rgba,
                             const float* depth, const uint8_t* cov, uint32_t n_img, uint32_t height,
