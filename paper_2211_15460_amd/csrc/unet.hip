@@ -1117,7 +1117,7 @@ constexpr int BLOCKS = RP * (HP / 16);             // 16-pixel blocks of the out
 constexpr int BPW = BLOCKS / CWAVES;               // blocks per computing wave
 constexpr int W1SLOTS = 3 * 2 * 64;                // first convolution's weights, one slot per lane and operand
 // then the first convolution's bias: 64 floats, one per lane of its load
-constexpr int LDS_ELEMS = (HSLOTS + S * ISLOTS + WSLOTS + W1SLOTS) * 8 + 64 * 2;
+constexpr int LDS_ELEMS = (2 * HSLOTS + S * ISLOTS + WSLOTS + W1SLOTS) * 8 + 64 * 2;
 static_assert(IINSTR == 13, "the loading wave's wait below allows one tile's loads in flight");
 static_assert(BLOCKS % CWAVES == 0, "whole blocks per wave");
 static_assert(CWAVES * 64 * EP <= HSLOTS * 8, "epilogue rows fit the output halo");
@@ -1138,11 +1138,11 @@ __global__ void __launch_bounds__(cv2::WAVES * kWave) k_conv33(Conv2Args a)
 {
     using namespace cv2;
     __shared__ __attribute__((aligned(16))) uint16_t lds[LDS_ELEMS];
-    // the output halo comes first: the second convolution's reads past its
-    // end (the two unstored pixels of the last row) stay inside the array
-    uint16_t* const h1 = lds;
-    uint16_t* const ist = lds + HSLOTS * 8;
-    uint16_t* const wts = lds + (HSLOTS + S * ISLOTS) * 8;
+    // the two output halos come first: the second convolution's reads past
+    // the end of one (the two unstored pixels of the last row) stay inside
+    // the array
+    uint16_t* const ist = lds + 2 * HSLOTS * 8;
+    uint16_t* const wts = lds + (2 * HSLOTS + S * ISLOTS) * 8;
     uint16_t* const w1s = wts + WSLOTS * 8;
     const float* const b1s = (const float*)(w1s + W1SLOTS * 8);
     const int lane = __lane_id(), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -1185,8 +1185,12 @@ __global__ void __launch_bounds__(cv2::WAVES * kWave) k_conv33(Conv2Args a)
                                                      16, off, 0, 0, 0);
         }
     };
-    // Barriers are plain s_barrier, four per tile on both sides: input
-    // staged, output halo written, output halo read, epilogue rows written.
+    // Barriers are plain s_barrier, the same sequence on both sides: one
+    // before the pipeline starts (tile 0 staged), then three per tile (the
+    // tile's output halo written and the next tile's input staged; the
+    // tile's output halo read; its epilogue rows written). Tile u's second
+    // convolution and tile u + 1's first run in the same phase, on the two
+    // output halos in turn.
     if (loader) {
         // the second convolution's weights, [tap][channel] rows
         const __amdgpu_buffer_rsrc_t wrs = rsrc(a.w2, 32 * 9 * 32 * 2);
@@ -1213,14 +1217,21 @@ __global__ void __launch_bounds__(cv2::WAVES * kWave) k_conv33(Conv2Args a)
                                                  lane < 32 ? (uint32_t)lane * 4 : kOob, 0, 0, 0);
         issue(0);
         if (U > 1) issue(1);
+        // tile 0 has landed once at most tile 1's loads are in flight
+        if (U > 1)
+            asm volatile("s_waitcnt vmcnt(13)\n\ts_barrier" ::: "memory");
+        else
+            asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+        if (U > 2) issue(2);
         for (uint32_t u = 0; u < U; ++u) {
-            // tile u has landed once at most the next tile's loads are in flight
-            if (u + 1 < U)
+            // tile u + 1 (read in this tile's phase) has landed once at most
+            // tile u + 2's loads are in flight
+            if (u + 2 < U)
                 asm volatile("s_waitcnt vmcnt(13)\n\ts_barrier" ::: "memory");
             else
                 asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
-            if (u + 2 < U) issue(u + 2);   // into the stage that tile u - 1 left
-            asm volatile("s_barrier\n\ts_barrier\n\ts_barrier" ::: "memory");
+            if (u + 3 < U) issue(u + 3);   // into tile u's stage, read before this barrier
+            asm volatile("s_barrier\n\ts_barrier" ::: "memory");
         }
         return;
     }
@@ -1237,9 +1248,10 @@ __global__ void __launch_bounds__(cv2::WAVES * kWave) k_conv33(Conv2Args a)
     uint32_t abase[3];
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx) abase[dx] = swz_slot((uint32_t)(wv * HP + l16 + dx), (uint32_t)g) * 16;
-    const uint32_t bbase = (HSLOTS + S * ISLOTS) * 16 + swz_slot((uint32_t)l16, (uint32_t)g) * 16;
+    const uint32_t bbase = (2 * HSLOTS + S * ISLOTS) * 16 + swz_slot((uint32_t)l16, (uint32_t)g) * 16;
     const char* const lb = (const char*)lds;
-    auto compute2 = [&]() {
+    auto compute2 = [&](int hb) {
+        const uint32_t hoff = (uint32_t)hb * HSLOTS * 16;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -1248,7 +1260,7 @@ __global__ void __launch_bounds__(cv2::WAVES * kWave) k_conv33(Conv2Args a)
         auto rd = [&](int tap, u32x4 (&A)[4], u32x4 (&B)[2]) {
             const int dy = tap / 3, dx = tap % 3;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) A[i] = *(const u32x4*)(lb + abase[dx] + (dy * 4096 + i * 1024));
+            for (int i = 0; i < 4; ++i) A[i] = *(const u32x4*)(lb + hoff + abase[dx] + (dy * 4096 + i * 1024));
 #pragma unroll
             for (int j = 0; j < 2; ++j) B[j] = *(const u32x4*)(lb + bbase + (tap * 2048 + j * 1024));
         };
@@ -1268,22 +1280,14 @@ __global__ void __launch_bounds__(cv2::WAVES * kWave) k_conv33(Conv2Args a)
             __builtin_amdgcn_sched_barrier(0);
         }
     };
-    for (uint32_t u = 0; u < U; ++u) {
-        // tile u staged (the loading wave waited); the previous tile's pool
-        // reads of the output halo are done
-        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    // first convolution of tile u into output halo hb: blocks wv, wv + 8,
+    // ... of the halo, each 16 pixels of one halo row x 32 channels. All
+    // operands of the wave's blocks are read first, then all products
+    // issued (ten independent accumulators), then the results written.
+    auto conv1 = [&](uint32_t u, int hb) {
         const Geo q = geo(u);
         const uint16_t* in_s = ist + (u % S) * ISLOTS * 8;
-        // first convolution: blocks wv, wv + 8, ... of the output halo, each
-        // 16 pixels of one halo row x 32 channels. All operands of the
-        // wave's blocks are read first, then all products issued (ten
-        // independent accumulators), then the results written.
-        if (u == 0) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int j = 0; j < 2; ++j) w1r[j][c] = *(const u32x4*)&w1s[((2 * c + j) * 64 + lane) * 8];
-        }
+        uint16_t* h1 = lds + hb * HSLOTS * 8;
         u32x4 xb[BPW][3];
 #pragma unroll
         for (int k = 0; k < BPW; ++k) {
@@ -1331,9 +1335,24 @@ __global__ void __launch_bounds__(cv2::WAVES * kWave) k_conv33(Conv2Args a)
                 *(uint2*)&h1[slot * 8 + (g & 1) * 4] = make_uint2(w[0], w[1]);
             }
         }
-        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");   // output halo complete
-        compute2();
-        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");   // every wave done with it
+    };
+    // tile 0 staged; the first convolution's weights have landed with it
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) w1r[j][c] = *(const u32x4*)&w1s[((2 * c + j) * 64 + lane) * 8];
+    conv1(0, 0);
+    for (uint32_t u = 0; u < U; ++u) {
+        // tile u's output halo complete, tile u + 1 staged; the previous
+        // tile's pool reads of the other output halo are done
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        const int hb = (int)(u & 1);
+        if (u + 1 < U) conv1(u + 1, hb ^ 1);
+        compute2(hb);
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");   // every wave done with tile u's halo
+        const Geo q = geo(u);
+        uint16_t* h1 = lds + hb * HSLOTS * 8;
         const uint32_t y = q.y0 + (uint32_t)wv;
         int ln = lane;
         asm volatile("" : "+v"(ln));   // keeps the epilogue's per-lane addresses out of the loop
