@@ -128,7 +128,7 @@ SCOPE_KERNELS = {
     "capture.setup": ("k_setup",), "capture.raster": ("k_raster",),
     "compact.hist": ("k_hist",), "compact.scatter": ("k_scatter",),
     "compact.brick": ("k_brick_wave", "k_brick"),
-    "splat.bin": ("k_chunk_box", "k_node_box"), "splat.splat": ("k_tile_splat",),
+    "splat.bin": ("k_chunk_box", "k_node_box"), "splat.est": ("k_tile_est",), "splat.splat": ("k_tile_splat",),
     "ray.occupancy": ("k_occ_build",), "ray.cast": ("k_raycast",),
 }
 

@@ -232,8 +232,9 @@ __device__ __forceinline__ uint64_t pack_pos(const uint4& r, uint64_t key, uint3
 template <int kMode, bool kBatch>
 __global__ void __launch_bounds__(kBlock)
 k_chunk_box(const uint4* __restrict__ frag, const uint64_t* __restrict__ oct_key, const uint64_t* __restrict__ n_frag,
-            TileArgs ta, float4* __restrict__ box, uint64_t* __restrict__ pos)
+            TileArgs ta, float4* __restrict__ box, uint64_t* __restrict__ pos, uint32_t* __restrict__ bucket)
 {
+    if (blockIdx.x == 0 && threadIdx.x < 9) bucket[threadIdx.x] = 0;   // the tile pass's item counters, anew
     if (ta.cap_occ == 0) return;   // no table rows: nothing to draw
     const uint64_t F = frag_total(n_frag, ta.cap_frag);
     const uint64_t nch = (F + kChunk - 1) / kChunk;
@@ -314,6 +315,15 @@ __device__ __forceinline__ uint32_t die_major(uint32_t b, uint32_t n)
 constexpr int kTileWaves = 16;                 // waves per tile workgroup
 constexpr int kTileThreads = kTileWaves * kWave;
 constexpr uint32_t kFront = 2048;              // breadth-first frontier capacity (node ids)
+// Ordering and splitting the tiles: a tile whose walk reaches n groups of
+// chunks is drawn by P workgroups, ceil(n / kSplitGroups) rounded up to a
+// power of two (at most kMaxParts), each on 64 / P of its columns, with at
+// most kMaxItems workgroups beyond one per tile per launch; the workgroups
+// start in decreasing order of their share of groups (8 classes), the
+// busiest first. Launches of 2^22 tiles or more keep one workgroup per tile
+// in the plain order.
+constexpr uint32_t kSplitGroups = 32, kMaxParts = 16, kMaxItems = 4096, kOrderTiles = 1u << 22;
+constexpr int kEstWaves = 4;                   // waves per workgroup of the estimate pass
 
 // What one tile's workgroup knows about its view.
 struct TileView {
@@ -322,7 +332,17 @@ struct TileView {
     int32_t k;
     uint32_t scene;
     int32_t X0, Y0;
+    int32_t XS, XE;   // the columns this workgroup draws: [XS, XE), within the tile
 };
+
+// Workgroups beyond one per tile: up to kMaxItems; none when the tiles are
+// not ordered.
+__host__ __device__ __forceinline__ uint32_t split_items(uint32_t n_tiles)
+{
+    if (n_tiles >= kOrderTiles) return 0;
+    const uint32_t m = 2 * ((n_tiles + 7) / 8 * 8);
+    return m < kMaxItems ? m : kMaxItems;
+}
 
 // Which of the kFan children of node `node` (on level l, children on level
 // l - 1) can reach the tile: a bit per lane.
@@ -341,8 +361,7 @@ __device__ __forceinline__ uint64_t test_children(const float4* __restrict__ box
     if (kBatch) ok = ok && __float_as_uint(lo.w) <= tv.scene && tv.scene <= __float_as_uint(hi.w);
     if (ok) {
         const PixRect r = chunk_rect(tv.M, tv.c, (uint32_t)tv.k, ta.width, ta.height, lo, hi);
-        ok = r.x0 <= r.x1 && r.y0 <= r.y1 && r.x1 >= tv.X0 && r.x0 < tv.X0 + kTile && r.y1 >= tv.Y0 &&
-             r.y0 < tv.Y0 + kTile;
+        ok = r.x0 <= r.x1 && r.y0 <= r.y1 && r.x1 >= tv.XS && r.x0 < tv.XE && r.y1 >= tv.Y0 && r.y0 < tv.Y0 + kTile;
     }
     return __ballot(ok);
 }
@@ -378,7 +397,7 @@ __device__ __forceinline__ void draw_pos(uint64_t p, uint64_t f, const TileArgs&
     if (k == 1) {
         if (fx >= 0.0f && fx < (float)ta.width && fy >= 0.0f && fy < (float)ta.height) {
             const int32_t px = (int32_t)fx - X0, py = (int32_t)fy - Y0;
-            if ((uint32_t)px < (uint32_t)kTile && (uint32_t)py < (uint32_t)kTile)
+            if ((uint32_t)((int32_t)fx - tv.XS) < (uint32_t)(tv.XE - tv.XS) && (uint32_t)py < (uint32_t)kTile)
                 atomicMin(zt + py * kTile + px, zk);
         }
         return;
@@ -387,9 +406,9 @@ __device__ __forceinline__ void draw_pos(uint64_t p, uint64_t f, const TileArgs&
     if (!(fy > -1073741824.0f && fy < 1073741824.0f)) return;
     int32_t xa = (int32_t)fx, ya = (int32_t)fy;
     int32_t xb = xa + k, yb = ya + k;   // exclusive
-    xa = xa < X0 ? X0 : xa;
+    xa = xa < tv.XS ? tv.XS : xa;
     ya = ya < Y0 ? Y0 : ya;
-    const int32_t xe = X0 + kTile < (int32_t)ta.width ? X0 + kTile : (int32_t)ta.width;
+    const int32_t xe = tv.XE < (int32_t)ta.width ? tv.XE : (int32_t)ta.width;
     const int32_t ye = Y0 + kTile < (int32_t)ta.height ? Y0 + kTile : (int32_t)ta.height;
     xb = xb > xe ? xe : xb;
     yb = yb > ye ? ye : yb;
@@ -411,25 +430,29 @@ __device__ __forceinline__ void draw_queue(const uint32_t* q, uint64_t base, uin
 {
     if (i0 >= n) return;
     const int lane = __lane_id();
-    auto chunk = [&](uint32_t i) { return q ? (uint64_t)q[i] : base + i; };
-    uint64_t ca[kDrawBatch], pa[kDrawBatch];
+    // chunk ids fit 32 bits (fewer than 2^32 chunks per launch)
+    auto chunk = [&](uint32_t i) -> uint32_t { return q ? q[i] : (uint32_t)base + i; };
+    uint32_t ca[kDrawBatch];
+    uint64_t pa[kDrawBatch];
 #pragma unroll
     for (int j = 0; j < kDrawBatch; ++j) {
         const uint32_t i = i0 + (uint32_t)j * step;
         ca[j] = i < n ? chunk(i) : 0;
-        pa[j] = i < n ? pos[ca[j] * kChunk + lane] : 0;
+        pa[j] = i < n ? pos[(uint64_t)ca[j] * kChunk + lane] : 0;
     }
     for (uint32_t ib = i0; ib < n; ib += kDrawBatch * step) {
-        uint64_t cb[kDrawBatch], pb[kDrawBatch];
+        uint32_t cb[kDrawBatch];
+        uint64_t pb[kDrawBatch];
 #pragma unroll
         for (int j = 0; j < kDrawBatch; ++j) {
             const uint32_t i = ib + (uint32_t)(kDrawBatch + j) * step;
             cb[j] = i < n ? chunk(i) : 0;
-            pb[j] = i < n ? pos[cb[j] * kChunk + lane] : 0;
+            pb[j] = i < n ? pos[(uint64_t)cb[j] * kChunk + lane] : 0;
         }
 #pragma unroll
         for (int j = 0; j < kDrawBatch; ++j)
-            if (ib + (uint32_t)j * step < n) draw_pos<kMode, kBatch>(pa[j], ca[j] * kChunk + lane, ta, tv, zt);
+            if (ib + (uint32_t)j * step < n)
+                draw_pos<kMode, kBatch>(pa[j], (uint64_t)ca[j] * kChunk + lane, ta, tv, zt);
 #pragma unroll
         for (int j = 0; j < kDrawBatch; ++j) {
             ca[j] = cb[j];
@@ -438,34 +461,165 @@ __device__ __forceinline__ void draw_queue(const uint32_t* q, uint64_t base, uin
     }
 }
 
-// One workgroup per 64 x 64 tile of one view slot: the chunk tree is
-// walked from the root breadth first (children tested one per lane) down to
-// the groups of 64 chunks that can reach the tile; then, in rounds of one
-// group per wave, the chunks of those groups that can reach the tile are
-// queued in LDS and drawn by all waves in turn into the z-tile in LDS with
-// 64-bit minima. Should a level's frontier not fit in LDS, every chunk
-// below the last frontier that did is drawn. Then each pixel of the tile is
-// written once.
+// The view of tile `tile` (slot g = tile / per_view) for the walk and the draw.
+template <bool kBatch>
+__device__ __forceinline__ TileView tile_view(uint32_t tile, const TileArgs& ta, const ViewArgs& va, const float* vm,
+                                              bool drawn, uint32_t part = 0, uint32_t n_parts = 1)
+{
+    const uint32_t g = tile / ta.per_view, t = tile % ta.per_view;
+    TileView tv;
+    tv.X0 = (int32_t)((t % ta.nx) * kTile);
+    tv.Y0 = (int32_t)((t / ta.nx) * kTile);
+    tv.XS = tv.X0 + (int32_t)(part * (kTile / n_parts));
+    tv.XE = tv.XS + (int32_t)(kTile / n_parts);
+    tv.scene = g / ta.n_views;
+    if (drawn) {
+        const ViewSrc<kBatch> vs{va, vm};
+#pragma unroll
+        for (int q = 0; q < 12; ++q) tv.M[q] = vs.m(g)[q];
+        tv.c = vs.c(g);
+        tv.k = (int32_t)vs.k(g);
+    }
+    return tv;
+}
+
+// Breadth-first walk of the chunk tree from the root (front[0][0]) by the
+// workgroup's kWaves waves, children tested one per lane, down to the
+// groups of chunks (level 1) that can reach the tile, or until a level's
+// frontier does not fit kFront. Returns the level lv of the final frontier
+// front[*cur] of *curn nodes (lv >= 2 when it stopped early).
+template <bool kBatch, int kWaves>
+__device__ __forceinline__ uint32_t walk_tree(const float4* __restrict__ box, const TileArgs& ta, const uint32_t* nl,
+                                              const TileView& tv, uint32_t (*front)[kFront], uint32_t* sh_next,
+                                              uint32_t* sh_over, uint32_t* cur, uint32_t* curn)
+{
+    const uint32_t wave = threadIdx.x / kWave;
+    const int lane = __lane_id();
+    uint32_t lv = ta.levels - 1, c = 0, n = 1;
+    while (lv >= 2) {
+        if (threadIdx.x == 0) {
+            *sh_next = 0;
+            *sh_over = 0;
+        }
+        __syncthreads();
+        for (uint32_t e = wave; e < n; e += kWaves) {
+            const uint32_t node = front[c][e];
+            const uint64_t m = test_children<kBatch>(box, ta, nl, lv, node, tv);
+            const uint32_t cnt = (uint32_t)__popcll(m);
+            uint32_t base = 0;
+            if (lane == 0 && cnt) base = atomicAdd(sh_next, cnt);
+            base = uniform32((uint32_t)__shfl((int)base, 0, kWave));
+            if ((m >> lane) & 1ull) {
+                const uint32_t pos = base + (uint32_t)__popcll(m & lanemask_lt());
+                if (pos < kFront) front[c ^ 1][pos] = node * kFan + (uint32_t)lane;
+                else *sh_over = 1;
+            }
+        }
+        __syncthreads();
+        const uint32_t nn = *sh_next, over = *sh_over;
+        __syncthreads();
+        if (over) break;   // keep the current frontier; depth first from here
+        c ^= 1;
+        n = nn;
+        --lv;
+    }
+    *cur = c;
+    *curn = n;
+    return lv;
+}
+
+// Estimate pass, one workgroup of kEstWaves waves per tile: the walk down to
+// the groups of chunks that can reach the tile sets how many workgroups
+// draw it (P, reserved from the launch's extra budget: counter[8]) and the
+// class of their share of groups (0 for nothing to draw, then 1 + log2 of
+// the share, at most 7). Its items (tile << 5 | part) go to its class's
+// list, items[class * item_cap + rank ...] (counter[class] counts the
+// class's items); parts[tile] = P.
+template <bool kBatch>
+__global__ void __launch_bounds__(kEstWaves * kWave)
+k_tile_est(const uint64_t* __restrict__ n_frag, TileArgs ta, ViewArgs va, const float* __restrict__ vm,
+           const float4* __restrict__ box, uint32_t* __restrict__ items, uint32_t* __restrict__ parts,
+           uint32_t* __restrict__ counter)
+{
+    __shared__ uint32_t front[2][kFront];
+    __shared__ uint32_t nl[kMaxLevels];
+    __shared__ uint32_t sh_next, sh_over;
+    const uint32_t tile = blockIdx.x;
+    const uint64_t F = frag_total(n_frag, ta.cap_frag);
+    const bool drawn = ta.cap_occ > 0 && F > 0;
+    const TileView tv = tile_view<kBatch>(tile, ta, va, vm, drawn);
+    if (threadIdx.x == 0) {
+        uint32_t n[kMaxLevels];
+        level_counts(F, ta.levels, n);
+        for (uint32_t l = 0; l < ta.levels; ++l) nl[l] = n[l];
+        front[0][0] = 0;
+    }
+    __syncthreads();
+    uint32_t groups = 0;   // groups of chunks that can reach the tile (a large value when uncounted)
+    if (drawn) {
+        uint32_t cur, curn;
+        const uint32_t lv = walk_tree<kBatch, kEstWaves>(box, ta, nl, tv, front, &sh_next, &sh_over, &cur, &curn);
+        groups = lv >= 2 ? 1u << 16 : (lv == 1 ? curn : 1);
+    }
+    if (threadIdx.x == 0) {
+        const uint32_t q = (groups + kSplitGroups - 1) / kSplitGroups;
+        uint32_t P = 1;
+        while (P < q && P < kMaxParts) P *= 2;
+        if (P > 1 && atomicAdd(counter + 8, P - 1) + (P - 1) > split_items(ta.n_tiles)) P = 1;
+        const uint32_t share = (groups + P - 1) / P;
+        const uint32_t cls = share == 0 ? 0u : (share >= 64 ? 7u : 32u - __builtin_clz(share));
+        const uint32_t r = atomicAdd(counter + cls, P);
+        uint32_t* it = items + (size_t)cls * (ta.n_tiles + split_items(ta.n_tiles)) + r;
+        for (uint32_t i = 0; i < P; ++i) it[i] = (tile << 5) | i;
+        parts[tile] = P;
+    }
+}
+
+// One workgroup per item: a 64 x 64 tile of one view slot, or a column
+// strip of one (items in the estimate's order; one per tile, in the plain
+// order, for launches of 2^22 tiles or more). The chunk tree is walked from
+// the root breadth first (children tested one per lane) down to the groups
+// of 64 chunks that can reach the workgroup's columns of the tile; then, in
+// rounds of one group per wave, the chunks of those groups that can reach
+// them are queued in LDS and drawn by all waves in turn into the z-tile in
+// LDS with 64-bit minima (fragments outside the columns rejected). Should a
+// level's frontier not fit in LDS, every chunk below the last frontier that
+// did is drawn. Then each pixel of the columns is written once.
 template <int kMode, bool kBatch>
-__global__ void __launch_bounds__(kTileThreads)
+__global__ void __launch_bounds__(kTileThreads, 8)   // 8 waves per SIMD (two workgroups per compute unit): 64 registers
 k_tile_splat(const uint4* __restrict__ frag, const uint64_t* __restrict__ pos, const uint64_t* __restrict__ n_frag,
              TileArgs ta, ViewArgs va, const float* __restrict__ vm, const float4* __restrict__ box,
-             unsigned long long* __restrict__ zbuf, uint32_t* __restrict__ rgba, float* __restrict__ depth,
-             uint8_t* __restrict__ cov)
+             const uint32_t* __restrict__ parts, const uint32_t* __restrict__ items,
+             const uint32_t* __restrict__ counter, unsigned long long* __restrict__ zbuf, uint32_t* __restrict__ rgba,
+             float* __restrict__ depth, uint8_t* __restrict__ cov)
 {
     __shared__ unsigned long long zt[kTilePix];
     __shared__ uint32_t front[2][kFront];
     __shared__ uint32_t queue[kTileWaves * kFan];
     __shared__ uint32_t nl[kMaxLevels];
     __shared__ uint32_t sh_next, sh_over, sh_q;
-    const uint32_t tile = uniform32(die_major(blockIdx.x, gridDim.x));
-    const uint32_t g = tile / ta.per_view, t = tile % ta.per_view;
-    TileView tv;
-    tv.X0 = (int32_t)((t % ta.nx) * kTile);
-    tv.Y0 = (int32_t)((t / ta.nx) * kTile);
-    tv.scene = g / ta.n_views;
-    for (int p = threadIdx.x; p < kTilePix; p += kTileThreads) zt[p] = ~0ull;
+    uint32_t tile, part = 0, P = 1;
+    if (ta.n_tiles < kOrderTiles) {
+        // item blockIdx.x of the classes' lists taken from class 7 down
+        uint32_t b = blockIdx.x, c = 8;
+        for (;;) {
+            if (c == 0) return;   // whole workgroup: past the last item
+            --c;
+            const uint32_t n = counter[c];
+            if (b < n) break;
+            b -= n;
+        }
+        const uint32_t it = items[(size_t)c * (ta.n_tiles + split_items(ta.n_tiles)) + b];
+        tile = uniform32(it >> 5);
+        part = uniform32(it & 31u);
+        P = uniform32(parts[tile]);
+    } else {
+        tile = uniform32(die_major(blockIdx.x, ta.n_tiles));
+    }
     const uint64_t F = frag_total(n_frag, ta.cap_frag);
+    const bool drawn = ta.cap_occ > 0 && F > 0;
+    const TileView tv = tile_view<kBatch>(tile, ta, va, vm, drawn, part, P);
+    for (int p = threadIdx.x; p < kTilePix; p += kTileThreads) zt[p] = ~0ull;
     if (threadIdx.x == 0) {
         uint32_t n[kMaxLevels];
         level_counts(F, ta.levels, n);
@@ -473,47 +627,16 @@ k_tile_splat(const uint4* __restrict__ frag, const uint64_t* __restrict__ pos, c
         front[0][0] = 0;   // the root
     }
     __syncthreads();
-    if (ta.cap_occ > 0 && F > 0) {
-        const ViewSrc<kBatch> vs{va, vm};
-#pragma unroll
-        for (int q = 0; q < 12; ++q) tv.M[q] = vs.m(g)[q];
-        tv.c = vs.c(g);
-        tv.k = (int32_t)vs.k(g);
+    if (drawn) {
         const uint32_t wave = threadIdx.x / kWave;
         const int lane = __lane_id();
-        // breadth first: the frontier holds nodes of level lv
-        uint32_t lv = ta.levels - 1, cur = 0, curn = 1;
-        while (lv >= 2) {
-            if (threadIdx.x == 0) {
-                sh_next = 0;
-                sh_over = 0;
-            }
-            __syncthreads();
-            for (uint32_t e = wave; e < curn; e += kTileWaves) {
-                const uint32_t node = front[cur][e];
-                const uint64_t m = test_children<kBatch>(box, ta, nl, lv, node, tv);
-                const uint32_t cnt = (uint32_t)__popcll(m);
-                uint32_t base = 0;
-                if (lane == 0 && cnt) base = atomicAdd(&sh_next, cnt);
-                base = uniform32((uint32_t)__shfl((int)base, 0, kWave));
-                if ((m >> lane) & 1ull) {
-                    const uint32_t pos = base + (uint32_t)__popcll(m & lanemask_lt());
-                    if (pos < kFront) front[cur ^ 1][pos] = node * kFan + (uint32_t)lane;
-                    else sh_over = 1;
-                }
-            }
-            __syncthreads();
-            const uint32_t nn = sh_next, over = sh_over;
-            __syncthreads();
-            if (over) break;   // keep the current frontier; depth first from here
-            cur ^= 1;
-            curn = nn;
-            --lv;
-        }
+        uint32_t cur, curn;
+        const uint32_t lv = walk_tree<kBatch, kTileWaves>(box, ta, nl, tv, front, &sh_next, &sh_over, &cur, &curn);
         const uint32_t* fr = front[cur];
         if (lv <= 1) {
             // rounds: every wave tests one group's chunks and queues those
-            // that can reach the tile; all waves then draw the queue
+            // that can reach the tile (its columns [XS, XE)); all waves then
+            // draw the queue
             for (uint32_t r0 = 0; r0 < curn; r0 += kTileWaves) {
                 if (threadIdx.x == 0) sh_q = 0;
                 __syncthreads();
@@ -547,11 +670,12 @@ k_tile_splat(const uint4* __restrict__ frag, const uint64_t* __restrict__ pos, c
         }
     }
     __syncthreads();
+    const uint32_t g = tile / ta.per_view;
     const uint64_t plane = (uint64_t)ta.width * ta.height;
     const uint32_t* f32 = (const uint32_t*)frag;
     for (int p = threadIdx.x; p < kTilePix; p += kTileThreads) {
         const int32_t X = tv.X0 + (p % kTile), Y = tv.Y0 + (p / kTile);
-        if (X >= (int32_t)ta.width || Y >= (int32_t)ta.height) continue;
+        if (X < tv.XS || X >= tv.XE || X >= (int32_t)ta.width || Y >= (int32_t)ta.height) continue;
         const uint64_t o = (uint64_t)g * plane + (uint64_t)Y * ta.width + (uint32_t)X;
         const unsigned long long zk = zt[p];
         zbuf[o] = zk;
@@ -599,9 +723,18 @@ TileArgs tile_args(uint32_t n_scenes, uint32_t n_views, uint32_t W, uint32_t H, 
 // chunks).
 size_t tile_pos_off(const TileArgs& ta) { return ((size_t)ta.n_nodes * 2 * sizeof(float4) + 255) & ~(size_t)255; }
 
+// Then, from tile_split_off: the parts of each tile, the items' lists of
+// the 8 classes (each with room for all items), 9 counters.
+size_t tile_split_off(const TileArgs& ta)
+{
+    return (tile_pos_off(ta) + (size_t)((ta.cap_frag + kChunk - 1) / kChunk) * kChunk * sizeof(uint64_t) + 255) &
+           ~(size_t)255;
+}
+
 size_t tile_ws_bytes(const TileArgs& ta)
 {
-    return tile_pos_off(ta) + (size_t)((ta.cap_frag + kChunk - 1) / kChunk) * kChunk * sizeof(uint64_t) + 256;
+    const size_t cap = ta.n_tiles < kOrderTiles ? (size_t)ta.n_tiles + split_items(ta.n_tiles) : 0;
+    return tile_split_off(ta) + ((size_t)ta.n_tiles + 8 * cap + 9) * sizeof(uint32_t) + 256;
 }
 
 template <bool kBatch>
@@ -612,6 +745,10 @@ hipError_t tiles_launch(const Device& dev, const fhv_pofa* a, int mode, TileArgs
     char* base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
     float4* box = (float4*)base;
     uint64_t* pos = (uint64_t*)(base + tile_pos_off(ta));
+    uint32_t* parts = (uint32_t*)(base + tile_split_off(ta));
+    uint32_t* items = parts + ta.n_tiles;
+    const bool ordered = ta.n_tiles < kOrderTiles;
+    uint32_t* bucket = items + (ordered ? 8 * ((size_t)ta.n_tiles + split_items(ta.n_tiles)) : 0);
     const uint64_t chunks = (a->cap_frag + kChunk - 1) / kChunk;
     const uint64_t gmax = (uint64_t)dev.cus * 16;
     auto grid_for = [&](uint64_t waves) {
@@ -623,10 +760,10 @@ hipError_t tiles_launch(const Device& dev, const fhv_pofa* a, int mode, TileArgs
         ProfScope ps(dev, "splat.bin", s);
         if (mode == FHV_PPFL)
             k_chunk_box<FHV_PPFL, kBatch><<<dim3(grid_for(chunks)), dim3(kBlock), 0, s>>>(
-                (const uint4*)a->frag, a->oct_key, a->n_frag, ta, box, pos);
+                (const uint4*)a->frag, a->oct_key, a->n_frag, ta, box, pos, bucket);
         else
             k_chunk_box<FHV_POFL, kBatch><<<dim3(grid_for(chunks)), dim3(kBlock), 0, s>>>(
-                (const uint4*)a->frag, a->oct_key, a->n_frag, ta, box, pos);
+                (const uint4*)a->frag, a->oct_key, a->n_frag, ta, box, pos, bucket);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         for (uint32_t l = 1; l < ta.levels; ++l) {
             const uint64_t nodes = (l + 1 < ta.levels ? ta.lv_off[l + 1] : ta.n_nodes) - ta.lv_off[l];
@@ -634,13 +771,22 @@ hipError_t tiles_launch(const Device& dev, const fhv_pofa* a, int mode, TileArgs
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
     }
+    if (ordered) {
+        ProfScope ps(dev, "splat.est", s);
+        k_tile_est<kBatch><<<dim3(ta.n_tiles), dim3(kEstWaves * kWave), 0, s>>>(a->n_frag, ta, va, vm, box, items,
+                                                                                  parts, bucket);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     ProfScope ps(dev, "splat.splat", s);
+    const dim3 grid(ta.n_tiles + split_items(ta.n_tiles));
     if (mode == FHV_PPFL)
-        k_tile_splat<FHV_PPFL, kBatch><<<dim3(ta.n_tiles), dim3(kTileThreads), 0, s>>>(
-            (const uint4*)a->frag, pos, a->n_frag, ta, va, vm, box, (unsigned long long*)zbuf, rgba, depth, cov);
+        k_tile_splat<FHV_PPFL, kBatch><<<grid, dim3(kTileThreads), 0, s>>>(
+            (const uint4*)a->frag, pos, a->n_frag, ta, va, vm, box, parts, items, bucket, (unsigned long long*)zbuf,
+            rgba, depth, cov);
     else
-        k_tile_splat<FHV_POFL, kBatch><<<dim3(ta.n_tiles), dim3(kTileThreads), 0, s>>>(
-            (const uint4*)a->frag, pos, a->n_frag, ta, va, vm, box, (unsigned long long*)zbuf, rgba, depth, cov);
+        k_tile_splat<FHV_POFL, kBatch><<<grid, dim3(kTileThreads), 0, s>>>(
+            (const uint4*)a->frag, pos, a->n_frag, ta, va, vm, box, parts, items, bucket, (unsigned long long*)zbuf,
+            rgba, depth, cov);
     return hipGetLastError();
 }
 
