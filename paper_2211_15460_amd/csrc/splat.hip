@@ -317,12 +317,13 @@ constexpr int kTileThreads = kTileWaves * kWave;
 constexpr uint32_t kFront = 2048;              // breadth-first frontier capacity (node ids)
 // Ordering and splitting the tiles: a tile whose walk reaches n groups of
 // chunks is drawn by P workgroups, ceil(n / kSplitGroups) rounded up to a
-// power of two (at most kMaxParts), each on 64 / P of its columns, with at
-// most kMaxItems workgroups beyond one per tile per launch; the workgroups
+// power of two (at most kMaxParts), each on a sub-tile of 64 x 64 / P
+// pixels (square or twice as wide as tall: fewer chunks straddle two
+// sub-tiles than narrow column strips), with at most kMaxItems workgroups beyond one per tile per launch; the workgroups
 // start in decreasing order of their share of groups (8 classes), the
 // busiest first. Launches of 2^22 tiles or more keep one workgroup per tile
 // in the plain order.
-constexpr uint32_t kSplitGroups = 32, kMaxParts = 16, kMaxItems = 4096, kOrderTiles = 1u << 22;
+constexpr uint32_t kSplitGroups = 64, kMaxParts = 16, kMaxItems = 4096, kOrderTiles = 1u << 22;
 constexpr int kEstWaves = 4;                   // waves per workgroup of the estimate pass
 
 // What one tile's workgroup knows about its view.
@@ -332,7 +333,8 @@ struct TileView {
     int32_t k;
     uint32_t scene;
     int32_t X0, Y0;
-    int32_t XS, XE;   // the columns this workgroup draws: [XS, XE), within the tile
+    int32_t XS, XE;   // the sub-tile this workgroup draws: columns [XS, XE),
+    int32_t YS, YE;   // rows [YS, YE), within the tile
 };
 
 // Workgroups beyond one per tile: up to kMaxItems; none when the tiles are
@@ -361,7 +363,7 @@ __device__ __forceinline__ uint64_t test_children(const float4* __restrict__ box
     if (kBatch) ok = ok && __float_as_uint(lo.w) <= tv.scene && tv.scene <= __float_as_uint(hi.w);
     if (ok) {
         const PixRect r = chunk_rect(tv.M, tv.c, (uint32_t)tv.k, ta.width, ta.height, lo, hi);
-        ok = r.x0 <= r.x1 && r.y0 <= r.y1 && r.x1 >= tv.XS && r.x0 < tv.XE && r.y1 >= tv.Y0 && r.y0 < tv.Y0 + kTile;
+        ok = r.x0 <= r.x1 && r.y0 <= r.y1 && r.x1 >= tv.XS && r.x0 < tv.XE && r.y1 >= tv.YS && r.y0 < tv.YE;
     }
     return __ballot(ok);
 }
@@ -397,7 +399,8 @@ __device__ __forceinline__ void draw_pos(uint64_t p, uint64_t f, const TileArgs&
     if (k == 1) {
         if (fx >= 0.0f && fx < (float)ta.width && fy >= 0.0f && fy < (float)ta.height) {
             const int32_t px = (int32_t)fx - X0, py = (int32_t)fy - Y0;
-            if ((uint32_t)((int32_t)fx - tv.XS) < (uint32_t)(tv.XE - tv.XS) && (uint32_t)py < (uint32_t)kTile)
+            if ((uint32_t)((int32_t)fx - tv.XS) < (uint32_t)(tv.XE - tv.XS) &&
+                (uint32_t)((int32_t)fy - tv.YS) < (uint32_t)(tv.YE - tv.YS))
                 atomicMin(zt + py * kTile + px, zk);
         }
         return;
@@ -407,9 +410,9 @@ __device__ __forceinline__ void draw_pos(uint64_t p, uint64_t f, const TileArgs&
     int32_t xa = (int32_t)fx, ya = (int32_t)fy;
     int32_t xb = xa + k, yb = ya + k;   // exclusive
     xa = xa < tv.XS ? tv.XS : xa;
-    ya = ya < Y0 ? Y0 : ya;
+    ya = ya < tv.YS ? tv.YS : ya;
     const int32_t xe = tv.XE < (int32_t)ta.width ? tv.XE : (int32_t)ta.width;
-    const int32_t ye = Y0 + kTile < (int32_t)ta.height ? Y0 + kTile : (int32_t)ta.height;
+    const int32_t ye = tv.YE < (int32_t)ta.height ? tv.YE : (int32_t)ta.height;
     xb = xb > xe ? xe : xb;
     yb = yb > ye ? ye : yb;
     for (int32_t yy = ya; yy < yb; ++yy)
@@ -470,8 +473,14 @@ __device__ __forceinline__ TileView tile_view(uint32_t tile, const TileArgs& ta,
     TileView tv;
     tv.X0 = (int32_t)((t % ta.nx) * kTile);
     tv.Y0 = (int32_t)((t / ta.nx) * kTile);
-    tv.XS = tv.X0 + (int32_t)(part * (kTile / n_parts));
-    tv.XE = tv.XS + (int32_t)(kTile / n_parts);
+    // n_parts (a power of two up to 16) square or 2:1 sub-tiles: 2 x 1,
+    // 2 x 2, 4 x 2, 4 x 4 (columns x rows), numbered along the rows
+    const uint32_t lg = 31u - (uint32_t)__builtin_clz(n_parts | 1u);
+    const uint32_t cols = 1u << ((lg + 1) >> 1), rows = n_parts >> ((lg + 1) >> 1);
+    tv.XS = tv.X0 + (int32_t)((part % cols) * (kTile / cols));
+    tv.XE = tv.XS + (int32_t)(kTile / cols);
+    tv.YS = tv.Y0 + (int32_t)((part / cols) * (kTile / rows));
+    tv.YE = tv.YS + (int32_t)(kTile / rows);
     tv.scene = g / ta.n_views;
     if (drawn) {
         const ViewSrc<kBatch> vs{va, vm};
@@ -575,16 +584,16 @@ k_tile_est(const uint64_t* __restrict__ n_frag, TileArgs ta, ViewArgs va, const 
     }
 }
 
-// One workgroup per item: a 64 x 64 tile of one view slot, or a column
-// strip of one (items in the estimate's order; one per tile, in the plain
-// order, for launches of 2^22 tiles or more). The chunk tree is walked from
-// the root breadth first (children tested one per lane) down to the groups
-// of 64 chunks that can reach the workgroup's columns of the tile; then, in
-// rounds of one group per wave, the chunks of those groups that can reach
-// them are queued in LDS and drawn by all waves in turn into the z-tile in
-// LDS with 64-bit minima (fragments outside the columns rejected). Should a
-// level's frontier not fit in LDS, every chunk below the last frontier that
-// did is drawn. Then each pixel of the columns is written once.
+// One workgroup per item: a 64 x 64 tile of one view slot, or a sub-tile
+// of one (items in the estimate's order; one per tile, in the plain order,
+// for launches of 2^22 tiles or more). The chunk tree is walked from the
+// root breadth first (children tested one per lane) down to the groups of
+// 64 chunks that can reach the workgroup's sub-tile; then, in rounds of one
+// group per wave, the chunks of those groups that can reach it are queued
+// in LDS and drawn by all waves in turn into the z-tile in LDS with 64-bit
+// minima (fragments outside the sub-tile rejected). Should a level's
+// frontier not fit in LDS, every chunk below the last frontier that did is
+// drawn. Then each pixel of the sub-tile is written once.
 template <int kMode, bool kBatch>
 __global__ void __launch_bounds__(kTileThreads, 8)   // 8 waves per SIMD (two workgroups per compute unit): 64 registers
 k_tile_splat(const uint4* __restrict__ frag, const uint64_t* __restrict__ pos, const uint64_t* __restrict__ n_frag,
@@ -635,7 +644,7 @@ k_tile_splat(const uint4* __restrict__ frag, const uint64_t* __restrict__ pos, c
         const uint32_t* fr = front[cur];
         if (lv <= 1) {
             // rounds: every wave tests one group's chunks and queues those
-            // that can reach the tile (its columns [XS, XE)); all waves then
+            // that can reach the tile (its sub-tile); all waves then
             // draw the queue
             for (uint32_t r0 = 0; r0 < curn; r0 += kTileWaves) {
                 if (threadIdx.x == 0) sh_q = 0;
@@ -675,7 +684,8 @@ k_tile_splat(const uint4* __restrict__ frag, const uint64_t* __restrict__ pos, c
     const uint32_t* f32 = (const uint32_t*)frag;
     for (int p = threadIdx.x; p < kTilePix; p += kTileThreads) {
         const int32_t X = tv.X0 + (p % kTile), Y = tv.Y0 + (p / kTile);
-        if (X < tv.XS || X >= tv.XE || X >= (int32_t)ta.width || Y >= (int32_t)ta.height) continue;
+        if (X < tv.XS || X >= tv.XE || Y < tv.YS || Y >= tv.YE || X >= (int32_t)ta.width || Y >= (int32_t)ta.height)
+            continue;
         const uint64_t o = (uint64_t)g * plane + (uint64_t)Y * ta.width + (uint32_t)X;
         const unsigned long long zk = zt[p];
         zbuf[o] = zk;
