@@ -479,12 +479,20 @@ def ceilings(torch, fhv, reps: int = 5) -> dict:
     ("sparse", as list-head exchanges land), or on every 8-byte word
     ("dense", as neighbouring pixels of a z-buffer do). Each figure is the
     mean of `reps` launches after one warm-up, from HIP events on the launch
-    stream; buffers are reset before every launch, outside the timing."""
+    stream; the atomic probes' buffers are reset before every launch,
+    outside the timing."""
     big = torch.empty(2 << 30, dtype=torch.uint8, device="cuda")
     small = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    mid = big[:512 << 20]
     cases = [("copy", fhv.FHV_PROBE_COPY, big, 128, 1, "probe.copy"),
              ("read", fhv.FHV_PROBE_READ, big, 128, 1, "probe.read"),
-             ("write", fhv.FHV_PROBE_WRITE, big, 128, 1, "probe.write")]
+             ("write", fhv.FHV_PROBE_WRITE, big, 128, 1, "probe.write"),
+             ("copy_cached", fhv.FHV_PROBE_COPY_CACHED, big, 128, 1, "probe.copy_cached"),
+             ("read_cached", fhv.FHV_PROBE_READ_CACHED, big, 128, 1, "probe.read_cached"),
+             ("write_cached", fhv.FHV_PROBE_WRITE_CACHED, big, 128, 1, "probe.write_cached"),
+             ("write_512mib", fhv.FHV_PROBE_WRITE, mid, 128, 1, "probe.write"),
+             ("write_cached_512mib", fhv.FHV_PROBE_WRITE_CACHED, mid, 128, 1, "probe.write_cached"),
+             ("write_cached_512mib_clean", fhv.FHV_PROBE_WRITE_CACHED, mid, 128, 1, "probe.write_cached")]
     for op, kind, scope in (("add_u32", fhv.FHV_PROBE_ADD_U32, "probe.add_u32"),
                             ("exch_u32", fhv.FHV_PROBE_EXCH_U32, "probe.exch_u32"),
                             ("min_u64", fhv.FHV_PROBE_MIN_U64, "probe.min_u64")):
@@ -493,11 +501,25 @@ def ceilings(torch, fhv, reps: int = 5) -> dict:
         if kind != fhv.FHV_PROBE_EXCH_U32:
             cases.append((op + ".dense_hbm", kind, big, 8, 1, scope))
             cases.append((op + ".dense_llc", kind, small, 8, 32, scope))
+    streams = (fhv.FHV_PROBE_COPY, fhv.FHV_PROBE_READ, fhv.FHV_PROBE_WRITE, fhv.FHV_PROBE_COPY_CACHED,
+               fhv.FHV_PROBE_READ_CACHED, fhv.FHV_PROBE_WRITE_CACHED)
     res = {}
     for name, kind, buf, line, passes, scope in cases:
         tot = 0.0
-        for r in range(reps + 1):
+        # a stream runs as in a steady state, launch after launch on a buffer
+        # filled once (a fill right before each launch would leave its own
+        # written lines in the caches for the probe to write back); the
+        # atomic probes start from a freshly filled buffer every time
+        if kind in streams:
             buf.fill_(0xFF)
+        for r in range(reps + 1):
+            if kind not in streams:
+                buf.fill_(0xFF)
+            if name.endswith("_clean"):
+                # a read-only stream over the rest of the 2 GiB buffer first,
+                # untimed: the previous launch's written lines leave the
+                # caches and the write starts with none to write back
+                fhv.probe(fhv.FHV_PROBE_READ, big[512 << 20:])
             torch.cuda.synchronize()
             fhv.profile_begin()
             fhv.probe(kind, buf, line, passes)
@@ -505,11 +527,16 @@ def ceilings(torch, fhv, reps: int = 5) -> dict:
             if r > 0:
                 tot += prof[scope][1]
         ms = tot / reps
-        if kind in (fhv.FHV_PROBE_COPY, fhv.FHV_PROBE_READ, fhv.FHV_PROBE_WRITE):
-            res[name + "_gbs"] = buf.numel() / (ms * 1e-3) / 1e9
+        if kind in streams:
+            res.setdefault("streams_gbs", {})[name] = buf.numel() / (ms * 1e-3) / 1e9
         else:
             res.setdefault("atomics_g_per_s", {})[name] = buf.numel() // line * passes / (ms * 1e-3) / 1e9
-    del big, small
+    del big, small, mid
+    # the stream ceilings over 2 GiB (far beyond the last-level cache): the
+    # faster of the two access forms
+    st = res["streams_gbs"]
+    for k in ("copy", "read", "write"):
+        res[k + "_gbs"] = max(st[k], st[k + "_cached"])
     # the matrix cores' practical rate: the vendor library's bf16 GEMM
     # (torch.matmul, fp32 accumulation) on 8192^3, the best case for it
     n = 8192
@@ -521,7 +548,10 @@ def ceilings(torch, fhv, reps: int = 5) -> dict:
     res["gemm_bf16_tflops"] = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
     del ga, gb
     res["note"] = ("copy: GB/s read+written over 2 GiB; read, write: GB/s of a read-only and a write-only "
-                   "stream over 2 GiB; atomics: G ops/s; hbm = 2 GiB buffer, one pass; "
+                   "stream over 2 GiB; each the faster of non-temporal and ordinary accesses (streams_gbs: "
+                   "both forms, and the write-only stream over 512 MiB, also right after a read of other memory (_clean), "
+                   "as a kernel that follows kernels writing little starts); "
+                   "atomics: G ops/s; hbm = 2 GiB buffer, one pass; "
                    "llc = 64 MiB buffer, 32 passes; one atomic per 128-B line, or per 8-B word (dense); "
                    "exch returns its value; gemm: the vendor library's bf16 matmul, 8192^3, TFLOP/s")
     return res

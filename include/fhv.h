@@ -528,6 +528,10 @@ FHV_API fhv_status fhv_profile_end(fhv_ctx* ctx, fhv_kernel_stat* out, uint32_t 
  *                       bytes)
  *   FHV_PROBE_WRITE     every byte of buf set to 0xFF with 16-byte stores
  *                       (bytes a multiple of 16)
+ *   The three streams above use non-temporal loads and stores (past the
+ *   caches); FHV_PROBE_COPY_CACHED, FHV_PROBE_READ_CACHED and
+ *   FHV_PROBE_WRITE_CACHED are the same streams with ordinary accesses, as
+ *   the library's kernels make them.
  *   FHV_PROBE_ADD_U32   per line of `line` bytes and per pass: atomic add of
  *                       1 to the line's first u32, result unused
  *   FHV_PROBE_EXCH_U32  atomic exchange of the line's first u32 with
@@ -539,14 +543,17 @@ FHV_API fhv_status fhv_profile_end(fhv_ctx* ctx, fhv_kernel_stat* out, uint32_t 
  * pointer owned by the caller, 16-byte aligned; `line` is a power of two in
  * [8, 4096] (atomic probes), `passes` in [1, 1024]; FHV_EINVAL otherwise.
  * Launches on `stream`; timed by fhv_profile_begin/end as "probe.copy",
- * "probe.read", "probe.write", "probe.add_u32", "probe.exch_u32",
- * "probe.min_u64". */
+ * "probe.read", "probe.write", "probe.copy_cached", "probe.read_cached",
+ * "probe.write_cached", "probe.add_u32", "probe.exch_u32", "probe.min_u64". */
 #define FHV_PROBE_COPY 0u
 #define FHV_PROBE_ADD_U32 1u
 #define FHV_PROBE_EXCH_U32 2u
 #define FHV_PROBE_MIN_U64 3u
 #define FHV_PROBE_READ 4u
 #define FHV_PROBE_WRITE 5u
+#define FHV_PROBE_COPY_CACHED 6u
+#define FHV_PROBE_READ_CACHED 7u
+#define FHV_PROBE_WRITE_CACHED 8u
 
 FHV_API fhv_status fhv_probe(fhv_ctx* ctx, uint32_t kind, void* buf, uint64_t bytes, uint32_t line,
                              uint32_t passes, fhv_stream stream);

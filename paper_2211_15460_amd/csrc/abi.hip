@@ -491,10 +491,11 @@ fhv_status fhv_splat_static(fhv_ctx* ctx, const fhv_pofa* arrays, const fhv_capt
 fhv_status fhv_probe(fhv_ctx* ctx, uint32_t kind, void* buf, uint64_t bytes, uint32_t line,
                      uint32_t passes, fhv_stream stream)
 {
-    if (!ctx || !buf || ((uintptr_t)buf & 15) || kind > FHV_PROBE_WRITE) return FHV_EINVAL;
-    if (kind == FHV_PROBE_COPY) {
+    if (!ctx || !buf || ((uintptr_t)buf & 15) || kind > FHV_PROBE_WRITE_CACHED) return FHV_EINVAL;
+    if (kind == FHV_PROBE_COPY || kind == FHV_PROBE_COPY_CACHED) {
         if (bytes < 32 || bytes % 32 != 0) return FHV_EINVAL;
-    } else if (kind == FHV_PROBE_READ || kind == FHV_PROBE_WRITE) {
+    } else if (kind == FHV_PROBE_READ || kind == FHV_PROBE_WRITE || kind == FHV_PROBE_READ_CACHED ||
+               kind == FHV_PROBE_WRITE_CACHED) {
         if (bytes < 16 || bytes % 16 != 0) return FHV_EINVAL;
     } else {
         if (line < 8 || line > 4096 || (line & (line - 1)) || bytes < line) return FHV_EINVAL;

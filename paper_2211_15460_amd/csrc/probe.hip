@@ -7,12 +7,15 @@
 // stay in the last-level cache.
 //
 //   k_probe_copy     dst <- src in 16-byte vector loads and stores, eight
-//                    per thread in flight, marked non-temporal (streamed
-//                    past the caches)
+//                    per thread in flight
 //   k_probe_read     every 16 bytes of the buffer loaded once (eight per
-//                    thread in flight, non-temporal) and folded into a value
-//                    that decides a store which never happens
-//   k_probe_write    every 16 bytes of the buffer stored once (non-temporal)
+//                    thread in flight) and folded into a value that decides
+//                    a store which never happens
+//   k_probe_write    every 16 bytes of the buffer stored once
+//   Each stream comes in two access forms: non-temporal (streamed past the
+//   caches) and ordinary (as the library's own kernels access memory, lines
+//   allocated in the caches on the way), since which of the two is faster
+//   depends on the stream's mix and size.
 //   k_probe_atomic   per line and pass: add 1 (u32, result unused), exchange
 //                    (u32, result used, as the list insertion does) or
 //                    minimum (u64, result unused, each pass storing a smaller
@@ -25,8 +28,10 @@ namespace {
 
 constexpr int kProbeU = 8;   // 16-byte units per thread and iteration
 
-__device__ __forceinline__ uint4 nt_load(const uint4* p)
+template <bool kNT>
+__device__ __forceinline__ uint4 load16(const uint4* p)
 {
+    if (!kNT) return *p;
     uint4 v;
     v.x = __builtin_nontemporal_load(&p->x);
     v.y = __builtin_nontemporal_load(&p->y);
@@ -35,8 +40,13 @@ __device__ __forceinline__ uint4 nt_load(const uint4* p)
     return v;
 }
 
-__device__ __forceinline__ void nt_store(uint4* p, uint4 v)
+template <bool kNT>
+__device__ __forceinline__ void store16(uint4* p, uint4 v)
 {
+    if (!kNT) {
+        *p = v;
+        return;
+    }
     __builtin_nontemporal_store(v.x, &p->x);
     __builtin_nontemporal_store(v.y, &p->y);
     __builtin_nontemporal_store(v.z, &p->z);
@@ -45,6 +55,7 @@ __device__ __forceinline__ void nt_store(uint4* p, uint4 v)
 
 // All loads of an iteration are issued before its stores, so that enough
 // reads are in flight to cover the memory latency.
+template <bool kNT>
 __global__ void __launch_bounds__(kBlock)
 k_probe_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, uint64_t n)
 {
@@ -53,13 +64,14 @@ k_probe_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, uint64_t n)
     for (; i + (kProbeU - 1) * stride < n; i += kProbeU * stride) {
         uint4 v[kProbeU];
 #pragma unroll
-        for (int u = 0; u < kProbeU; ++u) v[u] = nt_load(src + i + u * stride);
+        for (int u = 0; u < kProbeU; ++u) v[u] = load16<kNT>(src + i + u * stride);
 #pragma unroll
-        for (int u = 0; u < kProbeU; ++u) nt_store(dst + i + u * stride, v[u]);
+        for (int u = 0; u < kProbeU; ++u) store16<kNT>(dst + i + u * stride, v[u]);
     }
-    for (; i < n; i += stride) nt_store(dst + i, nt_load(src + i));
+    for (; i < n; i += stride) store16<kNT>(dst + i, load16<kNT>(src + i));
 }
 
+template <bool kNT>
 __global__ void __launch_bounds__(kBlock)
 k_probe_read(uint4* __restrict__ buf, uint64_t n)
 {
@@ -69,12 +81,12 @@ k_probe_read(uint4* __restrict__ buf, uint64_t n)
     for (; i + (kProbeU - 1) * stride < n; i += kProbeU * stride) {
         uint4 v[kProbeU];
 #pragma unroll
-        for (int u = 0; u < kProbeU; ++u) v[u] = nt_load(buf + i + u * stride);
+        for (int u = 0; u < kProbeU; ++u) v[u] = load16<kNT>(buf + i + u * stride);
 #pragma unroll
         for (int u = 0; u < kProbeU; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
     }
     for (; i < n; i += stride) {
-        const uint4 v = nt_load(buf + i);
+        const uint4 v = load16<kNT>(buf + i);
         acc ^= v.x ^ v.y ^ v.z ^ v.w;
     }
     // the probe's buffers are filled with 0xFF bytes, so the fold of an even
@@ -82,12 +94,13 @@ k_probe_read(uint4* __restrict__ buf, uint64_t n)
     if (acc == 0x5A5A5A5Au) buf[0].x = acc;
 }
 
+template <bool kNT>
 __global__ void __launch_bounds__(kBlock)
 k_probe_write(uint4* __restrict__ buf, uint64_t n)
 {
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     const uint4 v = make_uint4(~0u, ~0u, ~0u, ~0u);
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) nt_store(buf + i, v);
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) store16<kNT>(buf + i, v);
 }
 
 template <uint32_t kOp>
@@ -119,25 +132,52 @@ k_probe_atomic(uint8_t* __restrict__ buf, uint64_t n_lines, uint32_t line, uint3
 hipError_t probe_launch(const Device& dev, uint32_t kind, void* buf, uint64_t bytes, uint32_t line,
                         uint32_t passes, hipStream_t s)
 {
-    const uint64_t gmax = (uint64_t)dev.cus * 16;
-    if (kind == FHV_PROBE_COPY) {
+    // the streams launch as the library's own streaming kernels do: up to
+    // 32 workgroups per compute unit, each thread looping over the rest
+    const uint64_t gmax = (uint64_t)dev.cus * 16, smax = (uint64_t)dev.cus * 32;
+    if (kind == FHV_PROBE_COPY || kind == FHV_PROBE_COPY_CACHED) {
         const uint64_t n = bytes / 32;   // 16-byte units per half
         uint64_t g = (n + kBlock - 1) / kBlock;
-        g = g < 1 ? 1 : (g > gmax ? gmax : g);
-        ProfScope ps(dev, "probe.copy", s);
-        k_probe_copy<<<dim3((unsigned)g), dim3(kBlock), 0, s>>>((const uint4*)buf, (uint4*)buf + n, n);
+        g = g < 1 ? 1 : (g > smax ? smax : g);
+        const uint4* src = (const uint4*)buf;
+        uint4* dst = (uint4*)buf + n;
+        if (kind == FHV_PROBE_COPY) {
+            ProfScope ps(dev, "probe.copy", s);
+            k_probe_copy<true><<<dim3((unsigned)g), dim3(kBlock), 0, s>>>(src, dst, n);
+        } else {
+            ProfScope ps(dev, "probe.copy_cached", s);
+            k_probe_copy<false><<<dim3((unsigned)g), dim3(kBlock), 0, s>>>(src, dst, n);
+        }
         return hipGetLastError();
     }
-    if (kind == FHV_PROBE_READ || kind == FHV_PROBE_WRITE) {
+    if (kind == FHV_PROBE_READ || kind == FHV_PROBE_WRITE || kind == FHV_PROBE_READ_CACHED ||
+        kind == FHV_PROBE_WRITE_CACHED) {
         const uint64_t n = bytes / 16;
         uint64_t g = (n + kBlock - 1) / kBlock;
-        g = g < 1 ? 1 : (g > gmax ? gmax : g);
-        if (kind == FHV_PROBE_READ) {
+        g = g < 1 ? 1 : (g > smax ? smax : g);
+        uint4* b = (uint4*)buf;
+        const dim3 grid((unsigned)g), block(kBlock);
+        switch (kind) {
+        case FHV_PROBE_READ: {
             ProfScope ps(dev, "probe.read", s);
-            k_probe_read<<<dim3((unsigned)g), dim3(kBlock), 0, s>>>((uint4*)buf, n);
-        } else {
+            k_probe_read<true><<<grid, block, 0, s>>>(b, n);
+            break;
+        }
+        case FHV_PROBE_READ_CACHED: {
+            ProfScope ps(dev, "probe.read_cached", s);
+            k_probe_read<false><<<grid, block, 0, s>>>(b, n);
+            break;
+        }
+        case FHV_PROBE_WRITE: {
             ProfScope ps(dev, "probe.write", s);
-            k_probe_write<<<dim3((unsigned)g), dim3(kBlock), 0, s>>>((uint4*)buf, n);
+            k_probe_write<true><<<grid, block, 0, s>>>(b, n);
+            break;
+        }
+        default: {
+            ProfScope ps(dev, "probe.write_cached", s);
+            k_probe_write<false><<<grid, block, 0, s>>>(b, n);
+            break;
+        }
         }
         return hipGetLastError();
     }

@@ -473,6 +473,7 @@ def profile_end() -> dict[str, tuple[int, float]]:
 
 FHV_PROBE_COPY, FHV_PROBE_ADD_U32, FHV_PROBE_EXCH_U32, FHV_PROBE_MIN_U64 = 0, 1, 2, 3
 FHV_PROBE_READ, FHV_PROBE_WRITE = 4, 5
+FHV_PROBE_COPY_CACHED, FHV_PROBE_READ_CACHED, FHV_PROBE_WRITE_CACHED = 6, 7, 8
 
 
 def probe(kind: int, buf: torch.Tensor, line: int = 128, passes: int = 1):

@@ -20,13 +20,14 @@ def F():
     return fhv
 
 
-def test_probe_copy(F):
+@pytest.mark.parametrize("cached", [False, True])
+def test_probe_copy(F, cached):
     import torch
     g = torch.Generator().manual_seed(5)
     n = (3 << 20) + 96            # bytes, a multiple of 32 that is not a power of two
     host = torch.randint(0, 256, (n,), dtype=torch.uint8, generator=g)
     buf = host.cuda()
-    F.probe(F.FHV_PROBE_COPY, buf)
+    F.probe(F.FHV_PROBE_COPY_CACHED if cached else F.FHV_PROBE_COPY, buf)
     torch.cuda.synchronize()
     out = buf.cpu().numpy()
     h = host.numpy()
@@ -34,17 +35,18 @@ def test_probe_copy(F):
     assert np.array_equal(out[n // 2:], h[: n // 2])
 
 
-def test_probe_read_and_write(F):
+@pytest.mark.parametrize("cached", [False, True])
+def test_probe_read_and_write(F, cached):
     """The read probe leaves a 0xFF buffer as it was; the write probe sets
-    every byte to 0xFF and nothing beyond."""
+    every byte to 0xFF and nothing beyond (both access forms)."""
     import torch
     n = (5 << 20) + 48            # bytes, a multiple of 16 that is not a power of two
     buf = torch.full((n + 64,), 0x11, dtype=torch.uint8, device="cuda")
-    F.probe(F.FHV_PROBE_WRITE, buf[:n])
+    F.probe(F.FHV_PROBE_WRITE_CACHED if cached else F.FHV_PROBE_WRITE, buf[:n])
     torch.cuda.synchronize()
     out = buf.cpu().numpy()
     assert np.all(out[:n] == 0xFF) and np.all(out[n:] == 0x11)
-    F.probe(F.FHV_PROBE_READ, buf[:n])
+    F.probe(F.FHV_PROBE_READ_CACHED if cached else F.FHV_PROBE_READ, buf[:n])
     torch.cuda.synchronize()
     assert np.array_equal(buf.cpu().numpy(), out)
 
@@ -91,7 +93,7 @@ def test_probe_rejects_bad_arguments(F):
     buf = torch.zeros(4096, dtype=torch.uint8, device="cuda")
     L = F.lib()
     p = C.c_void_p(buf.data_ptr())
-    for kind, nbytes, line, passes in ((6, 4096, 128, 1), (1, 4096, 96, 1), (1, 4096, 4, 1),
+    for kind, nbytes, line, passes in ((9, 4096, 128, 1), (8, 40, 0, 0), (1, 4096, 96, 1), (1, 4096, 4, 1),
                                        (1, 4096, 8192, 1), (1, 64, 128, 1), (1, 4096, 128, 0),
                                        (1, 4096, 128, 1025), (0, 48, 0, 0), (0, 16, 0, 0)):
         assert L.fhv_probe(F.ctx(), kind, p, nbytes, line, passes, None) == -1
