@@ -3,7 +3,8 @@ walk has cases of its own: footprints up to the largest side (a chunk's box
 then reaches many tiles), one view per footprint side in one call, views of
 one pixel, ragged tile edges, views with part of the scene behind the viewer
 or entirely off screen, matrices that are not finite, a truncated octant
-table, and 32 views in one call."""
+table, 32 views in one call, and tiles that so many chunk groups reach that
+they are split into 2 to 16 sub-tiles drawn by separate workgroups."""
 from __future__ import annotations
 
 import numpy as np
@@ -120,3 +121,31 @@ def test_empty_arrays(F, orc):
     _, pofa = run_compact(F, lists, d)
     gr, gd, gc = run_splat(F, pofa, d, [S.cube_view(30.0, 5, 70, 70)])
     assert cnt == 0 and gc.sum() == 0 and np.all(gr == 0) and np.all(gd == 0)
+
+
+@pytest.fixture(scope="module")
+def dense_scene(F, orc):
+    # 2.7 M fragments, about 660 groups of 64 chunks: a view that holds the
+    # whole scene in one 64 x 64 tile splits that tile into 16 sub-tiles,
+    # larger views into fewer pieces per tile; with four one-tile views the
+    # launch's budget of extra workgroups (16) runs out after the first
+    # split, so the other tiles are drawn whole
+    mesh = S.cube_scene(80000, 3)
+    L = 9
+    d = F.desc(F.FHV_POFL, levels=L)
+    _, _, _, cnt, lists = run_capture(F, mesh, d, 1 << 22)
+    assert cnt <= 1 << 22
+    g, pofa = run_compact(F, lists, d)
+    print(f"dense scene F={cnt} n_occ={g['n_occ']}", flush=True)
+    return mesh, L, d, g, pofa
+
+
+@pytest.mark.parametrize("size,views", [(64, ((0.0, 1), (25.0, 3), (50.0, 1), (75.0, 2))),
+                                        (128, ((10.0, 1), (40.0, 2))),
+                                        (192, ((60.0, 3),))])
+def test_split_tiles(F, orc, dense_scene, size, views):
+    _, L, _, _, _ = dense_scene
+    vs = [S.cube_view(th, L, size, size, vertical_extent=1.7, splat_px=k) for th, k in views]
+    print(f"split tiles: {len(vs)} views of {size}x{size}", flush=True)
+    cov = check(F, orc, dense_scene, vs)
+    assert cov.reshape(len(vs), -1).sum(axis=1).min() > 0
