@@ -127,7 +127,8 @@ def test_empty_arrays(F, orc):
 def dense_scene(F, orc):
     # 2.7 M fragments, about 660 groups of 64 chunks: a view that holds the
     # whole scene in one 64 x 64 tile splits that tile into 16 sub-tiles,
-    # larger views into fewer pieces per tile; with four one-tile views the
+    # larger views into fewer pieces per tile (at 100 x 100 some of them
+    # partly outside the image); with four one-tile views the
     # launch's budget of extra workgroups (16) runs out after the first
     # split, so the other tiles are drawn whole
     mesh = S.cube_scene(80000, 3)
@@ -142,7 +143,8 @@ def dense_scene(F, orc):
 
 @pytest.mark.parametrize("size,views", [(64, ((0.0, 1), (25.0, 3), (50.0, 1), (75.0, 2))),
                                         (128, ((10.0, 1), (40.0, 2))),
-                                        (192, ((60.0, 3),))])
+                                        (192, ((60.0, 3),)),
+                                        (100, ((15.0, 1), (35.0, 2)))])
 def test_split_tiles(F, orc, dense_scene, size, views):
     _, L, _, _, _ = dense_scene
     vs = [S.cube_view(th, L, size, size, vertical_extent=1.7, splat_px=k) for th, k in views]
