@@ -16,7 +16,12 @@
 //                 positions (and the range of scenes its keys belong to)
 //   k_node_box    one wave per node of the next level up: the union of its
 //                 64 children's boxes, up to a single root
-//   k_tile_splat  one workgroup of 16 waves per tile: z-tile of 64-bit keys
+//   k_tile_est    a workgroup of 4 waves per tile: the tree walked down to
+//                 the groups of chunks that can reach the tile, which set
+//                 how many workgroups draw it (a busy tile is split into up
+//                 to 16 sub-tiles) and the order of the draw: items listed
+//                 in 8 classes of their share of groups, busiest first
+//   k_tile_splat  one workgroup of 16 waves per tile or sub-tile: z-tile of 64-bit keys
 //                 (fp32 depth bits << 32 | fragment index) in LDS, cleared;
 //                 the tree walked from the root, each node's 64 children
 //                 tested at once (one per lane) by projecting the child's box
@@ -24,8 +29,8 @@
 //                 of every fragment inside it; every chunk that can reach the
 //                 tile projected fragment by fragment (fp32 3x4 transform
 //                 without fused multiply-adds) with an LDS 64-bit minimum for
-//                 each footprint pixel inside the tile; then each pixel of the
-//                 tile written once: key, winner's colour (w1), depth and
+//                 each footprint pixel inside the (sub-)tile; then each pixel
+//                 of it written once: key, winner's colour (w1), depth and
 //                 coverage
 //
 // A batch (many scenes in one key space, key = scene << 3L | Morton code)
