@@ -1624,31 +1624,35 @@ __global__ void __launch_bounds__(cvu::WAVES * kWave) k_conv3u(ConvUpArgs a)
             for (int c = 0; c < 2; ++c)
                 xb[c] = *(const u32x4*)(lb + (O_LR + (lr * LP + lp) * 8 + ((4 * c + g) ^ (lp & 7))) * 16);
         };
-        u32x4 xb[2], xn[2];
-        rd1(0, xn);
-#pragma unroll 1
+        // all five items' operands read first, then their products: the
+        // items are independent, so one item's products run while another's
+        // results are rounded and stored (a loop over the items, each
+        // waiting for its own products, left the matrix units idle)
+        floatx4 bjs[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bjs[j] = *(const floatx4*)&bus[16 * j + 4 * g];
+        u32x4 xa[IPW][2];
+#pragma unroll
+        for (int k = 0; k < IPW; ++k) rd1(k, xa[k]);
+#pragma unroll
         for (int k = 0; k < IPW; ++k) {
             const int m = 5 * (wv & 1) + k, hr = 2 * (m >> 1) + 1 - sy, blk = m & 1;
             const int hp = 2 * (16 * blk + l16) + 1 - sx;
-#pragma unroll
-            for (int c = 0; c < 2; ++c) xb[c] = xn[c];
-            if (k + 1 < IPW) rd1(k + 1, xn);
             floatx4 d[2] = {floatx4{0.f, 0.f, 0.f, 0.f}, floatx4{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
             for (int c = 0; c < 2; ++c)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
                     d[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, wup[j][c]),
-                                                                   __builtin_bit_cast(bf16x8, xb[c]), d[j], 0, 0, 0);
+                                                                   __builtin_bit_cast(bf16x8, xa[k][c]), d[j], 0, 0, 0);
             const int y = (int)q.y0 - 1 + hr, x = (int)q.x0 - 1 + hp;
             const bool in = y >= 0 && y < (int)a.H && x >= 0 && x < (int)a.W;
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                const floatx4 bj = *(const floatx4*)&bus[16 * j + 4 * g];
                 uint32_t w[2];
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    const float v0 = d[j][2 * h] + bj[2 * h], v1 = d[j][2 * h + 1] + bj[2 * h + 1];
+                    const float v0 = d[j][2 * h] + bjs[j][2 * h], v1 = d[j][2 * h + 1] + bjs[j][2 * h + 1];
                     w[h] = in ? f2bf2(v0, v1) : 0u;
                 }
                 const uint32_t slot = O_UP + swz_slot((uint32_t)(hr * HP + hp), (uint32_t)(2 * j + (g >> 1)));
