@@ -330,6 +330,10 @@ constexpr uint32_t kFront = 2048;              // breadth-first frontier capacit
 // in the plain order.
 constexpr uint32_t kSplitGroups = 64, kMaxParts = 16, kMaxItems = 4096, kOrderTiles = 1u << 22;
 constexpr int kEstWaves = 4;                   // waves per workgroup of the estimate pass
+// A tile whose walk ends on at most kGroupList groups of chunks gets them
+// listed by the estimate pass, and its workgroup in the tile pass starts
+// from that list instead of walking the tree again.
+constexpr uint32_t kGroupList = 32;
 
 // What one tile's workgroup knows about its view.
 struct TileView {
@@ -548,12 +552,13 @@ __device__ __forceinline__ uint32_t walk_tree(const float4* __restrict__ box, co
 // class of their share of groups (0 for nothing to draw, then 1 + log2 of
 // the share, at most 7). Its items (tile << 5 | part) go to its class's
 // list, items[class * item_cap + rank ...] (counter[class] counts the
-// class's items); parts[tile] = P.
+// class's items); parts[tile] = P | (1 + listed groups, or 0) << 8, the
+// groups listed in glist[tile * kGroupList ...].
 template <bool kBatch>
 __global__ void __launch_bounds__(kEstWaves * kWave)
 k_tile_est(const uint64_t* __restrict__ n_frag, TileArgs ta, ViewArgs va, const float* __restrict__ vm,
            const float4* __restrict__ box, uint32_t* __restrict__ items, uint32_t* __restrict__ parts,
-           uint32_t* __restrict__ counter)
+           uint32_t* __restrict__ counter, uint32_t* __restrict__ glist)
 {
     __shared__ uint32_t front[2][kFront];
     __shared__ uint32_t nl[kMaxLevels];
@@ -570,10 +575,17 @@ k_tile_est(const uint64_t* __restrict__ n_frag, TileArgs ta, ViewArgs va, const 
     }
     __syncthreads();
     uint32_t groups = 0;   // groups of chunks that can reach the tile (a large value when uncounted)
+    uint32_t listed = 0;   // 1 + the number of groups listed for the tile, or 0: no list
     if (drawn) {
         uint32_t cur, curn;
         const uint32_t lv = walk_tree<kBatch, kEstWaves>(box, ta, nl, tv, front, &sh_next, &sh_over, &cur, &curn);
         groups = lv >= 2 ? 1u << 16 : (lv == 1 ? curn : 1);
+        if (lv == 1 && curn <= kGroupList) {
+            if (threadIdx.x < curn) glist[(size_t)tile * kGroupList + threadIdx.x] = front[cur][threadIdx.x];
+            listed = curn + 1;
+        }
+    } else {
+        listed = 1;   // nothing to draw: an empty list
     }
     if (threadIdx.x == 0) {
         const uint32_t q = (groups + kSplitGroups - 1) / kSplitGroups;
@@ -585,7 +597,7 @@ k_tile_est(const uint64_t* __restrict__ n_frag, TileArgs ta, ViewArgs va, const 
         const uint32_t r = atomicAdd(counter + cls, P);
         uint32_t* it = items + (size_t)cls * (ta.n_tiles + split_items(ta.n_tiles)) + r;
         for (uint32_t i = 0; i < P; ++i) it[i] = (tile << 5) | i;
-        parts[tile] = P;
+        parts[tile] = P | (listed << 8);
     }
 }
 
@@ -604,15 +616,16 @@ __global__ void __launch_bounds__(kTileThreads, 8)   // 8 waves per SIMD (two wo
 k_tile_splat(const uint4* __restrict__ frag, const uint64_t* __restrict__ pos, const uint64_t* __restrict__ n_frag,
              TileArgs ta, ViewArgs va, const float* __restrict__ vm, const float4* __restrict__ box,
              const uint32_t* __restrict__ parts, const uint32_t* __restrict__ items,
-             const uint32_t* __restrict__ counter, unsigned long long* __restrict__ zbuf, uint32_t* __restrict__ rgba,
-             float* __restrict__ depth, uint8_t* __restrict__ cov)
+             const uint32_t* __restrict__ counter, const uint32_t* __restrict__ glist,
+             unsigned long long* __restrict__ zbuf, uint32_t* __restrict__ rgba, float* __restrict__ depth,
+             uint8_t* __restrict__ cov)
 {
     __shared__ unsigned long long zt[kTilePix];
     __shared__ uint32_t front[2][kFront];
     __shared__ uint32_t queue[kTileWaves * kFan];
     __shared__ uint32_t nl[kMaxLevels];
     __shared__ uint32_t sh_next, sh_over, sh_q;
-    uint32_t tile, part = 0, P = 1;
+    uint32_t tile, part = 0, P = 1, listed = 0;
     if (ta.n_tiles < kOrderTiles) {
         // item blockIdx.x of the classes' lists taken from class 7 down
         uint32_t b = blockIdx.x, c = 8;
@@ -626,7 +639,9 @@ k_tile_splat(const uint4* __restrict__ frag, const uint64_t* __restrict__ pos, c
         const uint32_t it = items[(size_t)c * (ta.n_tiles + split_items(ta.n_tiles)) + b];
         tile = uniform32(it >> 5);
         part = uniform32(it & 31u);
-        P = uniform32(parts[tile]);
+        const uint32_t pw = uniform32(parts[tile]);
+        P = pw & 0xFFu;
+        listed = pw >> 8;
     } else {
         tile = uniform32(die_major(blockIdx.x, ta.n_tiles));
     }
@@ -640,12 +655,14 @@ k_tile_splat(const uint4* __restrict__ frag, const uint64_t* __restrict__ pos, c
         for (uint32_t l = 0; l < ta.levels; ++l) nl[l] = n[l];
         front[0][0] = 0;   // the root
     }
+    // the groups the estimate listed for the tile, as the walk's last frontier
+    if (listed > 0 && threadIdx.x < listed - 1) front[0][threadIdx.x] = glist[(size_t)tile * kGroupList + threadIdx.x];
     __syncthreads();
     if (drawn) {
         const uint32_t wave = threadIdx.x / kWave;
         const int lane = __lane_id();
-        uint32_t cur, curn;
-        const uint32_t lv = walk_tree<kBatch, kTileWaves>(box, ta, nl, tv, front, &sh_next, &sh_over, &cur, &curn);
+        uint32_t cur = 0, curn = listed > 0 ? listed - 1 : 0, lv = 1;
+        if (listed == 0) lv = walk_tree<kBatch, kTileWaves>(box, ta, nl, tv, front, &sh_next, &sh_over, &cur, &curn);
         const uint32_t* fr = front[cur];
         if (lv <= 1) {
             // rounds: every wave tests one group's chunks and queues those
@@ -739,7 +756,8 @@ TileArgs tile_args(uint32_t n_scenes, uint32_t n_views, uint32_t W, uint32_t H, 
 size_t tile_pos_off(const TileArgs& ta) { return ((size_t)ta.n_nodes * 2 * sizeof(float4) + 255) & ~(size_t)255; }
 
 // Then, from tile_split_off: the parts of each tile, the items' lists of
-// the 8 classes (each with room for all items), 9 counters.
+// the 8 classes (each with room for all items), 9 counters, and for ordered
+// launches kGroupList group ids per tile.
 size_t tile_split_off(const TileArgs& ta)
 {
     return (tile_pos_off(ta) + (size_t)((ta.cap_frag + kChunk - 1) / kChunk) * kChunk * sizeof(uint64_t) + 255) &
@@ -749,7 +767,8 @@ size_t tile_split_off(const TileArgs& ta)
 size_t tile_ws_bytes(const TileArgs& ta)
 {
     const size_t cap = ta.n_tiles < kOrderTiles ? (size_t)ta.n_tiles + split_items(ta.n_tiles) : 0;
-    return tile_split_off(ta) + ((size_t)ta.n_tiles + 8 * cap + 9) * sizeof(uint32_t) + 256;
+    const size_t lists = cap ? (size_t)ta.n_tiles * kGroupList : 0;
+    return tile_split_off(ta) + ((size_t)ta.n_tiles + 8 * cap + 9 + lists) * sizeof(uint32_t) + 256;
 }
 
 template <bool kBatch>
@@ -764,6 +783,7 @@ hipError_t tiles_launch(const Device& dev, const fhv_pofa* a, int mode, TileArgs
     uint32_t* items = parts + ta.n_tiles;
     const bool ordered = ta.n_tiles < kOrderTiles;
     uint32_t* bucket = items + (ordered ? 8 * ((size_t)ta.n_tiles + split_items(ta.n_tiles)) : 0);
+    uint32_t* glist = bucket + 9;   // ordered launches only
     const uint64_t chunks = (a->cap_frag + kChunk - 1) / kChunk;
     const uint64_t gmax = (uint64_t)dev.cus * 16;
     auto grid_for = [&](uint64_t waves) {
@@ -789,19 +809,19 @@ hipError_t tiles_launch(const Device& dev, const fhv_pofa* a, int mode, TileArgs
     if (ordered) {
         ProfScope ps(dev, "splat.est", s);
         k_tile_est<kBatch><<<dim3(ta.n_tiles), dim3(kEstWaves * kWave), 0, s>>>(a->n_frag, ta, va, vm, box, items,
-                                                                                  parts, bucket);
+                                                                                  parts, bucket, glist);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     ProfScope ps(dev, "splat.splat", s);
     const dim3 grid(ta.n_tiles + split_items(ta.n_tiles));
     if (mode == FHV_PPFL)
         k_tile_splat<FHV_PPFL, kBatch><<<grid, dim3(kTileThreads), 0, s>>>(
-            (const uint4*)a->frag, pos, a->n_frag, ta, va, vm, box, parts, items, bucket, (unsigned long long*)zbuf,
-            rgba, depth, cov);
+            (const uint4*)a->frag, pos, a->n_frag, ta, va, vm, box, parts, items, bucket, glist,
+            (unsigned long long*)zbuf, rgba, depth, cov);
     else
         k_tile_splat<FHV_POFL, kBatch><<<grid, dim3(kTileThreads), 0, s>>>(
-            (const uint4*)a->frag, pos, a->n_frag, ta, va, vm, box, parts, items, bucket, (unsigned long long*)zbuf,
-            rgba, depth, cov);
+            (const uint4*)a->frag, pos, a->n_frag, ta, va, vm, box, parts, items, bucket, glist,
+            (unsigned long long*)zbuf, rgba, depth, cov);
     return hipGetLastError();
 }
 
