@@ -2121,25 +2121,42 @@ struct PrepTable {
     } e[kMaxPrep];
 };
 
+// Eight consecutive elements per thread (every layer's count and start are
+// multiples of 8, and so is cpad: the eight share a tap and an output
+// channel): one walk of the table, eight conversions, one 16-byte store of
+// the forward layout; the backward layout's elements are scattered.
 __global__ void __launch_bounds__(kBlock) k_prep_all(PrepTable t, uint32_t total)
 {
-    const uint32_t g = blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t g = (blockIdx.x * kBlock + threadIdx.x) * 8;
     if (g >= total) return;
     uint32_t l = 0;
     while (l + 1 < t.n && g >= t.e[l + 1].start) ++l;
     const PrepTable::Entry& y = t.e[l];
     const uint32_t i = g - y.start;
+    uint16_t v[8];
     if (y.kind == 0) {
-        const uint32_t ci = i % y.cpad, tap = (i / y.cpad) % 9, co = i / (y.cpad * 9);
-        const uint16_t v = ci < y.cin ? f2bf(y.w[((size_t)co * 9 + tap) * y.cin + ci]) : (uint16_t)0;
-        y.wf[i] = v;
-        if (y.wb && ci < y.cin) y.wb[((size_t)ci * 9 + (8 - tap)) * y.cout + co] = v;
+        const uint32_t ci0 = i % y.cpad, tap = (i / y.cpad) % 9, co = i / (y.cpad * 9);
+        const float* src = y.w + ((size_t)co * 9 + tap) * y.cin;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const uint32_t ci = ci0 + (uint32_t)e;
+            v[e] = ci < y.cin ? f2bf(src[ci]) : (uint16_t)0;
+            if (y.wb && ci < y.cin) y.wb[((size_t)ci * 9 + (8 - tap)) * y.cout + co] = v[e];
+        }
     } else {
-        const uint32_t ci = i % y.cin, co = (i / y.cin) % y.cout, tap = i / (y.cin * y.cout);
-        const uint16_t v = f2bf(y.w[i]);
-        y.wf[i] = v;
-        y.wb[((size_t)ci * 4 + tap) * y.cout + co] = v;
+        const uint32_t ci0 = i % y.cin, co = (i / y.cin) % y.cout, tap = i / (y.cin * y.cout);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            v[e] = f2bf(y.w[i + e]);
+            y.wb[((size_t)(ci0 + e) * 4 + tap) * y.cout + co] = v[e];
+        }
     }
+    uint4 o;
+    o.x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
+    o.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
+    o.z = (uint32_t)v[4] | ((uint32_t)v[5] << 16);
+    o.w = (uint32_t)v[6] | ((uint32_t)v[7] << 16);
+    *(uint4*)(y.wf + i) = o;
 }
 
 }  // namespace nn
@@ -2533,7 +2550,7 @@ hipError_t prep_weights(const Net& net, const float* th, bool training, const Bu
         e.wb = y.kind == 1 || (training && i > 0) ? b.wt + y.wb_off : nullptr;
         total += y.kind == 0 ? y.cout * 9 * y.cpad : 4 * y.cout * y.cin;
     }
-    if (total) k_prep_all<<<blocks(total), dim3(kBlock), 0, s>>>(t, total);
+    if (total) k_prep_all<<<blocks(total / 8), dim3(kBlock), 0, s>>>(t, total);
     return hipGetLastError();
 }
 
