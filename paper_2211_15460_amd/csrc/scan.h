@@ -3,7 +3,9 @@
 // Three passes over chunks of 2048 values (256 threads x 8 consecutive
 // values): per-chunk sums, one workgroup that scans the chunk sums (with a
 // carry across its own chunks), then every chunk scanned again with its
-// offset and handed to the store functor. Within a workgroup each thread sums
+// offset and handed to the store functor. Up to 1024 chunks the second pass
+// is folded into the third: each chunk's workgroup sums the chunk sums
+// before it. Within a workgroup each thread sums
 // its 8 values, the 64 thread sums of a wave are scanned with shuffles and the
 // 4 wave totals through LDS.
 //
@@ -114,6 +116,38 @@ __global__ void __launch_bounds__(kBlock) k_scan_final(Load ld, Store st, uint64
     }
 }
 
+// k_scan_final without the separate pass over the chunk sums: each
+// workgroup adds up the sums of the chunks before its own (at most
+// kDirectChunks of them; integers, so in any order), and the last one
+// writes the total.
+constexpr uint64_t kDirectChunks = 1024;
+
+template <class T, class Load, class Store>
+__global__ void __launch_bounds__(kBlock) k_scan_direct(Load ld, Store st, uint64_t n, uint64_t nb,
+                                                        const T* __restrict__ partial, T* __restrict__ total)
+{
+    T pre = 0;
+    for (uint64_t c = threadIdx.x; c < blockIdx.x; c += kBlock) pre += partial[c];
+    T off;
+    block_excl_scan(pre, &off);
+    const uint64_t base = (uint64_t)blockIdx.x * kChunk + (uint64_t)threadIdx.x * kItems;
+    T v[kItems];
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        v[k] = (base + k < n) ? ld(base + k) : T(0);
+        s += v[k];
+    }
+    T tot;
+    T run = off + block_excl_scan(s, &tot);
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        if (base + k < n) st(base + k, v[k], run);
+        run += v[k];
+    }
+    if (total && threadIdx.x == 0 && blockIdx.x + 1 == nb) *total = off + tot;
+}
+
 }  // namespace scan_detail
 
 // Number of T elements of scratch scan() needs for n values.
@@ -130,6 +164,10 @@ hipError_t scan(Load ld, Store st, uint64_t n, T* partial, T* total, hipStream_t
     if (n == 0) return hipSuccess;
     const uint64_t nb = (n + kChunk - 1) / kChunk;
     k_reduce<T, Load><<<dim3((unsigned)nb), dim3(kBlock), 0, s>>>(ld, n, partial);
+    if (nb <= kDirectChunks) {
+        k_scan_direct<T, Load, Store><<<dim3((unsigned)nb), dim3(kBlock), 0, s>>>(ld, st, n, nb, partial, total);
+        return hipGetLastError();
+    }
     k_scan_partials<T><<<dim3(1), dim3(kBlock), 0, s>>>(partial, nb, total);
     k_scan_final<T, Load, Store><<<dim3((unsigned)nb), dim3(kBlock), 0, s>>>(ld, st, n, partial);
     return hipGetLastError();
